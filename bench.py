@@ -1,0 +1,176 @@
+"""Benchmark of the FV hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (decaying 2D NS, the paper's decaying flow at 512^2): 512 x 512
+MAC cells, batch 16 trajectories, FP32, nu = 1e-3, GRF initial vorticity
+peaked at k = 4 with unit energy, RK4 with a spectral projection after every
+sub-step, dt = 8.76e-4.  A step is one full RK4 time step of the batch (4
+fused stage kernels and 4 three-pass projections), launched through the C
+ABI on the current stream with the state already resident in HBM.  Prints
+one JSON line on stdout; progress goes to stderr.
+
+The line also carries
+* roofline: the dominant kernel class's average launch duration (HIP events
+  recorded around every launch of that class on its stream during the timed
+  region), its algorithmic bytes per launch, achieved GB/s against 8 TB/s;
+* cpu_baseline: the FP64 CPU oracle timed on this host on a bounded sample
+  of the same workload (2 of the 16 trajectories, one step);
+* learned: the learned step (64^2, batch 64, BF16 CNN on MFMA) when the
+  library provides it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+# algorithmic bytes per cell and launch (FP32, plain stencil), averaged over
+# the four RK4 stage variants for the stage kernel
+STAGE_BYTES = {0: (24 + 40 + 40 + 32) / 4.0, 1: 12.0, 2: 8.0, 3: 20.0}
+CLASS_NAMES = {0: "k_stage_mac (fused residual + RK stage)", 1: "k_div_rowfft",
+               2: "k_col_solve", 3: "k_rowifft_grad"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, u0, v0):
+    """The oracle as it stands on a bounded sample: trajectories 0..1, one step."""
+    import torch
+    from oracle import fv, timestep
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    nb = 2
+    u = u0[:nb].double().cpu()
+    v = v0[:nb].double().cpu()
+    prm = fv.grid_params(w["nx"], w["ny"], nu=w["nu"], dt=w["dt"])
+    t0 = time.perf_counter()
+    timestep.fv_step(u, v, prm)
+    t = time.perf_counter() - t0
+    cells = w["nx"] * w["ny"] * nb
+    return {"value": cells / t, "unit": "cell-steps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": "2 of 16 trajectories of the 512^2 workload, 1 RK4 step "
+            "(%.1f s)" % t}
+
+
+def learned_block(steps, warmup):
+    import torch
+    import synthetic_inputs as si
+    from oracle import cnn as ocnn
+    from paper_2507_01975_amd import ldsv
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    s = ldsv.Solver(n, n, B)
+    ws, bs = si.cnn_weights(0, ocnn.LAYERS)
+    net = ldsv.NetParams([torch.tensor(x) for x in ws], [torch.tensor(x) for x in bs])
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                      forcing_k=w["forcing_k"], drag=w["drag"], k_c=1)
+    try:
+        for k in range(warmup):
+            s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+    except ldsv.LdsvError as e:
+        return {"status": "unavailable: %s" % e}
+    torch.cuda.synchronize()
+    s.timer_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    conv_ms, conv_n = s.timer_read(ldsv.TIMER_CONV)
+    s.timer_enable(False)
+    cells = n * n * B
+    out = {"workload": "kolmogorov64 learned step (64^2, batch 64, 6-layer 64-channel BF16 CNN)",
+           "cell_steps_per_s": cells * steps / t, "ms_per_step": 1e3 * t / steps,
+           "sim_time_per_s": w["dt"] * steps / t}
+    if conv_n:
+        # layers 2..6 on MFMA: 2 * 9 * 64 * Cout FLOP per cell
+        flop = 2 * 9 * 64 * (64 * 4 + 66) * cells
+        per_launch_ms = conv_ms / conv_n
+        launches_per_step = conv_n / steps
+        out["mfma_conv"] = {"tflops": flop / launches_per_step / (per_launch_ms * 1e-3) / 1e12,
+                            "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}
+        out["mfma_conv"]["frac"] = out["mfma_conv"]["tflops"] / BF16_PEAK_TFLOPS
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs the batched step on a single MI355X "
+              "(trajectories would shard across GPUs with no communication); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthetic_inputs as si
+    from paper_2507_01975_amd import ldsv
+
+    w = si.WORKLOADS["decaying512"]
+    n, B = w["nx"], w["batch"]
+    log("workload decaying512: %dx%d, batch %d, fp32, rk4 + projection per stage" % (n, n, B))
+    s = ldsv.Solver(n, n, B)
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=0)
+    u0, v0 = u.clone(), v.clone()
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"])
+    for _ in range(a.warmup):
+        s.fv_step(prm, u, v, out=(u, v))
+    torch.cuda.synchronize()
+    log("warmup done")
+    s.timer_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s.fv_step(prm, u, v, out=(u, v))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cls = {c: s.timer_read(c) for c in range(4)}
+    s.timer_enable(False)
+    log("timed %d steps in %.3f s" % (a.steps, t))
+    diag = s.diagnostics(u, v).cpu()
+    assert bool((diag[:, 5] == 1).all()), "non-finite state after the timed steps"
+
+    cells = n * n * B
+    value = cells * a.steps / t
+    dom = max(cls, key=lambda c: cls[c][0])
+    ms, cnt = cls[dom]
+    avg_s = ms * 1e-3 / cnt
+    alg = STAGE_BYTES[dom] * cells
+    achieved = alg / avg_s / 1e9
+    roof = {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6,
+            "classes_ms_per_step": {CLASS_NAMES[c]: cls[c][0] / a.steps for c in cls}}
+    line = {"metric": "cell-steps/s + sim-time/s at corr>=0.9: learned coarse FV vs plain fine FV",
+            "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": 1e3 * t / a.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "decaying512", "nx": n, "ny": n, "batch": B, "nu": w["nu"],
+                       "dt": w["dt"], "rk": "rk4", "projection": "every sub-step",
+                       "ic": "GRF peaked at k=4, unit energy"},
+            "sim_time_per_s": w["dt"] * a.steps / t,
+            "roofline": roof}
+    if not a.no_learned:
+        log("learned step")
+        line["learned"] = learned_block(max(10, a.steps // 4), 3)
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(w, u0, v0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,270 @@
+/*
+ * ldsv.h -- C ABI of libldsv.so, an MI355X (gfx950) implementation of the
+ * hot path of the learnable-differentiable finite-volume solver (Yan et al.,
+ * KDD 2025): the batched time step on a periodic 2D grid (face interpolation
+ * and flux stencils, viscous fluxes, Runge-Kutta stages, a spectral pressure
+ * projection), with fixed or network-produced stencil coefficients, its
+ * rollout and its adjoint.
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Return value: LDSV_OK (0) or a negative status.  Nothing aborts or
+ *   throws across the ABI.  ldsv_last_error() returns a thread-local message
+ *   describing the last failure on the calling thread.
+ * - Buffers: every array argument is a caller-owned DEVICE pointer (unless
+ *   documented as host), valid for the duration of the stream-ordered work.
+ *   The library never frees or retains caller buffers.  The handle owns its
+ *   workspace (stage buffers, spectra, twiddle tables, activations).
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  All work is enqueued asynchronously on it; no call synchronises
+ *   the device unless documented.  One handle must not be used from two
+ *   streams at once (the workspace is shared).
+ * - Layout: fields are [B][Ny][Nx] row-major, x fastest, in the grid's dtype
+ *   (float for LDSV_F32, double for LDSV_F64).  MAC layout: u[b][j][i] is the
+ *   x-velocity on the west face of cell (i, j), at (i dx, (j+1/2) dy);
+ *   v[b][j][i] the y-velocity on its south face, at ((i+1/2) dx, j dy);
+ *   pressure at cell centres (App. B.1, staggered grid, Fig. S1).
+ *   COLLOCATED layout: u, v at cell centres.  Boundaries are periodic.
+ * - Sizes: Nx and Ny are powers of two in [8, 4096]; MAC grids (which carry
+ *   the spectral projection) are limited to 2048 (FP32) or 1024 (FP64) per
+ *   axis; batch >= 1.
+ */
+#ifndef LDSV_H
+#define LDSV_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(LDSV_BUILDING)
+#define LDSV_API __attribute__((visibility("default")))
+#else
+#define LDSV_API
+#endif
+
+/* ---- status codes ---- */
+#define LDSV_OK 0
+#define LDSV_EINVAL (-1)      /* null pointer or out-of-range argument */
+#define LDSV_ESHAPE (-2)      /* unsupported grid size */
+#define LDSV_EDTYPE (-3)      /* call not available for the grid's dtype/layout */
+#define LDSV_EHIP (-4)        /* HIP runtime error; message has the HIP code */
+#define LDSV_ENONFINITE (-5)  /* guard tripped and fallback disabled */
+#define LDSV_ENOMEM (-6)      /* workspace allocation failed */
+
+/* ---- enums ---- */
+#define LDSV_F32 0
+#define LDSV_F64 1
+#define LDSV_MAC 0           /* incompressible NS on the staggered grid */
+#define LDSV_COLLOCATED 1    /* 2D viscous Burgers on cell centres */
+#define LDSV_RK4 0           /* App. B.5 S15-S20, projection per sub-step */
+#define LDSV_SSPRK3 1        /* Shu-Osher SSP-RK3 (Burgers configuration) */
+#define LDSV_ADVECTION 1     /* physics_mask bits */
+#define LDSV_VISCOSITY 2
+#define LDSV_FORCING 4       /* forcing A sin(k y) and linear drag */
+#define LDSV_ALL_PHYSICS 7
+#define LDSV_IC_FOURIER_MODES 0
+#define LDSV_IC_GRF_PEAK 1
+#define LDSV_IC_TGV 2
+#define LDSV_IC_SHEAR_LAYER 3
+
+/* Number of raw network channels: 4 interpolation kinds x 16 footprint
+ * points (stencil coefficients) + 2 temporal-correction channels. */
+#define LDSV_NCOEF 64
+#define LDSV_NOUT 66
+#define LDSV_NLAYERS 6
+
+typedef struct ldsv_handle ldsv_handle;
+
+/* Grid: Nx x Ny cells on [0,lx) x [0,ly), `batch` independent trajectories. */
+typedef struct {
+  int nx, ny;
+  double lx, ly;
+  int batch;
+  int dtype;   /* LDSV_F32 | LDSV_F64 */
+  int layout;  /* LDSV_MAC | LDSV_COLLOCATED */
+} ldsv_grid;
+
+/* Physics and time-step parameters (Eq. 1 flux parameters mu, source S). */
+typedef struct {
+  double nu;            /* kinematic viscosity (1/Re) */
+  double forcing_amp;   /* A in f_x = A sin(k y)       (App. C.1 forced flow) */
+  double forcing_k;     /* k in f_x = A sin(k y)                               */
+  double drag;          /* d in f = -d u                                       */
+  double dt;            /* time step                                           */
+  int rk;               /* LDSV_RK4 | LDSV_SSPRK3                              */
+  int physics_mask;     /* LDSV_ADVECTION | LDSV_VISCOSITY | LDSV_FORCING      */
+  int k_c;              /* temporal-correction interval (Eq. 2); <= 0: never  */
+  double guard_threshold; /* rollout guard: max|u| bound (<= 0: finite check only) */
+  int fallback_enable;  /* rollout: redo a failed learned step with plain FV   */
+} ldsv_params;
+
+/* Initial-condition shape parameters; NULL selects the defaults in (). */
+typedef struct {
+  double amp;        /* TGV amplitude (1)                                      */
+  double k;          /* TGV wavenumber in units of 2 pi / L (1)                */
+  double delta;      /* shear-layer thickness (1/30)                           */
+  double pert;       /* shear-layer v perturbation amplitude (0.05)            */
+  double noise_rms;  /* shear-layer noise rms (1e-3)                           */
+  double kpeak;      /* GRF spectral peak (4)                                  */
+} ldsv_ic_args;
+
+/* The coefficient network: 6 conv3x3 layers 2->64->64->64->64->64->66, with
+ * bias, circular padding, exact GELU after layers 0..4.  Weights are bfloat16
+ * bit patterns laid out [Cout][3][3][Cin] (tap (dy,dx) row-major, Cin
+ * fastest); biases float [Cout]. */
+typedef struct {
+  const uint16_t* w[LDSV_NLAYERS];
+  const float* b[LDSV_NLAYERS];
+} ldsv_net;
+
+/* Gradient of the network parameters, float, same layouts as ldsv_net. */
+typedef struct {
+  float* w[LDSV_NLAYERS];
+  float* b[LDSV_NLAYERS];
+} ldsv_net_grad;
+
+/* ---- lifecycle ---- */
+LDSV_API int ldsv_version(void);
+LDSV_API const char* ldsv_last_error(void);
+/* Creates a handle for grid *g on the current HIP device and allocates its
+ * workspace (about 8 state-sized arrays plus network activations when the
+ * grid is LDSV_F32/LDSV_MAC).  Errors: EINVAL, ESHAPE, ENOMEM, EHIP. */
+LDSV_API int ldsv_create(ldsv_handle** h, const ldsv_grid* g);
+LDSV_API int ldsv_destroy(ldsv_handle* h);
+/* Bytes of device workspace the handle holds. */
+LDSV_API int ldsv_workspace_bytes(const ldsv_handle* h, size_t* bytes);
+
+/* ---- a0: seeded initial conditions (App. C.1; S30-S31) ----
+ * kind: LDSV_IC_FOURIER_MODES (collocated; 24 half-plane modes |k| <= 4,
+ * N(0,1) cos/sin amplitudes, max|u| = 1), LDSV_IC_GRF_PEAK (MAC; Gaussian
+ * random streamfunction with energy spectrum k^4 exp(-2 (k/kpeak)^2), unit
+ * energy), LDSV_IC_TGV (MAC Taylor-Green vortex), LDSV_IC_SHEAR_LAYER (MAC
+ * tanh shear layers + v perturbation + divergence-free noise).  Random draws:
+ * SplitMix64 stream seeded seed + b * 0xD1B54A32D192ED03 for trajectory b,
+ * Box-Muller normals.  Writes u, v ([B][Ny][Nx]). */
+LDSV_API int ldsv_init_state(ldsv_handle* h, int kind, uint64_t seed, const ldsv_ic_args* args,
+                    void* u, void* v, void* stream);
+
+/* ---- a1-a7: the FV residual R(u) without pressure (Eq. 4; S1-S7) ----
+ * coef: NULL for the physics stencil, else raw network values r, float
+ * [B][64][Ny][Nx] (channel 16K+s: kind K, footprint point s), constrained on
+ * the fly to c = c_P + r - mean(r) per kind and cell.  MAC/F32 only for coef.
+ * Writes ru, rv. */
+LDSV_API int ldsv_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coef,
+             const void* u, const void* v, void* ru, void* rv, void* stream);
+
+/* ---- a1-a11: the FV module, nsteps time steps (Sec. 3.2; S15-S20) ----
+ * RK4 with a projection after every sub-step (MAC) or SSP-RK3 (collocated,
+ * no pressure).  coef as in ldsv_rhs (same coefficients every step).
+ * In-place (u_out == u_in) is allowed.  nsteps >= 1. */
+LDSV_API int ldsv_fv_step(ldsv_handle* h, const ldsv_params* prm, const float* coef,
+                 const void* u_in, const void* v_in, void* u_out, void* v_out,
+                 int nsteps, void* stream);
+
+/* ---- a9-a11: pressure projection (App. B.3-B.4; S8-S14) ----
+ * u <- u - G p with D G p = D u, solved by FFT with the compact-MAC
+ * eigenvalues and a zero mean mode.  p_out (nullable): the potential p,
+ * [B][Ny][Nx].  MAC only.  The projection is symmetric, so it is also its
+ * own adjoint (ldsv_project_bwd is the same operation). */
+LDSV_API int ldsv_project(ldsv_handle* h, void* u, void* v, void* p_out, void* stream);
+LDSV_API int ldsv_project_bwd(ldsv_handle* h, void* gu, void* gv, void* stream);
+
+/* ---- a12: the coefficient network (Sec. 3.4) ----
+ * out: float [B][66][Ny][Nx] (64 raw stencil values, then TC_u, TC_v).
+ * F32/MAC grids only. */
+LDSV_API int ldsv_cnn_forward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                     float* out, void* stream);
+
+/* ---- a12-a13: the learned step (Eq. 2) ----
+ * Runs the network once on u_{k-1}, the FV module with its coefficients,
+ * and, when step_index % k_c == 0, adds the temporal correction before the
+ * last projection: u_k = P(FV(u_{k-1}) + TC).  step_index is k, the index
+ * of the output state.  net_out (nullable): receives the network output
+ * [B][66][Ny][Nx]. */
+LDSV_API int ldsv_learned_fv_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                         const float* u_in, const float* v_in, float* u_out, float* v_out,
+                         int step_index, float* net_out, void* stream);
+
+/* ---- a14: rollout (Eq. 2 recursion) ----
+ * net NULL: plain FV.  Writes states u_{first+save_every-1}, ... : snapshot t
+ * (t = 0 .. nsteps/save_every - 1) is the state after (t+1)*save_every steps,
+ * into traj_u/traj_v [T][B][Ny][Nx].  fallback_flags (nullable, int [B]):
+ * counts, per trajectory, learned steps that produced a non-finite state or
+ * max|u| > guard_threshold and were redone with the plain FV step (when
+ * fallback_enable), else the call returns LDSV_ENONFINITE.  The guard reads
+ * one int per step back to the host. */
+LDSV_API int ldsv_rollout(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                 const void* u0, const void* v0, int nsteps, int save_every, int first_index,
+                 void* traj_u, void* traj_v, int* fallback_flags, void* stream);
+
+/* ---- a15: adjoints ----
+ * ldsv_fv_step_bwd: vector-Jacobian product of ONE fv_step at (u_in, v_in)
+ * with fixed coef: given gu_out = dL/du_out, writes gu_in = dL/du_in and,
+ * if gcoef != NULL and coef != NULL, ACCUMULATES dL/dr into gcoef (float
+ * [B][64][Ny][Nx]).  Forward stage states are recomputed internally. */
+LDSV_API int ldsv_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef,
+                     const void* u_in, const void* v_in, const void* gu_out, const void* gv_out,
+                     void* gu_in, void* gv_in, float* gcoef, void* stream);
+/* ldsv_cnn_backward: given gout = dL/d(net output) [B][66][Ny][Nx], writes
+ * gu, gv = dL/d(u, v) (nullable) and ACCUMULATES parameter gradients into
+ * *dW.  Recomputes the forward activations from (u, v). */
+LDSV_API int ldsv_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                      const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
+                      void* stream);
+/* ldsv_learned_fv_step_bwd: VJP of ldsv_learned_fv_step (same arguments);
+ * writes gu_in, gv_in and accumulates dW. */
+LDSV_API int ldsv_learned_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                             const float* u_in, const float* v_in, int step_index,
+                             const float* gu_out, const float* gv_out,
+                             float* gu_in, float* gv_in, const ldsv_net_grad* dW, void* stream);
+
+/* ---- a16: loss and optimiser (Eq. 13; App. D.3) ----
+ * ldsv_mse_grad: loss contribution 0.5*(mean((u-lu)^2) + mean((v-lv)^2))
+ * accumulated in FP64 into *loss_dev (device double, nullable), and the
+ * gradient scale*(u-lu)/n, scale*(v-lv)/n written to gu, gv. */
+LDSV_API int ldsv_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* lu,
+                  const float* lv, double scale, float* gu, float* gv, double* loss_dev,
+                  void* stream);
+/* Adam with bias correction over n floats: m, v moments, step t >= 1. */
+LDSV_API int ldsv_adam_step(float* w, const float* g, float* m, float* v, size_t n, int t, double lr,
+                   double beta1, double beta2, double eps, void* stream);
+/* Round float master weights to bfloat16 bit patterns (nearest even). */
+LDSV_API int ldsv_to_bf16(const float* src, uint16_t* dst, size_t n, void* stream);
+
+/* ---- a17: down-sampling, vorticity, correlation (Sec. 4.1; S32-S36) ----
+ * MAC face averaging by integer ratio r (fine [B][r Ny][r Nx] -> coarse
+ * [B][Ny][Nx] of this handle's grid). */
+LDSV_API int ldsv_downsample(ldsv_handle* h, int r, const float* uf, const float* vf, float* uc,
+                    float* vc, void* stream);
+/* Corner vorticity w = (v - v[i-1])/dx - (u - u[j-1])/dy, [B][Ny][Nx]. */
+LDSV_API int ldsv_vorticity(ldsv_handle* h, const void* u, const void* v, void* w, void* stream);
+/* Pearson correlation per trajectory of two [B][Ny][Nx] fields, FP64
+ * moments, written to pcc_dev (device double [B]). */
+LDSV_API int ldsv_pcc(ldsv_handle* h, const void* a, const void* b, double* pcc_dev, void* stream);
+/* Per-trajectory diagnostics, FP64, into diag_dev (device double [B][6]):
+ * max|u|+|v|, kinetic energy 1/2<u^2+v^2>, mean u, mean v, ||D u||_2
+ * (MAC only, else 0), and 1 if every value is finite else 0. */
+LDSV_API int ldsv_diagnostics(ldsv_handle* h, const void* u, const void* v, double* diag_dev,
+                     void* stream);
+/* dt = cfl * min(dx, dy) / max over all cells and trajectories of |u|+|v|
+ * (synchronises the stream; host result). */
+LDSV_API int ldsv_cfl_dt(ldsv_handle* h, const void* u, const void* v, double cfl, double* dt_host,
+                void* stream);
+
+/* ---- measurement ----
+ * Kernel classes timed by ldsv_timer_*: 0 RK stage (fused residual), 1 row
+ * FFT + divergence, 2 column FFT + Poisson division, 3 inverse row FFT +
+ * gradient correction, 4 convolution (MFMA), 5 first convolution layer,
+ * 6 adjoint stage, 7 other.  While enabled, every launch of a class is
+ * bracketed by HIP events on its stream.  ldsv_timer_read synchronises the
+ * device and returns the summed duration (ms) and the launch count. */
+LDSV_API int ldsv_timer_enable(ldsv_handle* h, int on);
+LDSV_API int ldsv_timer_read(ldsv_handle* h, int cls, double* total_ms, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDSV_H */

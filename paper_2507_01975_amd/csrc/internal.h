@@ -1,0 +1,137 @@
+// Internal declarations of libldsv: the handle, error reporting, complex
+// arithmetic and the launch helpers shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ldsv.h"
+
+// ---------------------------------------------------------------- errors
+void ldsv_set_error(const char* fmt, ...);
+
+#define LDSV_REQUIRE(cond, code, ...)      \
+  do {                                     \
+    if (!(cond)) {                         \
+      ldsv_set_error(__VA_ARGS__);         \
+      return (code);                       \
+    }                                      \
+  } while (0)
+
+#define LDSV_HIP(call)                                                          \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ldsv_set_error("HIP error %d (%s) at %s:%d", (int)e_, hipGetErrorString(e_), \
+                     __FILE__, __LINE__);                                       \
+      return LDSV_EHIP;                                                         \
+    }                                                                           \
+  } while (0)
+
+#define LDSV_LAUNCHED() LDSV_HIP(hipGetLastError())
+
+#define LDSV_TRY(expr)          \
+  do {                          \
+    int s_ = (expr);            \
+    if (s_ != LDSV_OK) return s_; \
+  } while (0)
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct Cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// ---------------------------------------------------------------- timing
+// Optional per-kernel-class timing with HIP events recorded on the launch
+// stream around each launch (used by the benchmark to measure the dominant
+// kernel's average duration inside its timed region).
+constexpr int kTimerClasses = 8;
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev[kTimerClasses];  // start/stop pairs
+  std::vector<hipEvent_t> pool;
+};
+
+// ---------------------------------------------------------------- handle
+struct ldsv_handle {
+  ldsv_grid g;
+  int device;
+  int log2nx, log2ny;
+  size_t ncell;    // nx * ny
+  size_t nstate;   // batch * nx * ny
+  int npairs;      // ceil(batch / 2): trajectories packed two per complex FFT
+  size_t esize;    // sizeof element (4 or 8)
+
+  // workspace (element type = grid dtype)
+  void* ws_u = nullptr;   // RK stage state
+  void* ws_v = nullptr;
+  void* st_u = nullptr;   // pre-projection state u*
+  void* st_v = nullptr;
+  void* acc_u = nullptr;  // RK accumulator (acc_v follows acc_u contiguously)
+  void* acc_v = nullptr;
+  void* base_u = nullptr; // copy of u_n when a step runs in place
+  void* base_v = nullptr;
+  void* zspec = nullptr;  // complex spectrum [npairs][ny][nx]
+  void* twx = nullptr;    // exp(-2 pi i m / nx), complex of dtype
+  void* twy = nullptr;
+  double* red = nullptr;  // reduction partials
+  size_t red_len = 0;
+  double* small = nullptr;  // reduction results, 16 doubles per trajectory
+  double* small_host = nullptr;  // pinned host mirror of `small`
+  int* flag_dev = nullptr;
+
+  // learned-path workspace (F32 MAC grids only)
+  uint16_t* act[6] = {nullptr};  // bf16 activations [B][Ny][Nx][64] (input of layer l+1)
+  float* pre[5] = {nullptr};     // unused unless backward: pre-activation cache
+  float* netout = nullptr;       // [B][66][Ny][Nx]
+  float* gnet = nullptr;         // [B][66][Ny][Nx] gradient of network output
+  float* gact = nullptr;         // [B][Ny][Nx][64] float gradient buffers
+  float* gact2 = nullptr;
+  void* stage_keep = nullptr;    // forward stage states for the adjoint (4 x 2 x state)
+  void* adj_u = nullptr;         // adjoint work arrays (2 x state each)
+  void* adj_k = nullptr;
+  void* adj_g = nullptr;
+  void* save_u = nullptr;        // rollout fallback copy of u_{k-1}
+  size_t bytes = 0;
+  KernelTimer timer;
+};
+
+// RAII: records a start event at construction and a stop event at
+// destruction on stream st when timing is enabled for the handle.
+struct TimerScope {
+  ldsv_handle* h;
+  int cls;
+  hipStream_t st;
+  TimerScope(ldsv_handle* h_, int cls_, hipStream_t st_);
+  ~TimerScope();
+};
+
+int ldsv_check_handle(const ldsv_handle* h);
+
+// device-wide block size
+constexpr int kBlock = 256;
+
+inline dim3 grid1d(size_t n, int block = kBlock) {
+  size_t g = (n + block - 1) / block;
+  if (g > 65535u * 64u) g = 65535u * 64u;
+  return dim3((unsigned)g);
+}

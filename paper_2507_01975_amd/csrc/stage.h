@@ -1,0 +1,33 @@
+// Host-side interface of the fused RK stage kernels.
+#pragma once
+
+#include "internal.h"
+
+// One Runge-Kutta stage, fused with the finite-volume residual R(us):
+//   out   = alpha * un + beta * us + delta * acc + eps * R(us) [+ tc]
+//   acc'  = gamma * acc + wacc * R(us)
+// (delta and eps include the time step).  Pointers marked nullable are
+// skipped when their coefficient is zero / when absent.
+struct StageArgs {
+  const void* us = nullptr;
+  const void* vs = nullptr;
+  const void* un = nullptr;   // nullable when alpha == 0
+  const void* vn = nullptr;
+  const void* accu = nullptr; // nullable when delta == 0 and gamma == 0
+  const void* accv = nullptr;
+  void* ou = nullptr;
+  void* ov = nullptr;
+  void* oaccu = nullptr;      // nullable: no accumulator output
+  void* oaccv = nullptr;
+  const float* coef = nullptr;  // raw learned stencil values, planar, nullable
+  size_t coef_bstride = 0;      // elements between trajectories
+  const float* tcu = nullptr;   // temporal correction added to out, nullable
+  const float* tcv = nullptr;
+  size_t tc_bstride = 0;
+  double alpha = 0, beta = 0, delta = 0, eps = 0, gamma = 0, wacc = 0;
+};
+
+int ldsv_launch_stage(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a,
+                      hipStream_t st);
+int ldsv_launch_project(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo,
+                        void* po, hipStream_t st);

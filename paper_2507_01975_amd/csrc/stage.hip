@@ -1,0 +1,383 @@
+// Fused finite-volume residual + Runge-Kutta stage kernels.
+//
+// MAC (incompressible NS, Sec. 3.3 Eqs. 3-4; App. B.2 S1-S7): for the u
+// control volume centred at (i dx, (j+1/2) dy)
+//   R_u = -(Phi^u_x[i] - Phi^u_x[i-1])/dx - (Phi^u_y[j] - Phi^u_y[j-1])/dy + f_x
+// with face fluxes Phi = (advecting velocity)*(interpolated u) - nu*(face
+// derivative of u).  The advecting velocity is the linear average of the
+// normal velocity; the interpolated value is the physics stencil (midpoint
+// average) or the learned 16-point stencil c = c_P + r - mean(r); the face
+// derivative is the fourth-order [1, -27, 27, -1]/(24 h) kernel (S6).  The v
+// equation mirrors it.  Forcing f = [A sin(k y) - d u, -d v] (App. C.1).
+//
+// Collocated (2D viscous Burgers, S25): flux form minus q*div with a
+// second-order linear-upwind advected value and compact viscous term.
+//
+// One workgroup owns a TX x TY tile of cells.  It stages the stage state
+// with a periodic halo of 2 cells in LDS, computes every face flux once
+// (each face belongs to exactly one cell: the east face of the x-fluxes and
+// the north face of the y-fluxes, so flux differences telescope and
+// momentum is conserved), then forms R per cell and the RK combination in
+// registers.  HBM traffic per cell: one read of the stage state, the base
+// state and the accumulator as needed, one write of the outputs.
+#include "stage.h"
+
+namespace {
+
+constexpr int kMaxTX = 64;
+constexpr int kMaxTY = 16;
+constexpr int kH = 2;  // halo
+constexpr int kSX = kMaxTX + 2 * kH;
+constexpr int kSY = kMaxTY + 2 * kH;
+
+// footprint point s: along-normal offset A_OFF[s], across offset B_OFF[s]
+__constant__ int kAOff[16] = {-1, 0, 1, 2, -1, 0, 1, 2, -1, 0, 1, 2, 0, 1, 0, 1};
+__constant__ int kBOff[16] = {-1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -2, -2, 2, 2};
+
+struct Phys {
+  double nu, amp, kf, drag, dx, dy;
+  int mask;
+};
+
+struct Comb {
+  double alpha, beta, delta, eps, gamma, wacc;
+};
+
+template <typename T>
+struct StagePtrs {
+  const T* us;
+  const T* vs;
+  const T* un;
+  const T* vn;
+  const T* accu;
+  const T* accv;
+  T* ou;
+  T* ov;
+  T* oaccu;
+  T* oaccv;
+  const float* coef;
+  size_t cbs;
+  const float* tcu;
+  const float* tcv;
+  size_t tcbs;
+};
+
+// learned interpolation at a face owned by global cell (gi, gj), kind K;
+// q(a, b) is the tile value at along offset a, across offset b
+template <typename T, bool ALONG_X>
+__device__ __forceinline__ T learned_face(const T (*S)[kSX], int lj, int li, const float* cb,
+                                          int kind, size_t plane, size_t off) {
+  T r[16];
+  T m = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    r[s] = (T)cb[(size_t)(16 * kind + s) * plane + off];
+    m += r[s];
+  }
+  m *= (T)(1.0 / 16.0);
+  T acc = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const T q = ALONG_X ? S[lj + kBOff[s]][li + kAOff[s]] : S[lj + kAOff[s]][li + kBOff[s]];
+    acc += (r[s] - m) * q;
+  }
+  const T q0 = S[lj][li];
+  const T q1 = ALONG_X ? S[lj][li + 1] : S[lj + 1][li];
+  return acc + (T)0.5 * (q0 + q1);
+}
+
+template <typename T, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, Comb cb, int nx,
+                                                      int ny, int TX, int TY) {
+  __shared__ T su[kSY][kSX];
+  __shared__ T sv[kSY][kSX];
+  __shared__ T fux[kMaxTY][kMaxTX + 1];
+  __shared__ T fvx[kMaxTY][kMaxTX + 1];
+  __shared__ T fuy[kMaxTY + 1][kMaxTX];
+  __shared__ T fvy[kMaxTY + 1][kMaxTX];
+  __shared__ T frow[kMaxTY];
+
+  const int tilesx = nx / TX;
+  const int i0 = (blockIdx.x % tilesx) * TX;
+  const int j0 = (blockIdx.x / tilesx) * TY;
+  const int b = blockIdx.y;
+  const size_t plane = (size_t)nx * ny;
+  const size_t boff = (size_t)b * plane;
+  const int W = TX + 2 * kH, Hh = TY + 2 * kH;
+
+  for (int t = threadIdx.x; t < W * Hh; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    const int gj = (j0 - kH + r + ny) & (ny - 1);
+    const int gi = (i0 - kH + c + nx) & (nx - 1);
+    const size_t g = boff + (size_t)gj * nx + gi;
+    su[r][c] = p.us[g];
+    sv[r][c] = p.vs[g];
+  }
+  if ((ph.mask & LDSV_FORCING) && threadIdx.x < TY)
+    frow[threadIdx.x] = (T)(ph.amp * sin(ph.kf * ((j0 + threadIdx.x) + 0.5) * ph.dy));
+  __syncthreads();
+
+  const bool adv = ph.mask & LDSV_ADVECTION;
+  const bool visc = ph.mask & LDSV_VISCOSITY;
+  const T nu = (T)ph.nu;
+  const T i24dx = (T)(1.0 / (24.0 * ph.dx)), i24dy = (T)(1.0 / (24.0 * ph.dy));
+  const float* cbase = LEARNED ? p.coef + (size_t)b * p.cbs : nullptr;
+
+  // x-faces: owners i in [i0-1, i0+TX-1], rows j in [j0, j0+TY-1]
+  for (int t = threadIdx.x; t < TY * (TX + 1); t += blockDim.x) {
+    const int r = t / (TX + 1), c = t - r * (TX + 1);
+    const int li = c + 1, lj = r + kH;
+    T fu = 0, fv = 0;
+    if (adv) {
+      const T ubar = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
+      const T ubar_e = (T)0.5 * (su[lj - 1][li + 1] + su[lj][li + 1]);
+      T uf, vf;
+      if (LEARNED) {
+        const int gi = (i0 - 1 + c + nx) & (nx - 1);
+        const size_t off = (size_t)(j0 + r) * nx + gi;
+        uf = learned_face<T, true>(su, lj, li, cbase, 0, plane, off);
+        vf = learned_face<T, true>(sv, lj, li, cbase, 2, plane, off);
+      } else {
+        uf = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
+        vf = (T)0.5 * (sv[lj][li] + sv[lj][li + 1]);
+      }
+      fu = ubar * uf;
+      fv = ubar_e * vf;
+    }
+    if (visc) {
+      fu -= nu * (su[lj][li - 1] - (T)27 * su[lj][li] + (T)27 * su[lj][li + 1] - su[lj][li + 2]) * i24dx;
+      fv -= nu * (sv[lj][li - 1] - (T)27 * sv[lj][li] + (T)27 * sv[lj][li + 1] - sv[lj][li + 2]) * i24dx;
+    }
+    fux[r][c] = fu;
+    fvx[r][c] = fv;
+  }
+  // y-faces: owners j in [j0-1, j0+TY-1], columns i in [i0, i0+TX-1]
+  for (int t = threadIdx.x; t < (TY + 1) * TX; t += blockDim.x) {
+    const int r = t / TX, c = t - r * TX;
+    const int li = c + kH, lj = r + 1;
+    T fu = 0, fv = 0;
+    if (adv) {
+      const T vbar_n = (T)0.5 * (sv[lj + 1][li - 1] + sv[lj + 1][li]);
+      const T vbar_c = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
+      T uf, vf;
+      if (LEARNED) {
+        const int gj = (j0 - 1 + r + ny) & (ny - 1);
+        const size_t off = (size_t)gj * nx + (i0 + c);
+        uf = learned_face<T, false>(su, lj, li, cbase, 1, plane, off);
+        vf = learned_face<T, false>(sv, lj, li, cbase, 3, plane, off);
+      } else {
+        uf = (T)0.5 * (su[lj][li] + su[lj + 1][li]);
+        vf = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
+      }
+      fu = vbar_n * uf;
+      fv = vbar_c * vf;
+    }
+    if (visc) {
+      fu -= nu * (su[lj - 1][li] - (T)27 * su[lj][li] + (T)27 * su[lj + 1][li] - su[lj + 2][li]) * i24dy;
+      fv -= nu * (sv[lj - 1][li] - (T)27 * sv[lj][li] + (T)27 * sv[lj + 1][li] - sv[lj + 2][li]) * i24dy;
+    }
+    fuy[r][c] = fu;
+    fvy[r][c] = fv;
+  }
+  __syncthreads();
+
+  const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
+  const T drag = (T)ph.drag;
+  const bool force = ph.mask & LDSV_FORCING;
+  for (int t = threadIdx.x; t < TY * TX; t += blockDim.x) {
+    const int r = t / TX, c = t - r * TX;
+    const T uc = su[r + kH][c + kH], vc = sv[r + kH][c + kH];
+    T ru = -(fux[r][c + 1] - fux[r][c]) * idx - (fuy[r + 1][c] - fuy[r][c]) * idy;
+    T rv = -(fvx[r][c + 1] - fvx[r][c]) * idx - (fvy[r + 1][c] - fvy[r][c]) * idy;
+    if (force) {
+      ru += frow[r] - drag * uc;
+      rv -= drag * vc;
+    }
+    const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
+    T ou = (T)cb.beta * uc + (T)cb.eps * ru;
+    T ov = (T)cb.beta * vc + (T)cb.eps * rv;
+    if (cb.alpha != 0.0) {
+      ou += (T)cb.alpha * p.un[g];
+      ov += (T)cb.alpha * p.vn[g];
+    }
+    T au = 0, av = 0;
+    if (cb.delta != 0.0 || cb.gamma != 0.0) {
+      au = p.accu[g];
+      av = p.accv[g];
+      ou += (T)cb.delta * au;
+      ov += (T)cb.delta * av;
+    }
+    if (p.tcu) {
+      const size_t gt = (size_t)b * p.tcbs + (size_t)(j0 + r) * nx + (i0 + c);
+      ou += (T)p.tcu[gt];
+      ov += (T)p.tcv[gt];
+    }
+    p.ou[g] = ou;
+    p.ov[g] = ov;
+    if (p.oaccu) {
+      p.oaccu[g] = (T)cb.gamma * au + (T)cb.wacc * ru;
+      p.oaccv[g] = (T)cb.gamma * av + (T)cb.wacc * rv;
+    }
+  }
+}
+
+// collocated tiles are at most 64 x 8 (six flux arrays instead of four)
+constexpr int kMaxTYc = 8;
+constexpr int kSYc = kMaxTYc + 2 * kH;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, Phys ph, Comb cb, int nx,
+                                                      int ny, int TX, int TY) {
+  __shared__ T su[kSYc][kSX];
+  __shared__ T sv[kSYc][kSX];
+  __shared__ T ae[kMaxTYc][kMaxTX + 1];
+  __shared__ T fue[kMaxTYc][kMaxTX + 1];
+  __shared__ T fve[kMaxTYc][kMaxTX + 1];
+  __shared__ T bn[kMaxTYc + 1][kMaxTX];
+  __shared__ T fun[kMaxTYc + 1][kMaxTX];
+  __shared__ T fvn[kMaxTYc + 1][kMaxTX];
+
+  const int tilesx = nx / TX;
+  const int i0 = (blockIdx.x % tilesx) * TX;
+  const int j0 = (blockIdx.x / tilesx) * TY;
+  const int b = blockIdx.y;
+  const size_t plane = (size_t)nx * ny;
+  const size_t boff = (size_t)b * plane;
+  const int W = TX + 2 * kH, Hh = TY + 2 * kH;
+  for (int t = threadIdx.x; t < W * Hh; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    const int gj = (j0 - kH + r + ny) & (ny - 1);
+    const int gi = (i0 - kH + c + nx) & (nx - 1);
+    const size_t g = boff + (size_t)gj * nx + gi;
+    su[r][c] = p.us[g];
+    sv[r][c] = p.vs[g];
+  }
+  __syncthreads();
+  const bool adv = ph.mask & LDSV_ADVECTION;
+  if (adv) {
+    for (int t = threadIdx.x; t < TY * (TX + 1); t += blockDim.x) {
+      const int r = t / (TX + 1), c = t - r * (TX + 1);
+      const int li = c + 1, lj = r + kH;
+      const T a = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
+      T qu, qv;
+      if (a > (T)0) {
+        qu = (T)-0.5 * su[lj][li - 1] + (T)1.5 * su[lj][li];
+        qv = (T)-0.5 * sv[lj][li - 1] + (T)1.5 * sv[lj][li];
+      } else {
+        qu = (T)1.5 * su[lj][li + 1] - (T)0.5 * su[lj][li + 2];
+        qv = (T)1.5 * sv[lj][li + 1] - (T)0.5 * sv[lj][li + 2];
+      }
+      ae[r][c] = a;
+      fue[r][c] = a * qu;
+      fve[r][c] = a * qv;
+    }
+    for (int t = threadIdx.x; t < (TY + 1) * TX; t += blockDim.x) {
+      const int r = t / TX, c = t - r * TX;
+      const int li = c + kH, lj = r + 1;
+      const T bb = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
+      T qu, qv;
+      if (bb > (T)0) {
+        qu = (T)-0.5 * su[lj - 1][li] + (T)1.5 * su[lj][li];
+        qv = (T)-0.5 * sv[lj - 1][li] + (T)1.5 * sv[lj][li];
+      } else {
+        qu = (T)1.5 * su[lj + 1][li] - (T)0.5 * su[lj + 2][li];
+        qv = (T)1.5 * sv[lj + 1][li] - (T)0.5 * sv[lj + 2][li];
+      }
+      bn[r][c] = bb;
+      fun[r][c] = bb * qu;
+      fvn[r][c] = bb * qv;
+    }
+  }
+  __syncthreads();
+  const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
+  const T idx2 = idx * idx, idy2 = idy * idy;
+  const T nu = (T)ph.nu;
+  const bool visc = ph.mask & LDSV_VISCOSITY;
+  for (int t = threadIdx.x; t < TY * TX; t += blockDim.x) {
+    const int r = t / TX, c = t - r * TX;
+    const int lj = r + kH, li = c + kH;
+    const T uc = su[lj][li], vc = sv[lj][li];
+    T ru = 0, rv = 0;
+    if (adv) {
+      const T dv = (ae[r][c + 1] - ae[r][c]) * idx + (bn[r + 1][c] - bn[r][c]) * idy;
+      ru = -((fue[r][c + 1] - fue[r][c]) * idx + (fun[r + 1][c] - fun[r][c]) * idy) + uc * dv;
+      rv = -((fve[r][c + 1] - fve[r][c]) * idx + (fvn[r + 1][c] - fvn[r][c]) * idy) + vc * dv;
+    }
+    if (visc) {
+      ru += nu * ((su[lj][li + 1] - (T)2 * uc + su[lj][li - 1]) * idx2 +
+                  (su[lj + 1][li] - (T)2 * uc + su[lj - 1][li]) * idy2);
+      rv += nu * ((sv[lj][li + 1] - (T)2 * vc + sv[lj][li - 1]) * idx2 +
+                  (sv[lj + 1][li] - (T)2 * vc + sv[lj - 1][li]) * idy2);
+    }
+    const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
+    T ou = (T)cb.beta * uc + (T)cb.eps * ru;
+    T ov = (T)cb.beta * vc + (T)cb.eps * rv;
+    if (cb.alpha != 0.0) {
+      ou += (T)cb.alpha * p.un[g];
+      ov += (T)cb.alpha * p.vn[g];
+    }
+    T au = 0, av = 0;
+    if (cb.delta != 0.0 || cb.gamma != 0.0) {
+      au = p.accu[g];
+      av = p.accv[g];
+      ou += (T)cb.delta * au;
+      ov += (T)cb.delta * av;
+    }
+    p.ou[g] = ou;
+    p.ov[g] = ov;
+    if (p.oaccu) {
+      p.oaccu[g] = (T)cb.gamma * au + (T)cb.wacc * ru;
+      p.oaccv[g] = (T)cb.gamma * av + (T)cb.wacc * rv;
+    }
+  }
+}
+
+template <typename T>
+int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, hipStream_t st) {
+  StagePtrs<T> p;
+  p.us = (const T*)a.us;
+  p.vs = (const T*)a.vs;
+  p.un = (const T*)a.un;
+  p.vn = (const T*)a.vn;
+  p.accu = (const T*)a.accu;
+  p.accv = (const T*)a.accv;
+  p.ou = (T*)a.ou;
+  p.ov = (T*)a.ov;
+  p.oaccu = (T*)a.oaccu;
+  p.oaccv = (T*)a.oaccv;
+  p.coef = a.coef;
+  p.cbs = a.coef_bstride;
+  p.tcu = a.tcu;
+  p.tcv = a.tcv;
+  p.tcbs = a.tc_bstride;
+  Phys ph{prm->nu, prm->forcing_amp, prm->forcing_k, prm->drag, h->g.lx / h->g.nx,
+          h->g.ly / h->g.ny, prm->physics_mask};
+  Comb cb{a.alpha, a.beta, a.delta, a.eps, a.gamma, a.wacc};
+  const int nx = h->g.nx, ny = h->g.ny;
+  TimerScope ts(h, 0, st);
+  const int TX = nx < kMaxTX ? nx : kMaxTX;
+  if (h->g.layout == LDSV_COLLOCATED) {
+    const int TYc = ny < kMaxTYc ? ny : kMaxTYc;
+    dim3 gridc((nx / TX) * (ny / TYc), h->g.batch);
+    hipLaunchKernelGGL(k_stage_col<T>, gridc, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TYc);
+    LDSV_LAUNCHED();
+    return LDSV_OK;
+  }
+  const int TY = ny < kMaxTY ? ny : kMaxTY;
+  dim3 grid((nx / TX) * (ny / TY), h->g.batch);
+  if (a.coef) {
+    hipLaunchKernelGGL((k_stage_mac<T, true>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
+  } else {
+    hipLaunchKernelGGL((k_stage_mac<T, false>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
+  }
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}
+
+}  // namespace
+
+int ldsv_launch_stage(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a,
+                      hipStream_t st) {
+  if (h->g.dtype == LDSV_F64) return launch_stage_t<double>(h, prm, a, st);
+  return launch_stage_t<float>(h, prm, a, st);
+}

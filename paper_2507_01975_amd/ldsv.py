@@ -1,0 +1,384 @@
+"""ctypes binding of libldsv.so (argument marshalling only).
+
+Every function takes torch tensors that already live on the GPU, checks
+their dtype, shape and contiguity, and passes raw device pointers and the
+current HIP stream to the C ABI declared in include/ldsv.h.  No numerical
+step runs here.  If the shared library is missing the import fails loudly:
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libldsv.so")
+
+OK, EINVAL, ESHAPE, EDTYPE, EHIP, ENONFINITE, ENOMEM = 0, -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+MAC, COLLOCATED = 0, 1
+RK4, SSPRK3 = 0, 1
+ADVECTION, VISCOSITY, FORCING, ALL_PHYSICS = 1, 2, 4, 7
+IC_FOURIER_MODES, IC_GRF_PEAK, IC_TGV, IC_SHEAR_LAYER = 0, 1, 2, 3
+NCOEF, NOUT, NLAYERS = 64, 66, 6
+
+
+class LdsvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("ldsv error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libldsv.so is not built (%s); run `python -m paper_2507_01975_amd.build`"
+                          % LIB_PATH)
+    return ctypes.CDLL(LIB_PATH)
+
+
+_lib = _load()
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("batch", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("layout", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("forcing_amp", ctypes.c_double),
+                ("forcing_k", ctypes.c_double), ("drag", ctypes.c_double),
+                ("dt", ctypes.c_double), ("rk", ctypes.c_int), ("physics_mask", ctypes.c_int),
+                ("k_c", ctypes.c_int), ("guard_threshold", ctypes.c_double),
+                ("fallback_enable", ctypes.c_int)]
+
+
+class ICArgs(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("k", ctypes.c_double), ("delta", ctypes.c_double),
+                ("pert", ctypes.c_double), ("noise_rms", ctypes.c_double),
+                ("kpeak", ctypes.c_double)]
+
+
+class Net(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * NLAYERS), ("b", ctypes.c_void_p * NLAYERS)]
+
+
+class NetGrad(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * NLAYERS), ("b", ctypes.c_void_p * NLAYERS)]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "ldsv_version": ([], _i),
+    "ldsv_last_error": ([], ctypes.c_char_p),
+    "ldsv_create": ([ctypes.POINTER(_vp), ctypes.POINTER(Grid)], _i),
+    "ldsv_destroy": ([_vp], _i),
+    "ldsv_workspace_bytes": ([_vp, ctypes.POINTER(_sz)], _i),
+    "ldsv_init_state": ([_vp, _i, ctypes.c_uint64, ctypes.POINTER(ICArgs), _vp, _vp, _vp], _i),
+    "ldsv_rhs": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_fv_step": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _i, _vp], _i),
+    "ldsv_project": ([_vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_project_bwd": ([_vp, _vp, _vp, _vp], _i),
+    "ldsv_cnn_forward": ([_vp, ctypes.POINTER(Net), _vp, _vp, _vp, _vp], _i),
+    "ldsv_learned_fv_step": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _vp,
+                              _vp, _i, _vp, _vp], _i),
+    "ldsv_rollout": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _i, _i, _i,
+                      _vp, _vp, _vp, _vp], _i),
+    "ldsv_fv_step_bwd": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                          _vp], _i),
+    "ldsv_cnn_backward": ([_vp, ctypes.POINTER(Net), _vp, _vp, _vp, _vp, _vp,
+                           ctypes.POINTER(NetGrad), _vp], _i),
+    "ldsv_learned_fv_step_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _i,
+                                  _vp, _vp, _vp, _vp, ctypes.POINTER(NetGrad), _vp], _i),
+    "ldsv_mse_grad": ([_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp], _i),
+    "ldsv_adam_step": ([_vp, _vp, _vp, _vp, _sz, _i, _d, _d, _d, _d, _vp], _i),
+    "ldsv_to_bf16": ([_vp, _vp, _sz, _vp], _i),
+    "ldsv_downsample": ([_vp, _i, _vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_vorticity": ([_vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_pcc": ([_vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_diagnostics": ([_vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_cfl_dt": ([_vp, _vp, _vp, _d, ctypes.POINTER(_d), _vp], _i),
+    "ldsv_timer_enable": ([_vp, _i], _i),
+    "ldsv_timer_read": ([_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i)], _i),
+}
+
+# kernel classes of ldsv_timer_read
+TIMER_STAGE, TIMER_ROWFFT, TIMER_COLSOLVE, TIMER_ROWIFFT, TIMER_CONV, TIMER_CONV0, TIMER_ADJ, \
+    TIMER_OTHER = range(8)
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def last_error():
+    return _lib.ldsv_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise LdsvError(rc, last_error())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """A handle for one grid: nx x ny cells, `batch` trajectories."""
+
+    def __init__(self, nx, ny, batch, lx=2 * 3.141592653589793, ly=2 * 3.141592653589793,
+                 dtype=torch.float32, layout=MAC):
+        self.nx, self.ny, self.batch = nx, ny, batch
+        self.lx, self.ly = lx, ly
+        self.dtype = dtype
+        self.layout = layout
+        g = Grid(nx, ny, lx, ly, batch, F64 if dtype == torch.float64 else F32, layout)
+        h = ctypes.c_void_p()
+        _check(_lib.ldsv_create(ctypes.byref(h), ctypes.byref(g)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ldsv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- tensor checks
+    def _state(self, t, name="state", dtype=None):
+        dt = dtype or self.dtype
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()
+                and tuple(t.shape) == (self.batch, self.ny, self.nx)):
+            raise ValueError("%s must be a contiguous %s cuda tensor of shape %s, got %s %s %s"
+                             % (name, dt, (self.batch, self.ny, self.nx), t.dtype,
+                                tuple(t.shape), t.device))
+        return _ptr(t)
+
+    def new_state(self):
+        return torch.empty(self.batch, self.ny, self.nx, dtype=self.dtype, device="cuda")
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        _check(_lib.ldsv_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    # ---- calls
+    def init_state(self, kind, seed, u=None, v=None, **kw):
+        u = self.new_state() if u is None else u
+        v = self.new_state() if v is None else v
+        ic = None
+        if kw:
+            base = dict(amp=1.0, k=1.0, delta=1.0 / 30.0, pert=0.05, noise_rms=1e-3, kpeak=4.0)
+            base.update(kw)
+            ic = ctypes.byref(ICArgs(**base))
+        _check(_lib.ldsv_init_state(self._h, kind, seed, ic, self._state(u), self._state(v),
+                                    _stream()))
+        return u, v
+
+    def rhs(self, prm, u, v, coef=None):
+        ru, rv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_rhs(self._h, ctypes.byref(prm), self._coef(coef), self._state(u),
+                             self._state(v), _ptr(ru), _ptr(rv), _stream()))
+        return ru, rv
+
+    def _coef(self, coef):
+        if coef is None:
+            return None
+        if not (coef.is_cuda and coef.dtype == torch.float32 and coef.is_contiguous()
+                and tuple(coef.shape) == (self.batch, NCOEF, self.ny, self.nx)):
+            raise ValueError("coef must be float32 [B, 64, Ny, Nx] contiguous on cuda")
+        return _ptr(coef)
+
+    def fv_step(self, prm, u, v, nsteps=1, coef=None, out=None):
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        _check(_lib.ldsv_fv_step(self._h, ctypes.byref(prm), self._coef(coef), self._state(u),
+                                 self._state(v), self._state(uo), self._state(vo), nsteps,
+                                 _stream()))
+        return uo, vo
+
+    def project(self, u, v, want_p=False):
+        """In place; returns p if want_p."""
+        p = self.new_state() if want_p else None
+        _check(_lib.ldsv_project(self._h, self._state(u), self._state(v), _ptr(p), _stream()))
+        return p
+
+    def project_bwd(self, gu, gv):
+        _check(_lib.ldsv_project_bwd(self._h, self._state(gu), self._state(gv), _stream()))
+
+    def cnn_forward(self, net, u, v):
+        out = torch.empty(self.batch, NOUT, self.ny, self.nx, dtype=torch.float32, device="cuda")
+        _check(_lib.ldsv_cnn_forward(self._h, ctypes.byref(net.c), self._state(u),
+                                     self._state(v), _ptr(out), _stream()))
+        return out
+
+    def learned_fv_step(self, prm, net, u, v, step_index, want_net_out=False, out=None):
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        no = None
+        if want_net_out:
+            no = torch.empty(self.batch, NOUT, self.ny, self.nx, dtype=torch.float32,
+                             device="cuda")
+        _check(_lib.ldsv_learned_fv_step(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                         self._state(u), self._state(v), self._state(uo),
+                                         self._state(vo), step_index, _ptr(no), _stream()))
+        return (uo, vo, no) if want_net_out else (uo, vo)
+
+    def rollout(self, prm, u0, v0, nsteps, save_every=1, net=None, first_index=1,
+                fallback_flags=None):
+        T = nsteps // save_every
+        tu = torch.empty(T, self.batch, self.ny, self.nx, dtype=self.dtype, device="cuda")
+        tv = torch.empty_like(tu)
+        _check(_lib.ldsv_rollout(self._h, ctypes.byref(prm),
+                                 ctypes.byref(net.c) if net is not None else None,
+                                 self._state(u0), self._state(v0), nsteps, save_every,
+                                 first_index, _ptr(tu), _ptr(tv), _ptr(fallback_flags), _stream()))
+        return tu, tv
+
+    def fv_step_bwd(self, prm, u, v, gu_out, gv_out, coef=None, gcoef=None):
+        gu, gv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_fv_step_bwd(self._h, ctypes.byref(prm), self._coef(coef),
+                                     self._state(u), self._state(v), self._state(gu_out),
+                                     self._state(gv_out), _ptr(gu), _ptr(gv),
+                                     self._coef(gcoef), _stream()))
+        return gu, gv
+
+    def cnn_backward(self, net, u, v, gout, dW, want_input_grad=True):
+        gu = self.new_state() if want_input_grad else None
+        gv = self.new_state() if want_input_grad else None
+        _check(_lib.ldsv_cnn_backward(self._h, ctypes.byref(net.c), self._state(u),
+                                      self._state(v), _ptr(gout.contiguous()), _ptr(gu), _ptr(gv),
+                                      ctypes.byref(dW.c), _stream()))
+        return gu, gv
+
+    def learned_fv_step_bwd(self, prm, net, u, v, step_index, gu_out, gv_out, dW):
+        gu, gv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_learned_fv_step_bwd(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                             self._state(u), self._state(v), step_index,
+                                             self._state(gu_out), self._state(gv_out), _ptr(gu),
+                                             _ptr(gv), ctypes.byref(dW.c), _stream()))
+        return gu, gv
+
+    def mse_grad(self, u, v, lu, lv, scale=1.0, loss=None, want_grad=True):
+        gu = self.new_state() if want_grad else None
+        gv = self.new_state() if want_grad else None
+        _check(_lib.ldsv_mse_grad(self._h, self._state(u), self._state(v), self._state(lu),
+                                  self._state(lv), scale, _ptr(gu), _ptr(gv), _ptr(loss),
+                                  _stream()))
+        return gu, gv
+
+    def downsample(self, r, uf, vf):
+        uc, vc = self.new_state(), self.new_state()
+        shape = (self.batch, self.ny * r, self.nx * r)
+        for t in (uf, vf):
+            if tuple(t.shape) != shape or not t.is_contiguous() or t.dtype != self.dtype:
+                raise ValueError("fine field must be %s contiguous %s" % (shape, self.dtype))
+        _check(_lib.ldsv_downsample(self._h, r, _ptr(uf), _ptr(vf), _ptr(uc), _ptr(vc),
+                                    _stream()))
+        return uc, vc
+
+    def vorticity(self, u, v):
+        w = self.new_state()
+        _check(_lib.ldsv_vorticity(self._h, self._state(u), self._state(v), _ptr(w), _stream()))
+        return w
+
+    def pcc(self, a, b):
+        out = torch.empty(self.batch, dtype=torch.float64, device="cuda")
+        _check(_lib.ldsv_pcc(self._h, self._state(a), self._state(b), _ptr(out), _stream()))
+        return out
+
+    def diagnostics(self, u, v):
+        out = torch.empty(self.batch, 6, dtype=torch.float64, device="cuda")
+        _check(_lib.ldsv_diagnostics(self._h, self._state(u), self._state(v), _ptr(out),
+                                     _stream()))
+        return out
+
+    def timer_enable(self, on=True):
+        _check(_lib.ldsv_timer_enable(self._h, 1 if on else 0))
+
+    def timer_read(self, cls):
+        """(total ms, launch count) of kernel class `cls` since timer_enable."""
+        t = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(_lib.ldsv_timer_read(self._h, cls, ctypes.byref(t), ctypes.byref(n)))
+        return t.value, n.value
+
+    def cfl_dt(self, u, v, cfl):
+        d = ctypes.c_double()
+        _check(_lib.ldsv_cfl_dt(self._h, self._state(u), self._state(v), cfl, ctypes.byref(d),
+                                _stream()))
+        return d.value
+
+
+def params(nu=0.0, dt=0.0, forcing_amp=0.0, forcing_k=0.0, drag=0.0, rk=RK4,
+           mask=ALL_PHYSICS, k_c=1, guard_threshold=0.0, fallback_enable=1):
+    return Params(nu, forcing_amp, forcing_k, drag, dt, rk, mask, k_c, guard_threshold,
+                  fallback_enable)
+
+
+class NetParams:
+    """Device copies of the coefficient network: bf16 weights [Cout][3][3][Cin]
+    (bit patterns in int16 tensors) and float biases, plus an FP32 master
+    copy of the weights in the same layout for training."""
+
+    def __init__(self, weights, biases):
+        """weights: list of [Cout, Cin, 3, 3] tensors (any float dtype, any
+        device); biases: list of [Cout]."""
+        self.master_w = [w.detach().to("cuda", torch.float32).permute(0, 2, 3, 1).contiguous()
+                         for w in weights]
+        self.b = [b.detach().to("cuda", torch.float32).contiguous() for b in biases]
+        self.w = [torch.empty(w.shape, dtype=torch.int16, device="cuda") for w in self.master_w]
+        self.c = Net()
+        self.refresh()
+
+    def refresh(self):
+        """Round the master weights to bf16 into the device copies."""
+        for l in range(NLAYERS):
+            _check(_lib.ldsv_to_bf16(_ptr(self.master_w[l]), _ptr(self.w[l]),
+                                     self.master_w[l].numel(), _stream()))
+            self.c.w[l] = self.w[l].data_ptr()
+            self.c.b[l] = self.b[l].data_ptr()
+
+    def torch_weights(self):
+        """Master weights back in [Cout, Cin, 3, 3] order."""
+        return [w.permute(0, 3, 1, 2).contiguous() for w in self.master_w]
+
+    def bf16_weights(self):
+        return [w.view(torch.bfloat16).float().permute(0, 3, 1, 2).contiguous() for w in self.w]
+
+
+class NetGradBuffers:
+    def __init__(self, net):
+        self.w = [torch.zeros_like(w) for w in net.master_w]
+        self.b = [torch.zeros_like(b) for b in net.b]
+        self.c = NetGrad()
+        for l in range(NLAYERS):
+            self.c.w[l] = self.w[l].data_ptr()
+            self.c.b[l] = self.b[l].data_ptr()
+
+    def zero_(self):
+        for t in self.w + self.b:
+            t.zero_()
+
+
+def adam_step(w, g, m, v, t, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
+    _check(_lib.ldsv_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), t, lr, b1, b2, eps,
+                               _stream()))

@@ -1,0 +1,248 @@
+"""GPU parity of the plain FV path (residual, projection, RK steps, initial
+conditions, diagnostics) against the FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic_inputs as si
+from oracle import fv, ic, learned, metrics, projection, timestep
+from tests.gpu_common import L, announce, cpu64, dev, need_gpu, oracle_prm, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 8, 1), (16, 16, 3), (32, 16, 2), (64, 64, 2), (128, 32, 1)]
+
+
+def _fields(seed, b, ny, nx, dtype):
+    u = torch.tensor(si.smooth_field(seed, b, ny, nx))
+    v = torch.tensor(si.smooth_field(seed + 1, b, ny, nx))
+    # round to the device precision so both sides see identical inputs
+    return u.to(dtype).double(), v.to(dtype).double()
+
+
+@pytest.mark.parametrize("nx,ny,b", SHAPES)
+@pytest.mark.parametrize("mask", [fv.ALL_PHYSICS, fv.ADVECTION, fv.VISCOSITY])
+def test_rhs_mac_f32(nx, ny, b, mask):
+    L_ = need_gpu()
+    announce("rhs_mac_f32", nx, ny, b, mask)
+    u, v = _fields(1, b, ny, nx, torch.float32)
+    kw = dict(nu=0.01, forcing_amp=1.0, forcing_k=4.0, drag=0.1, mask=mask)
+    s = L_.Solver(nx, ny, b)
+    ru, rv = s.rhs(L_.params(**kw), dev(u, torch.float32), dev(v, torch.float32))
+    torch.cuda.synchronize()
+    eu, ev = fv.ns_rhs(u, v, oracle_prm(nx, ny, **kw))
+    assert rel_l2(ru, eu) < 1e-5 and rel_l2(rv, ev) < 1e-5
+
+
+@pytest.mark.parametrize("nx,ny,b", SHAPES)
+def test_rhs_mac_f64(nx, ny, b):
+    L_ = need_gpu()
+    announce("rhs_mac_f64", nx, ny, b)
+    u, v = _fields(2, b, ny, nx, torch.float64)
+    kw = dict(nu=0.02, forcing_amp=0.5, forcing_k=2.0, drag=0.3)
+    s = L_.Solver(nx, ny, b, dtype=torch.float64)
+    ru, rv = s.rhs(L_.params(**kw), dev(u, torch.float64), dev(v, torch.float64))
+    eu, ev = fv.ns_rhs(u, v, oracle_prm(nx, ny, **kw))
+    assert rel_l2(ru, eu) < 1e-13 and rel_l2(rv, ev) < 1e-13
+
+
+@pytest.mark.parametrize("nx,ny,b", [(16, 16, 2), (32, 16, 1), (64, 64, 3)])
+def test_rhs_learned_coefficients(nx, ny, b):
+    L_ = need_gpu()
+    announce("rhs_learned", nx, ny, b)
+    u, v = _fields(3, b, ny, nx, torch.float32)
+    raw = torch.tensor(si.random_field(5, (b, 64, ny, nx), scale=0.2)).float()
+    kw = dict(nu=0.01, forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+    s = L_.Solver(nx, ny, b)
+    ru, rv = s.rhs(L_.params(**kw), dev(u, torch.float32), dev(v, torch.float32),
+                   coef=dev(raw, torch.float32))
+    eu, ev = fv.ns_rhs(u, v, oracle_prm(nx, ny, **kw), learned.constrain(raw.double()))
+    assert rel_l2(ru, eu) < 1e-5 and rel_l2(rv, ev) < 1e-5
+    # conservation holds for any coefficients: sum of the flux part is zero
+    s2 = L_.Solver(nx, ny, b)
+    ru, rv = s2.rhs(L_.params(nu=0.01, mask=L_.ADVECTION | L_.VISCOSITY), dev(u, torch.float32),
+                    dev(v, torch.float32), coef=dev(raw, torch.float32))
+    assert ru.double().sum(dim=(-2, -1)).abs().max().item() < 1e-3 * ru.abs().max().item()
+
+
+@pytest.mark.parametrize("nx,ny,b", [(8, 8, 1), (16, 16, 3), (64, 32, 2)])
+def test_rhs_burgers_f64(nx, ny, b):
+    L_ = need_gpu()
+    announce("rhs_burgers", nx, ny, b)
+    u, v = _fields(4, b, ny, nx, torch.float64)
+    s = L_.Solver(nx, ny, b, dtype=torch.float64, layout=L_.COLLOCATED)
+    ru, rv = s.rhs(L_.params(nu=0.01, rk=L_.SSPRK3), dev(u, torch.float64), dev(v, torch.float64))
+    eu, ev = fv.burgers_rhs(u, v, oracle_prm(nx, ny, nu=0.01))
+    assert rel_l2(ru, eu) < 1e-13 and rel_l2(rv, ev) < 1e-13
+
+
+@pytest.mark.parametrize("nx,ny,b", SHAPES + [(512, 512, 2), (256, 1024, 1)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_projection(nx, ny, b, dtype):
+    L_ = need_gpu()
+    announce("project", nx, ny, b, dtype)
+    u, v = _fields(6, b, ny, nx, dtype)
+    s = L_.Solver(nx, ny, b, dtype=dtype)
+    gu, gv = dev(u, dtype), dev(v, dtype)
+    p = s.project(gu, gv, want_p=True)
+    prm = oracle_prm(nx, ny)
+    eu, ev, ep = projection.project(u, v, prm)
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    assert rel_l2(gu, eu) < tol and rel_l2(gv, ev) < tol
+    assert rel_l2(p, ep) < tol
+    # discretely divergence-free relative to the input divergence
+    d_in = projection.divergence(u, v, prm).norm()
+    d_out = projection.divergence(cpu64(gu), cpu64(gv), prm).norm()
+    assert d_out / d_in < (1e-5 if dtype == torch.float32 else 1e-12)
+
+
+@pytest.mark.parametrize("nx,ny,b", [(16, 16, 3), (64, 64, 2), (128, 64, 1)])
+def test_rk4_step_f32(nx, ny, b):
+    L_ = need_gpu()
+    announce("rk4_f32", nx, ny, b)
+    u, v = ic.grf_peak(b, nx, ny, L, L * ny / nx, seed=7)
+    u, v = u.float().double(), v.float().double()
+    kw = dict(nu=1e-3, dt=0.5 * (L / nx), forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+    s = L_.Solver(nx, ny, b, ly=L * ny / nx)
+    uo, vo = s.fv_step(L_.params(**kw), dev(u, torch.float32), dev(v, torch.float32))
+    eu, ev = timestep.fv_step(u, v, oracle_prm(nx, ny, ly=L * ny / nx, **kw))
+    assert rel_l2(uo, eu) < 1e-5 and rel_l2(vo, ev) < 1e-5
+
+
+@pytest.mark.parametrize("nx,ny,b", [(8, 8, 1), (16, 16, 3), (32, 16, 2)])
+def test_rk4_steps_f64(nx, ny, b):
+    L_ = need_gpu()
+    announce("rk4_f64", nx, ny, b)
+    u, v = ic.grf_peak(b, nx, ny, L, L, seed=8)
+    kw = dict(nu=1e-2, dt=0.05, forcing_amp=1.0, forcing_k=2.0, drag=0.1)
+    s = L_.Solver(nx, ny, b, dtype=torch.float64)
+    gu, gv = dev(u, torch.float64), dev(v, torch.float64)
+    uo, vo = s.fv_step(L_.params(**kw), gu, gv, nsteps=5, out=(gu, gv))   # in place
+    eu, ev = timestep.fv_step(u, v, oracle_prm(nx, ny, **kw), nsteps=5)
+    assert rel_l2(uo, eu) < 1e-12 and rel_l2(vo, ev) < 1e-12
+
+
+def test_learned_coefficient_step_f32():
+    L_ = need_gpu()
+    announce("fv_step_coef")
+    nx = ny = 32
+    b = 2
+    u, v = ic.grf_peak(b, nx, ny, L, L, seed=9)
+    u, v = u.float().double(), v.float().double()
+    raw = torch.tensor(si.random_field(11, (b, 64, ny, nx), scale=0.05)).float()
+    kw = dict(nu=1e-3, dt=0.05, forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+    s = L_.Solver(nx, ny, b)
+    uo, vo = s.fv_step(L_.params(**kw), dev(u, torch.float32), dev(v, torch.float32),
+                       coef=dev(raw, torch.float32))
+    eu, ev = timestep.fv_step(u, v, oracle_prm(nx, ny, **kw), coef=learned.constrain(raw.double()))
+    assert rel_l2(uo, eu) < 1e-5 and rel_l2(vo, ev) < 1e-5
+
+
+def test_burgers_config_200_steps_f64():
+    """The Burgers workload (64^2, FP64, SSP-RK3, CFL 0.5, 200 steps): initial
+    condition, CFL time step and the whole trajectory against the oracle."""
+    L_ = need_gpu()
+    announce("burgers64 200 steps")
+    w = si.WORKLOADS["burgers64"]
+    n = w["nx"]
+    s = L_.Solver(n, n, 1, dtype=torch.float64, layout=L_.COLLOCATED)
+    gu, gv = s.init_state(L_.IC_FOURIER_MODES, seed=0)
+    eu, ev = ic.fourier_modes(1, n, n, L, L, seed=0)
+    assert rel_l2(gu, eu) < 1e-13 and rel_l2(gv, ev) < 1e-13
+    dt = s.cfl_dt(gu, gv, w["cfl"])
+    prm = oracle_prm(n, n, nu=w["nu"], rk=timestep.SSPRK3, layout=timestep.COLLOCATED)
+    dt_ref = timestep.cfl_dt(eu, ev, prm, w["cfl"])
+    assert dt == pytest.approx(dt_ref, rel=1e-14)
+    prm["dt"] = dt_ref
+    uo, vo = s.fv_step(L_.params(nu=w["nu"], dt=dt, rk=L_.SSPRK3), gu, gv, nsteps=w["steps"])
+    ou, ov = timestep.fv_step(eu, ev, prm, nsteps=w["steps"])
+    assert rel_l2(uo, ou) < 1e-10 and rel_l2(vo, ov) < 1e-10
+
+
+@pytest.mark.parametrize("kind,nx,ny,b", [("grf", 32, 32, 3), ("grf", 64, 16, 2),
+                                          ("tgv", 16, 16, 2), ("shear", 64, 64, 2)])
+def test_initial_conditions_f64(kind, nx, ny, b):
+    L_ = need_gpu()
+    announce("init", kind, nx, ny, b)
+    s = L_.Solver(nx, ny, b, dtype=torch.float64)
+    if kind == "grf":
+        gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=12)
+        eu, ev = ic.grf_peak(b, nx, ny, L, L, seed=12)
+    elif kind == "tgv":
+        gu, gv = s.init_state(L_.IC_TGV, seed=0, k=2.0, amp=0.7)
+        eu, ev = ic.taylor_green(b, nx, ny, L, L, amp=0.7, k=2)
+    else:
+        gu, gv = s.init_state(L_.IC_SHEAR_LAYER, seed=3)
+        eu, ev = ic.shear_layer(b, nx, ny, L, L, seed=3)
+    assert rel_l2(gu, eu) < 1e-12 and rel_l2(gv, ev) < 1e-12
+
+
+def test_decaying512_full_size_step():
+    """One RK4 step of the decaying-flow workload at its full size (512^2,
+    batch 16, FP32) in the launch configuration the benchmark times;
+    trajectories 0 and 15 are checked against the oracle."""
+    L_ = need_gpu()
+    announce("decaying512 step")
+    w = si.WORKLOADS["decaying512"]
+    n, B = w["nx"], w["batch"]
+    s = L_.Solver(n, n, B)
+    gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=0)
+    kw = dict(nu=w["nu"], dt=w["dt"])
+    uo, vo = s.fv_step(L_.params(**kw), gu, gv)
+    for b in (0, B - 1):
+        u0, v0 = cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1])
+        eu, ev = timestep.fv_step(u0, v0, oracle_prm(n, n, **kw))
+        assert rel_l2(uo[b:b + 1], eu) < 1e-5 and rel_l2(vo[b:b + 1], ev) < 1e-5
+    # the state stays discretely divergence-free and mean-free
+    d = s.diagnostics(uo, vo).cpu()
+    assert (d[:, 4] < 1e-3).all() and (d[:, 5] == 1).all()
+
+
+def test_determinism_bitwise():
+    L_ = need_gpu()
+    announce("determinism")
+    s = L_.Solver(64, 64, 4)
+    gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=1)
+    prm = L_.params(nu=1e-3, dt=0.02, forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+    a = s.fv_step(prm, gu, gv, nsteps=3)
+    b = s.fv_step(prm, gu, gv, nsteps=3)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_diagnostics_vorticity_pcc_downsample():
+    L_ = need_gpu()
+    announce("diagnostics")
+    n, b = 32, 3
+    u, v = ic.grf_peak(b, n, n, L, L, seed=4)
+    u, v = (u + 0.3).float().double(), (v - 0.2).float().double()
+    s = L_.Solver(n, n, b)
+    gu, gv = dev(u, torch.float32), dev(v, torch.float32)
+    d = s.diagnostics(gu, gv).cpu()
+    assert torch.allclose(d[:, 0], (u.abs() + v.abs()).amax(dim=(-2, -1)), rtol=1e-6)
+    assert torch.allclose(d[:, 1], 0.5 * (u * u + v * v).mean(dim=(-2, -1)), rtol=1e-6)
+    assert torch.allclose(d[:, 2], u.mean(dim=(-2, -1)), atol=1e-7)
+    w = s.vorticity(gu, gv)
+    ew = metrics.vorticity(u, v, L / n, L / n)
+    assert rel_l2(w, ew) < 1e-6
+    p = s.pcc(w, gu).cpu()
+    assert torch.allclose(p, metrics.pcc(ew, u), atol=1e-6)
+    # fine 128^2 -> coarse 32^2
+    uf, vf = ic.grf_peak(b, 4 * n, 4 * n, L, L, seed=5)
+    uf, vf = uf.float().double(), vf.float().double()
+    uc, vc = s.downsample(4, dev(uf, torch.float32), dev(vf, torch.float32))
+    euc, evc = metrics.downsample_mac(uf, vf, 4)
+    assert rel_l2(uc, euc) < 1e-6 and rel_l2(vc, evc) < 1e-6
+
+
+def test_error_paths():
+    L_ = need_gpu()
+    s = L_.Solver(16, 16, 1)
+    u = s.new_state()
+    with pytest.raises(L_.LdsvError) as e:
+        s.fv_step(L_.params(nu=1e-3, dt=0.01), u, u, nsteps=0)
+    assert e.value.code == L_.EINVAL
+    c = L_.Solver(16, 16, 1, layout=L_.COLLOCATED)
+    with pytest.raises(L_.LdsvError):
+        c.project(c.new_state(), c.new_state())
