@@ -92,10 +92,16 @@ def test_projection(nx, ny, b, dtype):
     tol = 1e-5 if dtype == torch.float32 else 1e-12
     assert rel_l2(gu, eu) < tol and rel_l2(gv, ev) < tol
     assert rel_l2(p, ep) < tol
-    # discretely divergence-free relative to the input divergence
-    d_in = projection.divergence(u, v, prm).norm()
-    d_out = projection.divergence(cpu64(gu), cpu64(gv), prm).norm()
-    assert d_out / d_in < (1e-5 if dtype == torch.float32 else 1e-12)
+    # discretely divergence-free up to transform roundoff: an error of
+    # eps*sqrt(log2 N)*|p| spread over all wavenumbers, amplified by the
+    # largest eigenvalue of D G
+    eps = 6e-8 if dtype == torch.float32 else 1.2e-16
+    lam_max = 4 / (L / nx) ** 2 + 4 / (L / ny) ** 2
+    d_out = projection.divergence(cpu64(gu), cpu64(gv), prm)
+    bound = 4 * eps * math.sqrt(math.log2(nx * ny)) * lam_max * ep.pow(2).mean().sqrt()
+    assert d_out.pow(2).mean().sqrt() < bound
+    d_in = projection.divergence(u, v, prm)
+    assert d_out.norm() < 1e-3 * d_in.norm()
 
 
 @pytest.mark.parametrize("nx,ny,b", [(16, 16, 3), (64, 64, 2), (128, 64, 1)])
@@ -195,9 +201,12 @@ def test_decaying512_full_size_step():
         u0, v0 = cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1])
         eu, ev = timestep.fv_step(u0, v0, oracle_prm(n, n, **kw))
         assert rel_l2(uo[b:b + 1], eu) < 1e-5 and rel_l2(vo[b:b + 1], ev) < 1e-5
-    # the state stays discretely divergence-free and mean-free
+    # the state stays discretely divergence-free (relative to its vorticity)
+    # and finite
     d = s.diagnostics(uo, vo).cpu()
-    assert (d[:, 4] < 1e-3).all() and (d[:, 5] == 1).all()
+    w = s.vorticity(uo, vo).double()
+    w_norm = w.pow(2).sum(dim=(-2, -1)).sqrt().cpu()
+    assert (d[:, 4] < 1e-4 * w_norm).all() and (d[:, 5] == 1).all()
 
 
 def test_determinism_bitwise():
