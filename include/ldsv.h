@@ -178,6 +178,11 @@ LDSV_API int ldsv_project_bwd(ldsv_handle* h, void* gu, void* gv, void* stream);
 LDSV_API int ldsv_cnn_forward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                      float* out, void* stream);
 
+/* Copy the bf16 NHWC activation [B][Ny][Nx][64] that layer `layer` (0..4)
+ * produced in the last network evaluation on this handle into dst (device,
+ * uint16 bit patterns).  For per-layer parity checks. */
+LDSV_API int ldsv_cnn_activation(ldsv_handle* h, int layer, uint16_t* dst, void* stream);
+
 /* ---- a12-a13: the learned step (Eq. 2) ----
  * Runs the network once on u_{k-1}, the FV module with its coefficients,
  * and, when step_index % k_c == 0, adds the temporal correction before the

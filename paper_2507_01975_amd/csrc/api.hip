@@ -36,6 +36,19 @@ void ldsv_set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
+int ldsv_alloc(ldsv_handle* h, void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    ldsv_set_error("%s: cannot allocate %zu bytes", what, bytes);
+    return LDSV_ENOMEM;
+  }
+  h->allocs.push_back(*p);
+  h->bytes += bytes;
+  return LDSV_OK;
+}
+
 int ldsv_check_handle(const ldsv_handle* h) {
   LDSV_REQUIRE(h != nullptr, LDSV_EINVAL, "null handle");
   return LDSV_OK;
@@ -204,6 +217,7 @@ int ldsv_create(ldsv_handle** out, const ldsv_grid* g) {
     ldsv_set_error("create: cannot allocate %zu bytes of state workspace", 8 * sb);
     return LDSV_ENOMEM;
   }
+  h->allocs.push_back(blk);
   h->ws_u = blk;
   h->ws_v = blk + sb;
   h->st_u = blk + 2 * sb;
@@ -225,6 +239,7 @@ int ldsv_create(ldsv_handle** out, const ldsv_grid* g) {
     ldsv_set_error("create: cannot allocate spectrum workspace");
     return LDSV_ENOMEM;
   }
+  h->allocs.push_back(blk2);
   h->zspec = blk2;
   h->twx = blk2 + zb;
   h->twy = blk2 + zb + (size_t)g->nx * 2 * h->esize;
@@ -251,12 +266,7 @@ int ldsv_create(ldsv_handle** out, const ldsv_grid* g) {
 int ldsv_destroy(ldsv_handle* h) {
   if (!h) return LDSV_OK;
   (void)hipDeviceSynchronize();
-  (void)hipFree(h->ws_u);
-  (void)hipFree(h->zspec);
-  for (int l = 0; l < 6; ++l)
-    if (h->act[l]) (void)hipFree(h->act[l]);
-  if (h->netout) (void)hipFree(h->netout);
-  if (h->stage_keep) (void)hipFree(h->stage_keep);
+  for (void* p : h->allocs) (void)hipFree(p);
   if (h->small_host) (void)hipHostFree(h->small_host);
   for (int c = 0; c < kTimerClasses; ++c)
     for (auto e : h->timer.ev[c]) (void)hipEventDestroy(e);

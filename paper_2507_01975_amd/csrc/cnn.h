@@ -1,0 +1,9 @@
+// Host-side interface of the network kernels.
+#pragma once
+
+#include "internal.h"
+
+int ldsv_ensure_learned(ldsv_handle* h);
+int ldsv_check_net(const ldsv_net* net);
+int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                    float* out, float* const* zpre, hipStream_t st);

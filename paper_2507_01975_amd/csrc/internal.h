@@ -112,8 +112,12 @@ struct ldsv_handle {
   void* adj_g = nullptr;
   void* save_u = nullptr;        // rollout fallback copy of u_{k-1}
   size_t bytes = 0;
+  std::vector<void*> allocs;     // base pointers of every device allocation owned
   KernelTimer timer;
 };
+
+// device allocation owned by the handle (freed by ldsv_destroy)
+int ldsv_alloc(ldsv_handle* h, void** p, size_t bytes, const char* what);
 
 // RAII: records a start event at construction and a stop event at
 // destruction on stream st when timing is enabled for the handle.

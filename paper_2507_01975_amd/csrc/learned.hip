@@ -1,22 +1,182 @@
-// Learned path entry points (network forward/backward, learned step, rollout,
-// adjoints).
+// The learned step and the rollout (Eq. 2):
+//   u_k = FV(u_{k-1}; c(u_{k-1})) + TC(u_{k-1})   if k mod k_c == 0
+//   u_k = FV(u_{k-1}; c(u_{k-1}))                  otherwise
+// with the stencil coefficients c and the correction TC from one pass of the
+// coefficient network on u_{k-1}.  The correction enters the last RK stage
+// before its projection, u_k = P(u* + TC), which equals P(P(u*) + TC)
+// because P is a linear projector.  The rollout guards every learned step:
+// a trajectory whose new state is non-finite or exceeds the max-speed bound
+// is recomputed from u_{k-1} with the plain FV step.
+#include "cnn.h"
+#include "reduce.h"
 #include "stage.h"
 
+int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
+                       const void* su, const void* sv, void* du, void* dv, const float* tcu,
+                       const float* tcv, size_t tcbs, hipStream_t st);
+
+namespace {
+
+struct SpeedOrInf {
+  const float* u;
+  const float* v;
+  size_t n;
+  __device__ void operator()(int b, size_t i, double* out) const {
+    const float a = u[(size_t)b * n + i], c = v[(size_t)b * n + i];
+    const double s = (double)fabsf(a) + (double)fabsf(c);
+    out[0] = isfinite(s) ? s : 1.0e308;
+  }
+};
+
+__global__ void k_guard_flags(const double* maxspeed, int batch, double thr, int* bad, int* any) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int a = 0;
+  for (int b = 0; b < batch; ++b) {
+    const int f = !(maxspeed[b] < thr);
+    bad[b] = f;
+    a |= f;
+  }
+  *any = a;
+}
+
+__global__ void k_select(float* cu, float* cv, const float* fu, const float* fv, const int* bad,
+                         int* counts, size_t n, int batch) {
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n * batch;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(g / n);
+    if (bad[b]) {
+      cu[g] = fu[g];
+      cv[g] = fv[g];
+    }
+  }
+  if (blockIdx.x == 0 && counts)
+    for (int b = threadIdx.x; b < batch; b += blockDim.x)
+      if (bad[b]) counts[b] += 1;
+}
+
+int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, const float* u_in,
+                 const float* v_in, float* u_out, float* v_out, int step_index, float* net_out,
+                 hipStream_t st) {
+  float* out = net_out ? net_out : h->netout;
+  LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st));
+  const size_t N = h->ncell;
+  const size_t bs = (size_t)LDSV_NOUT * N;
+  const bool tc = prm->k_c > 0 && (step_index % prm->k_c) == 0;
+  return ldsv_internal_step(h, prm, out, bs, u_in, v_in, u_out, v_out,
+                            tc ? out + (size_t)LDSV_NCOEF * N : nullptr,
+                            tc ? out + (size_t)(LDSV_NCOEF + 1) * N : nullptr, bs, st);
+}
+
+int ensure_rollout_buffers(ldsv_handle* h) {
+  if (h->save_u) return LDSV_OK;
+  const size_t sb = h->nstate * h->esize;
+  return ldsv_alloc(h, &h->save_u, 4 * sb + 64 * sizeof(int) + (size_t)h->g.batch * sizeof(int),
+                    "rollout guard buffers");
+}
+
+}  // namespace
+
 extern "C" {
-int ldsv_cnn_forward(ldsv_handle*, const ldsv_net*, const float*, const float*, float*, void*) {
-  ldsv_set_error("cnn_forward: not available in this build");
-  return LDSV_EDTYPE;
+
+int ldsv_cnn_forward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                     float* out, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_TRY(ldsv_check_net(net));
+  LDSV_REQUIRE(u && v && out, LDSV_EINVAL, "cnn_forward: null array");
+  LDSV_TRY(ldsv_ensure_learned(h));
+  return ldsv_launch_cnn(h, net, u, v, out, nullptr, (hipStream_t)stream);
 }
-int ldsv_learned_fv_step(ldsv_handle*, const ldsv_params*, const ldsv_net*, const float*,
-                         const float*, float*, float*, int, float*, void*) {
-  ldsv_set_error("learned_fv_step: not available in this build");
-  return LDSV_EDTYPE;
+
+int ldsv_cnn_activation(ldsv_handle* h, int layer, uint16_t* dst, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(dst && layer >= 0 && layer < 5, LDSV_EINVAL, "cnn_activation: bad argument");
+  LDSV_REQUIRE(h->netout, LDSV_EINVAL, "cnn_activation: no network evaluation yet");
+  LDSV_HIP(hipMemcpyAsync(dst, h->act[layer], h->nstate * 64 * sizeof(uint16_t),
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return LDSV_OK;
 }
-int ldsv_rollout(ldsv_handle*, const ldsv_params*, const ldsv_net*, const void*, const void*, int,
-                 int, int, void*, void*, int*, void*) {
-  ldsv_set_error("rollout: not available in this build");
-  return LDSV_EDTYPE;
+
+int ldsv_learned_fv_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                         const float* u_in, const float* v_in, float* u_out, float* v_out,
+                         int step_index, float* net_out, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_TRY(ldsv_check_net(net));
+  LDSV_REQUIRE(prm && u_in && v_in && u_out && v_out, LDSV_EINVAL, "learned_fv_step: null argument");
+  LDSV_REQUIRE(prm->rk == LDSV_RK4 || prm->rk == LDSV_SSPRK3, LDSV_EINVAL, "learned_fv_step: bad rk");
+  LDSV_TRY(ldsv_ensure_learned(h));
+  return learned_step(h, prm, net, u_in, v_in, u_out, v_out, step_index, net_out,
+                      (hipStream_t)stream);
 }
+
+int ldsv_rollout(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, const void* u0,
+                 const void* v0, int nsteps, int save_every, int first_index, void* traj_u,
+                 void* traj_v, int* fallback_flags, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(prm && u0 && v0 && traj_u && traj_v, LDSV_EINVAL, "rollout: null argument");
+  LDSV_REQUIRE(nsteps >= 1 && save_every >= 1 && save_every <= nsteps, LDSV_EINVAL,
+               "rollout: nsteps=%d save_every=%d", nsteps, save_every);
+  LDSV_REQUIRE(h->g.layout == LDSV_MAC || prm->rk == LDSV_SSPRK3, LDSV_EDTYPE,
+               "rollout: the collocated layout integrates with SSPRK3");
+  const hipStream_t st = (hipStream_t)stream;
+  if (net) {
+    LDSV_TRY(ldsv_check_net(net));
+    LDSV_TRY(ldsv_ensure_learned(h));
+    LDSV_TRY(ensure_rollout_buffers(h));
+  }
+  const size_t sb = h->nstate * h->esize;
+  void* cu = h->base_u;
+  void* cv = h->base_v;
+  LDSV_HIP(hipMemcpyAsync(cu, u0, sb, hipMemcpyDeviceToDevice, st));
+  LDSV_HIP(hipMemcpyAsync(cv, v0, sb, hipMemcpyDeviceToDevice, st));
+  const bool guard = net && (prm->fallback_enable || prm->guard_threshold > 0);
+  char* save = (char*)h->save_u;
+  int* bad = save ? (int*)(save + 4 * sb) : nullptr;
+  int* any = bad ? bad + h->g.batch : nullptr;
+  const double thr = prm->guard_threshold > 0 ? prm->guard_threshold : 1.0e300;
+  for (int k = 0; k < nsteps; ++k) {
+    const int idx = first_index + k;
+    if (net) {
+      if (guard) {
+        LDSV_HIP(hipMemcpyAsync(save, cu, sb, hipMemcpyDeviceToDevice, st));
+        LDSV_HIP(hipMemcpyAsync(save + sb, cv, sb, hipMemcpyDeviceToDevice, st));
+      }
+      LDSV_TRY(learned_step(h, prm, net, (const float*)cu, (const float*)cv, (float*)cu,
+                            (float*)cv, idx, nullptr, st));
+      if (guard) {
+        LDSV_TRY((reduce_per_traj<kRedMax, 1>(h, SpeedOrInf{(const float*)cu, (const float*)cv, h->ncell},
+                                              h->ncell, h->g.batch, h->small, st)));
+        hipLaunchKernelGGL(k_guard_flags, dim3(1), dim3(64), 0, st, h->small, h->g.batch, thr, bad,
+                           any);
+        LDSV_LAUNCHED();
+        int any_h = 0;
+        LDSV_HIP(hipMemcpyAsync(&any_h, any, sizeof(int), hipMemcpyDeviceToHost, st));
+        LDSV_HIP(hipStreamSynchronize(st));
+        if (any_h) {
+          LDSV_REQUIRE(prm->fallback_enable, LDSV_ENONFINITE,
+                       "rollout: learned step %d left a trajectory non-finite or above the bound",
+                       idx);
+          // plain FV step from the saved state into the second save slot
+          LDSV_TRY(ldsv_internal_step(h, prm, nullptr, 0, save, save + sb, save + 2 * sb,
+                                      save + 3 * sb, nullptr, nullptr, 0, st));
+          hipLaunchKernelGGL(k_select, grid1d(h->nstate), dim3(kBlock), 0, st, (float*)cu,
+                             (float*)cv, (const float*)(save + 2 * sb),
+                             (const float*)(save + 3 * sb), bad, fallback_flags, h->ncell,
+                             h->g.batch);
+          LDSV_LAUNCHED();
+        }
+      }
+    } else {
+      LDSV_TRY(ldsv_internal_step(h, prm, nullptr, 0, cu, cv, cu, cv, nullptr, nullptr, 0, st));
+    }
+    if ((k + 1) % save_every == 0) {
+      const size_t t = (size_t)((k + 1) / save_every - 1);
+      LDSV_HIP(hipMemcpyAsync((char*)traj_u + t * sb, cu, sb, hipMemcpyDeviceToDevice, st));
+      LDSV_HIP(hipMemcpyAsync((char*)traj_v + t * sb, cv, sb, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  return LDSV_OK;
+}
+
 int ldsv_fv_step_bwd(ldsv_handle*, const ldsv_params*, const float*, const void*, const void*,
                      const void*, const void*, void*, void*, float*, void*) {
   ldsv_set_error("fv_step_bwd: not available in this build");
@@ -33,4 +193,5 @@ int ldsv_learned_fv_step_bwd(ldsv_handle*, const ldsv_params*, const ldsv_net*, 
   ldsv_set_error("learned_fv_step_bwd: not available in this build");
   return LDSV_EDTYPE;
 }
-}
+
+}  // extern "C"

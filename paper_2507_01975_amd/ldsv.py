@@ -84,6 +84,7 @@ _SIGS = {
     "ldsv_project": ([_vp, _vp, _vp, _vp, _vp], _i),
     "ldsv_project_bwd": ([_vp, _vp, _vp, _vp], _i),
     "ldsv_cnn_forward": ([_vp, ctypes.POINTER(Net), _vp, _vp, _vp, _vp], _i),
+    "ldsv_cnn_activation": ([_vp, _i, _vp, _vp], _i),
     "ldsv_learned_fv_step": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _vp,
                               _vp, _i, _vp, _vp], _i),
     "ldsv_rollout": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _i, _i, _i,
@@ -230,6 +231,13 @@ class Solver:
         _check(_lib.ldsv_cnn_forward(self._h, ctypes.byref(net.c), self._state(u),
                                      self._state(v), _ptr(out), _stream()))
         return out
+
+    def cnn_activation(self, layer):
+        """bf16 NHWC activation of layer 0..4 from the last network pass, as
+        float32 [B, 64, Ny, Nx]."""
+        a = torch.empty(self.batch, self.ny, self.nx, 64, dtype=torch.int16, device="cuda")
+        _check(_lib.ldsv_cnn_activation(self._h, layer, _ptr(a), _stream()))
+        return a.view(torch.bfloat16).float().permute(0, 3, 1, 2).contiguous()
 
     def learned_fv_step(self, prm, net, u, v, step_index, want_net_out=False, out=None):
         uo, vo = (self.new_state(), self.new_state()) if out is None else out

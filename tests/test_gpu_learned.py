@@ -1,0 +1,175 @@
+"""GPU parity of the learned path: the BF16 MFMA coefficient network, the
+learned step (coefficients + temporal correction), the rollout and its
+guard, against the FP64 oracle through the C ABI."""
+import math
+
+import pytest
+import torch
+
+import synthetic_inputs as si
+from oracle import cnn, fv, ic, learned, timestep
+from tests.gpu_common import L, announce, cpu64, dev, need_gpu, oracle_prm, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(nu=1e-3, dt=0.05, forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+
+
+def _net(L_, seed=0, last_scale=1e-3):
+    ws, bs = si.cnn_weights(seed, cnn.LAYERS, last_scale=last_scale)
+    net = L_.NetParams([torch.tensor(w) for w in ws], [torch.tensor(b) for b in bs])
+    wb = [w.double().cpu() for w in net.bf16_weights()]
+    bb = [b.double().cpu() for b in net.b]
+    return net, wb, bb
+
+
+@pytest.mark.parametrize("nx,ny,b", [(8, 8, 1), (16, 16, 3), (32, 16, 2), (64, 64, 4)])
+def test_cnn_forward(nx, ny, b):
+    L_ = need_gpu()
+    announce("cnn_forward", nx, ny, b)
+    net, wb, bb = _net(L_, seed=1, last_scale=1.0)
+    u, v = ic.grf_peak(b, nx, ny, L, L, seed=3)
+    u, v = u.float(), v.float()
+    s = L_.Solver(nx, ny, b)
+    out = s.cnn_forward(net, dev(u, torch.float32), dev(v, torch.float32))
+    x = torch.stack([u.double(), v.double()], dim=1)
+    ref64 = cnn.cnn_forward(x, wb, bb)
+    refbf = cnn.cnn_forward(x, wb, bb, bf16=True)
+    assert rel_l2(out, ref64) < 2e-2
+    # layer by layer from the device's own bf16 inputs: each layer matches the
+    # oracle's layer to FP32 accumulation and bf16 rounding of its output
+    prev = cnn.round_bf16(x)
+    errs = []
+    for li in range(6):
+        z = cnn.conv3x3_circular(prev, wb[li], bb[li])
+        if li < 5:
+            ref = cnn.round_bf16(cnn.gelu(z))
+            got = cpu64(s.cnn_activation(li))
+            # each value within one bf16 ulp (a rounding flip), flips rare
+            scale = torch.maximum(got.abs(), ref.abs())
+            ulp = 2.0 ** -7 * scale + 1e-6 * ref.pow(2).mean().sqrt()
+            assert ((got - ref).abs() <= 1.01 * ulp).all(), li
+            flips = ((got - ref).abs() > 1e-6 * ref.pow(2).mean().sqrt()).double().mean().item()
+            errs.append((rel_l2(got, ref), flips))
+            assert rel_l2(got, ref) < 1e-4 and flips < 1e-2, (li, errs)
+            prev = got
+        else:
+            errs.append((rel_l2(out, z), 0.0))
+            assert rel_l2(out, z) < 1e-5, errs
+    print("per-layer rel-L2 and rounding-flip fraction:", errs)
+    # end to end, rounding flips compound through the layers
+    assert rel_l2(out, refbf) < 5e-3
+
+
+def test_learned_step_matches_oracle_given_network_output():
+    L_ = need_gpu()
+    announce("learned_step")
+    nx = ny = 32
+    b = 3
+    net, wb, bb = _net(L_, seed=2, last_scale=0.05)
+    u, v = ic.grf_peak(b, nx, ny, L, L, seed=5)
+    u, v = u.float().double(), v.float().double()
+    s = L_.Solver(nx, ny, b)
+    prm = L_.params(k_c=1, **KW)
+    uo, vo, no = s.learned_fv_step(prm, net, dev(u, torch.float32), dev(v, torch.float32), 1,
+                                   want_net_out=True)
+    out = cpu64(no)
+    # the FV step with the device's coefficients and correction
+    oprm = oracle_prm(nx, ny, k_c=1, **KW)
+    eu, ev = timestep.fv_step(u, v, oprm, learned.constrain(out[:, :64]))
+    from oracle.projection import project
+    eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
+    assert rel_l2(uo, eu) < 1e-5 and rel_l2(vo, ev) < 1e-5
+    # and the whole learned step against the bf16-emulating oracle
+    lu, lv, lo = learned.learned_fv_step(u, v, oprm, wb, bb, 1, bf16=True)
+    assert rel_l2(no, lo) < 5e-3
+    assert rel_l2(uo, lu) < 1e-4
+
+
+def test_zero_head_reproduces_plain_fv_and_kc():
+    L_ = need_gpu()
+    announce("zero head")
+    n, b = 32, 2
+    ws, bs = si.cnn_weights(0, cnn.LAYERS)
+    ws[-1][:] = 0
+    bs[-1][:] = 0
+    bs[-1][64] = 0.1   # constant TC in u
+    net = L_.NetParams([torch.tensor(w) for w in ws], [torch.tensor(x) for x in bs])
+    s = L_.Solver(n, n, b)
+    u, v = s.init_state(L_.IC_GRF_PEAK, seed=4)
+    pu, pv = s.fv_step(L_.params(**KW), u, v)
+    prm = L_.params(k_c=2, **KW)
+    lu, lv = s.learned_fv_step(prm, net, u, v, 1)       # 1 % 2 != 0: no correction
+    assert (lu - pu).abs().max().item() < 1e-6 and (lv - pv).abs().max().item() < 1e-6
+    lu, lv = s.learned_fv_step(prm, net, u, v, 2)       # correction added
+    du = (lu.double() - pu.double()).mean(dim=(-2, -1))
+    assert torch.allclose(du.cpu(), torch.full((b,), 0.1, dtype=torch.float64), atol=1e-6)
+
+
+def test_rollout_equals_step_sequence():
+    L_ = need_gpu()
+    announce("rollout")
+    n, b = 32, 2
+    net, _, _ = _net(L_, seed=3)
+    s = L_.Solver(n, n, b)
+    u0, v0 = s.init_state(L_.IC_GRF_PEAK, seed=6)
+    prm = L_.params(k_c=2, fallback_enable=0, **KW)
+    tu, tv = s.rollout(prm, u0, v0, nsteps=6, save_every=2, net=net)
+    u, v = u0.clone(), v0.clone()
+    for k in range(6):
+        u, v = s.learned_fv_step(prm, net, u, v, k + 1)
+        if (k + 1) % 2 == 0:
+            assert torch.equal(tu[(k + 1) // 2 - 1], u) and torch.equal(tv[(k + 1) // 2 - 1], v)
+    # plain rollout
+    tu, tv = s.rollout(L_.params(**KW), u0, v0, nsteps=3, save_every=3)
+    pu, pv = s.fv_step(L_.params(**KW), u0, v0, nsteps=3)
+    assert torch.equal(tu[0], pu) and torch.equal(tv[0], pv)
+
+
+def test_guard_falls_back_to_plain_fv_for_the_failing_trajectory_only():
+    L_ = need_gpu()
+    announce("guard")
+    n, b = 32, 3
+    kw = dict(KW, dt=0.005)
+    net, _, _ = _net(L_, seed=4)
+    s = L_.Solver(n, n, b)
+    u0, v0 = s.init_state(L_.IC_GRF_PEAK, seed=7)
+    u0[2] *= 8.0
+    v0[2] *= 8.0
+    flags = torch.zeros(b, dtype=torch.int32, device="cuda")
+    bound = 4.0 * float((u0[:2].abs() + v0[:2].abs()).max())
+    prm = L_.params(k_c=1, guard_threshold=bound, fallback_enable=1, **kw)
+    tu, tv = s.rollout(prm, u0, v0, nsteps=2, save_every=1, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    assert flags.tolist() == [0, 0, 2]
+    assert torch.isfinite(tu).all() and torch.isfinite(tv).all()
+    # untouched trajectories follow the learned steps; the failing one the plain steps
+    u, v = u0.clone(), v0.clone()
+    pu, pv = u0.clone(), v0.clone()
+    for k in range(2):
+        u, v = s.learned_fv_step(prm, net, u, v, k + 1)
+        pu, pv = s.fv_step(L_.params(**kw), pu, pv)
+    assert torch.equal(tu[1, :2], u[:2]) and torch.equal(tu[1, 2], pu[2])
+    # with the fallback disabled the call reports the failure
+    prm = L_.params(k_c=1, guard_threshold=bound, fallback_enable=0, **kw)
+    with pytest.raises(L_.LdsvError) as e:
+        s.rollout(prm, u0, v0, nsteps=1, save_every=1, net=net)
+    assert e.value.code == L_.ENONFINITE
+
+
+def test_nan_network_falls_back_everywhere():
+    L_ = need_gpu()
+    announce("nan guard")
+    n, b = 16, 2
+    ws, bs = si.cnn_weights(5, cnn.LAYERS)
+    bs[-1][3] = float("nan")
+    net = L_.NetParams([torch.tensor(w) for w in ws], [torch.tensor(x) for x in bs])
+    s = L_.Solver(n, n, b)
+    u0, v0 = s.init_state(L_.IC_GRF_PEAK, seed=8)
+    flags = torch.zeros(b, dtype=torch.int32, device="cuda")
+    prm = L_.params(k_c=1, fallback_enable=1, **KW)
+    tu, tv = s.rollout(prm, u0, v0, nsteps=3, save_every=3, net=net, fallback_flags=flags)
+    pu, pv = s.fv_step(L_.params(**KW), u0, v0, nsteps=3)
+    torch.cuda.synchronize()
+    assert flags.tolist() == [3, 3]
+    assert torch.equal(tu[0], pu) and torch.equal(tv[0], pv)
