@@ -1,0 +1,318 @@
+// Adjoint (vector-Jacobian product) of the MAC finite-volume residual and of
+// the RK4 step with a projection after every sub-step (the differentiable
+// solver backbone of the method; Sec. 3.2 RK4 + projection, Sec. 3.3-3.4
+// flux stencils).
+//
+// Residual adjoint.  With cotangents (lu, lv) of R = (R_u, R_v), the face
+// cotangents are differences of the cotangents of the two control volumes
+// the face separates, e.g. for the east face of the u volume owned by cell o
+// Fb = (lu[o + x] - lu[o]) / dx.  Each face flux F = abar * atil - nu * D
+// then sends
+//   Fb * atil / 2   to the two velocities averaged into the advecting abar,
+//   Fb * abar * c_s to every point s of the interpolation stencil atil,
+//   -nu * Fb * w_m / (24 h) to the four points of the derivative D,
+// and the coefficient gradient dc_s = Fb * abar * q_s, projected through the
+// sum-to-one constraint (dr_t = dc_t - mean(dc)).  Drag adds -d * l
+// pointwise.  Two kernels, both gather-only (no atomics, deterministic):
+//   k_adj_faces   one thread per owner cell: the 12 face scalars (P: abar
+//                 part, Q: stencil multiplier, V: viscous multiplier for the
+//                 4 faces) and the per-kind coefficient means; accumulates the
+//                 coefficient gradient of its own cell;
+//   k_adj_gather  one thread per output cell: sums what every face whose
+//                 stencil touches the cell sends to it.
+//
+// RK4 reverse sweep, with P the (symmetric) projection and u1..u3 the
+// recomputed projected stage states:
+//   A = P g;  S = A
+//   l4 = dt/6 A           -> w3 = J(u3)^T l4, g3 = P w3, S += g3
+//   l3 = dt/3 A + dt g3   -> w2 = J(u2)^T l3, g2 = P w2, S += g2
+//   l2 = dt/3 A + dt/2 g2 -> w1 = J(u1)^T l2, g1 = P w1, S += g1
+//   l1 = dt/6 A + dt/2 g1 -> dL/du0 = S + J(u0)^T l1
+#include "adjoint.h"
+#include "stage.h"
+
+namespace {
+
+__constant__ int kAOffA[16] = {-1, 0, 1, 2, -1, 0, 1, 2, -1, 0, 1, 2, 0, 1, 0, 1};
+__constant__ int kBOffA[16] = {-1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -2, -2, 2, 2};
+
+struct AdjPhys {
+  double nu, drag, dx, dy;
+  int mask;
+};
+
+template <typename T>
+struct Field {
+  const T* p;
+  int nx, ny;
+  __device__ __forceinline__ T operator()(int i, int j) const {
+    return p[(size_t)(j & (ny - 1)) * nx + (i & (nx - 1))];
+  }
+};
+
+// scratch layout (per trajectory plane, 16 planes): P0..P3, Q0..Q3, V0..V3, M0..M3
+constexpr int kAdjPlanes = 16;
+
+template <typename T, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, const T* __restrict__ vs,
+                                                      const T* __restrict__ Au, const T* __restrict__ Av,
+                                                      const T* __restrict__ Gu, const T* __restrict__ Gv,
+                                                      double aA, double aG, const float* __restrict__ coef,
+                                                      size_t cbs, float* __restrict__ gcoef, size_t gcbs,
+                                                      T* __restrict__ scr, AdjPhys ph, int nx, int ny) {
+  const size_t n = (size_t)nx * ny;
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * n;
+  const Field<T> U{us + off, nx, ny}, V{vs + off, nx, ny};
+  const Field<T> LA_u{Au + off, nx, ny}, LA_v{Av + off, nx, ny};
+  const T* gu = Gu ? Gu + off : nullptr;
+  const T* gv = Gv ? Gv + off : nullptr;
+  T* S = scr + (size_t)b * kAdjPlanes * n;
+  const T cA = (T)aA, cG = (T)aG;
+  const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
+  const T nu = (T)ph.nu;
+  const bool adv = ph.mask & LDSV_ADVECTION, visc = ph.mask & LDSV_VISCOSITY;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx), j = (int)(c / nx);
+    auto lam_u = [&](int a, int bb) {
+      const size_t q = (size_t)((j + bb) & (ny - 1)) * nx + ((i + a) & (nx - 1));
+      T l = cA * LA_u.p[q];
+      if (gu) l += cG * gu[q];
+      return l;
+    };
+    auto lam_v = [&](int a, int bb) {
+      const size_t q = (size_t)((j + bb) & (ny - 1)) * nx + ((i + a) & (nx - 1));
+      T l = cA * LA_v.p[q];
+      if (gv) l += cG * gv[q];
+      return l;
+    };
+    const T l0u = lam_u(0, 0), l0v = lam_v(0, 0);
+    const T fxb = (lam_u(1, 0) - l0u) * idx;
+    const T fyb = (lam_u(0, 1) - l0u) * idy;
+    const T exb = (lam_v(1, 0) - l0v) * idx;
+    const T eyb = (lam_v(0, 1) - l0v) * idy;
+    T P[4] = {0, 0, 0, 0}, Q[4] = {0, 0, 0, 0}, Vm[4] = {0, 0, 0, 0}, M[4] = {0, 0, 0, 0};
+    if (adv) {
+      const T ubar_c = (T)0.5 * (U(i, j) + U(i + 1, j));
+      const T vbar_n = (T)0.5 * (V(i - 1, j + 1) + V(i, j + 1));
+      const T ubar_e = (T)0.5 * (U(i + 1, j - 1) + U(i + 1, j));
+      const T vbar_c = (T)0.5 * (V(i, j) + V(i, j + 1));
+      T face[4];
+      if (LEARNED) {
+        const float* cb = coef + (size_t)b * cbs;
+        float* gc = gcoef ? gcoef + (size_t)b * gcbs : nullptr;
+        const T qmul[4] = {fxb * ubar_c, fyb * vbar_n, exb * ubar_e, eyb * vbar_c};
+#pragma unroll
+        for (int K = 0; K < 4; ++K) {
+          const Field<T>& F = (K < 2) ? U : V;
+          const bool along_x = (K == 0 || K == 2);
+          T r[16], q[16];
+          T mr = 0, mq = 0;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            r[s] = (T)cb[(size_t)(16 * K + s) * n + c];
+            q[s] = along_x ? F(i + kAOffA[s], j + kBOffA[s]) : F(i + kBOffA[s], j + kAOffA[s]);
+            mr += r[s];
+            mq += q[s];
+          }
+          mr *= (T)(1.0 / 16.0);
+          mq *= (T)(1.0 / 16.0);
+          T val = 0;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) val += (r[s] - mr) * q[s];
+          val += (T)0.5 * (q[5] + q[6]);
+          face[K] = val;
+          M[K] = mr;
+          if (gc) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+              gc[(size_t)(16 * K + s) * n + c] += (float)(qmul[K] * (q[s] - mq));
+          }
+        }
+      } else {
+        face[0] = (T)0.5 * (U(i, j) + U(i + 1, j));
+        face[1] = (T)0.5 * (U(i, j) + U(i, j + 1));
+        face[2] = (T)0.5 * (V(i, j) + V(i + 1, j));
+        face[3] = (T)0.5 * (V(i, j) + V(i, j + 1));
+      }
+      P[0] = (T)0.5 * fxb * face[0];
+      P[1] = (T)0.5 * fyb * face[1];
+      P[2] = (T)0.5 * exb * face[2];
+      P[3] = (T)0.5 * eyb * face[3];
+      Q[0] = fxb * ubar_c;
+      Q[1] = fyb * vbar_n;
+      Q[2] = exb * ubar_e;
+      Q[3] = eyb * vbar_c;
+    }
+    if (visc) {
+      Vm[0] = -nu * fxb * (T)(1.0 / 24.0) * idx;
+      Vm[1] = -nu * fyb * (T)(1.0 / 24.0) * idy;
+      Vm[2] = -nu * exb * (T)(1.0 / 24.0) * idx;
+      Vm[3] = -nu * eyb * (T)(1.0 / 24.0) * idy;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      S[(size_t)k * n + c] = P[k];
+      S[(size_t)(4 + k) * n + c] = Q[k];
+      S[(size_t)(8 + k) * n + c] = Vm[k];
+      S[(size_t)(12 + k) * n + c] = M[k];
+    }
+  }
+}
+
+template <typename T, bool LEARNED>
+__global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr,
+                                                       const float* __restrict__ coef, size_t cbs,
+                                                       const T* __restrict__ Au, const T* __restrict__ Av,
+                                                       const T* __restrict__ Gu, const T* __restrict__ Gv,
+                                                       double aA, double aG,
+                                                       const T* __restrict__ addu, const T* __restrict__ addv,
+                                                       T* __restrict__ ou, T* __restrict__ ov, AdjPhys ph,
+                                                       int nx, int ny) {
+  const size_t n = (size_t)nx * ny;
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * n;
+  const T* S = scr + (size_t)b * kAdjPlanes * n;
+  const float* cb = LEARNED ? coef + (size_t)b * cbs : nullptr;
+  const T wv[4] = {(T)1, (T)-27, (T)27, (T)-1};  // derivative weights for offsets -1..2
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx), j = (int)(c / nx);
+    auto at = [&](int plane, int ii, int jj) {
+      return S[(size_t)plane * n + (size_t)(jj & (ny - 1)) * nx + (ii & (nx - 1))];
+    };
+    auto cidx = [&](int ii, int jj) { return (size_t)(jj & (ny - 1)) * nx + (ii & (nx - 1)); };
+    // stencil multiplier sent by owner o for point s of kind K
+    auto coefv = [&](int K, int s, int ii, int jj) -> T {
+      if (LEARNED) {
+        const size_t o = cidx(ii, jj);
+        return (T)cb[(size_t)(16 * K + s) * n + o] - S[(size_t)(12 + K) * n + o] +
+               ((s == 5 || s == 6) ? (T)0.5 : (T)0);
+      }
+      return (s == 5 || s == 6) ? (T)0.5 : (T)0;
+    };
+    T gu = 0, gv = 0;
+    // advecting-velocity parts
+    gu += at(0, i, j) + at(0, i - 1, j);          // P0: u(o), u(o+x)
+    gu += at(2, i - 1, j + 1) + at(2, i - 1, j);  // P2: u(o+x, o-y), u(o+x)
+    gv += at(1, i + 1, j - 1) + at(1, i, j - 1);  // P1: v(o-x+y), v(o+y)
+    gv += at(3, i, j) + at(3, i, j - 1);          // P3: v(o), v(o+y)
+    // interpolation stencils
+    if (LEARNED) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int a = kAOffA[s], bb = kBOffA[s];
+        gu += coefv(0, s, i - a, j - bb) * at(4, i - a, j - bb);
+        gu += coefv(1, s, i - bb, j - a) * at(5, i - bb, j - a);
+        gv += coefv(2, s, i - a, j - bb) * at(6, i - a, j - bb);
+        gv += coefv(3, s, i - bb, j - a) * at(7, i - bb, j - a);
+      }
+    } else {
+      gu += (T)0.5 * (at(4, i, j) + at(4, i - 1, j));
+      gu += (T)0.5 * (at(5, i, j) + at(5, i, j - 1));
+      gv += (T)0.5 * (at(6, i, j) + at(6, i - 1, j));
+      gv += (T)0.5 * (at(7, i, j) + at(7, i, j - 1));
+    }
+    // viscous face derivatives: owner o = p - m sends V * w_m to p
+#pragma unroll
+    for (int m = -1; m <= 2; ++m) {
+      const T w = wv[m + 1];
+      gu += w * (at(8, i - m, j) + at(9, i, j - m));
+      gv += w * (at(10, i - m, j) + at(11, i, j - m));
+    }
+    if (ph.mask & LDSV_FORCING) {
+      T lu = (T)aA * Au[off + c], lv = (T)aA * Av[off + c];
+      if (Gu) {
+        lu += (T)aG * Gu[off + c];
+        lv += (T)aG * Gv[off + c];
+      }
+      gu -= (T)ph.drag * lu;
+      gv -= (T)ph.drag * lv;
+    }
+    if (addu) {
+      gu += addu[off + c];
+      gv += addv[off + c];
+    }
+    ou[off + c] = gu;
+    ov[off + c] = gv;
+  }
+}
+
+template <typename T>
+__global__ void k_axpy2(T* yu, T* yv, const T* xu, const T* xv, T a, size_t n) {
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x) {
+    yu[g] += a * xu[g];
+    yv[g] += a * xv[g];
+  }
+}
+
+template <typename T>
+int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
+              float* gcoef, size_t gcbs, const void* us, const void* vs, const void* Au,
+              const void* Av, const void* Gu, const void* Gv, double aA, double aG,
+              const void* addu, const void* addv, void* ou, void* ov, hipStream_t st) {
+  AdjPhys ph{prm->nu, prm->drag, h->g.lx / h->g.nx, h->g.ly / h->g.ny, prm->physics_mask};
+  const int nx = h->g.nx, ny = h->g.ny;
+  dim3 grid((unsigned)std::min<size_t>((h->ncell + kBlock - 1) / kBlock, 4096), h->g.batch);
+  T* scr = (T*)h->adj_g;
+  TimerScope ts(h, 6, st);
+  if (coef) {
+    hipLaunchKernelGGL((k_adj_faces<T, true>), grid, dim3(kBlock), 0, st, (const T*)us,
+                       (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
+                       aG, coef, cbs, gcoef, gcbs, scr, ph, nx, ny);
+    hipLaunchKernelGGL((k_adj_gather<T, true>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
+                       cbs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA, aG,
+                       (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph, nx, ny);
+  } else {
+    hipLaunchKernelGGL((k_adj_faces<T, false>), grid, dim3(kBlock), 0, st, (const T*)us,
+                       (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
+                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, scr, ph,
+                       nx, ny);
+    hipLaunchKernelGGL((k_adj_gather<T, false>), grid, dim3(kBlock), 0, st, (const T*)scr,
+                       (const float*)nullptr, (size_t)0, (const T*)Au, (const T*)Av, (const T*)Gu,
+                       (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph,
+                       nx, ny);
+  }
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}
+
+}  // namespace
+
+int ldsv_ensure_adjoint(ldsv_handle* h) {
+  if (h->adj_g) return LDSV_OK;
+  const size_t sb = h->nstate * h->esize;
+  // 6 stage planes (u1..u3), A, S, W, G (2 planes each) and 16 scratch planes
+  void* blk = nullptr;
+  LDSV_TRY(ldsv_alloc(h, &blk, (6 + 8 + kAdjPlanes) * sb, "adjoint workspace"));
+  h->stage_keep = blk;
+  h->adj_u = (char*)blk + 6 * sb;  // A (2), S (2), W (2), G (2)
+  h->adj_g = (char*)blk + 14 * sb;
+  return LDSV_OK;
+}
+
+// w = J_R(u)^T (aA A + aG G) [+ add]; optional coefficient gradient
+int ldsv_launch_adj_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
+                        float* gcoef, size_t gcbs, const void* us, const void* vs, const void* Au,
+                        const void* Av, const void* Gu, const void* Gv, double aA, double aG,
+                        const void* addu, const void* addv, void* ou, void* ov, hipStream_t st) {
+  if (h->g.dtype == LDSV_F64)
+    return adj_rhs_t<double>(h, prm, coef, cbs, gcoef, gcbs, us, vs, Au, Av, Gu, Gv, aA, aG, addu,
+                             addv, ou, ov, st);
+  return adj_rhs_t<float>(h, prm, coef, cbs, gcoef, gcbs, us, vs, Au, Av, Gu, Gv, aA, aG, addu,
+                          addv, ou, ov, st);
+}
+
+int ldsv_launch_axpy2(ldsv_handle* h, void* yu, void* yv, const void* xu, const void* xv, double a,
+                      hipStream_t st) {
+  if (h->g.dtype == LDSV_F64)
+    hipLaunchKernelGGL(k_axpy2<double>, grid1d(h->nstate), dim3(kBlock), 0, st, (double*)yu,
+                       (double*)yv, (const double*)xu, (const double*)xv, a, h->nstate);
+  else
+    hipLaunchKernelGGL(k_axpy2<float>, grid1d(h->nstate), dim3(kBlock), 0, st, (float*)yu,
+                       (float*)yv, (const float*)xu, (const float*)xv, (float)a, h->nstate);
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <vector>
 
+#include "adjoint.h"
 #include "reduce.h"
 #include "stage.h"
 
@@ -86,10 +87,15 @@ int check_params(const ldsv_handle* h, const ldsv_params* p) {
   return LDSV_OK;
 }
 
-// one time step src -> dst (dst may equal src)
+// one time step src -> dst (dst may equal src).  keep (nullable, RK4/MAC):
+// the projected stage states u1, u2, u3 are written to keep[2s], keep[2s+1]
+// (state-sized planes) instead of the shared stage buffer.
 int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs, const void* su,
              const void* sv, void* du, void* dv, const float* tcu, const float* tcv, size_t tcbs,
-             hipStream_t st) {
+             hipStream_t st, void* keep = nullptr) {
+  const size_t sbk = h->nstate * h->esize;
+  auto ku = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s) * sbk : h->ws_u; };
+  auto kv = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s + 1) * sbk : h->ws_v; };
   const double dt = p->dt;
   const bool mac = h->g.layout == LDSV_MAC;
   StageArgs a;
@@ -98,8 +104,8 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
   if (p->rk == LDSV_RK4) {
     const double eps[4] = {0.5 * dt, 0.5 * dt, dt, dt / 6.0};
     for (int s = 0; s < 4; ++s) {
-      a.us = (s == 0) ? su : h->ws_u;
-      a.vs = (s == 0) ? sv : h->ws_v;
+      a.us = (s == 0) ? su : ku(s - 1);
+      a.vs = (s == 0) ? sv : kv(s - 1);
       a.un = (s == 0) ? nullptr : su;
       a.vn = (s == 0) ? nullptr : sv;
       a.alpha = (s == 0) ? 0.0 : 1.0;
@@ -119,8 +125,8 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
         a.ou = h->st_u;
         a.ov = h->st_v;
         LDSV_TRY(ldsv_launch_stage(h, p, a, st));
-        LDSV_TRY(ldsv_launch_project(h, h->st_u, h->st_v, s == 3 ? du : h->ws_u,
-                                     s == 3 ? dv : h->ws_v, nullptr, st));
+        LDSV_TRY(ldsv_launch_project(h, h->st_u, h->st_v, s == 3 ? du : ku(s),
+                                     s == 3 ? dv : kv(s), nullptr, st));
       } else {
         // collocated RK4 without projection: stage outputs ping-pong
         LDSV_REQUIRE(false, LDSV_EDTYPE, "RK4 on the collocated layout is not provided; use SSPRK3");
@@ -177,6 +183,43 @@ int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, 
                        const void* su, const void* sv, void* du, void* dv, const float* tcu,
                        const float* tcv, size_t tcbs, hipStream_t st) {
   return one_step(h, p, coef, cbs, su, sv, du, dv, tcu, tcv, tcbs, st);
+}
+
+// VJP of one RK4 step with a projection per sub-step (reverse sweep in
+// adjoint.hip's header comment)
+int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
+                  float* gcoef, size_t gcbs, const void* su, const void* sv, const void* gu_out,
+                  const void* gv_out, void* gu_in, void* gv_in, hipStream_t st) {
+  LDSV_REQUIRE(h->g.layout == LDSV_MAC && prm->rk == LDSV_RK4, LDSV_EDTYPE,
+               "adjoint: RK4 on the MAC layout only");
+  LDSV_TRY(ldsv_ensure_adjoint(h));
+  const size_t sb = h->nstate * h->esize;
+  char* K = (char*)h->stage_keep;
+  char* A = (char*)h->adj_u;
+  char* S = A + 2 * sb;
+  char* W = A + 4 * sb;
+  char* G = A + 6 * sb;
+  const double dt = prm->dt;
+  // forward recompute keeping u1, u2, u3 (the output goes to W, unused)
+  LDSV_TRY(one_step(h, prm, coef, cbs, su, sv, W, W + sb, nullptr, nullptr, 0, st, K));
+  // A = P g, S = A
+  LDSV_TRY(ldsv_launch_project(h, gu_out, gv_out, A, A + sb, nullptr, st));
+  LDSV_HIP(hipMemcpyAsync(S, A, 2 * sb, hipMemcpyDeviceToDevice, st));
+  // stage 4 .. 2
+  const double aA[3] = {dt / 6.0, dt / 3.0, dt / 3.0};
+  const double aG[3] = {0.0, dt, 0.5 * dt};
+  for (int k = 0; k < 3; ++k) {
+    const int s = 2 - k;  // stage state u_{s+1} at keep plane s
+    LDSV_TRY(ldsv_launch_adj_rhs(h, prm, coef, cbs, gcoef, gcbs, K + 2 * s * sb,
+                                 K + (2 * s + 1) * sb, A, A + sb, k ? G : nullptr,
+                                 k ? G + sb : nullptr, aA[k], aG[k], nullptr, nullptr, W, W + sb,
+                                 st));
+    LDSV_TRY(ldsv_launch_project(h, W, W + sb, G, G + sb, nullptr, st));
+    LDSV_TRY(ldsv_launch_axpy2(h, S, S + sb, G, G + sb, 1.0, st));
+  }
+  // stage 1: dL/du0 = S + J(u0)^T (dt/6 A + dt/2 g1)
+  return ldsv_launch_adj_rhs(h, prm, coef, cbs, gcoef, gcbs, su, sv, A, A + sb, G, G + sb,
+                             dt / 6.0, 0.5 * dt, S, S + sb, gu_in, gv_in, st);
 }
 
 extern "C" {

@@ -7,3 +7,6 @@ int ldsv_ensure_learned(ldsv_handle* h);
 int ldsv_check_net(const ldsv_net* net);
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                     float* out, float* const* zpre, hipStream_t st);
+int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                             const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
+                             hipStream_t st);

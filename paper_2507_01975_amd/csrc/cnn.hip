@@ -23,142 +23,10 @@
 // Layer 1 (2 input channels, K = 18) is not a contraction worth the matrix
 // cores; it runs on the vector ALUs with bf16-rounded inputs and weights and
 // FP32 accumulation, the same arithmetic as the MFMA layers.
-#include "cnn.h"
+#include "cnn_common.h"
 
 namespace {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kC = 64;             // hidden channels
-constexpr int kWRow = kC + 8;      // padded LDS weight row (bf16 elements)
-constexpr int kPixPerWave = 64;    // 4 pixel tiles of 16
-constexpr int kPixPerBlock = 256;
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
-  return __uint_as_float(((uint32_t)h) << 16);
-}
-
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t x = __float_as_uint(f);
-  if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
-  x += 0x7fffu + ((x >> 16) & 1u);
-  return (uint16_t)(x >> 16);
-}
-
-__device__ __forceinline__ float gelu_exact(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
-}
-
-struct PixMap {
-  int H, W;
-  int total;  // B * H * W
-  __device__ __forceinline__ int shift(int p, int dy, int dx) const {
-    const int hw = H * W;
-    const int b = p / hw;
-    const int r = p - b * hw;
-    const int y = r / W;
-    const int x = r - y * W;
-    return b * hw + ((y + dy) & (H - 1)) * W + ((x + dx) & (W - 1));
-  }
-};
-
-// MT: output-channel tiles of 16 (4 for 64 channels, 5 for 66 padded to 80).
-// EPI 0: z = acc + bias -> gelu -> bf16 NHWC (and z float NHWC if zout)
-// EPI 1: z = acc + bias -> float planar [B][cout][H][W]
-template <int MT, int EPI>
-__global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restrict__ X,
-                                                         const uint16_t* __restrict__ Wt,
-                                                         const float* __restrict__ bias, int cout,
-                                                         PixMap pm, uint16_t* __restrict__ Y,
-                                                         float* __restrict__ zout,
-                                                         float* __restrict__ out_planar) {
-  __shared__ __attribute__((aligned(16))) uint16_t wl[MT * 16 * kWRow];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int pbase = blockIdx.x * kPixPerBlock + wave * kPixPerWave;
-  const int col = lane & 15;   // pixel within a tile / channel row within an A tile
-  const int kq = lane >> 4;    // which 8-wide K slice
-
-  f32x4 acc[4][MT];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int m = 0; m < MT; ++m) acc[t][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  int pix[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int p = pbase + t * 16 + col;
-    pix[t] = p < pm.total ? p : pm.total - 1;
-  }
-
-  for (int tap = 0; tap < 9; ++tap) {
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    __syncthreads();
-    // stage W[:, tap, :] (cout x 64 bf16) into LDS rows of kWRow; rows past
-    // cout are zero
-    for (int e = threadIdx.x; e < MT * 16 * (kC / 8); e += blockDim.x) {
-      const int row = e / (kC / 8), q = e - row * (kC / 8);
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (row < cout) v = *reinterpret_cast<const uint4*>(Wt + ((size_t)row * 9 + tap) * kC + q * 8);
-      *reinterpret_cast<uint4*>(wl + row * kWRow + q * 8) = v;
-    }
-    __syncthreads();
-    int src[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) src[t] = pm.shift(pix[t], dy, dx);
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int cbase = half * 32 + kq * 8;
-      bf16x8 bfrag[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        bfrag[t] = *reinterpret_cast<const bf16x8*>(X + (size_t)src[t] * kC + cbase);
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(wl + (m * 16 + col) * kWRow + cbase);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[t][m], 0, 0, 0);
-      }
-    }
-  }
-
-  // epilogue: lane holds channels m*16 + 4*kq + i of pixel pbase + t*16 + col
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int p = pbase + t * 16 + col;
-    if (p >= pm.total) continue;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int c0 = m * 16 + kq * 4;
-      if (EPI == 0) {
-        float z[4];
-        uint16_t h[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          z[i] = acc[t][m][i] + bias[c0 + i];
-          h[i] = f32_to_bf16(gelu_exact(z[i]));
-        }
-        uint2 pk;
-        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-        *reinterpret_cast<uint2*>(Y + (size_t)p * kC + c0) = pk;
-        if (zout) *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
-      } else {
-        const int hw = pm.H * pm.W;
-        const int b = p / hw;
-        const int r = p - b * hw;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int c = c0 + i;
-          if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i] + bias[c];
-        }
-      }
-    }
-  }
-}
+using namespace cnnk;
 
 // layer 1: 2 -> 64 on the vector ALUs; one thread per pixel
 __global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__ u,
@@ -246,14 +114,14 @@ int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const f
   const int nblk = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
   for (int l = 1; l < 5; ++l) {
     TimerScope ts(h, 4, st);
-    hipLaunchKernelGGL((k_conv3x3_mfma<4, 0>), dim3(nblk), dim3(kBlock), 0, st, h->act[l - 1],
+    hipLaunchKernelGGL((k_conv3x3_mfma<4, 0, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[l - 1],
                        net->w[l], net->b[l], kC, pm, h->act[l], zpre ? zpre[l] : nullptr,
                        (float*)nullptr);
     LDSV_LAUNCHED();
   }
   {
     TimerScope ts(h, 4, st);
-    hipLaunchKernelGGL((k_conv3x3_mfma<5, 1>), dim3(nblk), dim3(kBlock), 0, st, h->act[4],
+    hipLaunchKernelGGL((k_conv3x3_mfma<5, 1, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[4],
                        net->w[5], net->b[5], LDSV_NOUT, pm, (uint16_t*)nullptr, (float*)nullptr,
                        out);
   }

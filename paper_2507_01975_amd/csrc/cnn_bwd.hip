@@ -1,0 +1,318 @@
+// Backward pass of the coefficient network on gfx950 matrix cores.
+//
+// For a layer y = conv3x3(x, W) + b (circular padding) with output cotangent
+// g and input x:
+//   db[co]          = sum_p g[p][co]
+//   dW[co][tap][ci] = sum_p g[p][co] * x[p + tap][ci]            (wgrad)
+//   dx[p][ci]       = sum_{tap, co} g[p - tap][co] * W[co][tap][ci]
+//                   = conv3x3(g, W')[p][ci],  W'[ci][t][co] = W[co][8 - t][ci]
+// and through GELU dz = dx * GELU'(z) with the pre-activation z recomputed
+// by a forward pass.  The data gradient reuses the forward implicit-GEMM
+// kernel with the flipped, transposed weights and a GELU' epilogue.  The
+// weight gradient is a GEMM with the pixels as the reduction dimension: per
+// chunk of 32 pixels a workgroup stages g transposed ([co][pixel]) and the 9
+// shifted copies of x transposed ([tap, ci][pixel]) in LDS, so both MFMA
+// operands are contiguous 8-element pixel runs; each workgroup reduces a
+// range of pixels in registers and writes one partial, and a second kernel
+// sums the partials in a fixed order (deterministic, no atomics).  Cotangents
+// are stored in bf16 between layers, products accumulate in FP32.  The first
+// layer (2 input channels) runs on the vector ALUs.
+#include "cnn_common.h"
+
+namespace {
+using namespace cnnk;
+
+constexpr int kChunk = 32;        // pixels per MFMA K step in wgrad
+constexpr int kTRow = kChunk + 8; // padded LDS row of transposed operands
+constexpr int kWgPix = 2048;      // pixels reduced per wgrad workgroup
+constexpr int kK = 9 * kC;        // 576 = (tap, ci) columns of dW
+
+// gout planar float [B][66][H][W] -> bf16 NHWC [P][96] (channels 66..95 zero)
+__global__ void k_gout_to_nhwc(const float* __restrict__ g, uint16_t* __restrict__ G, int hw,
+                               int total) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)total * 96;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / 96), c = (int)(e % 96);
+    float v = 0.f;
+    if (c < LDSV_NOUT) {
+      const int b = p / hw, r = p - b * hw;
+      v = g[((size_t)b * LDSV_NOUT + c) * hw + r];
+    }
+    G[e] = f32_to_bf16(v);
+  }
+}
+
+// W [cout][9][64] -> W' [64][9][cpad] with W'[ci][t][co] = W[co][8 - t][ci]
+__global__ void k_dgrad_weights(const uint16_t* __restrict__ W, uint16_t* __restrict__ Wp, int cout,
+                                int cpad) {
+  const int total = kC * 9 * cpad;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int ci = e / (9 * cpad);
+    const int t = (e / cpad) % 9;
+    const int co = e % cpad;
+    Wp[e] = (co < cout) ? W[((size_t)co * 9 + (8 - t)) * kC + ci] : (uint16_t)0;
+  }
+}
+
+// partial dW over the workgroup's pixel range; dz has CS channels, MT tiles
+template <int MT, int CS>
+__global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ dz,
+                                                  const uint16_t* __restrict__ x, PixMap pm,
+                                                  float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) uint16_t gT[MT * 16 * kTRow];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[kK * kTRow];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  f32x4 acc[MT][9];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < 9; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int p_begin = blockIdx.x * kWgPix;
+  const int p_end = min(p_begin + kWgPix, pm.total);
+  for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kChunk * MT * 16; e += blockDim.x) {
+      const int pl = e / (MT * 16), co = e % (MT * 16);
+      const int p = p0 + pl;
+      uint16_t v = 0;
+      if (p < p_end && co < CS) v = dz[(size_t)p * CS + co];
+      gT[co * kTRow + pl] = v;
+    }
+    for (int e = threadIdx.x; e < kChunk * 9 * (kC / 8); e += blockDim.x) {
+      const int pl = e / (9 * (kC / 8));
+      const int r = e - pl * (9 * (kC / 8));
+      const int tap = r / (kC / 8), q = r % (kC / 8);
+      const int p = p0 + pl;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (p < p_end) {
+        const int src = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
+        v = *reinterpret_cast<const uint4*>(x + (size_t)src * kC + q * 8);
+      }
+      const uint16_t h[8] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16),
+                             (uint16_t)(v.y & 0xffff), (uint16_t)(v.y >> 16),
+                             (uint16_t)(v.z & 0xffff), (uint16_t)(v.z >> 16),
+                             (uint16_t)(v.w & 0xffff), (uint16_t)(v.w >> 16)};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xT[(tap * kC + q * 8 + i) * kTRow + pl] = h[i];
+    }
+    __syncthreads();
+    bf16x8 af[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+      af[m] = *reinterpret_cast<const bf16x8*>(gT + (m * 16 + col) * kTRow + kq * 8);
+#pragma unroll
+    for (int n = 0; n < 9; ++n) {
+      const int kcol = (wave * 9 + n) * 16 + col;
+      const bf16x8 bf = *reinterpret_cast<const bf16x8*>(xT + kcol * kTRow + kq * 8);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bf, acc[m][n], 0, 0, 0);
+    }
+  }
+  float* out = partial + (size_t)blockIdx.x * (MT * 16) * kK;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < 9; ++n)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        out[(size_t)(m * 16 + kq * 4 + i) * kK + (wave * 9 + n) * 16 + col] = acc[m][n][i];
+}
+
+// dW[co][k] += sum over partials (fixed order); rows of partial = rows
+__global__ void k_partial_reduce(const float* __restrict__ partial, int nblk, int rows, int cout,
+                                 int ncol, float* __restrict__ dW) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cout * ncol; e += gridDim.x * blockDim.x) {
+    const int co = e / ncol, k = e % ncol;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += partial[((size_t)b * rows + co) * ncol + k];
+    dW[e] += s;
+  }
+}
+
+// bias gradient partials from bf16 NHWC cotangents (CS channels) or from the
+// float planar network-output cotangent (planar != 0, CS = 66)
+__global__ void k_bias_partial(const uint16_t* __restrict__ dz, const float* __restrict__ planar,
+                               int CS, int hw, int total, float* __restrict__ partial) {
+  // block b handles pixels [b * kWgPix, ...); thread t sums channel t
+  const int p_begin = blockIdx.x * kWgPix;
+  const int p_end = min(p_begin + kWgPix, total);
+  for (int c = threadIdx.x; c < CS; c += blockDim.x) {
+    float s = 0.f;
+    for (int p = p_begin; p < p_end; ++p) {
+      if (planar) {
+        const int b = p / hw, r = p - b * hw;
+        s += planar[((size_t)b * CS + c) * hw + r];
+      } else {
+        s += bf16_to_f32(dz[(size_t)p * CS + c]);
+      }
+    }
+    partial[(size_t)blockIdx.x * CS + c] = s;
+  }
+}
+
+// first layer: partial dW0[co][tap][ci] over a pixel range (VALU)
+__global__ void __launch_bounds__(kBlock) k_wgrad_first(const uint16_t* __restrict__ dz1,
+                                                        const float* __restrict__ u,
+                                                        const float* __restrict__ v, PixMap pm,
+                                                        float* __restrict__ partial) {
+  __shared__ float sx[kChunk][18];
+  __shared__ float sg[kChunk][kC];
+  const int p_begin = blockIdx.x * kWgPix;
+  const int p_end = min(p_begin + kWgPix, pm.total);
+  // thread owns outputs e = threadIdx.x + k * 256 (< 64 * 18 = 1152)
+  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kChunk * 18; e += blockDim.x) {
+      const int pl = e / 18, k = e % 18;
+      const int p = p0 + pl;
+      float val = 0.f;
+      if (p < p_end) {
+        const int tap = k / 2;
+        const int src = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
+        val = bf16_to_f32(f32_to_bf16((k & 1) ? v[src] : u[src]));
+      }
+      sx[pl][k] = val;
+    }
+    for (int e = threadIdx.x; e < kChunk * kC; e += blockDim.x) {
+      const int pl = e / kC, c = e % kC;
+      const int p = p0 + pl;
+      sg[pl][c] = (p < p_end) ? bf16_to_f32(dz1[(size_t)p * kC + c]) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < kC * 18) {
+        const int co = e / 18, kk = e % 18;
+        float s = 0.f;
+        for (int pl = 0; pl < kChunk; ++pl) s += sg[pl][co] * sx[pl][kk];
+        acc[k] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    if (e < kC * 18) partial[(size_t)blockIdx.x * kC * 18 + e] = acc[k];
+  }
+}
+
+// first layer data gradient: gu[p] = sum_{tap, co} dz1[p - tap][co] W1[co][tap][0]
+__global__ void __launch_bounds__(kBlock) k_dgrad_first(const uint16_t* __restrict__ dz1,
+                                                        const uint16_t* __restrict__ W1, PixMap pm,
+                                                        float* __restrict__ gu, float* __restrict__ gv) {
+  __shared__ float w[kC * 18];
+  for (int e = threadIdx.x; e < kC * 18; e += blockDim.x) w[e] = bf16_to_f32(W1[e]);
+  __syncthreads();
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= pm.total) return;
+  float su = 0.f, sv = 0.f;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int q = pm.shift(p, -(tap / 3 - 1), -(tap % 3 - 1));
+    const uint16_t* g = dz1 + (size_t)q * kC;
+    for (int co = 0; co < kC; ++co) {
+      const float gg = bf16_to_f32(g[co]);
+      su += gg * w[(co * 9 + tap) * 2];
+      sv += gg * w[(co * 9 + tap) * 2 + 1];
+    }
+  }
+  gu[p] = su;
+  gv[p] = sv;
+}
+
+}  // namespace
+
+int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                             const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
+                             hipStream_t st) {
+  const size_t P = h->nstate;
+  const int nwg = (int)((P + kWgPix - 1) / kWgPix);
+  // workspace: 5 pre-activation planes (float NHWC 64), G (bf16 96), two dz
+  // buffers (bf16 64), W' (bf16 64 x 9 x 96), wgrad partials
+  if (!h->zpre_blk) {
+    const size_t bytes = 5 * P * kC * 4 + P * 96 * 2 + 2 * P * kC * 2 + (size_t)kC * 9 * 96 * 2 +
+                         (size_t)nwg * 80 * kK * 4 + 256;
+    LDSV_TRY(ldsv_alloc(h, &h->zpre_blk, bytes, "network backward workspace"));
+  }
+  char* w = (char*)h->zpre_blk;
+  float* zpre[5];
+  for (int l = 0; l < 5; ++l) zpre[l] = (float*)(w + (size_t)l * P * kC * 4);
+  uint16_t* G = (uint16_t*)(w + 5 * P * kC * 4);
+  uint16_t* dzA = G + P * 96;
+  uint16_t* dzB = dzA + P * kC;
+  uint16_t* Wp = dzB + P * kC;
+  float* part = (float*)((char*)(Wp + (size_t)kC * 9 * 96) + 0);
+  part = (float*)(((uintptr_t)part + 255) & ~(uintptr_t)255);
+  PixMap pm{h->g.ny, h->g.nx, (int)P};
+  const int hw = (int)h->ncell;
+  const int nblk_conv = (int)((P + kPixPerBlock - 1) / kPixPerBlock);
+
+  // forward recompute with pre-activations
+  LDSV_TRY(ldsv_launch_cnn(h, net, u, v, h->netout, zpre, st));
+  // layer 6: bias from the float cotangent, G = bf16 NHWC copy
+  hipLaunchKernelGGL(k_bias_partial, dim3(nwg), dim3(128), 0, st, (const uint16_t*)nullptr, gout,
+                     LDSV_NOUT, hw, (int)P, part);
+  hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(128), 0, st, part, nwg, LDSV_NOUT, LDSV_NOUT,
+                     1, dW->b[5]);
+  hipLaunchKernelGGL(k_gout_to_nhwc, grid1d(P * 96), dim3(kBlock), 0, st, gout, G, hw, (int)P);
+  LDSV_LAUNCHED();
+  {
+    TimerScope ts(h, 4, st);
+    hipLaunchKernelGGL((k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, part);
+  }
+  hipLaunchKernelGGL(k_partial_reduce, grid1d((size_t)LDSV_NOUT * kK), dim3(kBlock), 0, st, part,
+                     nwg, 80, LDSV_NOUT, kK, dW->w[5]);
+  hipLaunchKernelGGL(k_dgrad_weights, grid1d((size_t)kC * 9 * 96), dim3(kBlock), 0, st, net->w[5],
+                     Wp, LDSV_NOUT, 96);
+  LDSV_LAUNCHED();
+  {
+    TimerScope ts(h, 4, st);
+    hipLaunchKernelGGL((k_conv3x3_mfma<4, 2, 96>), dim3(nblk_conv), dim3(kBlock), 0, st, G, Wp,
+                       (const float*)nullptr, kC, pm, dzA, zpre[4], (float*)nullptr);
+  }
+  LDSV_LAUNCHED();
+  uint16_t* dz = dzA;
+  uint16_t* dzn = dzB;
+  // layers 5..2 (index 4..1): dz is the cotangent of layer index li's pre-activation
+  for (int li = 4; li >= 1; --li) {
+    hipLaunchKernelGGL(k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC,
+                       hw, (int)P, part);
+    hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[li]);
+    {
+      TimerScope ts(h, 4, st);
+      hipLaunchKernelGGL((k_wgrad<4, 64>), dim3(nwg), dim3(kBlock), 0, st, dz, h->act[li - 1], pm,
+                         part);
+    }
+    hipLaunchKernelGGL(k_partial_reduce, grid1d((size_t)kC * kK), dim3(kBlock), 0, st, part, nwg,
+                       64, kC, kK, dW->w[li]);
+    hipLaunchKernelGGL(k_dgrad_weights, grid1d((size_t)kC * 9 * 64), dim3(kBlock), 0, st,
+                       net->w[li], Wp, kC, 64);
+    {
+      TimerScope ts(h, 4, st);
+      hipLaunchKernelGGL((k_conv3x3_mfma<4, 2, 64>), dim3(nblk_conv), dim3(kBlock), 0, st, dz, Wp,
+                         (const float*)nullptr, kC, pm, dzn, zpre[li - 1], (float*)nullptr);
+    }
+    LDSV_LAUNCHED();
+    uint16_t* t = dz;
+    dz = dzn;
+    dzn = t;
+  }
+  // layer 1
+  hipLaunchKernelGGL(k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC, hw,
+                     (int)P, part);
+  hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[0]);
+  hipLaunchKernelGGL(k_wgrad_first, dim3(nwg), dim3(kBlock), 0, st, dz, u, v, pm, part);
+  hipLaunchKernelGGL(k_partial_reduce, grid1d((size_t)kC * 18), dim3(kBlock), 0, st, part, nwg,
+                     kC * 18, kC * 18, 1, dW->w[0]);
+  LDSV_LAUNCHED();
+  if (gu && gv) {
+    hipLaunchKernelGGL(k_dgrad_first, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       st, dz, net->w[0], pm, gu, gv);
+    LDSV_LAUNCHED();
+  }
+  return LDSV_OK;
+}

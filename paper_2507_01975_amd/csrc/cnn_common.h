@@ -1,0 +1,158 @@
+// Device code shared by the forward and backward network kernels: bf16
+// helpers, the periodic pixel map and the implicit-GEMM 3x3 convolution on
+// v_mfma_f32_16x16x32_bf16 (see cnn.hip for the design).
+#pragma once
+
+#include "cnn.h"
+
+namespace cnnk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kC = 64;             // hidden channels
+constexpr int kPixPerWave = 64;    // 4 pixel tiles of 16
+constexpr int kPixPerBlock = 256;
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t x = __float_as_uint(f);
+  if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
+  x += 0x7fffu + ((x >> 16) & 1u);
+  return (uint16_t)(x >> 16);
+}
+
+__device__ __forceinline__ float gelu_exact(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+// d/dz of the exact GELU: Phi(z) + z phi(z)
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+struct PixMap {
+  int H, W;
+  int total;  // B * H * W
+  __device__ __forceinline__ int shift(int p, int dy, int dx) const {
+    const int hw = H * W;
+    const int b = p / hw;
+    const int r = p - b * hw;
+    const int y = r / W;
+    const int x = r - y * W;
+    return b * hw + ((y + dy) & (H - 1)) * W + ((x + dx) & (W - 1));
+  }
+};
+
+// MT: output-channel tiles of 16.  CIN: input channels (multiple of 32).
+// EPI 0: z = acc + bias -> gelu -> bf16 NHWC [P][64] (and z float NHWC if zout)
+// EPI 1: z = acc + bias -> float planar [B][cout][H][W]
+// EPI 2: g = acc * gelu'(zin[p][c]) -> bf16 NHWC [P][64] (data gradient)
+template <int MT, int EPI, int CIN>
+__global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restrict__ X,
+                                                         const uint16_t* __restrict__ Wt,
+                                                         const float* __restrict__ bias, int cout,
+                                                         PixMap pm, uint16_t* __restrict__ Y,
+                                                         float* __restrict__ zio,
+                                                         float* __restrict__ out_planar) {
+  constexpr int kWRow = CIN + 8;  // padded LDS weight row (bf16 elements)
+  __shared__ __attribute__((aligned(16))) uint16_t wl[MT * 16 * kWRow];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int pbase = blockIdx.x * kPixPerBlock + wave * kPixPerWave;
+  const int col = lane & 15;   // pixel within a tile / channel row within an A tile
+  const int kq = lane >> 4;    // which 8-wide K slice
+
+  f32x4 acc[4][MT];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[t][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  int pix[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int p = pbase + t * 16 + col;
+    pix[t] = p < pm.total ? p : pm.total - 1;
+  }
+
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    __syncthreads();
+    // stage W[:, tap, :] (cout x CIN bf16) into LDS rows of kWRow; rows past
+    // cout are zero
+    for (int e = threadIdx.x; e < MT * 16 * (CIN / 8); e += blockDim.x) {
+      const int row = e / (CIN / 8), q = e - row * (CIN / 8);
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (row < cout) v = *reinterpret_cast<const uint4*>(Wt + ((size_t)row * 9 + tap) * CIN + q * 8);
+      *reinterpret_cast<uint4*>(wl + row * kWRow + q * 8) = v;
+    }
+    __syncthreads();
+    int src[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) src[t] = pm.shift(pix[t], dy, dx);
+#pragma unroll
+    for (int half = 0; half < CIN / 32; ++half) {
+      const int cbase = half * 32 + kq * 8;
+      bf16x8 bfrag[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        bfrag[t] = *reinterpret_cast<const bf16x8*>(X + (size_t)src[t] * CIN + cbase);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(wl + (m * 16 + col) * kWRow + cbase);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[t][m], 0, 0, 0);
+      }
+    }
+  }
+
+  // epilogue: lane holds channels m*16 + 4*kq + i of pixel pbase + t*16 + col
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int p = pbase + t * 16 + col;
+    if (p >= pm.total) continue;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int c0 = m * 16 + kq * 4;
+      if (EPI == 0 || EPI == 2) {
+        float z[4];
+        uint16_t h[4];
+        if (EPI == 2) {
+          const float4 zi = *reinterpret_cast<const float4*>(zio + (size_t)p * kC + c0);
+          const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = f32_to_bf16(acc[t][m][i] * gelu_grad(zz[i]));
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            z[i] = acc[t][m][i] + bias[c0 + i];
+            h[i] = f32_to_bf16(gelu_exact(z[i]));
+          }
+        }
+        uint2 pk;
+        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        *reinterpret_cast<uint2*>(Y + (size_t)p * kC + c0) = pk;
+        if (EPI == 0 && zio)
+          *reinterpret_cast<float4*>(zio + (size_t)p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
+      } else {
+        const int hw = pm.H * pm.W;
+        const int b = p / hw;
+        const int r = p - b * hw;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = c0 + i;
+          if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i] + bias[c];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace cnnk

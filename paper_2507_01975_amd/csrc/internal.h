@@ -111,6 +111,7 @@ struct ldsv_handle {
   void* adj_k = nullptr;
   void* adj_g = nullptr;
   void* save_u = nullptr;        // rollout fallback copy of u_{k-1}
+  void* zpre_blk = nullptr;      // network backward workspace
   size_t bytes = 0;
   std::vector<void*> allocs;     // base pointers of every device allocation owned
   KernelTimer timer;

@@ -7,6 +7,7 @@
 // because P is a linear projector.  The rollout guards every learned step:
 // a trajectory whose new state is non-finite or exceeds the max-speed bound
 // is recomputed from u_{k-1} with the plain FV step.
+#include "adjoint.h"
 #include "cnn.h"
 #include "reduce.h"
 #include "stage.h"
@@ -177,21 +178,70 @@ int ldsv_rollout(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
   return LDSV_OK;
 }
 
-int ldsv_fv_step_bwd(ldsv_handle*, const ldsv_params*, const float*, const void*, const void*,
-                     const void*, const void*, void*, void*, float*, void*) {
-  ldsv_set_error("fv_step_bwd: not available in this build");
-  return LDSV_EDTYPE;
+int ldsv_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, const void* u_in,
+                     const void* v_in, const void* gu_out, const void* gv_out, void* gu_in,
+                     void* gv_in, float* gcoef, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(prm && u_in && v_in && gu_out && gv_out && gu_in && gv_in, LDSV_EINVAL,
+               "fv_step_bwd: null argument");
+  const size_t cbs = (size_t)LDSV_NCOEF * h->ncell;
+  return ldsv_step_bwd(h, prm, coef, cbs, coef ? gcoef : nullptr, cbs, u_in, v_in, gu_out, gv_out,
+                       gu_in, gv_in, (hipStream_t)stream);
 }
-int ldsv_cnn_backward(ldsv_handle*, const ldsv_net*, const float*, const float*, const float*,
-                      float*, float*, const ldsv_net_grad*, void*) {
-  ldsv_set_error("cnn_backward: not available in this build");
-  return LDSV_EDTYPE;
+int ldsv_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                      const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
+                      void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_TRY(ldsv_check_net(net));
+  LDSV_REQUIRE(u && v && gout && dW, LDSV_EINVAL, "cnn_backward: null argument");
+  for (int l = 0; l < LDSV_NLAYERS; ++l)
+    LDSV_REQUIRE(dW->w[l] && dW->b[l], LDSV_EINVAL, "cnn_backward: null gradient of layer %d", l);
+  LDSV_REQUIRE((gu == nullptr) == (gv == nullptr), LDSV_EINVAL, "cnn_backward: gu and gv together");
+  LDSV_TRY(ldsv_ensure_learned(h));
+  return ldsv_launch_cnn_backward(h, net, u, v, gout, gu, gv, dW, (hipStream_t)stream);
 }
-int ldsv_learned_fv_step_bwd(ldsv_handle*, const ldsv_params*, const ldsv_net*, const float*,
-                             const float*, int, const float*, const float*, float*, float*,
-                             const ldsv_net_grad*, void*) {
-  ldsv_set_error("learned_fv_step_bwd: not available in this build");
-  return LDSV_EDTYPE;
+
+int ldsv_learned_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                             const float* u_in, const float* v_in, int step_index,
+                             const float* gu_out, const float* gv_out, float* gu_in, float* gv_in,
+                             const ldsv_net_grad* dW, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_TRY(ldsv_check_net(net));
+  LDSV_REQUIRE(prm && u_in && v_in && gu_out && gv_out && gu_in && gv_in && dW, LDSV_EINVAL,
+               "learned_fv_step_bwd: null argument");
+  LDSV_TRY(ldsv_ensure_learned(h));
+  LDSV_TRY(ldsv_ensure_adjoint(h));
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = h->ncell;
+  const size_t bs = (size_t)LDSV_NOUT * N;
+  const size_t sb = h->nstate * h->esize;
+  if (!h->gnet) {
+    void* p = nullptr;
+    LDSV_TRY(ldsv_alloc(h, &p, h->nstate * LDSV_NOUT * sizeof(float), "network-output gradient"));
+    h->gnet = (float*)p;
+  }
+  // the step's coefficients and correction
+  LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st));
+  LDSV_HIP(hipMemsetAsync(h->gnet, 0, h->nstate * LDSV_NOUT * sizeof(float), st));
+  // FV path: d/du_in and d/d(raw coefficients)
+  LDSV_TRY(ldsv_step_bwd(h, prm, h->netout, bs, h->gnet, bs, u_in, v_in, gu_out, gv_out, gu_in,
+                         gv_in, st));
+  // temporal correction: u_k = P(w + TC) so dL/dTC = P g (kept by the sweep)
+  const bool tc = prm->k_c > 0 && (step_index % prm->k_c) == 0;
+  const char* A = (const char*)h->adj_u;
+  if (tc) {
+    LDSV_HIP(hipMemcpy2DAsync(h->gnet + (size_t)LDSV_NCOEF * N, bs * sizeof(float), A,
+                              N * sizeof(float), N * sizeof(float), h->g.batch,
+                              hipMemcpyDeviceToDevice, st));
+    LDSV_HIP(hipMemcpy2DAsync(h->gnet + (size_t)(LDSV_NCOEF + 1) * N, bs * sizeof(float), A + sb,
+                              N * sizeof(float), N * sizeof(float), h->g.batch,
+                              hipMemcpyDeviceToDevice, st));
+  }
+  // network path: d/d(weights) and d/du_in through the network input
+  char* W = (char*)h->adj_u + 4 * sb;
+  LDSV_TRY(ldsv_launch_cnn_backward(h, net, u_in, v_in, h->gnet, (float*)W, (float*)(W + sb), dW,
+                                    st));
+  return ldsv_launch_axpy2(h, gu_in, gv_in, W, W + sb, 1.0, st);
 }
 
 }  // extern "C"
