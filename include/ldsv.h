@@ -226,6 +226,22 @@ LDSV_API int ldsv_learned_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, co
                              const float* gu_out, const float* gv_out,
                              float* gu_in, float* gv_in, const ldsv_net_grad* dW, void* stream);
 
+/* ldsv_rollout_bwd: unrolled backward of a learned rollout of nsteps steps
+ * from (u0, v0) with activation checkpointing: the forward keeps the state
+ * every checkpoint_every steps, the backward recomputes one segment at a
+ * time and runs the per-step adjoint in reverse.  The cotangent of state
+ * u_{first+k} (k = 0..nsteps-1, the state after k+1 steps) is
+ *   loss_scale * d/du [0.5 (mean((u - lu_k)^2) + mean((v - lv_k)^2))]
+ * when labels ([nsteps][B][Ny][Nx]) are given, plus g_traj_u/v[k] when
+ * given.  The loss value is accumulated into *loss_dev (device double,
+ * nullable).  Writes gu0, gv0 (nullable) and ACCUMULATES dW.  F32 MAC. */
+LDSV_API int ldsv_rollout_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                              const float* u0, const float* v0, int nsteps, int checkpoint_every,
+                              int first_index, const float* labels_u, const float* labels_v,
+                              double loss_scale, const float* g_traj_u, const float* g_traj_v,
+                              float* gu0, float* gv0, const ldsv_net_grad* dW, double* loss_dev,
+                              void* stream);
+
 /* ---- a16: loss and optimiser (Eq. 13; App. D.3) ----
  * ldsv_mse_grad: loss contribution 0.5*(mean((u-lu)^2) + mean((v-lv)^2))
  * accumulated in FP64 into *loss_dev (device double, nullable), and the

@@ -24,7 +24,7 @@ int ldsv_launch_vorticity(ldsv_handle* h, const void* u, const void* v, void* w,
 int ldsv_launch_pcc(ldsv_handle* h, const void* a, const void* b, double* out, hipStream_t st);
 int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* lu,
                          const float* lv, double scale, float* gu, float* gv, double* loss,
-                         hipStream_t st);
+                         hipStream_t st, int accumulate);
 
 namespace {
 thread_local char g_err[512] = "";
@@ -439,7 +439,7 @@ int ldsv_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* l
   LDSV_TRY(ldsv_check_handle(h));
   LDSV_REQUIRE(u && v && lu && lv, LDSV_EINVAL, "mse_grad: null array");
   LDSV_REQUIRE(h->g.dtype == LDSV_F32, LDSV_EDTYPE, "mse_grad: F32 grids");
-  return ldsv_launch_mse_grad(h, u, v, lu, lv, scale, gu, gv, loss, (hipStream_t)stream);
+  return ldsv_launch_mse_grad(h, u, v, lu, lv, scale, gu, gv, loss, (hipStream_t)stream, 0);
 }
 
 }  // extern "C"

@@ -112,6 +112,8 @@ struct ldsv_handle {
   void* adj_g = nullptr;
   void* save_u = nullptr;        // rollout fallback copy of u_{k-1}
   void* zpre_blk = nullptr;      // network backward workspace
+  void* roll_blk = nullptr;      // rollout-backward checkpoints and segment states
+  size_t roll_bytes = 0;
   size_t bytes = 0;
   std::vector<void*> allocs;     // base pointers of every device allocation owned
   KernelTimer timer;

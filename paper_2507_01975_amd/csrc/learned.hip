@@ -12,6 +12,9 @@
 #include "reduce.h"
 #include "stage.h"
 
+int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* lu,
+                         const float* lv, double scale, float* gu, float* gv, double* loss,
+                         hipStream_t st, int accumulate);
 int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
                        const void* su, const void* sv, void* du, void* dv, const float* tcu,
                        const float* tcv, size_t tcbs, hipStream_t st);
@@ -242,6 +245,80 @@ int ldsv_learned_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_
   LDSV_TRY(ldsv_launch_cnn_backward(h, net, u_in, v_in, h->gnet, (float*)W, (float*)(W + sb), dW,
                                     st));
   return ldsv_launch_axpy2(h, gu_in, gv_in, W, W + sb, 1.0, st);
+}
+
+int ldsv_rollout_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, const float* u0,
+                     const float* v0, int nsteps, int checkpoint_every, int first_index,
+                     const float* labels_u, const float* labels_v, double loss_scale,
+                     const float* g_traj_u, const float* g_traj_v, float* gu0, float* gv0,
+                     const ldsv_net_grad* dW, double* loss_dev, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_TRY(ldsv_check_net(net));
+  LDSV_REQUIRE(prm && u0 && v0 && dW && nsteps >= 1 && checkpoint_every >= 1, LDSV_EINVAL,
+               "rollout_bwd: bad argument");
+  LDSV_REQUIRE((labels_u != nullptr) == (labels_v != nullptr) &&
+                   (g_traj_u != nullptr) == (g_traj_v != nullptr) && (labels_u || g_traj_u),
+               LDSV_EINVAL, "rollout_bwd: give labels and/or trajectory cotangents, u and v together");
+  LDSV_TRY(ldsv_ensure_learned(h));
+  LDSV_TRY(ldsv_ensure_adjoint(h));
+  const hipStream_t st = (hipStream_t)stream;
+  const int ce = checkpoint_every < nsteps ? checkpoint_every : nsteps;
+  const int nseg = (nsteps + ce - 1) / ce;
+  const size_t sb = h->nstate * h->esize;
+  const size_t need = (size_t)(nseg + 1 + ce + 2) * 2 * sb;
+  if (h->roll_bytes < need) {
+    void* p = nullptr;
+    LDSV_TRY(ldsv_alloc(h, &p, need, "rollout backward checkpoints"));
+    h->roll_blk = p;
+    h->roll_bytes = need;
+  }
+  char* ck = (char*)h->roll_blk;                        // nseg + 1 checkpoints
+  char* seg = ck + (size_t)(nseg + 1) * 2 * sb;         // ce segment states
+  char* ga = seg + (size_t)ce * 2 * sb;                 // two cotangent buffers
+  char* gb = ga + 2 * sb;
+  auto U = [&](char* base, int i) { return base + (size_t)i * 2 * sb; };
+  // forward, keeping the state at the start of every segment and the end
+  LDSV_HIP(hipMemcpyAsync(U(seg, 0), u0, sb, hipMemcpyDeviceToDevice, st));
+  LDSV_HIP(hipMemcpyAsync(U(seg, 0) + sb, v0, sb, hipMemcpyDeviceToDevice, st));
+  for (int k = 0; k < nsteps; ++k) {
+    if (k % ce == 0) LDSV_HIP(hipMemcpyAsync(U(ck, k / ce), U(seg, 0), 2 * sb, hipMemcpyDeviceToDevice, st));
+    LDSV_TRY(learned_step(h, prm, net, (const float*)U(seg, 0), (const float*)(U(seg, 0) + sb),
+                          (float*)U(seg, 0), (float*)(U(seg, 0) + sb), first_index + k, nullptr, st));
+  }
+  LDSV_HIP(hipMemcpyAsync(U(ck, nseg), U(seg, 0), 2 * sb, hipMemcpyDeviceToDevice, st));
+  LDSV_HIP(hipMemsetAsync(ga, 0, 2 * sb, st));
+  char* g = ga;
+  char* gn = gb;
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int k0 = s * ce, k1 = (k0 + ce < nsteps) ? k0 + ce : nsteps;
+    LDSV_HIP(hipMemcpyAsync(U(seg, 0), U(ck, s), 2 * sb, hipMemcpyDeviceToDevice, st));
+    for (int k = k0; k < k1 - 1; ++k)
+      LDSV_TRY(learned_step(h, prm, net, (const float*)U(seg, k - k0), (const float*)(U(seg, k - k0) + sb),
+                            (float*)U(seg, k - k0 + 1), (float*)(U(seg, k - k0 + 1) + sb),
+                            first_index + k, nullptr, st));
+    for (int k = k1 - 1; k >= k0; --k) {
+      // cotangent of u_{k+1}: loss term and caller-supplied cotangent
+      char* nxt = (k + 1 < k1) ? U(seg, k + 1 - k0) : U(ck, s + 1);
+      if (labels_u)
+        LDSV_TRY(ldsv_launch_mse_grad(h, (const float*)nxt, (const float*)(nxt + sb),
+                                      labels_u + (size_t)k * h->nstate, labels_v + (size_t)k * h->nstate,
+                                      loss_scale, (float*)g, (float*)(g + sb), loss_dev, st, 1));
+      if (g_traj_u) {
+        LDSV_TRY(ldsv_launch_axpy2(h, g, g + sb, g_traj_u + (size_t)k * h->nstate,
+                                   g_traj_v + (size_t)k * h->nstate, 1.0, st));
+      }
+      LDSV_TRY(ldsv_learned_fv_step_bwd(h, prm, net, (const float*)U(seg, k - k0),
+                                        (const float*)(U(seg, k - k0) + sb), first_index + k,
+                                        (const float*)g, (const float*)(g + sb), (float*)gn,
+                                        (float*)(gn + sb), dW, stream));
+      char* t = g;
+      g = gn;
+      gn = t;
+    }
+  }
+  if (gu0) LDSV_HIP(hipMemcpyAsync(gu0, g, sb, hipMemcpyDeviceToDevice, st));
+  if (gv0) LDSV_HIP(hipMemcpyAsync(gv0, g + sb, sb, hipMemcpyDeviceToDevice, st));
+  return LDSV_OK;
 }
 
 }  // extern "C"

@@ -134,11 +134,12 @@ struct MseF {
 };
 
 __global__ void k_mse_grad(const float* u, const float* v, const float* lu, const float* lv,
-                           float* gu, float* gv, size_t total, float s) {
+                           float* gu, float* gv, size_t total, float s, int accumulate) {
   for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (size_t)gridDim.x * blockDim.x) {
-    gu[g] = s * (u[g] - lu[g]);
-    gv[g] = s * (v[g] - lv[g]);
+    const float a = s * (u[g] - lu[g]), b = s * (v[g] - lv[g]);
+    gu[g] = accumulate ? gu[g] + a : a;
+    gv[g] = accumulate ? gv[g] + b : b;
   }
 }
 
@@ -246,7 +247,7 @@ int ldsv_launch_pcc(ldsv_handle* h, const void* a, const void* b, double* out, h
 
 int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* lu,
                          const float* lv, double scale, float* gu, float* gv, double* loss,
-                         hipStream_t st) {
+                         hipStream_t st, int accumulate) {
   const size_t total = h->nstate;
   if (loss) {
     LDSV_TRY((reduce_per_traj<kRedSum, 1>(h, MseF{u, v, lu, lv, h->ncell}, h->ncell, h->g.batch,
@@ -257,7 +258,7 @@ int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const f
   }
   if (gu && gv) {
     hipLaunchKernelGGL(k_mse_grad, grid1d(total), dim3(kBlock), 0, st, u, v, lu, lv, gu, gv, total,
-                       (float)(scale / (double)total));
+                       (float)(scale / (double)total), accumulate);
     LDSV_LAUNCHED();
   }
   return LDSV_OK;

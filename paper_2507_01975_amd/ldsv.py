@@ -95,6 +95,8 @@ _SIGS = {
                            ctypes.POINTER(NetGrad), _vp], _i),
     "ldsv_learned_fv_step_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _i,
                                   _vp, _vp, _vp, _vp, ctypes.POINTER(NetGrad), _vp], _i),
+    "ldsv_rollout_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _i, _i, _i,
+                          _vp, _vp, _d, _vp, _vp, _vp, _vp, ctypes.POINTER(NetGrad), _vp, _vp], _i),
     "ldsv_mse_grad": ([_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp], _i),
     "ldsv_adam_step": ([_vp, _vp, _vp, _vp, _sz, _i, _d, _d, _d, _d, _vp], _i),
     "ldsv_to_bf16": ([_vp, _vp, _sz, _vp], _i),
@@ -284,6 +286,26 @@ class Solver:
                                              self._state(gu_out), self._state(gv_out), _ptr(gu),
                                              _ptr(gv), ctypes.byref(dW.c), _stream()))
         return gu, gv
+
+    def rollout_bwd(self, prm, net, u0, v0, nsteps, dW, checkpoint_every=8, first_index=1,
+                    labels=None, loss_scale=1.0, g_traj=None, want_input_grad=False, loss=None):
+        """Unrolled backward with checkpoints; returns (gu0, gv0) or None."""
+        lu = lv = gtu = gtv = None
+        if labels is not None:
+            lu, lv = labels
+            for t in (lu, lv):
+                if tuple(t.shape) != (nsteps, self.batch, self.ny, self.nx) or not t.is_contiguous():
+                    raise ValueError("labels must be contiguous [nsteps, B, Ny, Nx]")
+        if g_traj is not None:
+            gtu, gtv = g_traj
+        gu = self.new_state() if want_input_grad else None
+        gv = self.new_state() if want_input_grad else None
+        _check(_lib.ldsv_rollout_bwd(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                     self._state(u0), self._state(v0), nsteps, checkpoint_every,
+                                     first_index, _ptr(lu), _ptr(lv), loss_scale, _ptr(gtu),
+                                     _ptr(gtv), _ptr(gu), _ptr(gv), ctypes.byref(dW.c), _ptr(loss),
+                                     _stream()))
+        return (gu, gv) if want_input_grad else None
 
     def mse_grad(self, u, v, lu, lv, scale=1.0, loss=None, want_grad=True):
         gu = self.new_state() if want_grad else None
