@@ -16,8 +16,15 @@ The line also carries
   region), its algorithmic bytes per launch, achieved GB/s against 8 TB/s;
 * cpu_baseline: the FP64 CPU oracle timed on this host on a bounded sample
   of the same workload (the full batch, as many steps as fit in ~10 s);
-* learned: the learned step (64^2, batch 64, BF16 CNN on MFMA) when the
-  library provides it.
+* learned: the learned step (64^2, batch 64, BF16 CNN on MFMA);
+* corr: the accuracy-matched comparison of the metric on forced Kolmogorov
+  flow: the learned 64^2 solver is trained (Adam through the hand-written
+  adjoint) on labels from 1024^2 plain FV down-sampled 16x; on held-out seeds
+  the time until the vorticity correlation with the down-sampled 1024^2
+  reference drops below 0.9 is measured for the learned solver and for plain
+  FV at 64, 128, 256, 512; the coarsest plain resolution that lasts as long
+  is timed at the same batch, giving the sim-time/s ratio at equal
+  correlation.
 """
 import argparse
 import json
@@ -113,6 +120,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-corr", action="store_true",
+                    help="skip the corr>=0.9 comparison (training + resolution sweep, ~2 min)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the batched step on a single MI355X "
@@ -171,6 +180,13 @@ def main():
     if not a.no_learned:
         log("learned step")
         line["learned"] = learned_block(max(10, a.steps // 4), 3)
+    if not a.no_corr:
+        log("corr>=0.9 comparison: learned coarse vs plain FV resolution sweep")
+        from paper_2507_01975_amd import train as T
+        try:
+            line["corr"] = T.corr_metric(progress=log)
+        except Exception as e:  # report, do not lose the throughput line
+            line["corr"] = {"status": "failed: %r" % (e,)}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(w, u0, v0)

@@ -27,9 +27,12 @@ def physics(w):
 
 
 def generate_labels(fine_n, coarse_n, batch, seed, nsteps, dt_fine, phys, warmup_steps=0,
-                    ic=ldsv.IC_GRF_PEAK, lx=2 * math.pi, progress=None):
+                    ic=ldsv.IC_GRF_PEAK, lx=2 * math.pi, progress=None, ic_resolutions=()):
     """Coarse labels [nsteps + 1, B, n, n] (u and v): the fine plain-FV
-    solution down-sampled every r fine steps, r = fine_n / coarse_n."""
+    solution down-sampled every r fine steps, r = fine_n / coarse_n.  With
+    ic_resolutions, also returns {N: (u, v)}: the state after the warm-up
+    down-sampled to N x N (the common initial condition of a resolution
+    sweep)."""
     r = fine_n // coarse_n
     fine = ldsv.Solver(fine_n, fine_n, batch, lx=lx, ly=lx)
     coarse = ldsv.Solver(coarse_n, coarse_n, batch, lx=lx, ly=lx)
@@ -45,6 +48,14 @@ def generate_labels(fine_n, coarse_n, batch, seed, nsteps, dt_fine, phys, warmup
             if progress:
                 torch.cuda.synchronize()
                 progress("warm-up %d/%d fine steps" % (done, warmup_steps))
+    ics = {}
+    for N in ic_resolutions:
+        if N == fine_n:
+            ics[N] = (u.clone(), v.clone())
+        else:
+            sN = ldsv.Solver(N, N, batch, lx=lx, ly=lx)
+            ics[N] = sN.downsample(fine_n // N, u, v)
+            sN.close()
     lu = torch.empty(nsteps + 1, batch, coarse_n, coarse_n, device="cuda")
     lv = torch.empty_like(lu)
     uc, vc = coarse.downsample(r, u, v)
@@ -59,6 +70,8 @@ def generate_labels(fine_n, coarse_n, batch, seed, nsteps, dt_fine, phys, warmup
     torch.cuda.synchronize()
     fine.close()
     coarse.close()
+    if ic_resolutions:
+        return (lu, lv), ics
     return lu, lv
 
 
@@ -156,6 +169,147 @@ def evaluate(solver, prm, labels, nsteps, net=None):
     wall = time.perf_counter() - t0
     ref = (lu[1:nsteps + 1], lv[1:nsteps + 1])
     pcc = vorticity_pcc_series(solver, (tu, tv), ref)
-    mse = (((tu - ref[0]) ** 2).mean(dim=(-2, -1)) + ((tv - ref[1]) ** 2).mean(dim=(-2, -1))) * 0.5
+    mse = torch.zeros(nsteps, dtype=torch.float64, device="cuda")
+    for t in range(nsteps):
+        solver.mse_grad(tu[t], tv[t], ref[0][t].contiguous(), ref[1][t].contiguous(),
+                        loss=mse[t:t + 1], want_grad=False)
     return {"pcc": pcc, "t09": first_drop(pcc.cpu(), prm.dt), "mse": mse, "wall_s": wall,
             "fallbacks": flags.tolist() if net is not None else None}
+
+
+def plain_sweep_pcc(N, n, ic, labels, dt_coarse, phys, horizon, lx=2 * math.pi):
+    """Plain FV at N x N from ic (already at N), advanced N/n steps of dt
+    dt_coarse * n / N per coarse step, down-sampled to n and compared with
+    labels[1..horizon] by vorticity PCC: returns (pcc [T, B], wall seconds of
+    the rollout)."""
+    u0, v0 = ic
+    B = u0.shape[0]
+    rN = N // n
+    sN = ldsv.Solver(N, N, B, lx=lx, ly=lx)
+    sn = ldsv.Solver(n, n, B, lx=lx, ly=lx)
+    prm = ldsv.params(dt=dt_coarse / rN, **phys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tu, tv = sN.rollout(prm, u0.contiguous(), v0.contiguous(), horizon * rN, save_every=rN)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cu = torch.empty(horizon, B, n, n, device="cuda")
+    cv = torch.empty_like(cu)
+    for t in range(horizon):
+        if rN == 1:
+            cu[t], cv[t] = tu[t], tv[t]
+        else:
+            cu[t], cv[t] = sn.downsample(rN, tu[t].contiguous(), tv[t].contiguous())
+    lu, lv = labels
+    pcc = vorticity_pcc_series(sn, (cu, cv), (lu[1:horizon + 1], lv[1:horizon + 1]))
+    sN.close()
+    sn.close()
+    return pcc, wall
+
+
+def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi):
+    """(cell-steps/s, sim-time/s per trajectory, ms/step) of the plain or
+    learned step at N x N, batch B, on device-resident state."""
+    s = ldsv.Solver(N, N, B, lx=lx, ly=lx)
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=7)
+    for k in range(warmup):
+        if net is None:
+            s.fv_step(prm, u, v, out=(u, v))
+        else:
+            s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if net is None:
+            s.fv_step(prm, u, v, out=(u, v))
+        else:
+            s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.close()
+    return N * N * B * steps / t, prm.dt * steps / t, 1e3 * t / steps
+
+
+def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, test_batch=4,
+                train_fine_steps=10000, warmup_fine=4000, horizon=300, iters=400, unroll=16,
+                lr=1e-4, speed_batch=64, speed_steps=40, progress=None, seeds=(100, 200)):
+    """The forced-flow measurement: train the 64^2 learned solver on labels
+    down-sampled from fine plain FV, then on held-out seeds find T_0.9 (time
+    until the vorticity PCC against the down-sampled fine reference first
+    drops below 0.9) for the learned solver and for plain FV at each sweep
+    resolution, and the throughput of the learned step and of the coarsest
+    plain resolution that reaches the learned T_0.9."""
+    log = progress or (lambda *a: None)
+    phys = dict(nu=1e-3, forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+    dtf = 2.19e-4 * 2048 / fine_n
+    r = fine_n // n
+    dtc = r * dtf
+    t0 = time.perf_counter()
+    lab_tr = generate_labels(fine_n, n, train_batch, seeds[0], train_fine_steps // r, dtf, phys,
+                             warmup_steps=warmup_fine, progress=log)
+    lab_te, ics = generate_labels(fine_n, n, test_batch, seeds[1], horizon, dtf, phys,
+                                  warmup_steps=warmup_fine, progress=log,
+                                  ic_resolutions=tuple(N for N in sweep if N != n))
+    log("labels ready (%.1f s)" % (time.perf_counter() - t0))
+    net = init_network(seed=0)
+    st = ldsv.Solver(n, n, train_batch)
+    prm = ldsv.params(dt=dtc, k_c=1, fallback_enable=0, **phys)
+    hist = train(st, net, lab_tr, prm, iters=iters, unroll=unroll, checkpoint_every=8, lr=lr,
+                 progress=log, log_every=50)
+    st.close()
+    log("trained (%.1f s)" % (time.perf_counter() - t0))
+    se = ldsv.Solver(n, n, test_batch)
+    ev = evaluate(se, prm, lab_te, horizon, net=net)
+    ev_plain = evaluate(se, prm, lab_te, horizon)
+    se.close()
+    t09 = {"learned_%d" % n: sum(ev["t09"]) / test_batch}
+    t09["plain_%d" % n] = sum(ev_plain["t09"]) / test_batch
+    for N in sweep:
+        if N == n:
+            continue
+        pcc, _ = plain_sweep_pcc(N, n, ics[N], lab_te, dtc, phys, horizon)
+        t09["plain_%d" % N] = sum(first_drop(pcc.cpu(), dtc)) / test_batch
+        log("plain %d: T_0.9 = %.3f" % (N, t09["plain_%d" % N]))
+    target = t09["learned_%d" % n]
+    match = None
+    for N in sorted(sweep):
+        if t09["plain_%d" % N] >= target:
+            match = N
+            break
+    # throughput at the inference batch on device-resident state
+    cs_l, st_l, ms_l = throughput(n, speed_batch, prm, speed_steps, net=net)
+    out = {"workload": "forced Kolmogorov flow, nu=1e-3, drag 0.1; learned %d^2 trained on %d^2 "
+                       "plain FV down-sampled %dx (%d trajectories, %d fine steps each)"
+                       % (n, fine_n, r, train_batch, train_fine_steps),
+           "horizon_s": horizon * dtc, "t09_s": t09, "test_trajectories": test_batch,
+           "final_train_loss": hist[-1][1], "initial_train_loss": hist[0][1],
+           "learned": {"n": n, "batch": speed_batch, "cell_steps_per_s": cs_l,
+                       "sim_time_per_s": st_l, "ms_per_step": ms_l},
+           "mse_at_horizon": {"learned": ev["mse"][-1].item(), "plain_%d" % n: ev_plain["mse"][-1].item()}}
+    if match is not None:
+        pm = ldsv.params(dt=dtc * n / match, **phys)
+        steps = max(10, speed_steps * n // match)
+        cs_p, st_p, ms_p = throughput(match, speed_batch, pm, steps)
+        out["plain_match"] = {"n": match, "batch": speed_batch, "cell_steps_per_s": cs_p,
+                              "sim_time_per_s": st_p, "ms_per_step": ms_p}
+        out["sim_time_speedup_at_equal_corr"] = st_l / st_p
+    else:
+        out["plain_match"] = "no plain resolution up to %d reached the learned T_0.9" % max(sweep)
+    log("corr metric done (%.1f s)" % (time.perf_counter() - t0))
+    return out
+
+
+def init_network(seed=0, last_scale=1e-3):
+    """He-normal 3x3 kernels and zero biases, the last layer scaled by
+    last_scale so that the learned correction starts small (Sec. 3.4: the
+    learnable kernel starts from small random values)."""
+    g = torch.Generator().manual_seed(seed)
+    layers = [(2, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 66)]
+    ws, bs = [], []
+    for li, (ci, co) in enumerate(layers):
+        w = torch.randn(co, ci, 3, 3, generator=g) * math.sqrt(2.0 / (9 * ci))
+        if li == len(layers) - 1:
+            w = w * last_scale
+        ws.append(w)
+        bs.append(torch.zeros(co))
+    return ldsv.NetParams(ws, bs)
