@@ -257,20 +257,19 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
   const int nx = h->g.nx, ny = h->g.ny;
   dim3 grid((unsigned)std::min<size_t>((h->ncell + kBlock - 1) / kBlock, 4096), h->g.batch);
   T* scr = (T*)h->adj_g;
-  TimerScope ts(h, 6, st);
   if (coef) {
-    hipLaunchKernelGGL((k_adj_faces<T, true>), grid, dim3(kBlock), 0, st, (const T*)us,
+    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, true>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
                        aG, coef, cbs, gcoef, gcbs, scr, ph, nx, ny);
-    hipLaunchKernelGGL((k_adj_gather<T, true>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, true>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
                        cbs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA, aG,
                        (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph, nx, ny);
   } else {
-    hipLaunchKernelGGL((k_adj_faces<T, false>), grid, dim3(kBlock), 0, st, (const T*)us,
+    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, false>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
                        aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, scr, ph,
                        nx, ny);
-    hipLaunchKernelGGL((k_adj_gather<T, false>), grid, dim3(kBlock), 0, st, (const T*)scr,
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, false>), grid, dim3(kBlock), 0, st, (const T*)scr,
                        (const float*)nullptr, (size_t)0, (const T*)Au, (const T*)Av, (const T*)Gu,
                        (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph,
                        nx, ny);
@@ -308,10 +307,10 @@ int ldsv_launch_adj_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coe
 int ldsv_launch_axpy2(ldsv_handle* h, void* yu, void* yv, const void* xu, const void* xv, double a,
                       hipStream_t st) {
   if (h->g.dtype == LDSV_F64)
-    hipLaunchKernelGGL(k_axpy2<double>, grid1d(h->nstate), dim3(kBlock), 0, st, (double*)yu,
+    LDSV_TLAUNCH(h, 7, k_axpy2<double>, grid1d(h->nstate), dim3(kBlock), 0, st, (double*)yu,
                        (double*)yv, (const double*)xu, (const double*)xv, a, h->nstate);
   else
-    hipLaunchKernelGGL(k_axpy2<float>, grid1d(h->nstate), dim3(kBlock), 0, st, (float*)yu,
+    LDSV_TLAUNCH(h, 7, k_axpy2<float>, grid1d(h->nstate), dim3(kBlock), 0, st, (float*)yu,
                        (float*)yv, (const float*)xu, (const float*)xv, (float)a, h->nstate);
   LDSV_LAUNCHED();
   return LDSV_OK;

@@ -445,31 +445,26 @@ int ldsv_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* l
 }  // extern "C"
 
 // ---------------------------------------------------------------- timing
-TimerScope::TimerScope(ldsv_handle* h_, int cls_, hipStream_t st_) : h(h_), cls(cls_), st(st_) {
-  if (!h->timer.on) return;
-  hipEvent_t e;
-  if (h->timer.pool.empty()) {
-    if (hipEventCreate(&e) != hipSuccess) return;
-  } else {
-    e = h->timer.pool.back();
-    h->timer.pool.pop_back();
+bool ldsv_timer_pair(ldsv_handle* h, int cls, hipEvent_t* e0, hipEvent_t* e1) {
+  if (!h->timer.on) return false;
+  hipEvent_t e[2];
+  for (int k = 0; k < 2; ++k) {
+    if (h->timer.pool.empty()) {
+      if (hipEventCreate(&e[k]) != hipSuccess) {
+        (void)hipGetLastError();
+        if (k == 1) h->timer.pool.push_back(e[0]);
+        return false;
+      }
+    } else {
+      e[k] = h->timer.pool.back();
+      h->timer.pool.pop_back();
+    }
   }
-  (void)hipEventRecord(e, st);
-  h->timer.ev[cls].push_back(e);
-}
-
-TimerScope::~TimerScope() {
-  if (!h->timer.on) return;
-  if (h->timer.ev[cls].size() % 2 == 0) return;  // start failed
-  hipEvent_t e;
-  if (h->timer.pool.empty()) {
-    if (hipEventCreate(&e) != hipSuccess) return;
-  } else {
-    e = h->timer.pool.back();
-    h->timer.pool.pop_back();
-  }
-  (void)hipEventRecord(e, st);
-  h->timer.ev[cls].push_back(e);
+  h->timer.ev[cls].push_back(e[0]);
+  h->timer.ev[cls].push_back(e[1]);
+  *e0 = e[0];
+  *e1 = e[1];
+  return true;
 }
 
 extern "C" int ldsv_timer_enable(ldsv_handle* h, int on) {

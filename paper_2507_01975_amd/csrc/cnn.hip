@@ -106,22 +106,19 @@ int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const f
   PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
   const int nblk_first = (int)((h->nstate + kBlock - 1) / kBlock);
   {
-    TimerScope ts(h, 5, st);
-    hipLaunchKernelGGL(k_conv_first, dim3(nblk_first), dim3(kBlock), 0, st, u, v, net->w[0],
+    LDSV_TLAUNCH(h, 5, k_conv_first, dim3(nblk_first), dim3(kBlock), 0, st, u, v, net->w[0],
                        net->b[0], pm, h->act[0], zpre ? zpre[0] : nullptr);
   }
   LDSV_LAUNCHED();
   const int nblk = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
   for (int l = 1; l < 5; ++l) {
-    TimerScope ts(h, 4, st);
-    hipLaunchKernelGGL((k_conv3x3_mfma<4, 0, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[l - 1],
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<4, 0, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[l - 1],
                        net->w[l], net->b[l], kC, pm, h->act[l], zpre ? zpre[l] : nullptr,
                        (float*)nullptr);
     LDSV_LAUNCHED();
   }
   {
-    TimerScope ts(h, 4, st);
-    hipLaunchKernelGGL((k_conv3x3_mfma<5, 1, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[4],
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<5, 1, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[4],
                        net->w[5], net->b[5], LDSV_NOUT, pm, (uint16_t*)nullptr, (float*)nullptr,
                        out);
   }

@@ -261,17 +261,15 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   hipLaunchKernelGGL(k_gout_to_nhwc, grid1d(P * 96), dim3(kBlock), 0, st, gout, G, hw, (int)P);
   LDSV_LAUNCHED();
   {
-    TimerScope ts(h, 4, st);
-    hipLaunchKernelGGL((k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, part);
+    LDSV_TLAUNCH(h, 4, (k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, part);
   }
-  hipLaunchKernelGGL(k_partial_reduce, grid1d((size_t)LDSV_NOUT * kK), dim3(kBlock), 0, st, part,
+  LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)LDSV_NOUT * kK), dim3(kBlock), 0, st, part,
                      nwg, 80, LDSV_NOUT, kK, dW->w[5]);
-  hipLaunchKernelGGL(k_dgrad_weights, grid1d((size_t)kC * 9 * 96), dim3(kBlock), 0, st, net->w[5],
+  LDSV_TLAUNCH(h, 7, k_dgrad_weights, grid1d((size_t)kC * 9 * 96), dim3(kBlock), 0, st, net->w[5],
                      Wp, LDSV_NOUT, 96);
   LDSV_LAUNCHED();
   {
-    TimerScope ts(h, 4, st);
-    hipLaunchKernelGGL((k_conv3x3_mfma<4, 2, 96>), dim3(nblk_conv), dim3(kBlock), 0, st, G, Wp,
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<4, 2, 96>), dim3(nblk_conv), dim3(kBlock), 0, st, G, Wp,
                        (const float*)nullptr, kC, pm, dzA, zpre[4], (float*)nullptr);
   }
   LDSV_LAUNCHED();
@@ -279,21 +277,19 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   uint16_t* dzn = dzB;
   // layers 5..2 (index 4..1): dz is the cotangent of layer index li's pre-activation
   for (int li = 4; li >= 1; --li) {
-    hipLaunchKernelGGL(k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC,
+    LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC,
                        hw, (int)P, part);
-    hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[li]);
+    LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[li]);
     {
-      TimerScope ts(h, 4, st);
-      hipLaunchKernelGGL((k_wgrad<4, 64>), dim3(nwg), dim3(kBlock), 0, st, dz, h->act[li - 1], pm,
+      LDSV_TLAUNCH(h, 4, (k_wgrad<4, 64>), dim3(nwg), dim3(kBlock), 0, st, dz, h->act[li - 1], pm,
                          part);
     }
-    hipLaunchKernelGGL(k_partial_reduce, grid1d((size_t)kC * kK), dim3(kBlock), 0, st, part, nwg,
+    LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)kC * kK), dim3(kBlock), 0, st, part, nwg,
                        64, kC, kK, dW->w[li]);
-    hipLaunchKernelGGL(k_dgrad_weights, grid1d((size_t)kC * 9 * 64), dim3(kBlock), 0, st,
+    LDSV_TLAUNCH(h, 7, k_dgrad_weights, grid1d((size_t)kC * 9 * 64), dim3(kBlock), 0, st,
                        net->w[li], Wp, kC, 64);
     {
-      TimerScope ts(h, 4, st);
-      hipLaunchKernelGGL((k_conv3x3_mfma<4, 2, 64>), dim3(nblk_conv), dim3(kBlock), 0, st, dz, Wp,
+      LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<4, 2, 64>), dim3(nblk_conv), dim3(kBlock), 0, st, dz, Wp,
                          (const float*)nullptr, kC, pm, dzn, zpre[li - 1], (float*)nullptr);
     }
     LDSV_LAUNCHED();
@@ -302,15 +298,15 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
     dzn = t;
   }
   // layer 1
-  hipLaunchKernelGGL(k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC, hw,
+  LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC, hw,
                      (int)P, part);
-  hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[0]);
-  hipLaunchKernelGGL(k_wgrad_first, dim3(nwg), dim3(kBlock), 0, st, dz, u, v, pm, part);
-  hipLaunchKernelGGL(k_partial_reduce, grid1d((size_t)kC * 18), dim3(kBlock), 0, st, part, nwg,
+  LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[0]);
+  LDSV_TLAUNCH(h, 7, k_wgrad_first, dim3(nwg), dim3(kBlock), 0, st, dz, u, v, pm, part);
+  LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)kC * 18), dim3(kBlock), 0, st, part, nwg,
                      kC * 18, kC * 18, 1, dW->w[0]);
   LDSV_LAUNCHED();
   if (gu && gv) {
-    hipLaunchKernelGGL(k_dgrad_first, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+    LDSV_TLAUNCH(h, 7, k_dgrad_first, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        st, dz, net->w[0], pm, gu, gv);
     LDSV_LAUNCHED();
   }

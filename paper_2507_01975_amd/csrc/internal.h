@@ -2,6 +2,7 @@
 // arithmetic and the launch helpers shared by the HIP translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -122,15 +123,20 @@ struct ldsv_handle {
 // device allocation owned by the handle (freed by ldsv_destroy)
 int ldsv_alloc(ldsv_handle* h, void** p, size_t bytes, const char* what);
 
-// RAII: records a start event at construction and a stop event at
-// destruction on stream st when timing is enabled for the handle.
-struct TimerScope {
-  ldsv_handle* h;
-  int cls;
-  hipStream_t st;
-  TimerScope(ldsv_handle* h_, int cls_, hipStream_t st_);
-  ~TimerScope();
-};
+// When timing is enabled on the handle, hands out a start/stop event pair
+// recorded for kernel class cls and returns true.
+bool ldsv_timer_pair(ldsv_handle* h, int cls, hipEvent_t* e0, hipEvent_t* e1);
+
+// Launch a kernel; when the handle's timer is on, the launch carries a pair of
+// events that the runtime stamps with that kernel's own start and end.
+#define LDSV_TLAUNCH(h, cls, kern, grid, block, shm, st, ...)                        \
+  do {                                                                              \
+    hipEvent_t e0_, e1_;                                                            \
+    if (ldsv_timer_pair((h), (cls), &e0_, &e1_))                                    \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, st, e0_, e1_, 0, __VA_ARGS__);   \
+    else                                                                            \
+      hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);                  \
+  } while (0)
 
 int ldsv_check_handle(const ldsv_handle* h);
 

@@ -169,8 +169,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   LDSV_HIP(hipFuncSetAttribute((const void*)k_div_rowfft<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
-  TimerScope ts(h, 1, st);
-  hipLaunchKernelGGL(k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
+  LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
                      (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
                      h->log2nx, B, rows, idx, idy);
   }
@@ -184,8 +183,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   LDSV_HIP(hipFuncSetAttribute((const void*)k_col_solve<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
-  TimerScope ts(h, 2, st);
-  hipLaunchKernelGGL(k_col_solve<T>, dim3(nx / cols, h->npairs), dim3(kBlock), lds, st,
+  LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3(nx / cols, h->npairs), dim3(kBlock), lds, st,
                      (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, nx, ny, h->log2ny, cols, h->g.lx / nx,
                      h->g.ly / ny);
   }
@@ -195,8 +193,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   LDSV_HIP(hipFuncSetAttribute((const void*)k_rowifft_grad<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
-  TimerScope ts(h, 3, st);
-  hipLaunchKernelGGL(k_rowifft_grad<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
+  LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
                      (const Cx<T>*)h->zspec, (const Cx<T>*)h->twx, (const T*)us, (const T*)vs,
                      (T*)uo, (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows, idx, idy);
   }

@@ -354,21 +354,20 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
           h->g.ly / h->g.ny, prm->physics_mask};
   Comb cb{a.alpha, a.beta, a.delta, a.eps, a.gamma, a.wacc};
   const int nx = h->g.nx, ny = h->g.ny;
-  TimerScope ts(h, 0, st);
   const int TX = nx < kMaxTX ? nx : kMaxTX;
   if (h->g.layout == LDSV_COLLOCATED) {
     const int TYc = ny < kMaxTYc ? ny : kMaxTYc;
     dim3 gridc((nx / TX) * (ny / TYc), h->g.batch);
-    hipLaunchKernelGGL(k_stage_col<T>, gridc, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TYc);
+    LDSV_TLAUNCH(h, 0, k_stage_col<T>, gridc, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TYc);
     LDSV_LAUNCHED();
     return LDSV_OK;
   }
   const int TY = ny < kMaxTY ? ny : kMaxTY;
   dim3 grid((nx / TX) * (ny / TY), h->g.batch);
   if (a.coef) {
-    hipLaunchKernelGGL((k_stage_mac<T, true>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, true>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
   } else {
-    hipLaunchKernelGGL((k_stage_mac<T, false>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, false>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
   }
   LDSV_LAUNCHED();
   return LDSV_OK;
