@@ -301,6 +301,26 @@ int ldsv_create(ldsv_handle** out, const ldsv_grid* g) {
     LDSV_HIP(hipMemcpy(h->twx, tx.data(), tx.size() * sizeof(tx[0]), hipMemcpyHostToDevice));
     LDSV_HIP(hipMemcpy(h->twy, ty.data(), ty.size() * sizeof(ty[0]), hipMemcpyHostToDevice));
   }
+  if (g->layout == LDSV_MAC) {
+    // Poisson factors: the eigenvalues of the compact D G pair,
+    // lambda_h = (2/dx)^2 sin^2(pi kx/Nx) + (2/dy)^2 sin^2(pi ky/Ny), in FP64
+    std::vector<double> pinv(h->ncell);
+    const double dx = g->lx / g->nx, dy = g->ly / g->ny;
+    const double pi = 3.14159265358979323846;
+    const double nrm = 1.0 / ((double)g->nx * (double)g->ny);
+    for (int ky = 0; ky < g->ny; ++ky) {
+      const double sy = std::sin(pi * ky / g->ny);
+      for (int kx = 0; kx < g->nx; ++kx) {
+        const double sx = std::sin(pi * kx / g->nx);
+        const double lam = 4.0 / (dx * dx) * sx * sx + 4.0 / (dy * dy) * sy * sy;
+        pinv[(size_t)ky * g->nx + kx] = (kx == 0 && ky == 0) ? 0.0 : -nrm / lam;
+      }
+    }
+    void* p = nullptr;
+    LDSV_TRY(ldsv_alloc(h, &p, h->ncell * sizeof(double), "Poisson factors"));
+    h->pinv = (double*)p;
+    LDSV_HIP(hipMemcpy(h->pinv, pinv.data(), h->ncell * sizeof(double), hipMemcpyHostToDevice));
+  }
   LDSV_HIP(hipHostMalloc((void**)&h->small_host, smallb, hipHostMallocDefault));
   *out = h;
   return LDSV_OK;

@@ -111,16 +111,60 @@ int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const f
   }
   LDSV_LAUNCHED();
   const int nblk = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
+  // 16 x 16 LDS tiles when both sides are multiples of 16
+  const bool tiled = (h->g.nx % 16 == 0) && (h->g.ny % 16 == 0);
+  const int ntile = (int)(h->nstate / 256);
+  (void)ntile;
   for (int l = 1; l < 5; ++l) {
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<4, 0, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[l - 1],
-                       net->w[l], net->b[l], kC, pm, h->act[l], zpre ? zpre[l] : nullptr,
-                       (float*)nullptr);
+    if (tiled)
+      LDSV_TRY(ldsv_launch_conv_tile(h, 4, 0, h->act[l - 1], net->w[l], net->b[l], kC, h->act[l],
+                                     zpre ? zpre[l] : nullptr, nullptr, st));
+    else
+      LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<4, 0, 64>), dim3(nblk), dim3(kBlock), 0, st,
+                   h->act[l - 1], net->w[l], net->b[l], kC, pm, h->act[l],
+                   zpre ? zpre[l] : nullptr, (float*)nullptr);
     LDSV_LAUNCHED();
   }
-  {
+  if (tiled)
+    LDSV_TRY(ldsv_launch_conv_tile(h, 5, 1, h->act[4], net->w[5], net->b[5], LDSV_NOUT, nullptr,
+                                   nullptr, out, st));
+  else
     LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<5, 1, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[4],
-                       net->w[5], net->b[5], LDSV_NOUT, pm, (uint16_t*)nullptr, (float*)nullptr,
-                       out);
+                 net->w[5], net->b[5], LDSV_NOUT, pm, (uint16_t*)nullptr, (float*)nullptr, out);
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}
+
+int ldsv_launch_conv_tile(ldsv_handle* h, int mt, int epi, const uint16_t* X, const uint16_t* W,
+                          const float* bias, int cout, uint16_t* Y, float* zio, float* out,
+                          hipStream_t st) {
+  PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
+  const int ntiles = (int)(h->nstate / 256);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int grid = ntiles < ncu ? ntiles : ncu;
+  if (mt == 4 && epi == 0) {
+    const size_t lds = conv_tile_lds_bytes<4>();
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<4, 0>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 0>), dim3(grid), dim3(kBlock), lds, st, X, W, bias, cout,
+                 pm, Y, zio, out);
+  } else if (mt == 4 && epi == 2) {
+    const size_t lds = conv_tile_lds_bytes<4>();
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<4, 2>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 2>), dim3(grid), dim3(kBlock), lds, st, X, W, bias, cout,
+                 pm, Y, zio, out);
+  } else if (mt == 5 && epi == 1) {
+    const size_t lds = conv_tile_lds_bytes<5>();
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<5, 1>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<5, 1>), dim3(grid), dim3(kBlock), lds, st, X, W, bias, cout,
+                 pm, Y, zio, out);
+  } else {
+    ldsv_set_error("conv tile: unsupported configuration");
+    return LDSV_EINVAL;
   }
   LDSV_LAUNCHED();
   return LDSV_OK;

@@ -288,10 +288,11 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
                        64, kC, kK, dW->w[li]);
     LDSV_TLAUNCH(h, 7, k_dgrad_weights, grid1d((size_t)kC * 9 * 64), dim3(kBlock), 0, st,
                        net->w[li], Wp, kC, 64);
-    {
+    if (h->g.nx % 16 == 0 && h->g.ny % 16 == 0)
+      LDSV_TRY(ldsv_launch_conv_tile(h, 4, 2, dz, Wp, nullptr, kC, dzn, zpre[li - 1], nullptr, st));
+    else
       LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<4, 2, 64>), dim3(nblk_conv), dim3(kBlock), 0, st, dz, Wp,
-                         (const float*)nullptr, kC, pm, dzn, zpre[li - 1], (float*)nullptr);
-    }
+                   (const float*)nullptr, kC, pm, dzn, zpre[li - 1], (float*)nullptr);
     LDSV_LAUNCHED();
     uint16_t* t = dz;
     dz = dzn;

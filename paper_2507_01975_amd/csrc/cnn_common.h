@@ -155,4 +155,168 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restr
   }
 }
 
+// The same convolution for grids whose sides are multiples of 16, as a
+// persistent kernel: a workgroup first stages the layer's whole weight
+// matrix (cout x 576 bf16, rows padded to 1168 bytes) in LDS, then loops
+// over 16 x 16 pixel tiles; for each tile it stages the tile with its
+// 1-pixel periodic halo (18 x 18 pixels x 64 channels, rows padded to 144
+// bytes) and runs all 9 taps from LDS.  Both paddings put the 16 rows that
+// one fragment read touches in distinct LDS banks.  Wavefront w computes tile
+// rows 4w..4w+3.  LDS: 122 KB (64 outputs) or 140 KB (80 padded outputs),
+// one workgroup per CU.
+constexpr int kWRowAll = 9 * kC + 8;   // padded weight row (bf16 elements)
+constexpr int kTileRow = kC + 8;       // padded tile pixel row
+constexpr int kTileH = 18;
+
+template <int MT>
+constexpr size_t conv_tile_lds_bytes() {
+  return (size_t)(MT * 16 * kWRowAll + kTileH * kTileH * kTileRow) * 2;
+}
+
+template <int MT, int EPI>
+__global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restrict__ X,
+                                                         const uint16_t* __restrict__ Wt,
+                                                         const float* __restrict__ bias, int cout,
+                                                         PixMap pm, uint16_t* __restrict__ Y,
+                                                         float* __restrict__ zio,
+                                                         float* __restrict__ out_planar) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
+  uint16_t* wl = lds_u16;
+  uint16_t* xt = lds_u16 + MT * 16 * kWRowAll;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int kq = lane >> 4;
+  const int tiles_x = pm.W / 16, tiles_y = pm.H / 16;
+  const int ntiles = (pm.total / (pm.H * pm.W)) * tiles_x * tiles_y;
+  const int hw = pm.H * pm.W;
+  // whole weight matrix, once; loads are issued in batches before the LDS
+  // stores so their latencies overlap
+  {
+    constexpr int kChunks = MT * 16 * (9 * kC / 8);
+    constexpr int kBatch = 6;
+    for (int e0 = 0; e0 < kChunks; e0 += kBatch * kBlock) {
+      uint4 v[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int e = e0 + k * kBlock + (int)threadIdx.x;
+        const int row = e / (9 * kC / 8), q = e - row * (9 * kC / 8);
+        v[k] = uint4{0u, 0u, 0u, 0u};
+        if (e < kChunks && row < cout)
+          v[k] = *reinterpret_cast<const uint4*>(Wt + (size_t)row * 9 * kC + q * 8);
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int e = e0 + k * kBlock + (int)threadIdx.x;
+        const int row = e / (9 * kC / 8), q = e - row * (9 * kC / 8);
+        if (e < kChunks) *reinterpret_cast<uint4*>(wl + row * kWRowAll + q * 8) = v[k];
+      }
+    }
+  }
+  // the tile with its halo is loaded into registers one tile ahead (the
+  // loads of tile k+1 are in flight while tile k is computed), then stored
+  // to LDS between two barriers
+  constexpr int kTChunks = kTileH * kTileH * (kC / 8);
+  constexpr int kTPer = (kTChunks + kBlock - 1) / kBlock;
+  uint4 tv[kTPer];
+  auto load_tile = [&](int tile) {
+    const int b = tile / (tiles_x * tiles_y);
+    const int tr = tile - b * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+#pragma unroll
+    for (int k = 0; k < kTPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      tv[k] = uint4{0u, 0u, 0u, 0u};
+      if (e < kTChunks) {
+        const int px = e / (kC / 8), q = e - px * (kC / 8);
+        const int ry = px / kTileH, rx = px - ry * kTileH;
+        const int gy = (y0 - 1 + ry) & (pm.H - 1), gx = (x0 - 1 + rx) & (pm.W - 1);
+        tv[k] = *reinterpret_cast<const uint4*>(X + ((size_t)b * hw + gy * pm.W + gx) * kC + q * 8);
+      }
+    }
+  };
+  if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y);
+    const int tr = tile - b * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      if (e < kTChunks) {
+        const int px = e / (kC / 8), q = e - px * (kC / 8);
+        *reinterpret_cast<uint4*>(xt + px * kTileRow + q * 8) = tv[k];
+      }
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+    f32x4 acc[4][MT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[t][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int cbase = half * 32 + kq * 8;
+        bf16x8 bfrag[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int ry = wave * 4 + t + 1 + dy, rx = col + 1 + dx;
+          bfrag[t] = *reinterpret_cast<const bf16x8*>(xt + (ry * kTileH + rx) * kTileRow + cbase);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(
+              wl + (m * 16 + col) * kWRowAll + tap * kC + cbase);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[t][m], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int y = y0 + wave * 4 + t, x = x0 + col;
+      const int r = y * pm.W + x;
+      const size_t p = (size_t)b * hw + r;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int c0 = m * 16 + kq * 4;
+        if (EPI == 0 || EPI == 2) {
+          float z[4];
+          uint16_t h[4];
+          if (EPI == 2) {
+            const float4 zi = *reinterpret_cast<const float4*>(zio + p * kC + c0);
+            const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = f32_to_bf16(acc[t][m][i] * gelu_grad(zz[i]));
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              z[i] = acc[t][m][i] + bias[c0 + i];
+              h[i] = f32_to_bf16(gelu_exact(z[i]));
+            }
+          }
+          uint2 pk;
+          pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+          pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+          *reinterpret_cast<uint2*>(Y + p * kC + c0) = pk;
+          if (EPI == 0 && zio)
+            *reinterpret_cast<float4*>(zio + p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = c0 + i;
+            if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i] + bias[c];
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace cnnk

@@ -1,65 +1,149 @@
 // In-LDS batched complex FFT used by the spectral Poisson solve (App. B.4,
-// S11-S14).  Stockham autosort formulation with radix-4 stages and one
-// radix-2 stage when log2(n) is odd, so the result comes out in natural
-// order without a bit-reversal pass.  All threads of the block cooperate on
-// `nrows` independent transforms of length n stored row-major in LDS.
+// S11-S14).
+//
+// Stockham autosort formulation (natural-order output, no bit reversal)
+// with radix-8 stages and one radix-4 or radix-2 stage when log2(n) is not a
+// multiple of 3.  Each stage is done in place in one LDS buffer: every thread
+// first loads the inputs of its butterflies into registers, the block
+// synchronises, then every thread twiddles, transforms in registers and
+// stores its outputs, and the block synchronises again.  The buffer holds
+// `nrows` transforms of length n; element j of transform r lives at
+// buf[r * rs + j * es].  Threads walk the elements with the unit-stride
+// index fastest (j when es == 1, r otherwise), so each wavefront reads and
+// writes consecutive LDS words.
 #pragma once
 
 #include "internal.h"
 
-// tw[m] = exp(-2 pi i m / n), m in [0, n).  sign = -1 forward, +1 inverse
-// (unnormalised).  Returns the buffer (a or b) holding the result.
 template <typename T>
-__device__ Cx<T>* lds_fft(Cx<T>* a, Cx<T>* b, int n, int log2n, int nrows, int sign,
-                          const Cx<T>* __restrict__ tw) {
+__device__ __forceinline__ Cx<T> mul_i(Cx<T> a, int sign) {
+  // multiply by -i (sign < 0) or +i (sign > 0)
+  return sign < 0 ? Cx<T>{a.y, -a.x} : Cx<T>{-a.y, a.x};
+}
+
+template <typename T>
+__device__ __forceinline__ void dft2(Cx<T>* x) {
+  const Cx<T> a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(Cx<T>& x0, Cx<T>& x1, Cx<T>& x2, Cx<T>& x3, int sign) {
+  const Cx<T> t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3);
+  const Cx<T> t3 = mul_i(csub(x1, x3), sign);
+  x0 = cadd(t0, t2);
+  x1 = cadd(t1, t3);
+  x2 = csub(t0, t2);
+  x3 = csub(t1, t3);
+}
+
+// 8-point DFT: two 4-point DFTs of the even and odd samples, combined with
+// the 8th roots of unity exp(sign * 2 pi i k / 8)
+template <typename T>
+__device__ __forceinline__ void dft8(Cx<T>* x, int sign) {
+  Cx<T> e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  Cx<T> o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  dft4(e0, e1, e2, e3, sign);
+  dft4(o0, o1, o2, o3, sign);
+  const T h = (T)0.70710678118654752440;
+  // o1 *= w8^1, o2 *= w8^2, o3 *= w8^3
+  if (sign < 0) {
+    o1 = Cx<T>{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    o3 = Cx<T>{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+  } else {
+    o1 = Cx<T>{h * (o1.x - o1.y), h * (o1.x + o1.y)};
+    o3 = Cx<T>{-h * (o3.x + o3.y), h * (o3.x - o3.y)};
+  }
+  o2 = mul_i(o2, sign);
+  x[0] = cadd(e0, o0);
+  x[4] = csub(e0, o0);
+  x[1] = cadd(e1, o1);
+  x[5] = csub(e1, o1);
+  x[2] = cadd(e2, o2);
+  x[6] = csub(e2, o2);
+  x[3] = cadd(e3, o3);
+  x[7] = csub(e3, o3);
+}
+
+// One Stockham stage of radix R over all butterflies of the block; E is the
+// compile-time bound on elements per thread (nrows * n <= E * blockDim).
+template <typename T, int R, int E>
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nrows, int rs, int es, int ns,
+                                          int sign, const Cx<T>* __restrict__ tw) {
+  constexpr int BPT = (E / R) > 0 ? (E / R) : 1;  // butterflies per thread
+  const int nb = n / R;
+  const int total = nb * nrows;
+  const int twstep = n / (ns * R);
+  Cx<T> x[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int t = threadIdx.x + q * blockDim.x;
+    if (t < total) {
+      int row, j;
+      if (es == 1) {
+        row = t / nb;
+        j = t - row * nb;
+      } else {
+        j = t / nrows;
+        row = t - j * nrows;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[q][r] = buf[row * rs + (j + r * nb) * es];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int t = threadIdx.x + q * blockDim.x;
+    if (t < total) {
+      int row, j;
+      if (es == 1) {
+        row = t / nb;
+        j = t - row * nb;
+      } else {
+        j = t / nrows;
+        row = t - j * nrows;
+      }
+      const int k = j & (ns - 1);
+      if (ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const Cx<T> w = tw[r * k * twstep];
+          x[q][r] = sign < 0 ? cmul(x[q][r], w) : cmulc(x[q][r], w);
+        }
+      }
+      if (R == 8) dft8(x[q], sign);
+      else if (R == 4) dft4(x[q][0], x[q][1], x[q][2], x[q][3], sign);
+      else dft2(x[q]);
+      const int d = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[row * rs + (d + r * ns) * es] = x[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform (sign -1 forward, +1 inverse, unnormalised), in place.
+// tw[m] = exp(-2 pi i m / n).  The caller synchronises before the call.
+template <typename T, int E>
+__device__ void lds_fft(Cx<T>* buf, int n, int log2n, int nrows, int rs, int es, int sign,
+                        const Cx<T>* __restrict__ tw) {
   int ns = 1;
   int left = log2n;
   while (left > 0) {
-    const int radix = (left >= 2) ? 4 : 2;
-    const int nb = n / radix;
-    const int total = nb * nrows;
-    const int twstep = n / (ns * radix);
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-      const int row = t / nb;
-      const int j = t - row * nb;
-      const Cx<T>* in = a + row * n;
-      Cx<T>* out = b + row * n;
-      const int k = j & (ns - 1);
-      const int d = (j - k) * radix + k;
-      if (radix == 4) {
-        Cx<T> x0 = in[j], x1 = in[j + nb], x2 = in[j + 2 * nb], x3 = in[j + 3 * nb];
-        if (ns > 1) {
-          const Cx<T> w1 = tw[k * twstep], w2 = tw[2 * k * twstep], w3 = tw[3 * k * twstep];
-          if (sign < 0) {
-            x1 = cmul(x1, w1); x2 = cmul(x2, w2); x3 = cmul(x3, w3);
-          } else {
-            x1 = cmulc(x1, w1); x2 = cmulc(x2, w2); x3 = cmulc(x3, w3);
-          }
-        }
-        const Cx<T> t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3);
-        const Cx<T> df = csub(x1, x3);
-        // multiply by w^1 of the 4-point DFT: -i (forward) or +i (inverse)
-        const Cx<T> t3 = (sign < 0) ? Cx<T>{df.y, -df.x} : Cx<T>{-df.y, df.x};
-        out[d] = cadd(t0, t2);
-        out[d + ns] = cadd(t1, t3);
-        out[d + 2 * ns] = csub(t0, t2);
-        out[d + 3 * ns] = csub(t1, t3);
-      } else {
-        Cx<T> x0 = in[j], x1 = in[j + nb];
-        if (ns > 1) {
-          const Cx<T> w1 = tw[k * twstep];
-          x1 = (sign < 0) ? cmul(x1, w1) : cmulc(x1, w1);
-        }
-        out[d] = cadd(x0, x1);
-        out[d + ns] = csub(x0, x1);
-      }
+    if (left >= 3 && left != 4) {
+      fft_stage<T, 8, E>(buf, n, nrows, rs, es, ns, sign, tw);
+      ns *= 8;
+      left -= 3;
+    } else if (left >= 2) {
+      fft_stage<T, 4, E>(buf, n, nrows, rs, es, ns, sign, tw);
+      ns *= 4;
+      left -= 2;
+    } else {
+      fft_stage<T, 2, E>(buf, n, nrows, rs, es, ns, sign, tw);
+      ns *= 2;
+      left -= 1;
     }
-    __syncthreads();
-    Cx<T>* tmp = a;
-    a = b;
-    b = tmp;
-    ns *= radix;
-    left -= (radix == 4) ? 2 : 1;
   }
-  return a;
 }

@@ -94,6 +94,7 @@ struct ldsv_handle {
   void* zspec = nullptr;  // complex spectrum [npairs][ny][nx]
   void* twx = nullptr;    // exp(-2 pi i m / nx), complex of dtype
   void* twy = nullptr;
+  double* pinv = nullptr; // FP64 Poisson factors -1/(lambda_h Nx Ny) [ny][nx] (MAC)
   double* red = nullptr;  // reduction partials
   size_t red_len = 0;
   double* small = nullptr;  // reduction results, 16 doubles per trajectory

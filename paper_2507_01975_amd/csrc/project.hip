@@ -14,13 +14,20 @@
 //
 // Three passes, each one HBM sweep:
 //   k_div_rowfft     reads u*, v*; forms d for the pair; FFT along x; writes z
-//   k_col_solve      FFT along y, FP64 division (with the 1/(Nx Ny) inverse
-//                    normalisation folded in), inverse FFT along y, in place
+//   k_col_solve      FFT along y, multiply by the FP64 factor -1/(lambda_h Nx Ny)
+//                    (the division by the eigenvalue with the inverse
+//                    normalisation folded in; tabulated in FP64 when the
+//                    handle is created), inverse FFT along y, in place
 //   k_rowifft_grad   inverse FFT along x for rows j-1..j+R-1, then
 //                    u = u* - (p - p[i-1])/dx, v = v* - (p - p[j-1])/dy
 #include "fft_lds.h"
 
 namespace {
+
+constexpr int kRowE = 8;    // elements per thread, row passes (<= 2048 per block)
+constexpr int kRowE3 = 16;  // pass 3 holds one extra halo row
+constexpr int kColE = 16;   // column pass (<= 8192 per block of kColBlock threads)
+constexpr int kColBlock = 512;
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
@@ -29,9 +36,8 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
                                                        const Cx<T>* __restrict__ twx, int nx,
                                                        int ny, int log2nx, int batch, int rows,
                                                        T idx, T idy) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* Bf = A + rows * nx;
   const int pair = blockIdx.y;
   const int b0 = 2 * pair;
   const bool has1 = (b0 + 1) < batch;
@@ -41,63 +47,84 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
   const T* v0 = vs + (size_t)b0 * plane;
   const T* u1 = u0 + plane;
   const T* v1 = v0 + plane;
-  for (int t = threadIdx.x; t < rows * nx; t += blockDim.x) {
-    const int r = t / nx;
-    const int i = t - r * nx;
-    const int j = j0 + r;
-    const int ip = (i + 1) & (nx - 1);
-    const int jp = (j + 1) & (ny - 1);
-    const size_t c = (size_t)j * nx + i;
-    const T d0 = (u0[(size_t)j * nx + ip] - u0[c]) * idx + (v0[(size_t)jp * nx + i] - v0[c]) * idy;
-    T d1 = 0;
-    if (has1) d1 = (u1[(size_t)j * nx + ip] - u1[c]) * idx + (v1[(size_t)jp * nx + i] - v1[c]) * idy;
-    A[t] = Cx<T>{d0, d1};
+#pragma unroll
+  for (int k = 0; k < kRowE; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t < rows * nx) {
+      const int r = t / nx;
+      const int i = t - r * nx;
+      const int j = j0 + r;
+      const int ip = (i + 1) & (nx - 1);
+      const int jp = (j + 1) & (ny - 1);
+      const size_t c = (size_t)j * nx + i;
+      const T d0 = (u0[(size_t)j * nx + ip] - u0[c]) * idx + (v0[(size_t)jp * nx + i] - v0[c]) * idy;
+      T d1 = 0;
+      if (has1) d1 = (u1[(size_t)j * nx + ip] - u1[c]) * idx + (v1[(size_t)jp * nx + i] - v1[c]) * idy;
+      A[t] = Cx<T>{d0, d1};
+    }
   }
   __syncthreads();
-  Cx<T>* res = lds_fft<T>(A, Bf, nx, log2nx, rows, -1, twx);
+  lds_fft<T, kRowE>(A, nx, log2nx, rows, nx, 1, -1, twx);
   Cx<T>* zo = z + (size_t)pair * plane + (size_t)j0 * nx;
-  for (int t = threadIdx.x; t < rows * nx; t += blockDim.x) zo[t] = res[t];
+#pragma unroll
+  for (int k = 0; k < kRowE; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t < rows * nx) zo[t] = A[t];
+  }
 }
 
+// columns x0..x0+cols-1 of one pair: forward FFT along y, multiply by the
+// FP64 Poisson factor -1/(lambda_h Nx Ny) (0 for the zero mode), inverse FFT
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_col_solve(Cx<T>* __restrict__ z,
-                                                      const Cx<T>* __restrict__ twy, int nx,
-                                                      int ny, int log2ny, int cols, double dx,
-                                                      double dy) {
-  extern __shared__ unsigned char smem_raw[];
-  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* Bf = A + cols * ny;
+__global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
+                                                      const Cx<T>* __restrict__ twy,
+                                                      const double* __restrict__ pinv, int nx,
+                                                      int ny, int log2ny, int cols) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);  // element (column c, y) at y * cols + c
   const int pair = blockIdx.y;
   const int x0 = blockIdx.x * cols;
   Cx<T>* zp = z + (size_t)pair * nx * ny;
-  // load columns x0..x0+cols-1 (row segments are contiguous), transpose into LDS
-  for (int t = threadIdx.x; t < cols * ny; t += blockDim.x) {
-    const int y = t / cols;
-    const int c = t - y * cols;
-    A[c * ny + y] = zp[(size_t)y * nx + x0 + c];
+  {
+    Cx<T> tmp[kColE];
+#pragma unroll
+    for (int k = 0; k < kColE; ++k) {
+      const int t = k * kColBlock + (int)threadIdx.x;
+      if (t < cols * ny) {
+        const int y = t / cols;
+        const int c = t - y * cols;
+        tmp[k] = zp[(size_t)y * nx + x0 + c];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kColE; ++k) {
+      const int t = k * kColBlock + (int)threadIdx.x;
+      if (t < cols * ny) A[t] = tmp[k];
+    }
   }
   __syncthreads();
-  Cx<T>* fwd = lds_fft<T>(A, Bf, ny, log2ny, cols, -1, twy);
-  Cx<T>* other = (fwd == A) ? Bf : A;
-  const double pi = 3.14159265358979323846;
-  const double cx = 4.0 / (dx * dx), cy = 4.0 / (dy * dy);
-  const double norm = 1.0 / ((double)nx * (double)ny);
-  for (int t = threadIdx.x; t < cols * ny; t += blockDim.x) {
-    const int c = t / ny;
-    const int ky = t - c * ny;
-    const int kx = x0 + c;
-    const double sx = sin(pi * kx / nx), sy = sin(pi * ky / ny);
-    const double lam = cx * sx * sx + cy * sy * sy;
-    const double s = (lam > 0.0) ? -norm / lam : 0.0;
-    const Cx<T> v = fwd[t];
-    fwd[t] = Cx<T>{(T)((double)v.x * s), (T)((double)v.y * s)};
+  lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, -1, twy);
+#pragma unroll
+  for (int k = 0; k < kColE; ++k) {
+    const int t = k * kColBlock + (int)threadIdx.x;
+    if (t < cols * ny) {
+      const int ky = t / cols;
+      const int c = t - ky * cols;
+      const double s = pinv[(size_t)ky * nx + x0 + c];
+      const Cx<T> v = A[t];
+      A[t] = Cx<T>{(T)((double)v.x * s), (T)((double)v.y * s)};
+    }
   }
   __syncthreads();
-  Cx<T>* inv = lds_fft<T>(fwd, other, ny, log2ny, cols, +1, twy);
-  for (int t = threadIdx.x; t < cols * ny; t += blockDim.x) {
-    const int y = t / cols;
-    const int c = t - y * cols;
-    zp[(size_t)y * nx + x0 + c] = inv[c * ny + y];
+  lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, +1, twy);
+#pragma unroll
+  for (int k = 0; k < kColE; ++k) {
+    const int t = k * kColBlock + (int)threadIdx.x;
+    if (t < cols * ny) {
+      const int y = t / cols;
+      const int c = t - y * cols;
+      zp[(size_t)y * nx + x0 + c] = A[t];
+    }
   }
 }
 
@@ -110,25 +137,39 @@ __global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict
                                                          T* __restrict__ po, int nx, int ny,
                                                          int log2nx, int batch, int rows, T idx,
                                                          T idy) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int nr = rows + 1;
-  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* Bf = A + nr * nx;
+  Cx<T>* P = reinterpret_cast<Cx<T>*>(smem_raw);
   const int pair = blockIdx.y;
   const int b0 = 2 * pair;
   const bool has1 = (b0 + 1) < batch;
   const int j0 = blockIdx.x * rows;
   const size_t plane = (size_t)nx * ny;
   const Cx<T>* zp = z + (size_t)pair * plane;
-  for (int t = threadIdx.x; t < nr * nx; t += blockDim.x) {
-    const int r = t / nx;
-    const int i = t - r * nx;
-    const int j = (j0 - 1 + r + ny) & (ny - 1);
-    A[t] = zp[(size_t)j * nx + i];
+  {
+    Cx<T> tmp[kRowE3];
+#pragma unroll
+    for (int k = 0; k < kRowE3; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < nr * nx) {
+        const int r = t / nx;
+        const int i = t - r * nx;
+        const int j = (j0 - 1 + r + ny) & (ny - 1);
+        tmp[k] = zp[(size_t)j * nx + i];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRowE3; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < nr * nx) P[t] = tmp[k];
+    }
   }
   __syncthreads();
-  const Cx<T>* P = lds_fft<T>(A, Bf, nx, log2nx, nr, +1, twx);
-  for (int t = threadIdx.x; t < rows * nx; t += blockDim.x) {
+  lds_fft<T, kRowE3>(P, nx, log2nx, nr, nx, 1, +1, twx);
+#pragma unroll
+  for (int k = 0; k < kRowE; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t >= rows * nx) break;
     const int r = t / nx;
     const int i = t - r * nx;
     const int j = j0 + r;
@@ -155,48 +196,43 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch;
   const T idx = (T)(nx / h->g.lx), idy = (T)(ny / h->g.ly);
   const size_t cs = sizeof(Cx<T>);
-  // every pass keeps its two LDS buffers within 64 KB
-  const size_t kLds = 65536;
-  // pass 1 and 3: rows per block (power of two dividing ny) with up to 2048
-  // values per block and room for one halo row in pass 3
-  int rows = 2048 / nx;
+  // passes 1 and 3: rows per block (a power of two dividing ny), at most
+  // kRowE * kBlock values in pass 1 and kRowE3 * kBlock (with the halo row)
+  // in pass 3
+  int rows = (kRowE * kBlock) / nx;
   if (rows < 1) rows = 1;
   if (rows > ny) rows = ny;
-  while (rows > 1 && 2 * (size_t)(rows + 1) * nx * cs > kLds) rows >>= 1;
-  LDSV_REQUIRE(2 * (size_t)(rows + 1) * nx * cs <= kLds, LDSV_ESHAPE,
-               "project: nx=%d too large for the LDS row transform", nx);
-  size_t lds = 2 * (size_t)rows * nx * cs;
+  LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * kBlock &&
+                   (size_t)(rows + 1) * nx <= (size_t)kRowE3 * kBlock,
+               LDSV_ESHAPE, "project: nx=%d too large for the LDS row transform", nx);
+  size_t lds = (size_t)rows * nx * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_div_rowfft<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  {
   LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
-                     (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
-                     h->log2nx, B, rows, idx, idy);
-  }
+               (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
+               h->log2nx, B, rows, idx, idy);
   LDSV_LAUNCHED();
-  // pass 2: columns per block within the LDS budget
-  int cols = (int)(kLds / (2 * (size_t)ny * cs));
-  LDSV_REQUIRE(cols >= 1, LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
+  // pass 2: up to 16 columns (128-byte row segments in FP32) within
+  // kColE * kBlock values and 64 KB of LDS
+  int cols = 16;
+  while (cols > 1 && ((size_t)cols * ny > (size_t)kColE * kColBlock || (size_t)cols * ny * cs > 65536))
+    cols >>= 1;
   if (cols > nx) cols = nx;
-  while (nx % cols) cols >>= 1;
-  lds = 2 * (size_t)cols * ny * cs;
+  LDSV_REQUIRE((size_t)cols * ny <= (size_t)kColE * kColBlock && (size_t)cols * ny * cs <= 65536,
+               LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
+  lds = (size_t)cols * ny * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_col_solve<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  {
-  LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3(nx / cols, h->npairs), dim3(kBlock), lds, st,
-                     (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, nx, ny, h->log2ny, cols, h->g.lx / nx,
-                     h->g.ly / ny);
-  }
+  LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3(nx / cols, h->npairs), dim3(kColBlock), lds, st,
+               (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2ny,
+               cols);
   LDSV_LAUNCHED();
-  // pass 3 (same rows as pass 1)
-  lds = 2 * (size_t)(rows + 1) * nx * cs;
+  lds = (size_t)(rows + 1) * nx * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_rowifft_grad<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  {
   LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
-                     (const Cx<T>*)h->zspec, (const Cx<T>*)h->twx, (const T*)us, (const T*)vs,
-                     (T*)uo, (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows, idx, idy);
-  }
+               (const Cx<T>*)h->zspec, (const Cx<T>*)h->twx, (const T*)us, (const T*)vs, (T*)uo,
+               (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows, idx, idy);
   LDSV_LAUNCHED();
   return LDSV_OK;
 }

@@ -64,8 +64,8 @@ struct StagePtrs {
 
 // learned interpolation at a face owned by global cell (gi, gj), kind K;
 // q(a, b) is the tile value at along offset a, across offset b
-template <typename T, bool ALONG_X>
-__device__ __forceinline__ T learned_face(const T (*S)[kSX], int lj, int li, const float* cb,
+template <typename T, bool ALONG_X, int W>
+__device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const float* cb,
                                           int kind, size_t plane, size_t off) {
   T r[16];
   T m = 0;
@@ -86,16 +86,21 @@ __device__ __forceinline__ T learned_face(const T (*S)[kSX], int lj, int li, con
   return acc + (T)0.5 * (q0 + q1);
 }
 
-template <typename T, bool LEARNED>
+template <typename T, bool LEARNED, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, Comb cb, int nx,
-                                                      int ny, int TX, int TY) {
-  __shared__ T su[kSY][kSX];
-  __shared__ T sv[kSY][kSX];
-  __shared__ T fux[kMaxTY][kMaxTX + 1];
-  __shared__ T fvx[kMaxTY][kMaxTX + 1];
-  __shared__ T fuy[kMaxTY + 1][kMaxTX];
-  __shared__ T fvy[kMaxTY + 1][kMaxTX];
-  __shared__ T frow[kMaxTY];
+                                                      int ny) {
+  constexpr int W = TX + 2 * kH, Hh = TY + 2 * kH;
+  constexpr int kTile = W * Hh;
+  constexpr int kTilePer = (kTile + kBlock - 1) / kBlock;
+  constexpr int kCells = TX * TY;
+  constexpr int kCellPer = (kCells + kBlock - 1) / kBlock;
+  __shared__ T su[Hh][W];
+  __shared__ T sv[Hh][W];
+  __shared__ T fux[TY][TX + 1];
+  __shared__ T fvx[TY][TX + 1];
+  __shared__ T fuy[TY + 1][TX];
+  __shared__ T fvy[TY + 1][TX];
+  __shared__ T frow[TY];
 
   const int tilesx = nx / TX;
   const int i0 = (blockIdx.x % tilesx) * TX;
@@ -103,18 +108,56 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
   const int b = blockIdx.y;
   const size_t plane = (size_t)nx * ny;
   const size_t boff = (size_t)b * plane;
-  const int W = TX + 2 * kH, Hh = TY + 2 * kH;
 
-  for (int t = threadIdx.x; t < W * Hh; t += blockDim.x) {
-    const int r = t / W, c = t - r * W;
-    const int gj = (j0 - kH + r + ny) & (ny - 1);
-    const int gi = (i0 - kH + c + nx) & (nx - 1);
-    const size_t g = boff + (size_t)gj * nx + gi;
-    su[r][c] = p.us[g];
-    sv[r][c] = p.vs[g];
+  // stage state with its periodic halo: every load of the thread in flight
+  // before the LDS stores
+  {
+    T tu[kTilePer], tvv[kTilePer];
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kTile) {
+        const int r = t / W, c = t - r * W;
+        const int gj = (j0 - kH + r + ny) & (ny - 1);
+        const int gi = (i0 - kH + c + nx) & (nx - 1);
+        const size_t g = boff + (size_t)gj * nx + gi;
+        tu[k] = p.us[g];
+        tvv[k] = p.vs[g];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kTile) {
+        const int r = t / W, c = t - r * W;
+        su[r][c] = tu[k];
+        sv[r][c] = tvv[k];
+      }
+    }
   }
   if ((ph.mask & LDSV_FORCING) && threadIdx.x < TY)
     frow[threadIdx.x] = (T)(ph.amp * sin(ph.kf * ((j0 + threadIdx.x) + 0.5) * ph.dy));
+  // operands of the RK combination, prefetched before the flux phases
+  T pun[kCellPer], pvn[kCellPer], pau[kCellPer], pav[kCellPer];
+  const bool need_un = cb.alpha != 0.0;
+  const bool need_acc = cb.delta != 0.0 || cb.gamma != 0.0;
+#pragma unroll
+  for (int k = 0; k < kCellPer; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    pun[k] = pvn[k] = pau[k] = pav[k] = (T)0;
+    if (t < kCells) {
+      const int r = t / TX, c = t - r * TX;
+      const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
+      if (need_un) {
+        pun[k] = p.un[g];
+        pvn[k] = p.vn[g];
+      }
+      if (need_acc) {
+        pau[k] = p.accu[g];
+        pav[k] = p.accv[g];
+      }
+    }
+  }
   __syncthreads();
 
   const bool adv = ph.mask & LDSV_ADVECTION;
@@ -124,7 +167,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
   const float* cbase = LEARNED ? p.coef + (size_t)b * p.cbs : nullptr;
 
   // x-faces: owners i in [i0-1, i0+TX-1], rows j in [j0, j0+TY-1]
-  for (int t = threadIdx.x; t < TY * (TX + 1); t += blockDim.x) {
+  constexpr int kXF = TY * (TX + 1);
+#pragma unroll
+  for (int k = 0; k < (kXF + kBlock - 1) / kBlock; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t >= kXF) break;
     const int r = t / (TX + 1), c = t - r * (TX + 1);
     const int li = c + 1, lj = r + kH;
     T fu = 0, fv = 0;
@@ -135,8 +182,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
       if (LEARNED) {
         const int gi = (i0 - 1 + c + nx) & (nx - 1);
         const size_t off = (size_t)(j0 + r) * nx + gi;
-        uf = learned_face<T, true>(su, lj, li, cbase, 0, plane, off);
-        vf = learned_face<T, true>(sv, lj, li, cbase, 2, plane, off);
+        uf = learned_face<T, true, W>(su, lj, li, cbase, 0, plane, off);
+        vf = learned_face<T, true, W>(sv, lj, li, cbase, 2, plane, off);
       } else {
         uf = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
         vf = (T)0.5 * (sv[lj][li] + sv[lj][li + 1]);
@@ -152,7 +199,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
     fvx[r][c] = fv;
   }
   // y-faces: owners j in [j0-1, j0+TY-1], columns i in [i0, i0+TX-1]
-  for (int t = threadIdx.x; t < (TY + 1) * TX; t += blockDim.x) {
+  constexpr int kYF = (TY + 1) * TX;
+#pragma unroll
+  for (int k = 0; k < (kYF + kBlock - 1) / kBlock; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t >= kYF) break;
     const int r = t / TX, c = t - r * TX;
     const int li = c + kH, lj = r + 1;
     T fu = 0, fv = 0;
@@ -163,8 +214,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
       if (LEARNED) {
         const int gj = (j0 - 1 + r + ny) & (ny - 1);
         const size_t off = (size_t)gj * nx + (i0 + c);
-        uf = learned_face<T, false>(su, lj, li, cbase, 1, plane, off);
-        vf = learned_face<T, false>(sv, lj, li, cbase, 3, plane, off);
+        uf = learned_face<T, false, W>(su, lj, li, cbase, 1, plane, off);
+        vf = learned_face<T, false, W>(sv, lj, li, cbase, 3, plane, off);
       } else {
         uf = (T)0.5 * (su[lj][li] + su[lj + 1][li]);
         vf = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
@@ -184,7 +235,10 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
   const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
   const T drag = (T)ph.drag;
   const bool force = ph.mask & LDSV_FORCING;
-  for (int t = threadIdx.x; t < TY * TX; t += blockDim.x) {
+#pragma unroll
+  for (int k = 0; k < kCellPer; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t >= kCells) break;
     const int r = t / TX, c = t - r * TX;
     const T uc = su[r + kH][c + kH], vc = sv[r + kH][c + kH];
     T ru = -(fux[r][c + 1] - fux[r][c]) * idx - (fuy[r + 1][c] - fuy[r][c]) * idy;
@@ -194,19 +248,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
       rv -= drag * vc;
     }
     const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
-    T ou = (T)cb.beta * uc + (T)cb.eps * ru;
-    T ov = (T)cb.beta * vc + (T)cb.eps * rv;
-    if (cb.alpha != 0.0) {
-      ou += (T)cb.alpha * p.un[g];
-      ov += (T)cb.alpha * p.vn[g];
-    }
-    T au = 0, av = 0;
-    if (cb.delta != 0.0 || cb.gamma != 0.0) {
-      au = p.accu[g];
-      av = p.accv[g];
-      ou += (T)cb.delta * au;
-      ov += (T)cb.delta * av;
-    }
+    T ou = (T)cb.beta * uc + (T)cb.eps * ru + (T)cb.alpha * pun[k] + (T)cb.delta * pau[k];
+    T ov = (T)cb.beta * vc + (T)cb.eps * rv + (T)cb.alpha * pvn[k] + (T)cb.delta * pav[k];
     if (p.tcu) {
       const size_t gt = (size_t)b * p.tcbs + (size_t)(j0 + r) * nx + (i0 + c);
       ou += (T)p.tcu[gt];
@@ -215,8 +258,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
     p.ou[g] = ou;
     p.ov[g] = ov;
     if (p.oaccu) {
-      p.oaccu[g] = (T)cb.gamma * au + (T)cb.wacc * ru;
-      p.oaccv[g] = (T)cb.gamma * av + (T)cb.wacc * rv;
+      p.oaccu[g] = (T)cb.gamma * pau[k] + (T)cb.wacc * ru;
+      p.oaccv[g] = (T)cb.gamma * pav[k] + (T)cb.wacc * rv;
     }
   }
 }
@@ -364,11 +407,24 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   }
   const int TY = ny < kMaxTY ? ny : kMaxTY;
   dim3 grid((nx / TX) * (ny / TY), h->g.batch);
-  if (a.coef) {
-    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, true>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
-  } else {
-    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, false>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TY);
+#define LDSV_STAGE_CASE(tx, ty)                                                                   \
+  if (TX == tx && TY == ty) {                                                                     \
+    if (a.coef)                                                                                   \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, true, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, \
+                   ny);                                                                           \
+    else                                                                                          \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, false, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb,   \
+                   nx, ny);                                                                       \
   }
+  LDSV_STAGE_CASE(64, 16)
+  else LDSV_STAGE_CASE(32, 16) else LDSV_STAGE_CASE(16, 16) else LDSV_STAGE_CASE(8, 16)
+  else LDSV_STAGE_CASE(64, 8) else LDSV_STAGE_CASE(32, 8) else LDSV_STAGE_CASE(16, 8)
+  else LDSV_STAGE_CASE(8, 8)
+  else {
+    ldsv_set_error("stage: no tile for %d x %d", nx, ny);
+    return LDSV_ESHAPE;
+  }
+#undef LDSV_STAGE_CASE
   LDSV_LAUNCHED();
   return LDSV_OK;
 }
