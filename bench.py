@@ -122,6 +122,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-corr", action="store_true",
                     help="skip the corr>=0.9 comparison (training + resolution sweep, ~2 min)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="profiling aid: time only the learned 64^2 step and print its record")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="profiling aid: one device-to-device copy of this many MiB before the "
+                    "timed loop, the known-size kernel that calibrates HBM byte counters")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the batched step on a single MI355X "
@@ -132,6 +137,17 @@ def main():
     import torch
     import synthetic_inputs as si
     from paper_2507_01975_amd import ldsv
+
+    if a.copy_probe_mib:
+        src = torch.ones(a.copy_probe_mib << 18, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB" % a.copy_probe_mib)
+        del src, dst
+    if a.learned_only:
+        print(json.dumps({"learned": learned_block(a.steps, a.warmup)}), flush=True)
+        return
 
     w = si.WORKLOADS["decaying512"]
     n, B = w["nx"], w["batch"]

@@ -20,55 +20,82 @@
 // from L1/L2).  FP32 accumulation; bias, GELU and bf16 rounding (round to
 // nearest even) in the epilogue.
 //
-// Layer 1 (2 input channels, K = 18) is not a contraction worth the matrix
-// cores; it runs on the vector ALUs with bf16-rounded inputs and weights and
-// FP32 accumulation, the same arithmetic as the MFMA layers.
+// Layer 1 (2 input channels, K = 18) is a single zero-padded K = 32 step of
+// the same instruction with the im2col gather done in registers.
 #include "cnn_common.h"
 
 namespace {
 using namespace cnnk;
 
-// layer 1: 2 -> 64 on the vector ALUs; one thread per pixel
+// layer 1: 2 -> 64 as one K = 32 step of the same MFMA (K = 18 real
+// entries: tap-major, channel-minor, as the weights are stored, zero-padded).
+// Wavefront w owns pixels 64w..64w+63 (4 tiles of 16) and all 64 channels:
+// lane l gathers the 8 K entries 8(l/16)..+7 of pixel l%16 of each tile
+// (bf16-rounded u, v of the taps), holds the matching 8 weights of 4 channel
+// tiles, and the epilogue is the one of the other layers.
 __global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__ u,
                                                        const float* __restrict__ v,
                                                        const uint16_t* __restrict__ W1,
                                                        const float* __restrict__ b1, PixMap pm,
                                                        uint16_t* __restrict__ Y,
                                                        float* __restrict__ zout) {
-  __shared__ float w[kC * 18];
-  __shared__ float bb[kC];
-  for (int e = threadIdx.x; e < kC * 18; e += blockDim.x) w[e] = bf16_to_f32(W1[e]);
-  for (int e = threadIdx.x; e < kC; e += blockDim.x) bb[e] = b1[e];
-  __syncthreads();
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pm.total) return;
-  float in[18];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int kq = lane >> 4;
+  const int pbase = (blockIdx.x * (kBlock / 64) + wave) * 64;
+  bf16x8 afrag[4];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int q = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
-    in[2 * tap] = bf16_to_f32(f32_to_bf16(u[q]));
-    in[2 * tap + 1] = bf16_to_f32(f32_to_bf16(v[q]));
-  }
-  for (int c0 = 0; c0 < kC; c0 += 8) {
-    uint16_t h[8];
-    float z[8];
+  for (int m = 0; m < 4; ++m) {
+    const int co = m * 16 + col;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      float a = 0.f;
-#pragma unroll
-      for (int k = 0; k < 18; ++k) a += w[(c0 + i) * 18 + k] * in[k];
-      z[i] = a + bb[c0 + i];
-      h[i] = f32_to_bf16(gelu_exact(z[i]));
+    for (int e = 0; e < 8; ++e) {
+      const int k = kq * 8 + e;
+      afrag[m][e] = __builtin_bit_cast(__bf16, k < 18 ? W1[co * 18 + k] : (uint16_t)0);
     }
-    uint4 pk;
-    pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-    pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-    pk.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
-    pk.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
-    *reinterpret_cast<uint4*>(Y + (size_t)p * kC + c0) = pk;
-    if (zout) {
-      *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
-      *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0 + 4) = float4{z[4], z[5], z[6], z[7]};
+    f32x4 b0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b0[i] = b1[m * 16 + kq * 4 + i];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t][m] = b0;
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    int p = pbase + t * 16 + col;
+    p = p < pm.total ? p : pm.total - 1;
+    bf16x8 bfrag;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const int tap = (kq * 8 + e) / 2;
+      float a = 0.f, b = 0.f;
+      if (tap < 9) {
+        const int q = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
+        a = u[q];
+        b = v[q];
+      }
+      const uint32_t pk = pack_bf16x2(a, b);
+      bfrag[e] = __builtin_bit_cast(__bf16, (uint16_t)(pk & 0xffffu));
+      bfrag[e + 1] = __builtin_bit_cast(__bf16, (uint16_t)(pk >> 16));
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag[m], bfrag, acc[t][m], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int p = pbase + t * 16 + col;
+    if (p >= pm.total) continue;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int c0 = m * 16 + kq * 4;
+      uint2 pk;
+      pk.x = pack_bf16x2(gelu_exact(acc[t][m][0]), gelu_exact(acc[t][m][1]));
+      pk.y = pack_bf16x2(gelu_exact(acc[t][m][2]), gelu_exact(acc[t][m][3]));
+      *reinterpret_cast<uint2*>(Y + (size_t)p * kC + c0) = pk;
+      if (zout)
+        *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0) =
+            float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
     }
   }
 }
@@ -104,7 +131,7 @@ int ldsv_check_net(const ldsv_net* net) {
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                     float* out, float* const* zpre, hipStream_t st) {
   PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
-  const int nblk_first = (int)((h->nstate + kBlock - 1) / kBlock);
+  const int nblk_first = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
   {
     LDSV_TLAUNCH(h, 5, k_conv_first, dim3(nblk_first), dim3(kBlock), 0, st, u, v, net->w[0],
                        net->b[0], pm, h->act[0], zpre ? zpre[0] : nullptr);
@@ -148,19 +175,19 @@ int ldsv_launch_conv_tile(ldsv_handle* h, int mt, int epi, const uint16_t* X, co
     const size_t lds = conv_tile_lds_bytes<4>();
     LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<4, 0>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 0>), dim3(grid), dim3(kBlock), lds, st, X, W, bias, cout,
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 0>), dim3(grid), dim3(kConvBlock), lds, st, X, W, bias, cout,
                  pm, Y, zio, out);
   } else if (mt == 4 && epi == 2) {
     const size_t lds = conv_tile_lds_bytes<4>();
     LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<4, 2>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 2>), dim3(grid), dim3(kBlock), lds, st, X, W, bias, cout,
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 2>), dim3(grid), dim3(kConvBlock), lds, st, X, W, bias, cout,
                  pm, Y, zio, out);
   } else if (mt == 5 && epi == 1) {
     const size_t lds = conv_tile_lds_bytes<5>();
     LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<5, 1>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<5, 1>), dim3(grid), dim3(kBlock), lds, st, X, W, bias, cout,
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<5, 1>), dim3(grid), dim3(kConvBlock), lds, st, X, W, bias, cout,
                  pm, Y, zio, out);
   } else {
     ldsv_set_error("conv tile: unsupported configuration");

@@ -18,21 +18,53 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(((uint32_t)h) << 16);
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t x = __float_as_uint(f);
-  if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);
-  x += 0x7fffu + ((x >> 16) & 1u);
-  return (uint16_t)(x >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// round-to-nearest-even float -> bf16 of two values, packed low | high << 16
+// (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const bf16x2 b = __builtin_convertvector((f32x2{lo, hi}), bf16x2);
+  return __builtin_bit_cast(uint32_t, b);
 }
 
-__device__ __forceinline__ float gelu_exact(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  return (uint16_t)(pack_bf16x2(f, 0.0f) & 0xffffu);
 }
+
+// erfc(x) for x >= 0 by the Chebyshev-fitted form of Press et al.,
+// Numerical Recipes (sec. 6.2, erfcc): t exp(-x^2 + P(t)), t = 1/(1 + x/2),
+// fractional error below 1.2e-7 in exact arithmetic; in float32 the error is
+// dominated by the rounding of -x^2 + P(t), about 1e-6 relative for x < 6.
+// Fewer than half the instructions of erff, which matters because the GELU
+// epilogue, not the MFMA work, bounds the convolution kernels.
+__device__ __forceinline__ float erfc_pos(float x) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  return t * __expf(fmaf(-x, x, p));
+}
+
+// standard normal CDF Phi(z) = erfc(-z / sqrt 2) / 2
+__device__ __forceinline__ float normal_cdf(float z) {
+  const float e = 0.5f * erfc_pos(fabsf(z) * 0.70710678118654752f);
+  return z >= 0.0f ? 1.0f - e : e;
+}
+
+// exact (erf) GELU: z Phi(z)
+__device__ __forceinline__ float gelu_exact(float z) { return z * normal_cdf(z); }
 
 // d/dz of the exact GELU: Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return normal_cdf(z) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 struct PixMap {
@@ -122,22 +154,22 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restr
       const int c0 = m * 16 + kq * 4;
       if (EPI == 0 || EPI == 2) {
         float z[4];
-        uint16_t h[4];
+        float h[4];
         if (EPI == 2) {
           const float4 zi = *reinterpret_cast<const float4*>(zio + (size_t)p * kC + c0);
           const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) h[i] = f32_to_bf16(acc[t][m][i] * gelu_grad(zz[i]));
+          for (int i = 0; i < 4; ++i) h[i] = acc[t][m][i] * gelu_grad(zz[i]);
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             z[i] = acc[t][m][i] + bias[c0 + i];
-            h[i] = f32_to_bf16(gelu_exact(z[i]));
+            h[i] = gelu_exact(z[i]);
           }
         }
         uint2 pk;
-        pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        pk.x = pack_bf16x2(h[0], h[1]);
+        pk.y = pack_bf16x2(h[2], h[3]);
         *reinterpret_cast<uint2*>(Y + (size_t)p * kC + c0) = pk;
         if (EPI == 0 && zio)
           *reinterpret_cast<float4*>(zio + (size_t)p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
@@ -161,9 +193,18 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restr
 // over 16 x 16 pixel tiles; for each tile it stages the tile with its
 // 1-pixel periodic halo (18 x 18 pixels x 64 channels, rows padded to 144
 // bytes) and runs all 9 taps from LDS.  Both paddings put the 16 rows that
-// one fragment read touches in distinct LDS banks.  Wavefront w computes tile
-// rows 4w..4w+3.  LDS: 122 KB (64 outputs) or 140 KB (80 padded outputs),
-// one workgroup per CU.
+// one fragment read touches in distinct LDS banks.  LDS: 122 KB (64 outputs)
+// or 140 KB (80 padded outputs), one workgroup per CU.
+//
+// Eight wavefronts, wavefront w computing tile rows 2w and 2w+1 for every
+// output channel.  The epilogue (GELU on every output, bf16 rounding) costs
+// more vector-ALU time than the tile's matrix-core time, so the wavefronts
+// are split into two groups that share each SIMD (w and w + 4 run on the
+// same SIMD): group 0 accumulates tile k and then runs its epilogue, group 1
+// first runs the epilogue of tile k-1 (its accumulators carried across the
+// tile barrier) and then accumulates tile k.  On every SIMD one wavefront's
+// MFMAs overlap the other's vector work.
+constexpr int kConvBlock = 512;
 constexpr int kWRowAll = 9 * kC + 8;   // padded weight row (bf16 elements)
 constexpr int kTileRow = kC + 8;       // padded tile pixel row
 constexpr int kTileH = 18;
@@ -174,17 +215,19 @@ constexpr size_t conv_tile_lds_bytes() {
 }
 
 template <int MT, int EPI>
-__global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restrict__ X,
-                                                         const uint16_t* __restrict__ Wt,
-                                                         const float* __restrict__ bias, int cout,
-                                                         PixMap pm, uint16_t* __restrict__ Y,
-                                                         float* __restrict__ zio,
-                                                         float* __restrict__ out_planar) {
+__global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __restrict__ X,
+                                                             const uint16_t* __restrict__ Wt,
+                                                             const float* __restrict__ bias,
+                                                             int cout, PixMap pm,
+                                                             uint16_t* __restrict__ Y,
+                                                             float* __restrict__ zio,
+                                                             float* __restrict__ out_planar) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
   uint16_t* wl = lds_u16;
   uint16_t* xt = lds_u16 + MT * 16 * kWRowAll;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int grp = wave >> 2;
   const int col = lane & 15;
   const int kq = lane >> 4;
   const int tiles_x = pm.W / 16, tiles_y = pm.H / 16;
@@ -194,12 +237,12 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restr
   // stores so their latencies overlap
   {
     constexpr int kChunks = MT * 16 * (9 * kC / 8);
-    constexpr int kBatch = 6;
-    for (int e0 = 0; e0 < kChunks; e0 += kBatch * kBlock) {
+    constexpr int kBatch = 4;
+    for (int e0 = 0; e0 < kChunks; e0 += kBatch * kConvBlock) {
       uint4 v[kBatch];
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
-        const int e = e0 + k * kBlock + (int)threadIdx.x;
+        const int e = e0 + k * kConvBlock + (int)threadIdx.x;
         const int row = e / (9 * kC / 8), q = e - row * (9 * kC / 8);
         v[k] = uint4{0u, 0u, 0u, 0u};
         if (e < kChunks && row < cout)
@@ -207,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restr
       }
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
-        const int e = e0 + k * kBlock + (int)threadIdx.x;
+        const int e = e0 + k * kConvBlock + (int)threadIdx.x;
         const int row = e / (9 * kC / 8), q = e - row * (9 * kC / 8);
         if (e < kChunks) *reinterpret_cast<uint4*>(wl + row * kWRowAll + q * 8) = v[k];
       }
@@ -217,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restr
   // loads of tile k+1 are in flight while tile k is computed), then stored
   // to LDS between two barriers
   constexpr int kTChunks = kTileH * kTileH * (kC / 8);
-  constexpr int kTPer = (kTChunks + kBlock - 1) / kBlock;
+  constexpr int kTPer = (kTChunks + kConvBlock - 1) / kConvBlock;
   uint4 tv[kTPer];
   auto load_tile = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y);
@@ -225,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restr
     const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
 #pragma unroll
     for (int k = 0; k < kTPer; ++k) {
-      const int e = k * kBlock + (int)threadIdx.x;
+      const int e = k * kConvBlock + (int)threadIdx.x;
       tv[k] = uint4{0u, 0u, 0u, 0u};
       if (e < kTChunks) {
         const int px = e / (kC / 8), q = e - px * (kC / 8);
@@ -235,37 +278,32 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restr
       }
     }
   };
-  if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int b = tile / (tiles_x * tiles_y);
-    const int tr = tile - b * tiles_x * tiles_y;
-    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
-    __syncthreads();
+  f32x4 acc[2][MT];
+  // accumulate the staged tile: rows 2 wave + t, bias-initialised (EPI 0, 1)
+  auto mma = [&]() {
 #pragma unroll
-    for (int k = 0; k < kTPer; ++k) {
-      const int e = k * kBlock + (int)threadIdx.x;
-      if (e < kTChunks) {
-        const int px = e / (kC / 8), q = e - px * (kC / 8);
-        *reinterpret_cast<uint4*>(xt + px * kTileRow + q * 8) = tv[k];
+    for (int m = 0; m < MT; ++m) {
+      f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (EPI != 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = m * 16 + kq * 4 + i;
+          b0[i] = c < cout ? bias[c] : 0.f;
+        }
       }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[t][m] = b0;
     }
-    __syncthreads();
-    if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
-    f32x4 acc[4][MT];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int m = 0; m < MT; ++m) acc[t][m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const int cbase = half * 32 + kq * 8;
-        bf16x8 bfrag[4];
+        bf16x8 bfrag[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ry = wave * 4 + t + 1 + dy, rx = col + 1 + dx;
+        for (int t = 0; t < 2; ++t) {
+          const int ry = wave * 2 + t + 1 + dy, rx = col + 1 + dx;
           bfrag[t] = *reinterpret_cast<const bf16x8*>(xt + (ry * kTileH + rx) * kTileRow + cbase);
         }
 #pragma unroll
@@ -273,50 +311,72 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_tile(const uint16_t* __restr
           const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(
               wl + (m * 16 + col) * kWRowAll + tap * kC + cbase);
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
+          for (int t = 0; t < 2; ++t)
             acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[t][m], 0, 0, 0);
         }
       }
     }
+  };
+  auto epilogue = [&](int tile) {
+    const int b = tile / (tiles_x * tiles_y);
+    const int tr = tile - b * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int y = y0 + wave * 4 + t, x = x0 + col;
+    for (int t = 0; t < 2; ++t) {
+      const int y = y0 + wave * 2 + t, x = x0 + col;
       const int r = y * pm.W + x;
       const size_t p = (size_t)b * hw + r;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
         const int c0 = m * 16 + kq * 4;
         if (EPI == 0 || EPI == 2) {
-          float z[4];
-          uint16_t h[4];
+          float h[4];
           if (EPI == 2) {
             const float4 zi = *reinterpret_cast<const float4*>(zio + p * kC + c0);
             const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = f32_to_bf16(acc[t][m][i] * gelu_grad(zz[i]));
+            for (int i = 0; i < 4; ++i) h[i] = acc[t][m][i] * gelu_grad(zz[i]);
           } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              z[i] = acc[t][m][i] + bias[c0 + i];
-              h[i] = f32_to_bf16(gelu_exact(z[i]));
-            }
+            for (int i = 0; i < 4; ++i) h[i] = gelu_exact(acc[t][m][i]);
           }
           uint2 pk;
-          pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-          pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+          pk.x = pack_bf16x2(h[0], h[1]);
+          pk.y = pack_bf16x2(h[2], h[3]);
           *reinterpret_cast<uint2*>(Y + p * kC + c0) = pk;
           if (EPI == 0 && zio)
-            *reinterpret_cast<float4*>(zio + p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
+            *reinterpret_cast<float4*>(zio + p * kC + c0) =
+                float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = c0 + i;
-            if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i] + bias[c];
+            if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i];
           }
         }
       }
     }
+  };
+  if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
+  int prev = -1;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTPer; ++k) {
+      const int e = k * kConvBlock + (int)threadIdx.x;
+      if (e < kTChunks) {
+        const int px = e / (kC / 8), q = e - px * (kC / 8);
+        *reinterpret_cast<uint4*>(xt + px * kTileRow + q * 8) = tv[k];
+      }
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+    if (grp == 1 && prev >= 0) epilogue(prev);
+    mma();
+    if (grp == 0) epilogue(tile);
+    prev = tile;
   }
+  if (grp == 1 && prev >= 0) epilogue(prev);
 }
 
 }  // namespace cnnk

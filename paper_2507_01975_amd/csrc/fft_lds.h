@@ -66,15 +66,22 @@ __device__ __forceinline__ void dft8(Cx<T>* x, int sign) {
   x[7] = csub(e3, o3);
 }
 
-// One Stockham stage of radix R over all butterflies of the block; E is the
-// compile-time bound on elements per thread (nrows * n <= E * blockDim).
-template <typename T, int R, int E>
-__device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nrows, int rs, int es, int ns,
-                                          int sign, const Cx<T>* __restrict__ tw) {
+// One Stockham stage of radix R (LR = log2 R) over all butterflies of the
+// block; E is the compile-time bound on elements per thread
+// (nrows * n <= E * blockDim).  n, the stage sizes and, for strided
+// transforms (es != 1), nrows are powers of two passed as base-2 logarithms,
+// so index arithmetic is shifts and masks: the vector ALU time of these
+// kernels is comparable to their memory time.  Row transforms (es == 1) take
+// any nrows (the gradient pass transforms a halo row more).
+template <typename T, int R, int LR, int E>
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int log2nrows, int rs,
+                                          int es, int log2ns, int sign,
+                                          const Cx<T>* __restrict__ tw) {
   constexpr int BPT = (E / R) > 0 ? (E / R) : 1;  // butterflies per thread
-  const int nb = n / R;
-  const int total = nb * nrows;
-  const int twstep = n / (ns * R);
+  const int lnb = log2n - LR;                      // log2 of butterflies per transform
+  const int total = nrows << lnb;
+  const int ns = 1 << log2ns;
+  const int ltw = log2n - log2ns - LR;             // twiddle stride n / (ns R)
   Cx<T> x[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -82,14 +89,14 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nrows, int rs, 
     if (t < total) {
       int row, j;
       if (es == 1) {
-        row = t / nb;
-        j = t - row * nb;
+        row = t >> lnb;
+        j = t & ((1 << lnb) - 1);
       } else {
-        j = t / nrows;
-        row = t - j * nrows;
+        j = t >> log2nrows;
+        row = t & ((1 << log2nrows) - 1);
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[q][r] = buf[row * rs + (j + r * nb) * es];
+      for (int r = 0; r < R; ++r) x[q][r] = buf[row * rs + ((j + (r << lnb)) * es)];
     }
   }
   __syncthreads();
@@ -99,50 +106,56 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int n, int nrows, int rs, 
     if (t < total) {
       int row, j;
       if (es == 1) {
-        row = t / nb;
-        j = t - row * nb;
+        row = t >> lnb;
+        j = t & ((1 << lnb) - 1);
       } else {
-        j = t / nrows;
-        row = t - j * nrows;
+        j = t >> log2nrows;
+        row = t & ((1 << log2nrows) - 1);
       }
       const int k = j & (ns - 1);
       if (ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const Cx<T> w = tw[r * k * twstep];
+          const Cx<T> w = tw[(r * k) << ltw];
           x[q][r] = sign < 0 ? cmul(x[q][r], w) : cmulc(x[q][r], w);
         }
       }
       if (R == 8) dft8(x[q], sign);
       else if (R == 4) dft4(x[q][0], x[q][1], x[q][2], x[q][3], sign);
       else dft2(x[q]);
-      const int d = (j - k) * R + k;
+      const int d = ((j - k) << LR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[row * rs + (d + r * ns) * es] = x[q][r];
+      for (int r = 0; r < R; ++r) buf[row * rs + (d + (r << log2ns)) * es] = x[q][r];
     }
   }
   __syncthreads();
 }
 
-// Full transform (sign -1 forward, +1 inverse, unnormalised), in place.
-// tw[m] = exp(-2 pi i m / n).  The caller synchronises before the call.
+// Full transform (sign -1 forward, +1 inverse, unnormalised), in place, of
+// the nrows transforms of length n = 2^log2n (nrows a power of two when
+// es != 1).
+// tw[m] = exp(-2 pi i m / n), a table the caller has copied into LDS (every
+// stage reads it, and a global-memory latency per stage would serialise the
+// transform).  The caller synchronises before the call.
 template <typename T, int E>
-__device__ void lds_fft(Cx<T>* buf, int n, int log2n, int nrows, int rs, int es, int sign,
-                        const Cx<T>* __restrict__ tw) {
-  int ns = 1;
+__device__ __forceinline__ void lds_fft(Cx<T>* buf, int n, int log2n, int nrows, int rs, int es,
+                                        int sign, const Cx<T>* __restrict__ tw) {
+  (void)n;
+  const int log2nrows = es == 1 ? 0 : __builtin_ctz((unsigned)nrows);
+  int log2ns = 0;
   int left = log2n;
   while (left > 0) {
     if (left >= 3 && left != 4) {
-      fft_stage<T, 8, E>(buf, n, nrows, rs, es, ns, sign, tw);
-      ns *= 8;
+      fft_stage<T, 8, 3, E>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
+      log2ns += 3;
       left -= 3;
     } else if (left >= 2) {
-      fft_stage<T, 4, E>(buf, n, nrows, rs, es, ns, sign, tw);
-      ns *= 4;
+      fft_stage<T, 4, 2, E>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
+      log2ns += 2;
       left -= 2;
     } else {
-      fft_stage<T, 2, E>(buf, n, nrows, rs, es, ns, sign, tw);
-      ns *= 2;
+      fft_stage<T, 2, 1, E>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
+      log2ns += 1;
       left -= 1;
     }
   }

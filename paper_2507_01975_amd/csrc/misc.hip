@@ -164,12 +164,15 @@ __global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, f
   }
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// round-to-nearest-even float -> bf16 by the hardware conversion
+// (v_cvt_pk_bf16_f32), the same instruction the network kernels use for
+// their activations
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t x = __float_as_uint(f);
-  if ((x & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((x >> 16) | 0x40u);  // quiet NaN
-  const uint32_t lsb = (x >> 16) & 1u;
-  x += 0x7fffu + lsb;
-  return (uint16_t)(x >> 16);
+  const bf16x2_t b = __builtin_convertvector((f32x2_t{f, 0.0f}), bf16x2_t);
+  return (uint16_t)(__builtin_bit_cast(uint32_t, b) & 0xffffu);
 }
 
 __global__ void k_to_bf16(const float* s, uint16_t* d, size_t n) {

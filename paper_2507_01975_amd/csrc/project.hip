@@ -38,6 +38,8 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
                                                        T idx, T idy) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
+  Cx<T>* W = A + rows * nx;  // twiddles, read by every stage
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
   const int pair = blockIdx.y;
   const int b0 = 2 * pair;
   const bool has1 = (b0 + 1) < batch;
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
     }
   }
   __syncthreads();
-  lds_fft<T, kRowE>(A, nx, log2nx, rows, nx, 1, -1, twx);
+  lds_fft<T, kRowE>(A, nx, log2nx, rows, nx, 1, -1, W);
   Cx<T>* zo = z + (size_t)pair * plane + (size_t)j0 * nx;
 #pragma unroll
   for (int k = 0; k < kRowE; ++k) {
@@ -82,6 +84,8 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
                                                       int ny, int log2ny, int cols) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);  // element (column c, y) at y * cols + c
+  Cx<T>* W = A + cols * ny;
+  for (int e = threadIdx.x; e < ny; e += blockDim.x) W[e] = twy[e];
   const int pair = blockIdx.y;
   const int x0 = blockIdx.x * cols;
   Cx<T>* zp = z + (size_t)pair * nx * ny;
@@ -103,7 +107,7 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
     }
   }
   __syncthreads();
-  lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, -1, twy);
+  lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, -1, W);
 #pragma unroll
   for (int k = 0; k < kColE; ++k) {
     const int t = k * kColBlock + (int)threadIdx.x;
@@ -116,7 +120,7 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
     }
   }
   __syncthreads();
-  lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, +1, twy);
+  lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, +1, W);
 #pragma unroll
   for (int k = 0; k < kColE; ++k) {
     const int t = k * kColBlock + (int)threadIdx.x;
@@ -140,6 +144,8 @@ __global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int nr = rows + 1;
   Cx<T>* P = reinterpret_cast<Cx<T>*>(smem_raw);
+  Cx<T>* W = P + nr * nx;
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
   const int pair = blockIdx.y;
   const int b0 = 2 * pair;
   const bool has1 = (b0 + 1) < batch;
@@ -165,7 +171,7 @@ __global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict
     }
   }
   __syncthreads();
-  lds_fft<T, kRowE3>(P, nx, log2nx, nr, nx, 1, +1, twx);
+  lds_fft<T, kRowE3>(P, nx, log2nx, nr, nx, 1, +1, W);
 #pragma unroll
   for (int k = 0; k < kRowE; ++k) {
     const int t = k * kBlock + (int)threadIdx.x;
@@ -190,12 +196,142 @@ __global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict
   }
 }
 
+// The whole projection of one pair in one workgroup, for grids whose complex
+// pair field fits in LDS (FP32 up to 128 x 128): divergence, FFT along x and
+// y, FP64 factor, inverse FFTs and the gradient correction with one read of
+// u*, v* and one write of u, v.  Used for the coarse grids of the learned
+// solver, where the three-pass version launches too few workgroups to hide
+// its latencies.
+constexpr int kOneBlock = 1024;
+
+// E: elements per thread (nx * ny <= E * kOneBlock).  With E <= 4 the centre
+// values of u*, v* and the Poisson factors stay in registers from the first
+// global read to the last use, so the kernel has a single round of global
+// loads; with larger E they are re-read at the end.
+template <typename T, int E>
+__global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__ us,
+                                                          const T* __restrict__ vs,
+                                                          T* __restrict__ uo, T* __restrict__ vo,
+                                                          T* __restrict__ po,
+                                                          const Cx<T>* __restrict__ twx,
+                                                          const Cx<T>* __restrict__ twy,
+                                                          const double* __restrict__ pinv, int nx,
+                                                          int ny, int log2nx, int log2ny, int batch,
+                                                          T idx, T idy) {
+  constexpr bool kKeep = E <= 4;
+  constexpr int KE = kKeep ? E : 1;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);  // element (i, j) at j * nx + i
+  Cx<T>* Wx = A + nx * ny;
+  Cx<T>* Wy = Wx + nx;
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) Wx[e] = twx[e];
+  for (int e = threadIdx.x; e < ny; e += blockDim.x) Wy[e] = twy[e];
+  const int pair = blockIdx.x;
+  const int b0 = 2 * pair;
+  const bool has1 = (b0 + 1) < batch;
+  const int n = nx * ny;
+  const size_t plane = (size_t)n;
+  const T* u0 = us + (size_t)b0 * plane;
+  const T* v0 = vs + (size_t)b0 * plane;
+  T cu0[KE], cv0[KE], cu1[KE], cv1[KE];
+  double fac[KE];
+  // groups of 4 elements per thread: their loads are in flight together
+  // without holding all 16 in registers
+#pragma unroll
+  for (int g = 0; g < E; g += 4) {
+    if (g * kOneBlock >= n) break;
+    T d0[4], d1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = (g + k) * kOneBlock + (int)threadIdx.x;
+      d0[k] = 0;
+      d1[k] = 0;
+      if (t < n) {
+        const int j = t >> log2nx;
+        const int i = t & (nx - 1);
+        const int ip = (i + 1) & (nx - 1);
+        const int jp = (j + 1) & (ny - 1);
+        const T a0 = u0[t], c0v = v0[t];
+        d0[k] = (u0[j * nx + ip] - a0) * idx + (v0[jp * nx + i] - c0v) * idy;
+        T a1 = 0, c1v = 0;
+        if (has1) {
+          a1 = u0[plane + t];
+          c1v = v0[plane + t];
+          d1[k] = (u0[plane + j * nx + ip] - a1) * idx + (v0[plane + jp * nx + i] - c1v) * idy;
+        }
+        if (kKeep) {
+          cu0[(g + k) % KE] = a0;
+          cv0[(g + k) % KE] = c0v;
+          cu1[(g + k) % KE] = a1;
+          cv1[(g + k) % KE] = c1v;
+          fac[(g + k) % KE] = pinv[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = (g + k) * kOneBlock + (int)threadIdx.x;
+      if (t < n) A[t] = Cx<T>{d0[k], d1[k]};
+    }
+  }
+  __syncthreads();
+  lds_fft<T, E>(A, nx, log2nx, ny, nx, 1, -1, Wx);
+  lds_fft<T, E>(A, ny, log2ny, nx, 1, nx, -1, Wy);
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int t = k * kOneBlock + (int)threadIdx.x;
+    if (t < n) {
+      const double s = kKeep ? fac[k % KE] : pinv[t];
+      const Cx<T> v = A[t];
+      A[t] = Cx<T>{(T)((double)v.x * s), (T)((double)v.y * s)};
+    }
+  }
+  __syncthreads();
+  lds_fft<T, E>(A, ny, log2ny, nx, 1, nx, +1, Wy);
+  lds_fft<T, E>(A, nx, log2nx, ny, nx, 1, +1, Wx);
+#pragma unroll 4
+  for (int k = 0; k < E; ++k) {
+    const int t = k * kOneBlock + (int)threadIdx.x;
+    if (t >= n) break;
+    const int j = t >> log2nx;
+    const int i = t & (nx - 1);
+    const Cx<T> pc = A[t];
+    const Cx<T> pw = A[j * nx + ((i - 1) & (nx - 1))];
+    const Cx<T> ps = A[((j - 1) & (ny - 1)) * nx + i];
+    const size_t c0 = (size_t)b0 * plane + t;
+    uo[c0] = (kKeep ? cu0[k % KE] : us[c0]) - (pc.x - pw.x) * idx;
+    vo[c0] = (kKeep ? cv0[k % KE] : vs[c0]) - (pc.x - ps.x) * idy;
+    if (po) po[c0] = pc.x;
+    if (has1) {
+      const size_t c1 = c0 + plane;
+      uo[c1] = (kKeep ? cu1[k % KE] : us[c1]) - (pc.y - pw.y) * idx;
+      vo[c1] = (kKeep ? cv1[k % KE] : vs[c1]) - (pc.y - ps.y) * idy;
+      if (po) po[c1] = pc.y;
+    }
+  }
+}
+
 template <typename T>
 int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo, void* po,
                  hipStream_t st) {
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch;
   const T idx = (T)(nx / h->g.lx), idy = (T)(ny / h->g.ly);
   const size_t cs = sizeof(Cx<T>);
+  if ((size_t)nx * ny <= (size_t)16 * kOneBlock && (size_t)nx * ny * cs <= 131072) {
+    // u*, v* are read only by the cells that write u, v at the same index
+    // after all reads of neighbours are done (the divergence is formed
+    // before the first barrier), so in-place calls are safe here as well
+    const size_t lds = ((size_t)nx * ny + nx + ny) * cs;
+    auto kern = (size_t)nx * ny <= (size_t)4 * kOneBlock ? k_project_lds<T, 4> : k_project_lds<T, 16>;
+    LDSV_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    LDSV_TLAUNCH(h, 2, kern, dim3(h->npairs), dim3(kOneBlock), lds, st, (const T*)us,
+                 (const T*)vs, (T*)uo, (T*)vo, (T*)po, (const Cx<T>*)h->twx,
+                 (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2nx, h->log2ny, B,
+                 idx, idy);
+    LDSV_LAUNCHED();
+    return LDSV_OK;
+  }
   // passes 1 and 3: rows per block (a power of two dividing ny), at most
   // kRowE * kBlock values in pass 1 and kRowE3 * kBlock (with the halo row)
   // in pass 3
@@ -205,7 +341,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * kBlock &&
                    (size_t)(rows + 1) * nx <= (size_t)kRowE3 * kBlock,
                LDSV_ESHAPE, "project: nx=%d too large for the LDS row transform", nx);
-  size_t lds = (size_t)rows * nx * cs;
+  size_t lds = ((size_t)rows * nx + nx) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_div_rowfft<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
@@ -220,14 +356,14 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   if (cols > nx) cols = nx;
   LDSV_REQUIRE((size_t)cols * ny <= (size_t)kColE * kColBlock && (size_t)cols * ny * cs <= 65536,
                LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
-  lds = (size_t)cols * ny * cs;
+  lds = ((size_t)cols * ny + ny) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_col_solve<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3(nx / cols, h->npairs), dim3(kColBlock), lds, st,
                (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2ny,
                cols);
   LDSV_LAUNCHED();
-  lds = (size_t)(rows + 1) * nx * cs;
+  lds = ((size_t)(rows + 1) * nx + nx) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_rowifft_grad<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,

@@ -173,3 +173,36 @@ def test_nan_network_falls_back_everywhere():
     torch.cuda.synchronize()
     assert flags.tolist() == [3, 3]
     assert torch.equal(tu[0], pu) and torch.equal(tv[0], pv)
+
+
+def test_bf16_conversion_rounds_to_nearest_even():
+    """The hardware float -> bf16 conversion used for weights and activations
+    against round-to-nearest-even (torch's CPU conversion): random values,
+    exact ties with even and odd kept bit, subnormals, signed zeros, the
+    overflow boundary and infinities; NaN only as NaN."""
+    L_ = need_gpu()
+    announce("bf16 rounding")
+    g = torch.Generator().manual_seed(7)
+    rnd = torch.randint(0, 2**31 - 1, (1 << 16,), generator=g, dtype=torch.int64)
+    hi = (rnd & 0x7FFF7FFF) | ((rnd & 1) << 31)           # random sign, exponent, mantissa
+    ties = (hi & ~0xFFFF) | 0x8000                          # exactly half-way
+    near = (hi & ~0xFFFF) | 0x7FFF                          # just below half-way
+    above = (hi & ~0xFFFF) | 0x8001                         # just above
+    special = torch.tensor([0x00000000, 0x80000000, 0x00000001, 0x00008000, 0x00018000,
+                            0x007FFFFF, 0x7F7F7FFF, 0x7F7F8000, 0x7F7FFFFF, 0x7F800000,
+                            0xFF800000, 0x3F808000, 0x3F818000, 0xBF808000], dtype=torch.int64)
+    bits = torch.cat([hi, ties, near, above, special]).to(torch.int64)
+    bits = torch.where(bits >= 2**31, bits - 2**32, bits).to(torch.int32)
+    x = bits.view(torch.float32)
+    finite = ~torch.isnan(x)
+    x = x[finite].contiguous()
+    xd = x.cuda()
+    out = torch.empty(x.numel(), dtype=torch.int16, device="cuda")
+    L_._check(L_._lib.ldsv_to_bf16(L_._ptr(xd), L_._ptr(out), x.numel(), L_._stream()))
+    torch.cuda.synchronize()
+    ref = x.to(torch.bfloat16).view(torch.int16)
+    assert torch.equal(out.cpu(), ref)
+    nan = torch.tensor([float("nan")], dtype=torch.float32).cuda()
+    o1 = torch.empty(1, dtype=torch.int16, device="cuda")
+    L_._check(L_._lib.ldsv_to_bf16(L_._ptr(nan), L_._ptr(o1), 1, L_._stream()))
+    assert torch.isnan(o1.cpu().view(torch.bfloat16).float()).all()
