@@ -12,8 +12,10 @@ one JSON line on stdout; progress goes to stderr.
 
 The line also carries
 * roofline: the dominant kernel class's average launch duration (HIP events
-  recorded around every launch of that class on its stream during the timed
-  region), its algorithmic bytes per launch, achieved GB/s against 8 TB/s;
+  recorded around every launch on its stream, in a second pass of the same K
+  steps right after the timed one, since the events themselves add gaps
+  between launches), its algorithmic bytes per launch, achieved GB/s against
+  8 TB/s;
 * cpu_baseline: the FP64 CPU oracle timed on this host on a bounded sample
   of the same workload (the full batch, as many steps as fit in ~10 s);
 * learned: the learned step (64^2, batch 64, BF16 CNN on MFMA);
@@ -90,12 +92,18 @@ def learned_block(steps, warmup):
     except ldsv.LdsvError as e:
         return {"status": "unavailable: %s" % e}
     torch.cuda.synchronize()
-    s.timer_enable(True)
     t0 = time.perf_counter()
     for k in range(steps):
         s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    # kernel durations from a second, instrumented pass (per-launch events
+    # add several microseconds between launches, so the throughput above is
+    # timed without them)
+    s.timer_enable(True)
+    for k in range(steps):
+        s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
     conv_ms, conv_n = s.timer_read(ldsv.TIMER_CONV)
     s.timer_enable(False)
     cells = n * n * B
@@ -160,16 +168,25 @@ def main():
         s.fv_step(prm, u, v, out=(u, v))
     torch.cuda.synchronize()
     log("warmup done")
-    s.timer_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         s.fv_step(prm, u, v, out=(u, v))
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (a.steps, t))
+    # per-kernel durations: the same K steps again with a HIP event pair
+    # recorded around every launch on the launch stream (the events add
+    # several microseconds between launches, so the throughput above is
+    # timed without them)
+    s.timer_enable(True)
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        s.fv_step(prm, u, v, out=(u, v))
+    torch.cuda.synchronize()
+    t_inst = time.perf_counter() - t1
     cls = {c: s.timer_read(c) for c in range(4)}
     s.timer_enable(False)
-    log("timed %d steps in %.3f s" % (a.steps, t))
     diag = s.diagnostics(u, v).cpu()
     assert bool((diag[:, 5] == 1).all()), "non-finite state after the timed steps"
 
@@ -183,7 +200,8 @@ def main():
     roof = {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6,
-            "classes_ms_per_step": {CLASS_NAMES[c]: cls[c][0] / a.steps for c in cls}}
+            "classes_ms_per_step": {CLASS_NAMES[c]: cls[c][0] / a.steps for c in cls},
+            "instrumented_ms_per_step": 1e3 * t_inst / a.steps}
     line = {"metric": "cell-steps/s + sim-time/s at corr>=0.9: learned coarse FV vs plain fine FV",
             "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "ms_per_step": 1e3 * t / a.steps, "higher_is_better": True,

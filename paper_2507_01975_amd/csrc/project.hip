@@ -40,10 +40,13 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
   Cx<T>* W = A + rows * nx;  // twiddles, read by every stage
   for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
-  const int pair = blockIdx.y;
+  // row bands renumbered so one XCD walks consecutive bands (the halo row
+  // of a band is the next band's first row)
+  const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int pair = band / gridDim.x;
   const int b0 = 2 * pair;
   const bool has1 = (b0 + 1) < batch;
-  const int j0 = blockIdx.x * rows;
+  const int j0 = (band - pair * gridDim.x) * rows;
   const size_t plane = (size_t)nx * ny;
   const T* u0 = us + (size_t)b0 * plane;
   const T* v0 = vs + (size_t)b0 * plane;
@@ -146,10 +149,13 @@ __global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict
   Cx<T>* P = reinterpret_cast<Cx<T>*>(smem_raw);
   Cx<T>* W = P + nr * nx;
   for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
-  const int pair = blockIdx.y;
+  // row bands renumbered so one XCD walks consecutive bands (the halo row
+  // of a band is the next band's first row)
+  const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int pair = band / gridDim.x;
   const int b0 = 2 * pair;
   const bool has1 = (b0 + 1) < batch;
-  const int j0 = blockIdx.x * rows;
+  const int j0 = (band - pair * gridDim.x) * rows;
   const size_t plane = (size_t)nx * ny;
   const Cx<T>* zp = z + (size_t)pair * plane;
   {

@@ -34,13 +34,20 @@ constexpr int kSY = kMaxTY + 2 * kH;
 __constant__ int kAOff[16] = {-1, 0, 1, 2, -1, 0, 1, 2, -1, 0, 1, 2, 0, 1, 0, 1};
 __constant__ int kBOff[16] = {-1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -2, -2, 2, 2};
 
-struct Phys {
-  double nu, amp, kf, drag, dx, dy;
+// Physical constants, rounded to the kernel's type on the host (the same
+// double-to-T roundings as before, without per-thread double divisions);
+// the forcing keeps its FP64 inputs for the per-row sine.
+template <typename T>
+struct PhysT {
+  T nu, drag, idx, idy, i24dx, i24dy, idx2, idy2;
+  double amp, kf, dy;
   int mask;
 };
 
-struct Comb {
-  double alpha, beta, delta, eps, gamma, wacc;
+template <typename T>
+struct CombT {
+  T alpha, beta, delta, eps, gamma, wacc;
+  int need_un, need_acc;
 };
 
 template <typename T>
@@ -87,7 +94,7 @@ __device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const
 }
 
 template <typename T, bool LEARNED, int TX, int TY>
-__global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, Comb cb, int nx,
+__global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny) {
   constexpr int W = TX + 2 * kH, Hh = TY + 2 * kH;
   constexpr int kTile = W * Hh;
@@ -103,9 +110,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
   __shared__ T frow[TY];
 
   const int tilesx = nx / TX;
-  const int i0 = (blockIdx.x % tilesx) * TX;
-  const int j0 = (blockIdx.x / tilesx) * TY;
-  const int b = blockIdx.y;
+  const int tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int b = tile / gridDim.x;
+  const int tp = tile - b * gridDim.x;
+  const int i0 = (tp % tilesx) * TX;
+  const int j0 = (tp / tilesx) * TY;
   const size_t plane = (size_t)nx * ny;
   const size_t boff = (size_t)b * plane;
 
@@ -136,11 +145,12 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
     }
   }
   if ((ph.mask & LDSV_FORCING) && threadIdx.x < TY)
-    frow[threadIdx.x] = (T)(ph.amp * sin(ph.kf * ((j0 + threadIdx.x) + 0.5) * ph.dy));
+    frow[threadIdx.x] =
+        ph.amp != 0.0 ? (T)(ph.amp * sin(ph.kf * ((j0 + threadIdx.x) + 0.5) * ph.dy)) : (T)0;
   // operands of the RK combination, prefetched before the flux phases
   T pun[kCellPer], pvn[kCellPer], pau[kCellPer], pav[kCellPer];
-  const bool need_un = cb.alpha != 0.0;
-  const bool need_acc = cb.delta != 0.0 || cb.gamma != 0.0;
+  const bool need_un = cb.need_un;
+  const bool need_acc = cb.need_acc;
 #pragma unroll
   for (int k = 0; k < kCellPer; ++k) {
     const int t = k * kBlock + (int)threadIdx.x;
@@ -162,8 +172,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
 
   const bool adv = ph.mask & LDSV_ADVECTION;
   const bool visc = ph.mask & LDSV_VISCOSITY;
-  const T nu = (T)ph.nu;
-  const T i24dx = (T)(1.0 / (24.0 * ph.dx)), i24dy = (T)(1.0 / (24.0 * ph.dy));
+  const T nu = ph.nu;
+  const T i24dx = ph.i24dx, i24dy = ph.i24dy;
   const float* cbase = LEARNED ? p.coef + (size_t)b * p.cbs : nullptr;
 
   // x-faces: owners i in [i0-1, i0+TX-1], rows j in [j0, j0+TY-1]
@@ -232,8 +242,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
   }
   __syncthreads();
 
-  const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
-  const T drag = (T)ph.drag;
+  const T idx = ph.idx, idy = ph.idy;
+  const T drag = ph.drag;
   const bool force = ph.mask & LDSV_FORCING;
 #pragma unroll
   for (int k = 0; k < kCellPer; ++k) {
@@ -248,8 +258,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
       rv -= drag * vc;
     }
     const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
-    T ou = (T)cb.beta * uc + (T)cb.eps * ru + (T)cb.alpha * pun[k] + (T)cb.delta * pau[k];
-    T ov = (T)cb.beta * vc + (T)cb.eps * rv + (T)cb.alpha * pvn[k] + (T)cb.delta * pav[k];
+    T ou = cb.beta * uc + cb.eps * ru + cb.alpha * pun[k] + cb.delta * pau[k];
+    T ov = cb.beta * vc + cb.eps * rv + cb.alpha * pvn[k] + cb.delta * pav[k];
     if (p.tcu) {
       const size_t gt = (size_t)b * p.tcbs + (size_t)(j0 + r) * nx + (i0 + c);
       ou += (T)p.tcu[gt];
@@ -258,8 +268,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, Phys ph, C
     p.ou[g] = ou;
     p.ov[g] = ov;
     if (p.oaccu) {
-      p.oaccu[g] = (T)cb.gamma * pau[k] + (T)cb.wacc * ru;
-      p.oaccv[g] = (T)cb.gamma * pav[k] + (T)cb.wacc * rv;
+      p.oaccu[g] = cb.gamma * pau[k] + cb.wacc * ru;
+      p.oaccv[g] = cb.gamma * pav[k] + cb.wacc * rv;
     }
   }
 }
@@ -269,7 +279,7 @@ constexpr int kMaxTYc = 8;
 constexpr int kSYc = kMaxTYc + 2 * kH;
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, Phys ph, Comb cb, int nx,
+__global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny, int TX, int TY) {
   __shared__ T su[kSYc][kSX];
   __shared__ T sv[kSYc][kSX];
@@ -281,9 +291,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, Phys ph, C
   __shared__ T fvn[kMaxTYc + 1][kMaxTX];
 
   const int tilesx = nx / TX;
-  const int i0 = (blockIdx.x % tilesx) * TX;
-  const int j0 = (blockIdx.x / tilesx) * TY;
-  const int b = blockIdx.y;
+  const int tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int b = tile / gridDim.x;
+  const int tp = tile - b * gridDim.x;
+  const int i0 = (tp % tilesx) * TX;
+  const int j0 = (tp / tilesx) * TY;
   const size_t plane = (size_t)nx * ny;
   const size_t boff = (size_t)b * plane;
   const int W = TX + 2 * kH, Hh = TY + 2 * kH;
@@ -332,9 +344,9 @@ __global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, Phys ph, C
     }
   }
   __syncthreads();
-  const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
-  const T idx2 = idx * idx, idy2 = idy * idy;
-  const T nu = (T)ph.nu;
+  const T idx = ph.idx, idy = ph.idy;
+  const T idx2 = ph.idx2, idy2 = ph.idy2;
+  const T nu = ph.nu;
   const bool visc = ph.mask & LDSV_VISCOSITY;
   for (int t = threadIdx.x; t < TY * TX; t += blockDim.x) {
     const int r = t / TX, c = t - r * TX;
@@ -353,24 +365,24 @@ __global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, Phys ph, C
                   (sv[lj + 1][li] - (T)2 * vc + sv[lj - 1][li]) * idy2);
     }
     const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
-    T ou = (T)cb.beta * uc + (T)cb.eps * ru;
-    T ov = (T)cb.beta * vc + (T)cb.eps * rv;
-    if (cb.alpha != 0.0) {
-      ou += (T)cb.alpha * p.un[g];
-      ov += (T)cb.alpha * p.vn[g];
+    T ou = cb.beta * uc + cb.eps * ru;
+    T ov = cb.beta * vc + cb.eps * rv;
+    if (cb.need_un) {
+      ou += cb.alpha * p.un[g];
+      ov += cb.alpha * p.vn[g];
     }
     T au = 0, av = 0;
-    if (cb.delta != 0.0 || cb.gamma != 0.0) {
+    if (cb.need_acc) {
       au = p.accu[g];
       av = p.accv[g];
-      ou += (T)cb.delta * au;
-      ov += (T)cb.delta * av;
+      ou += cb.delta * au;
+      ov += cb.delta * av;
     }
     p.ou[g] = ou;
     p.ov[g] = ov;
     if (p.oaccu) {
-      p.oaccu[g] = (T)cb.gamma * au + (T)cb.wacc * ru;
-      p.oaccv[g] = (T)cb.gamma * av + (T)cb.wacc * rv;
+      p.oaccu[g] = cb.gamma * au + cb.wacc * ru;
+      p.oaccv[g] = cb.gamma * av + cb.wacc * rv;
     }
   }
 }
@@ -393,9 +405,22 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   p.tcu = a.tcu;
   p.tcv = a.tcv;
   p.tcbs = a.tc_bstride;
-  Phys ph{prm->nu, prm->forcing_amp, prm->forcing_k, prm->drag, h->g.lx / h->g.nx,
-          h->g.ly / h->g.ny, prm->physics_mask};
-  Comb cb{a.alpha, a.beta, a.delta, a.eps, a.gamma, a.wacc};
+  const double dx = h->g.lx / h->g.nx, dy = h->g.ly / h->g.ny;
+  PhysT<T> ph;
+  ph.nu = (T)prm->nu;
+  ph.drag = (T)prm->drag;
+  ph.idx = (T)(1.0 / dx);
+  ph.idy = (T)(1.0 / dy);
+  ph.i24dx = (T)(1.0 / (24.0 * dx));
+  ph.i24dy = (T)(1.0 / (24.0 * dy));
+  ph.idx2 = ph.idx * ph.idx;
+  ph.idy2 = ph.idy * ph.idy;
+  ph.amp = prm->forcing_amp;
+  ph.kf = prm->forcing_k;
+  ph.dy = dy;
+  ph.mask = prm->physics_mask;
+  CombT<T> cb{(T)a.alpha, (T)a.beta, (T)a.delta, (T)a.eps, (T)a.gamma, (T)a.wacc,
+              a.alpha != 0.0, a.delta != 0.0 || a.gamma != 0.0};
   const int nx = h->g.nx, ny = h->g.ny;
   const int TX = nx < kMaxTX ? nx : kMaxTX;
   if (h->g.layout == LDSV_COLLOCATED) {
