@@ -24,13 +24,15 @@
 
 namespace {
 
-constexpr int kRowE = 8;    // elements per thread, row passes (<= 2048 per block)
-constexpr int kRowE3 = 16;  // pass 3 holds one extra halo row
-constexpr int kColE = 16;   // column pass (<= 8192 per block of kColBlock threads)
-constexpr int kColBlock = 512;
+constexpr int kRowE = 4;       // elements per thread, pass 1
+constexpr int kRow1MaxBlock = 512;
+constexpr int kRowE3 = 8;      // pass 3, with its extra halo row
+constexpr int kRow3Block = 1024;
+constexpr int kColE = 16;      // column pass
+constexpr int kColBlock = 512; // largest column-pass block
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
+__global__ void __launch_bounds__(kRow1MaxBlock) k_div_rowfft(const T* __restrict__ us,
                                                        const T* __restrict__ vs,
                                                        Cx<T>* __restrict__ z,
                                                        const Cx<T>* __restrict__ twx, int nx,
@@ -54,10 +56,10 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
   const T* v1 = v0 + plane;
 #pragma unroll
   for (int k = 0; k < kRowE; ++k) {
-    const int t = k * kBlock + (int)threadIdx.x;
+    const int t = k * blockDim.x + threadIdx.x;
     if (t < rows * nx) {
-      const int r = t / nx;
-      const int i = t - r * nx;
+      const int r = t >> log2nx;
+      const int i = t & (nx - 1);
       const int j = j0 + r;
       const int ip = (i + 1) & (nx - 1);
       const int jp = (j + 1) & (ny - 1);
@@ -73,51 +75,65 @@ __global__ void __launch_bounds__(kBlock) k_div_rowfft(const T* __restrict__ us,
   Cx<T>* zo = z + (size_t)pair * plane + (size_t)j0 * nx;
 #pragma unroll
   for (int k = 0; k < kRowE; ++k) {
-    const int t = k * kBlock + (int)threadIdx.x;
+    const int t = k * blockDim.x + threadIdx.x;
     if (t < rows * nx) zo[t] = A[t];
   }
 }
 
 // columns x0..x0+cols-1 of one pair: forward FFT along y, multiply by the
-// FP64 Poisson factor -1/(lambda_h Nx Ny) (0 for the zero mode), inverse FFT
+// FP64 Poisson factor -1/(lambda_h Nx Ny) (0 for the zero mode), inverse FFT.
+// Blocks of 8 columns (64-byte row segments in FP32): two or more blocks per
+// CU overlap one block's memory phase with another's transform.  XCD x takes
+// the column groups [x ncx/8, (x+1) ncx/8) of every pair, so the two halves
+// of a 128-byte line and the matching rows of the factor table stay in its
+// L2.
 template <typename T>
 __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
                                                       const Cx<T>* __restrict__ twy,
                                                       const double* __restrict__ pinv, int nx,
-                                                      int ny, int log2ny, int cols) {
+                                                      int ny, int log2ny, int log2cols) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int cols = 1 << log2cols;
+  const int n = cols << log2ny;
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);  // element (column c, y) at y * cols + c
-  Cx<T>* W = A + cols * ny;
+  Cx<T>* W = A + n;
   for (int e = threadIdx.x; e < ny; e += blockDim.x) W[e] = twy[e];
-  const int pair = blockIdx.y;
-  const int x0 = blockIdx.x * cols;
+  const int ncx = nx >> log2cols;
+  int cx, pair;
+  {
+    const int lid = blockIdx.x;
+    if ((ncx & 7) == 0) {
+      const int cpx = ncx >> 3, slot = lid >> 3;
+      const int q = slot / cpx;
+      cx = (lid & 7) * cpx + (slot - q * cpx);
+      pair = q;
+    } else {
+      pair = lid / ncx;
+      cx = lid - pair * ncx;
+    }
+  }
+  const int x0 = cx << log2cols;
   Cx<T>* zp = z + (size_t)pair * nx * ny;
   {
     Cx<T> tmp[kColE];
 #pragma unroll
     for (int k = 0; k < kColE; ++k) {
-      const int t = k * kColBlock + (int)threadIdx.x;
-      if (t < cols * ny) {
-        const int y = t / cols;
-        const int c = t - y * cols;
-        tmp[k] = zp[(size_t)y * nx + x0 + c];
-      }
+      const int t = k * blockDim.x + threadIdx.x;
+      if (t < n) tmp[k] = zp[(size_t)(t >> log2cols) * nx + x0 + (t & (cols - 1))];
     }
 #pragma unroll
     for (int k = 0; k < kColE; ++k) {
-      const int t = k * kColBlock + (int)threadIdx.x;
-      if (t < cols * ny) A[t] = tmp[k];
+      const int t = k * blockDim.x + threadIdx.x;
+      if (t < n) A[t] = tmp[k];
     }
   }
   __syncthreads();
   lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, -1, W);
 #pragma unroll
   for (int k = 0; k < kColE; ++k) {
-    const int t = k * kColBlock + (int)threadIdx.x;
-    if (t < cols * ny) {
-      const int ky = t / cols;
-      const int c = t - ky * cols;
-      const double s = pinv[(size_t)ky * nx + x0 + c];
+    const int t = k * blockDim.x + threadIdx.x;
+    if (t < n) {
+      const double s = pinv[(size_t)(t >> log2cols) * nx + x0 + (t & (cols - 1))];
       const Cx<T> v = A[t];
       A[t] = Cx<T>{(T)((double)v.x * s), (T)((double)v.y * s)};
     }
@@ -126,17 +142,13 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
   lds_fft<T, kColE>(A, ny, log2ny, cols, 1, cols, +1, W);
 #pragma unroll
   for (int k = 0; k < kColE; ++k) {
-    const int t = k * kColBlock + (int)threadIdx.x;
-    if (t < cols * ny) {
-      const int y = t / cols;
-      const int c = t - y * cols;
-      zp[(size_t)y * nx + x0 + c] = A[t];
-    }
+    const int t = k * blockDim.x + threadIdx.x;
+    if (t < n) zp[(size_t)(t >> log2cols) * nx + x0 + (t & (cols - 1))] = A[t];
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict__ z,
+__global__ void __launch_bounds__(kRow3Block) k_rowifft_grad(const Cx<T>* __restrict__ z,
                                                          const Cx<T>* __restrict__ twx,
                                                          const T* __restrict__ us,
                                                          const T* __restrict__ vs,
@@ -162,28 +174,28 @@ __global__ void __launch_bounds__(kBlock) k_rowifft_grad(const Cx<T>* __restrict
     Cx<T> tmp[kRowE3];
 #pragma unroll
     for (int k = 0; k < kRowE3; ++k) {
-      const int t = k * kBlock + (int)threadIdx.x;
+      const int t = k * blockDim.x + threadIdx.x;
       if (t < nr * nx) {
-        const int r = t / nx;
-        const int i = t - r * nx;
+        const int r = t >> log2nx;
+        const int i = t & (nx - 1);
         const int j = (j0 - 1 + r + ny) & (ny - 1);
         tmp[k] = zp[(size_t)j * nx + i];
       }
     }
 #pragma unroll
     for (int k = 0; k < kRowE3; ++k) {
-      const int t = k * kBlock + (int)threadIdx.x;
+      const int t = k * blockDim.x + threadIdx.x;
       if (t < nr * nx) P[t] = tmp[k];
     }
   }
   __syncthreads();
   lds_fft<T, kRowE3>(P, nx, log2nx, nr, nx, 1, +1, W);
 #pragma unroll
-  for (int k = 0; k < kRowE; ++k) {
-    const int t = k * kBlock + (int)threadIdx.x;
+  for (int k = 0; k < kRowE3; ++k) {
+    const int t = k * blockDim.x + threadIdx.x;
     if (t >= rows * nx) break;
-    const int r = t / nx;
-    const int i = t - r * nx;
+    const int r = t >> log2nx;
+    const int i = t & (nx - 1);
     const int j = j0 + r;
     const int im = (i - 1) & (nx - 1);
     const Cx<T> pc = P[(r + 1) * nx + i];
@@ -338,43 +350,54 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
     LDSV_LAUNCHED();
     return LDSV_OK;
   }
-  // passes 1 and 3: rows per block (a power of two dividing ny), at most
-  // kRowE * kBlock values in pass 1 and kRowE3 * kBlock (with the halo row)
-  // in pass 3
+  // pass 1: rows per block (a power of two dividing ny) for kRowE values
+  // per thread in blocks of 256 (512 for the longest rows)
   int rows = (kRowE * kBlock) / nx;
   if (rows < 1) rows = 1;
   if (rows > ny) rows = ny;
-  LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * kBlock &&
-                   (size_t)(rows + 1) * nx <= (size_t)kRowE3 * kBlock,
-               LDSV_ESHAPE, "project: nx=%d too large for the LDS row transform", nx);
+  const int block1 = rows * nx / kRowE > kBlock ? kRow1MaxBlock : kBlock;
+  LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * block1, LDSV_ESHAPE,
+               "project: nx=%d too large for the LDS row transform", nx);
   size_t lds = ((size_t)rows * nx + nx) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_div_rowfft<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
+  LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(block1), lds, st,
                (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
                h->log2nx, B, rows, idx, idy);
   LDSV_LAUNCHED();
-  // pass 2: up to 16 columns (128-byte row segments in FP32) within
-  // kColE * kBlock values and 64 KB of LDS
-  int cols = 16;
+  // pass 2: 8 columns (fewer when the column does not fit) within
+  // kColE * kColBlock values and 64 KB of LDS
+  int cols = 8;
   while (cols > 1 && ((size_t)cols * ny > (size_t)kColE * kColBlock || (size_t)cols * ny * cs > 65536))
     cols >>= 1;
   if (cols > nx) cols = nx;
   LDSV_REQUIRE((size_t)cols * ny <= (size_t)kColE * kColBlock && (size_t)cols * ny * cs <= 65536,
                LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
+  // 8 values per thread where the block allows it: twice the wavefronts of
+  // the minimum, to hide the latency of the transform's LDS round trips
+  int cblock = (int)(((size_t)cols * ny / 8 + 63) / 64 * 64);
+  if (cblock > kColBlock) cblock = kColBlock;
+  if (cblock < 64) cblock = 64;
   lds = ((size_t)cols * ny + ny) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_col_solve<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3(nx / cols, h->npairs), dim3(kColBlock), lds, st,
+  LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3((nx / cols) * h->npairs), dim3(cblock), lds, st,
                (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2ny,
-               cols);
+               __builtin_ctz((unsigned)cols));
   LDSV_LAUNCHED();
-  lds = ((size_t)(rows + 1) * nx + nx) * cs;
+  // pass 3: rows + 1 halo row per block of kRow3Block threads; more rows
+  // than pass 1 so the halo row costs less
+  int rows3 = 4096 / nx;
+  if (rows3 < 1) rows3 = 1;
+  if (rows3 > ny) rows3 = ny;
+  LDSV_REQUIRE((size_t)(rows3 + 1) * nx <= (size_t)kRowE3 * kRow3Block, LDSV_ESHAPE,
+               "project: nx=%d too large for the LDS row transform", nx);
+  lds = ((size_t)(rows3 + 1) * nx + nx) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_rowifft_grad<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows, h->npairs), dim3(kBlock), lds, st,
+  LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows3, h->npairs), dim3(kRow3Block), lds, st,
                (const Cx<T>*)h->zspec, (const Cx<T>*)h->twx, (const T*)us, (const T*)vs, (T*)uo,
-               (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows, idx, idy);
+               (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows3, idx, idy);
   LDSV_LAUNCHED();
   return LDSV_OK;
 }
