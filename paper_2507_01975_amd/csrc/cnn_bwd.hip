@@ -24,7 +24,6 @@ using namespace cnnk;
 
 constexpr int kChunk = 32;        // pixels per MFMA K step in wgrad
 constexpr int kTRow = kChunk + 8; // padded LDS row of transposed operands
-constexpr int kWgPix = 2048;      // pixels reduced per wgrad workgroup
 constexpr int kK = 9 * kC;        // 576 = (tap, ci) columns of dW
 
 // gout planar float [B][66][H][W] -> bf16 NHWC [P][96] (channels 66..95 zero)
@@ -58,7 +57,7 @@ __global__ void k_dgrad_weights(const uint16_t* __restrict__ W, uint16_t* __rest
 template <int MT, int CS>
 __global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ dz,
                                                   const uint16_t* __restrict__ x, PixMap pm,
-                                                  float* __restrict__ partial) {
+                                                  int wgpix, float* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) uint16_t gT[MT * 16 * kTRow];
   __shared__ __attribute__((aligned(16))) uint16_t xT[kK * kTRow];
   const int lane = threadIdx.x & 63;
@@ -69,8 +68,8 @@ __global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ d
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int n = 0; n < 9; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int p_begin = blockIdx.x * kWgPix;
-  const int p_end = min(p_begin + kWgPix, pm.total);
+  const int p_begin = blockIdx.x * wgpix;
+  const int p_end = min(p_begin + wgpix, pm.total);
   for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
     __syncthreads();
     for (int e = threadIdx.x; e < kChunk * MT * 16; e += blockDim.x) {
@@ -121,47 +120,87 @@ __global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ d
         out[(size_t)(m * 16 + kq * 4 + i) * kK + (wave * 9 + n) * 16 + col] = acc[m][n][i];
 }
 
-// dW[co][k] += sum over partials (fixed order); rows of partial = rows
+// dW[co][k] += sum over partials, in a fixed order (four interleaved
+// running sums, so that many loads of a thread are in flight, added
+// pairwise at the end); rows of partial = rows
 __global__ void k_partial_reduce(const float* __restrict__ partial, int nblk, int rows, int cout,
                                  int ncol, float* __restrict__ dW) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cout * ncol; e += gridDim.x * blockDim.x) {
     const int co = e / ncol, k = e % ncol;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partial[((size_t)b * rows + co) * ncol + k];
-    dW[e] += s;
+    const size_t stride = (size_t)rows * ncol;
+    const float* src = partial + (size_t)co * ncol + k;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[i & 3] += src[(size_t)(b + i) * stride];
+    }
+    for (; b < nblk; ++b) s[b & 3] += src[(size_t)b * stride];
+    dW[e] += (s[0] + s[1]) + (s[2] + s[3]);
   }
 }
 
-// bias gradient partials from bf16 NHWC cotangents (CS channels) or from the
-// float planar network-output cotangent (planar != 0, CS = 66)
-__global__ void k_bias_partial(const uint16_t* __restrict__ dz, const float* __restrict__ planar,
-                               int CS, int hw, int total, float* __restrict__ partial) {
-  // block b handles pixels [b * kWgPix, ...); thread t sums channel t
-  const int p_begin = blockIdx.x * kWgPix;
-  const int p_end = min(p_begin + kWgPix, total);
-  for (int c = threadIdx.x; c < CS; c += blockDim.x) {
-    float s = 0.f;
-    for (int p = p_begin; p < p_end; ++p) {
-      if (planar) {
-        const int b = p / hw, r = p - b * hw;
-        s += planar[((size_t)b * CS + c) * hw + r];
-      } else {
-        s += bf16_to_f32(dz[(size_t)p * CS + c]);
-      }
+// bias gradient partials from the bf16 NHWC cotangent of a 64-channel layer:
+// a workgroup sums kBiasPix pixels; thread t accumulates channels
+// 8 (t % 8) .. +7 (one 16-byte load per pixel) over pixels t / 8 + 32 k, and
+// the 32 pixel lanes are then added in a fixed order through LDS
+constexpr int kBiasPix = 512;
+__global__ void __launch_bounds__(kBlock) k_bias_partial(const uint16_t* __restrict__ dz,
+                                                         int total, float* __restrict__ partial) {
+  __shared__ float red[32][kC + 1];
+  const int q = threadIdx.x & 7, r = threadIdx.x >> 3;
+  const int p0 = blockIdx.x * kBiasPix;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int p = p0 + r; p < min(p0 + kBiasPix, total); p += 32) {
+    const uint4 v = *reinterpret_cast<const uint4*>(dz + (size_t)p * kC + q * 8);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s[2 * i] += bf16_to_f32((uint16_t)(w[i] & 0xffffu));
+      s[2 * i + 1] += bf16_to_f32((uint16_t)(w[i] >> 16));
     }
-    partial[(size_t)blockIdx.x * CS + c] = s;
   }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[r][q * 8 + i] = s[i];
+  __syncthreads();
+  if (threadIdx.x < kC) {
+    float t = 0.f;
+    for (int k = 0; k < 32; ++k) t += red[k][threadIdx.x];
+    partial[(size_t)blockIdx.x * kC + threadIdx.x] = t;
+  }
+}
+
+// the same for the float planar network-output cotangent [B][66][H][W]:
+// workgroup (x, c) sums pixels [x kBiasPix, ...) of channel c
+__global__ void __launch_bounds__(kBlock) k_bias_partial_planar(const float* __restrict__ g,
+                                                                int hw, int total,
+                                                                float* __restrict__ partial) {
+  __shared__ float red[kBlock];
+  const int c = blockIdx.y;
+  const int p0 = blockIdx.x * kBiasPix;
+  float s = 0.f;
+  for (int p = p0 + (int)threadIdx.x; p < min(p0 + kBiasPix, total); p += kBlock) {
+    const int b = p / hw, rr = p - b * hw;
+    s += g[((size_t)b * LDSV_NOUT + c) * hw + rr];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDSV_NOUT + c] = red[0];
 }
 
 // first layer: partial dW0[co][tap][ci] over a pixel range (VALU)
 __global__ void __launch_bounds__(kBlock) k_wgrad_first(const uint16_t* __restrict__ dz1,
                                                         const float* __restrict__ u,
                                                         const float* __restrict__ v, PixMap pm,
-                                                        float* __restrict__ partial) {
+                                                        int wgpix, float* __restrict__ partial) {
   __shared__ float sx[kChunk][18];
   __shared__ float sg[kChunk][kC];
-  const int p_begin = blockIdx.x * kWgPix;
-  const int p_end = min(p_begin + kWgPix, pm.total);
+  const int p_begin = blockIdx.x * wgpix;
+  const int p_end = min(p_begin + wgpix, pm.total);
   // thread owns outputs e = threadIdx.x + k * 256 (< 64 * 18 = 1152)
   float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
@@ -230,12 +269,20 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
                              const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
                              hipStream_t st) {
   const size_t P = h->nstate;
-  const int nwg = (int)((P + kWgPix - 1) / kWgPix);
+  // weight-gradient workgroups: about one per CU, each reducing a range of
+  // whole 32-pixel chunks
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int wgpix = (int)(((P + ncu - 1) / ncu + kChunk - 1) / kChunk * kChunk);
+  const int nwg = (int)((P + wgpix - 1) / wgpix);
+  const int nbias = (int)((P + kBiasPix - 1) / kBiasPix);
+  const int npart = nwg > nbias ? nwg : nbias;
   // workspace: 5 pre-activation planes (float NHWC 64), G (bf16 96), two dz
   // buffers (bf16 64), W' (bf16 64 x 9 x 96), wgrad partials
   if (!h->zpre_blk) {
     const size_t bytes = 5 * P * kC * 4 + P * 96 * 2 + 2 * P * kC * 2 + (size_t)kC * 9 * 96 * 2 +
-                         (size_t)nwg * 80 * kK * 4 + 256;
+                         (size_t)npart * 80 * kK * 4 + 256;
     LDSV_TRY(ldsv_alloc(h, &h->zpre_blk, bytes, "network backward workspace"));
   }
   char* w = (char*)h->zpre_blk;
@@ -254,14 +301,15 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   // forward recompute with pre-activations
   LDSV_TRY(ldsv_launch_cnn(h, net, u, v, h->netout, zpre, st));
   // layer 6: bias from the float cotangent, G = bf16 NHWC copy
-  hipLaunchKernelGGL(k_bias_partial, dim3(nwg), dim3(128), 0, st, (const uint16_t*)nullptr, gout,
-                     LDSV_NOUT, hw, (int)P, part);
-  hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(128), 0, st, part, nwg, LDSV_NOUT, LDSV_NOUT,
-                     1, dW->b[5]);
+  hipLaunchKernelGGL(k_bias_partial_planar, dim3(nbias, LDSV_NOUT), dim3(kBlock), 0, st, gout, hw,
+                     (int)P, part);
+  hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(128), 0, st, part, nbias, LDSV_NOUT,
+                     LDSV_NOUT, 1, dW->b[5]);
   hipLaunchKernelGGL(k_gout_to_nhwc, grid1d(P * 96), dim3(kBlock), 0, st, gout, G, hw, (int)P);
   LDSV_LAUNCHED();
   {
-    LDSV_TLAUNCH(h, 4, (k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, part);
+    LDSV_TLAUNCH(h, 4, (k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, wgpix,
+                 part);
   }
   LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)LDSV_NOUT * kK), dim3(kBlock), 0, st, part,
                      nwg, 80, LDSV_NOUT, kK, dW->w[5]);
@@ -277,13 +325,11 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   uint16_t* dzn = dzB;
   // layers 5..2 (index 4..1): dz is the cotangent of layer index li's pre-activation
   for (int li = 4; li >= 1; --li) {
-    LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC,
-                       hw, (int)P, part);
-    LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[li]);
-    {
-      LDSV_TLAUNCH(h, 4, (k_wgrad<4, 64>), dim3(nwg), dim3(kBlock), 0, st, dz, h->act[li - 1], pm,
-                         part);
-    }
+    LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nbias), dim3(kBlock), 0, st, dz, (int)P, part);
+    LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nbias, kC, kC, 1,
+                 dW->b[li]);
+    LDSV_TLAUNCH(h, 4, (k_wgrad<4, 64>), dim3(nwg), dim3(kBlock), 0, st, dz, h->act[li - 1], pm,
+                 wgpix, part);
     LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)kC * kK), dim3(kBlock), 0, st, part, nwg,
                        64, kC, kK, dW->w[li]);
     LDSV_TLAUNCH(h, 7, k_dgrad_weights, grid1d((size_t)kC * 9 * 64), dim3(kBlock), 0, st,
@@ -299,10 +345,9 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
     dzn = t;
   }
   // layer 1
-  LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nwg), dim3(64), 0, st, dz, (const float*)nullptr, kC, hw,
-                     (int)P, part);
-  LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nwg, kC, kC, 1, dW->b[0]);
-  LDSV_TLAUNCH(h, 7, k_wgrad_first, dim3(nwg), dim3(kBlock), 0, st, dz, u, v, pm, part);
+  LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nbias), dim3(kBlock), 0, st, dz, (int)P, part);
+  LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nbias, kC, kC, 1, dW->b[0]);
+  LDSV_TLAUNCH(h, 7, k_wgrad_first, dim3(nwg), dim3(kBlock), 0, st, dz, u, v, pm, wgpix, part);
   LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)kC * 18), dim3(kBlock), 0, st, part, nwg,
                      kC * 18, kC * 18, 1, dW->w[0]);
   LDSV_LAUNCHED();
