@@ -96,12 +96,14 @@ class Adam:
 
 
 def train(solver, net, labels, prm, iters, unroll=32, checkpoint_every=8, lr=1e-4, seed=0,
-          batch_from=None, progress=None, log_every=10):
-    """Adam on the unrolled rollout MSE.  labels: (lu, lv) [T+1, B, n, n] with
-    the solver's batch B.  Each iteration starts from labels[t0] at a random
-    t0 and unrolls `unroll` learned steps.  Returns the loss history."""
+          batch_from=None, progress=None, log_every=10, windows=1):
+    """Adam on the unrolled rollout MSE.  labels: (lu, lv) [T+1, B, n, n].
+    Each iteration draws `windows` random start times t0 and unrolls `unroll`
+    learned steps from labels[t0] for every trajectory of every window at
+    once; the solver's batch is windows * B.  Returns the loss history."""
     lu, lv = labels
     T = lu.shape[0] - 1
+    assert solver.batch == windows * lu.shape[1], "solver batch must be windows * label batch"
     g = torch.Generator().manual_seed(seed)
     opt = Adam(net, lr=lr)
     dW = ldsv.NetGradBuffers(net)
@@ -109,14 +111,15 @@ def train(solver, net, labels, prm, iters, unroll=32, checkpoint_every=8, lr=1e-
     hist = []
     t_start = time.perf_counter()
     for it in range(iters):
-        t0 = int(torch.randint(0, T - unroll + 1, (1,), generator=g))
+        t0s = [int(x) for x in torch.randint(0, T - unroll + 1, (windows,), generator=g)]
+        u0 = torch.cat([lu[t] for t in t0s]).contiguous()
+        v0 = torch.cat([lv[t] for t in t0s]).contiguous()
+        yu = torch.cat([lu[t + 1:t + 1 + unroll] for t in t0s], dim=1).contiguous()
+        yv = torch.cat([lv[t + 1:t + 1 + unroll] for t in t0s], dim=1).contiguous()
         dW.zero_()
         loss.zero_()
-        solver.rollout_bwd(prm, net, lu[t0].contiguous(), lv[t0].contiguous(), unroll, dW,
-                           checkpoint_every=checkpoint_every, first_index=1,
-                           labels=(lu[t0 + 1:t0 + 1 + unroll].contiguous(),
-                                   lv[t0 + 1:t0 + 1 + unroll].contiguous()),
-                           loss_scale=1.0 / unroll, loss=loss)
+        solver.rollout_bwd(prm, net, u0, v0, unroll, dW, checkpoint_every=checkpoint_every,
+                           first_index=1, labels=(yu, yv), loss_scale=1.0 / unroll, loss=loss)
         opt.step(dW)
         if (it + 1) % log_every == 0 or it == 0:
             l = loss.item()
@@ -231,8 +234,9 @@ def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi):
 
 
 def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, test_batch=4,
-                train_fine_steps=10000, warmup_fine=4000, horizon=300, iters=400, unroll=16,
-                lr=1e-4, speed_batch=64, speed_steps=40, progress=None, seeds=(100, 200)):
+                train_fine_steps=10000, warmup_fine=4000, horizon=600, iters=600, unroll=16,
+                windows=4, lr=1e-4, speed_batch=64, speed_steps=40, progress=None,
+                seeds=(100, 200)):
     """The forced-flow measurement: train the 64^2 learned solver on labels
     down-sampled from fine plain FV, then on held-out seeds find T_0.9 (time
     until the vorticity PCC against the down-sampled fine reference first
@@ -252,11 +256,13 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
                                   ic_resolutions=tuple(N for N in sweep if N != n))
     log("labels ready (%.1f s)" % (time.perf_counter() - t0))
     net = init_network(seed=0)
-    st = ldsv.Solver(n, n, train_batch)
+    t_tr0 = time.perf_counter()
+    st = ldsv.Solver(n, n, train_batch * windows)
     prm = ldsv.params(dt=dtc, k_c=1, fallback_enable=0, **phys)
     hist = train(st, net, lab_tr, prm, iters=iters, unroll=unroll, checkpoint_every=8, lr=lr,
-                 progress=log, log_every=50)
+                 progress=log, log_every=50, windows=windows)
     st.close()
+    t_train = time.perf_counter() - t_tr0
     log("trained (%.1f s)" % (time.perf_counter() - t0))
     se = ldsv.Solver(n, n, test_batch)
     ev = evaluate(se, prm, lab_te, horizon, net=net)
@@ -282,6 +288,8 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
                        "plain FV down-sampled %dx (%d trajectories, %d fine steps each)"
                        % (n, fine_n, r, train_batch, train_fine_steps),
            "horizon_s": horizon * dtc, "t09_s": t09, "test_trajectories": test_batch,
+           "training": {"iters": iters, "unroll": unroll, "windows_per_iter": windows,
+                        "lr": lr, "seconds": t_train},
            "final_train_loss": hist[-1][1], "initial_train_loss": hist[0][1],
            "learned": {"n": n, "batch": speed_batch, "cell_steps_per_s": cs_l,
                        "sim_time_per_s": st_l, "ms_per_step": ms_l},
