@@ -43,10 +43,36 @@ BF16_PEAK_TFLOPS = 2500.0
 STAGE_BYTES = {0: (24 + 40 + 40 + 32) / 4.0, 1: 12.0, 2: 8.0, 3: 20.0}
 CLASS_NAMES = {0: "k_stage_mac (fused residual + RK stage)", 1: "k_div_rowfft",
                2: "k_col_solve", 3: "k_rowifft_grad"}
+KERNEL_KEYS = {0: "k_stage_mac", 1: "k_div_rowfft", 2: "k_col_solve", 3: "k_rowifft_grad"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "hbm_traffic_decaying512.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, copy-calibrated), or None when the
+    summary is missing or the kernel's sources changed since it was taken
+    (the summary records a hash of those sources)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)["kernels"][kernel]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def cpu_baseline(w, u0, v0, budget_s=10.0):
@@ -199,7 +225,8 @@ def main():
     achieved = alg / avg_s / 1e9
     roof = {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6,
+            "traffic": measured_traffic(KERNEL_KEYS[dom]), "traffic_unit": "bytes per launch",
+            "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6,
             "classes_ms_per_step": {CLASS_NAMES[c]: cls[c][0] / a.steps for c in cls},
             "instrumented_ms_per_step": 1e3 * t_inst / a.steps}
     line = {"metric": "cell-steps/s + sim-time/s at corr>=0.9: learned coarse FV vs plain fine FV",

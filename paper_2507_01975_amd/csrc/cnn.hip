@@ -12,13 +12,17 @@
 //   B (32 x 16): activations X[pixel + tap][ci], 8 contiguous bf16 per lane
 //   D (16 x 16): lane l holds channels 4(l/16)..+3 of pixel l%16, so a lane
 //                stores 4 consecutive channels (8 bytes) of one NHWC pixel.
-// A workgroup (4 wavefronts) owns 256 consecutive pixels and every output
-// channel; per tap it stages that tap's weight slice in LDS (rows padded to
-// 144 bytes so the 16 rows a fragment read touches fall in distinct banks),
-// and each wavefront multiplies it against its 4 pixel tiles.  Activation
-// fragments come straight from global memory (the 9 taps re-read each pixel
-// from L1/L2).  FP32 accumulation; bias, GELU and bf16 rounding (round to
-// nearest even) in the epilogue.
+// Kernels (cnn_common.h):
+//   k_conv3x3_dma   64-output layers on grids whose sides are multiples of
+//                   16: persistent, weights and two 16 x 16 halo tiles in LDS
+//                   (tiles loaded straight to LDS, double-buffered)
+//   k_conv3x3_tile  the 66-output last layer on such grids (80 padded rows)
+//   k_conv3x3_mfma  any grid: 256 pixels per workgroup, the weight slice of
+//                   each tap staged in LDS, activation fragments read from
+//                   global memory (L1/L2), also the 96-channel data gradient
+//                   of the last layer in the backward pass
+// FP32 accumulation; bias, GELU and bf16 rounding (round to nearest even) in
+// the epilogue.
 //
 // Layer 1 (2 input channels, K = 18) is a single zero-padded K = 32 step of
 // the same instruction with the im2col gather done in registers.
@@ -166,33 +170,36 @@ int ldsv_launch_conv_tile(ldsv_handle* h, int mt, int epi, const uint16_t* X, co
                           const float* bias, int cout, uint16_t* Y, float* zio, float* out,
                           hipStream_t st) {
   PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
-  const int ntiles = (int)(h->nstate / 256);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int ntiles = (int)(h->nstate / 256);
   const int grid = ntiles < ncu ? ntiles : ncu;
-  if (mt == 4 && epi == 0) {
-    const size_t lds = conv_tile_lds_bytes<4>();
-    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<4, 0>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 0>), dim3(grid), dim3(kConvBlock), lds, st, X, W, bias, cout,
-                 pm, Y, zio, out);
-  } else if (mt == 4 && epi == 2) {
-    const size_t lds = conv_tile_lds_bytes<4>();
-    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<4, 2>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<4, 2>), dim3(grid), dim3(kConvBlock), lds, st, X, W, bias, cout,
-                 pm, Y, zio, out);
-  } else if (mt == 5 && epi == 1) {
-    const size_t lds = conv_tile_lds_bytes<5>();
-    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<5, 1>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<5, 1>), dim3(grid), dim3(kConvBlock), lds, st, X, W, bias, cout,
-                 pm, Y, zio, out);
-  } else {
+#define LDSV_CONV_TILE(MT_, EPI_, TW_)                                                          \
+  {                                                                                            \
+    const size_t lds = conv_tile_lds_bytes<MT_, TW_>();                                        \
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_tile<MT_, EPI_, TW_>,                   \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_tile<MT_, EPI_, TW_>), dim3(grid), dim3(kConvBlock), lds, st, \
+                 X, W, bias, cout, pm, Y, zio, out);                                           \
+  }
+#define LDSV_CONV_DMA(EPI_)                                                                   \
+  {                                                                                          \
+    const size_t lds = conv_dma_lds_bytes();                                                 \
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_dma<EPI_>,                            \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));     \
+    LDSV_TLAUNCH(h, 4, (k_conv3x3_dma<EPI_>), dim3(grid), dim3(kConvBlock), lds, st, X, W,    \
+                 bias, pm, Y, zio);                                                          \
+  }
+  if (mt == 4 && epi == 0 && cout == kC) LDSV_CONV_DMA(0)
+  else if (mt == 4 && epi == 2 && cout == kC) LDSV_CONV_DMA(2)
+  else if (mt == 5 && epi == 1) LDSV_CONV_TILE(5, 1, 16)
+  else {
     ldsv_set_error("conv tile: unsupported configuration");
     return LDSV_EINVAL;
   }
+#undef LDSV_CONV_TILE
+#undef LDSV_CONV_DMA
   LDSV_LAUNCHED();
   return LDSV_OK;
 }

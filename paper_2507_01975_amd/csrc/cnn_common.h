@@ -188,33 +188,39 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restr
 }
 
 // The same convolution for grids whose sides are multiples of 16, as a
-// persistent kernel: a workgroup first stages the layer's whole weight
-// matrix (cout x 576 bf16, rows padded to 1168 bytes) in LDS, then loops
-// over 16 x 16 pixel tiles; for each tile it stages the tile with its
-// 1-pixel periodic halo (18 x 18 pixels x 64 channels, rows padded to 144
-// bytes) and runs all 9 taps from LDS.  Both paddings put the 16 rows that
-// one fragment read touches in distinct LDS banks.  LDS: 122 KB (64 outputs)
-// or 140 KB (80 padded outputs), one workgroup per CU.
+// persistent kernel (used for the 66-output last layer; the 64-output layers
+// use k_conv3x3_dma below): a workgroup first stages the layer's whole weight
+// matrix (cout padded to 16 MT rows x 576 bf16, rows padded to 1168 bytes) in
+// LDS, then loops over 16-row pixel tiles TW pixels wide; for each tile it
+// stages the tile with its 1-pixel periodic halo (18 x (TW + 2) pixels x 64
+// channels, rows padded to 144 bytes) and runs all 9 taps from LDS.  Both
+// paddings put the rows that one fragment read touches in distinct LDS
+// banks.  LDS: 137 KB for 80 padded outputs and 16-wide tiles, one
+// workgroup per CU.  (32-wide tiles, which halve the weight-fragment traffic
+// per pixel, need more than the 256 registers two wavefronts per SIMD allow
+// and were slower.)
 //
 // Eight wavefronts, wavefront w computing tile rows 2w and 2w+1 for every
-// output channel.  The epilogue (GELU on every output, bf16 rounding) costs
-// more vector-ALU time than the tile's matrix-core time, so the wavefronts
-// are split into two groups that share each SIMD (w and w + 4 run on the
-// same SIMD): group 0 accumulates tile k and then runs its epilogue, group 1
-// first runs the epilogue of tile k-1 (its accumulators carried across the
-// tile barrier) and then accumulates tile k.  On every SIMD one wavefront's
-// MFMAs overlap the other's vector work.
+// output channel.  The epilogue (bias-initialised accumulators, bf16
+// rounding, and GELU in the hidden layers) costs vector-ALU time comparable
+// to the tile's matrix-core time, so the wavefronts are split into two groups
+// that share each SIMD (w and w + 4 run on the same SIMD): group 0
+// accumulates tile k and then runs its epilogue, group 1 first runs the
+// epilogue of tile k-1 (its accumulators carried across the tile barrier) and
+// then accumulates tile k.  On every SIMD one wavefront's MFMAs overlap the
+// other's vector work.
 constexpr int kConvBlock = 512;
 constexpr int kWRowAll = 9 * kC + 8;   // padded weight row (bf16 elements)
 constexpr int kTileRow = kC + 8;       // padded tile pixel row
-constexpr int kTileH = 18;
+constexpr int kTileH = 18;             // 16 rows + halo
 
-template <int MT>
+// TW: tile width in pixels (16 or 32); the staged tile is 18 x (TW + 2)
+template <int MT, int TW>
 constexpr size_t conv_tile_lds_bytes() {
-  return (size_t)(MT * 16 * kWRowAll + kTileH * kTileH * kTileRow) * 2;
+  return (size_t)(MT * 16 * kWRowAll + kTileH * (TW + 2) * kTileRow) * 2;
 }
 
-template <int MT, int EPI>
+template <int MT, int EPI, int TW>
 __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __restrict__ X,
                                                              const uint16_t* __restrict__ Wt,
                                                              const float* __restrict__ bias,
@@ -230,7 +236,10 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
   const int grp = wave >> 2;
   const int col = lane & 15;
   const int kq = lane >> 4;
-  const int tiles_x = pm.W / 16, tiles_y = pm.H / 16;
+  constexpr int kTW = TW + 2;        // staged tile width
+  constexpr int kNX = TW / 16;       // 16-pixel groups per tile row
+  constexpr int NT = 2 * kNX;        // pixel tiles of 16 per wavefront
+  const int tiles_x = pm.W / TW, tiles_y = pm.H / 16;
   const int ntiles = (pm.total / (pm.H * pm.W)) * tiles_x * tiles_y;
   const int hw = pm.H * pm.W;
   // whole weight matrix, once; loads are issued in batches before the LDS
@@ -259,27 +268,28 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
   // the tile with its halo is loaded into registers one tile ahead (the
   // loads of tile k+1 are in flight while tile k is computed), then stored
   // to LDS between two barriers
-  constexpr int kTChunks = kTileH * kTileH * (kC / 8);
+  constexpr int kTChunks = kTileH * kTW * (kC / 8);
   constexpr int kTPer = (kTChunks + kConvBlock - 1) / kConvBlock;
   uint4 tv[kTPer];
   auto load_tile = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y);
     const int tr = tile - b * tiles_x * tiles_y;
-    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * TW;
 #pragma unroll
     for (int k = 0; k < kTPer; ++k) {
       const int e = k * kConvBlock + (int)threadIdx.x;
       tv[k] = uint4{0u, 0u, 0u, 0u};
       if (e < kTChunks) {
         const int px = e / (kC / 8), q = e - px * (kC / 8);
-        const int ry = px / kTileH, rx = px - ry * kTileH;
+        const int ry = px / kTW, rx = px - ry * kTW;
         const int gy = (y0 - 1 + ry) & (pm.H - 1), gx = (x0 - 1 + rx) & (pm.W - 1);
         tv[k] = *reinterpret_cast<const uint4*>(X + ((size_t)b * hw + gy * pm.W + gx) * kC + q * 8);
       }
     }
   };
-  f32x4 acc[2][MT];
-  // accumulate the staged tile: rows 2 wave + t, bias-initialised (EPI 0, 1)
+  f32x4 acc[NT][MT];
+  // accumulate the staged tile: pixel tile t covers row 2 wave + t / kNX,
+  // columns 16 (t % kNX) .. +15; bias-initialised (EPI 0, 1)
   auto mma = [&]() {
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -292,7 +302,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
         }
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) acc[t][m] = b0;
+      for (int t = 0; t < NT; ++t) acc[t][m] = b0;
     }
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
@@ -300,18 +310,18 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const int cbase = half * 32 + kq * 8;
-        bf16x8 bfrag[2];
+        bf16x8 bfrag[NT];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int ry = wave * 2 + t + 1 + dy, rx = col + 1 + dx;
-          bfrag[t] = *reinterpret_cast<const bf16x8*>(xt + (ry * kTileH + rx) * kTileRow + cbase);
+        for (int t = 0; t < NT; ++t) {
+          const int ry = wave * 2 + t / kNX + 1 + dy, rx = (t % kNX) * 16 + col + 1 + dx;
+          bfrag[t] = *reinterpret_cast<const bf16x8*>(xt + (ry * kTW + rx) * kTileRow + cbase);
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(
               wl + (m * 16 + col) * kWRowAll + tap * kC + cbase);
 #pragma unroll
-          for (int t = 0; t < 2; ++t)
+          for (int t = 0; t < NT; ++t)
             acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[t][m], 0, 0, 0);
         }
       }
@@ -320,10 +330,10 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
   auto epilogue = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y);
     const int tr = tile - b * tiles_x * tiles_y;
-    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * TW;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int y = y0 + wave * 2 + t, x = x0 + col;
+    for (int t = 0; t < NT; ++t) {
+      const int y = y0 + wave * 2 + t / kNX, x = x0 + (t % kNX) * 16 + col;
       const int r = y * pm.W + x;
       const size_t p = (size_t)b * hw + r;
 #pragma unroll
@@ -375,6 +385,158 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
     mma();
     if (grp == 0) epilogue(tile);
     prev = tile;
+  }
+  if (grp == 1 && prev >= 0) epilogue(prev);
+}
+
+// The 64-output layers (and their data gradients) with the tiles brought
+// into LDS by the load-to-LDS path (global_load_lds_dwordx4: each lane's 16
+// bytes go straight to LDS at the instruction's base + 16 x lane, no
+// registers), double-buffered: while tile k is multiplied, tile k+1 is in
+// flight.  Without the register staging of k_conv3x3_tile the loads of a
+// tile overlap all of the previous tile's work and the loop needs one
+// barrier per tile.  Eight wavefronts, rows 2w and 2w+1 of the tile each, in
+// the same two phase-shifted groups as k_conv3x3_tile.  The LDS rows are not
+// padded (two tiles and the weights must fit in 160 KB): 16-byte chunk c of
+// row r sits at chunk position c ^ (r & 7), which spreads the 8 rows of every
+// fragment read over all banks; the load-to-LDS path writes chunk positions
+// in lane order, so the swizzle is applied to the source addresses.
+// LDS: 72 KB weights + 2 x 40.5 KB tiles.
+constexpr int kDmaTile = 18 * 18 * kC;  // bf16 elements per staged tile
+
+constexpr size_t conv_dma_lds_bytes() { return (size_t)(kC * 9 * kC + 2 * kDmaTile) * 2; }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int EPI>
+__global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __restrict__ X,
+                                                            const uint16_t* __restrict__ Wt,
+                                                            const float* __restrict__ bias,
+                                                            PixMap pm, uint16_t* __restrict__ Y,
+                                                            float* __restrict__ zio) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
+  uint16_t* wl = lds_u16;                   // [64][576], swizzled chunks
+  uint16_t* xbuf = lds_u16 + kC * 9 * kC;   // two tiles [18 * 18][64], swizzled
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int grp = wave >> 2;
+  const int col = lane & 15;
+  const int kq = lane >> 4;
+  const int tiles_x = pm.W / 16, tiles_y = pm.H / 16;
+  const int ntiles = (pm.total / (pm.H * pm.W)) * tiles_x * tiles_y;
+  const int hw = pm.H * pm.W;
+  // weights: slot (row, pos) receives logical chunk pos ^ (row & 7);
+  // 64 x 72 chunks = 72 instructions of 64 lanes, 9 per wavefront
+  for (int i = wave; i < kC * 72 / 64; i += kConvBlock / 64) {
+    const int e = i * 64 + lane;
+    const int row = e / 72, pos = e - row * 72;
+    const int c = pos ^ (row & 7);
+    __builtin_amdgcn_global_load_lds((const void*)(Wt + ((size_t)row * 72 + c) * 8),
+                                     (lds_void*)(wl + (size_t)i * 64 * 8), 16, 0, 0);
+  }
+  // tile t into buffer s: 18 x 18 pixels x 8 chunks = 2592 slots, 40.5
+  // instructions of 64 lanes over the 8 wavefronts (lanes past the end idle)
+  constexpr int kTChunks = 18 * 18 * 8;
+  constexpr int kTInst = (kTChunks + 63) / 64;
+  auto issue_tile = [&](int tile, int sbuf) {
+    const int b = tile / (tiles_x * tiles_y);
+    const int tr = tile - b * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+    uint16_t* dst = xbuf + sbuf * kDmaTile;
+    for (int i = wave; i < kTInst; i += kConvBlock / 64) {
+      const int e = i * 64 + lane;
+      if (e < kTChunks) {
+        const int px = e >> 3, pos = e & 7;
+        const int ry = px / 18, rx = px - ry * 18;
+        const int gy = (y0 - 1 + ry) & (pm.H - 1), gx = (x0 - 1 + rx) & (pm.W - 1);
+        const int q = pos ^ (px & 7);
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(X + ((size_t)b * hw + gy * pm.W + gx) * kC + q * 8),
+            (lds_void*)(dst + (size_t)i * 64 * 8), 16, 0, 0);
+      }
+    }
+  };
+  f32x4 acc[2][4];
+  auto mma = [&](const uint16_t* xt) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (EPI != 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b0[i] = bias[m * 16 + kq * 4 + i];
+      }
+      acc[0][m] = b0;
+      acc[1][m] = b0;
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int q = half * 4 + kq;
+        bf16x8 bfrag[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int px = (wave * 2 + t + 1 + dy) * 18 + col + 1 + dx;
+          bfrag[t] = *reinterpret_cast<const bf16x8*>(xt + px * kC + ((q ^ (px & 7)) << 3));
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int row = m * 16 + col;
+          const int c = tap * 8 + q;
+          const bf16x8 afrag =
+              *reinterpret_cast<const bf16x8*>(wl + row * 576 + ((c ^ (row & 7)) << 3));
+          acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[0], acc[0][m], 0, 0, 0);
+          acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[1], acc[1][m], 0, 0, 0);
+        }
+      }
+    }
+  };
+  auto epilogue = [&](int tile) {
+    const int b = tile / (tiles_x * tiles_y);
+    const int tr = tile - b * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const size_t p = (size_t)b * hw + (size_t)(y0 + wave * 2 + t) * pm.W + x0 + col;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int c0 = m * 16 + kq * 4;
+        float h[4];
+        if (EPI == 2) {
+          const float4 zi = *reinterpret_cast<const float4*>(zio + p * kC + c0);
+          const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = acc[t][m][i] * gelu_grad(zz[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) h[i] = gelu_exact(acc[t][m][i]);
+        }
+        uint2 pk;
+        pk.x = pack_bf16x2(h[0], h[1]);
+        pk.y = pack_bf16x2(h[2], h[3]);
+        *reinterpret_cast<uint2*>(Y + p * kC + c0) = pk;
+        if (EPI == 0 && zio)
+          *reinterpret_cast<float4*>(zio + p * kC + c0) =
+              float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
+      }
+    }
+  };
+  int sbuf = 0;
+  if ((int)blockIdx.x < ntiles) issue_tile(blockIdx.x, 0);
+  int prev = -1;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // this wavefront's loads of the current tile (and, the first time, of
+    // the weights) have landed; after the barrier everyone's have, and every
+    // wavefront is done reading the other buffer
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) issue_tile(tile + gridDim.x, sbuf ^ 1);
+    if (grp == 1 && prev >= 0) epilogue(prev);
+    mma(xbuf + sbuf * kDmaTile);
+    if (grp == 0) epilogue(tile);
+    prev = tile;
+    sbuf ^= 1;
   }
   if (grp == 1 && prev >= 0) epilogue(prev);
 }

@@ -259,3 +259,30 @@ def test_error_paths():
     c = L_.Solver(16, 16, 1, layout=L_.COLLOCATED)
     with pytest.raises(L_.LdsvError):
         c.project(c.new_state(), c.new_state())
+
+
+@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048)])
+def test_projection_extreme_aspect_fp32(nx, ny):
+    """The longest rows and columns the FP32 MAC grid allows (2048): the row
+    passes switch to 512-thread blocks with one row each, the column pass to
+    4-column blocks."""
+    L_ = need_gpu()
+    announce("project extreme", nx, ny)
+    u, v = _fields(9, 1, ny, nx, torch.float32)
+    s = L_.Solver(nx, ny, 1)
+    gu, gv = dev(u, torch.float32), dev(v, torch.float32)
+    p = s.project(gu, gv, want_p=True)
+    prm = oracle_prm(nx, ny)
+    eu, ev, ep = projection.project(u, v, prm)
+    # FP32 transform roundoff in p, about eps sqrt(log2 N) rms(p) spread over
+    # all wavenumbers, reaches u through G, which amplifies the highest ones
+    # by up to 2 / min(dx, dy): at this aspect ratio that bound exceeds the
+    # 1e-5 of the step tests
+    eps = 6e-8
+    hmin = min(L / nx, L / ny)
+    rms = lambda t: t.pow(2).mean().sqrt().item()
+    bound = 2 * eps * math.sqrt(math.log2(nx * ny)) * (2 / hmin) * rms(ep) / min(rms(u), rms(v))
+    tol = max(1e-5, bound)
+    print("extreme-aspect projection tolerance %.3g" % tol)
+    assert rel_l2(gu, eu) < tol and rel_l2(gv, ev) < tol
+    assert rel_l2(p, ep) < 1e-5

@@ -206,3 +206,34 @@ def test_bf16_conversion_rounds_to_nearest_even():
     o1 = torch.empty(1, dtype=torch.int16, device="cuda")
     L_._check(L_._lib.ldsv_to_bf16(L_._ptr(nan), L_._ptr(o1), 1, L_._stream()))
     assert torch.isnan(o1.cpu().view(torch.bfloat16).float()).all()
+
+
+def test_kolmogorov64_full_size_learned_step():
+    """The learned step at the benchmark's inference configuration (64^2,
+    batch 64, the forced-flow parameters and time step), in the launch
+    configuration the benchmark times; trajectories 0, 31 and 63 are checked
+    against the oracle given the device's network output, and the network
+    output of trajectory 63 against the bf16-emulating oracle network."""
+    L_ = need_gpu()
+    announce("kolmogorov64 learned step")
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    net, wb, bb = _net(L_, seed=0)
+    s = L_.Solver(n, n, B)
+    gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=200)
+    kw = dict(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"], forcing_k=w["forcing_k"],
+              drag=w["drag"])
+    uo, vo, no = s.learned_fv_step(L_.params(k_c=1, **kw), net, gu, gv, 1, want_net_out=True)
+    oprm = oracle_prm(n, n, k_c=1, **kw)
+    from oracle.projection import project
+    for b in (0, 31, B - 1):
+        u0, v0 = cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1])
+        out = cpu64(no[b:b + 1])
+        eu, ev = timestep.fv_step(u0, v0, oprm, learned.constrain(out[:, :64]))
+        eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
+        assert rel_l2(uo[b:b + 1], eu) < 1e-5 and rel_l2(vo[b:b + 1], ev) < 1e-5, b
+    x = torch.stack([cpu64(gu[B - 1:B]), cpu64(gv[B - 1:B])], dim=1)
+    ref = cnn.cnn_forward(x, wb, bb, bf16=True)
+    assert rel_l2(no[B - 1:B], ref) < 5e-3
+    d = s.diagnostics(uo, vo).cpu()
+    assert (d[:, 5] == 1).all()
