@@ -19,6 +19,10 @@ The line also carries
 * cpu_baseline: the FP64 CPU oracle timed on this host on a bounded sample
   of the same workload (the full batch, as many steps as fit in ~10 s);
 * learned: the learned step (64^2, batch 64, BF16 CNN on MFMA);
+* streaming: the plain step at 1024^2 x 128 (a state far larger than the
+  last-level cache) with its own roofline record;
+* burgers64: microseconds per step of the FP64 Burgers configuration,
+  eager and as a captured HIP graph;
 * corr: the accuracy-matched comparison of the metric on forced Kolmogorov
   flow: the learned 64^2 solver is trained (Adam through the hand-written
   adjoint) on labels from 1024^2 plain FV down-sampled 16x; on held-out seeds
@@ -147,6 +151,93 @@ def learned_block(steps, warmup):
     return out
 
 
+def burgers_block(repeats=7):
+    """The 2D viscous Burgers configuration (64^2, FP64, collocated, SSP-RK3,
+    dt from CFL 0.5, 200 steps): microseconds per step, eager launches and a
+    captured HIP graph of the whole 200-step call (median of `repeats`).  The
+    state is 64 KB, so this is launch latency, not bandwidth."""
+    import statistics
+    import torch
+    import synthetic_inputs as si
+    from paper_2507_01975_amd import ldsv
+    w = si.WORKLOADS["burgers64"]
+    n, steps = w["nx"], w["steps"]
+    s = ldsv.Solver(n, n, 1, dtype=torch.float64, layout=ldsv.COLLOCATED)
+    u0, v0 = s.init_state(ldsv.IC_FOURIER_MODES, seed=0)
+    prm = ldsv.params(nu=w["nu"], dt=s.cfl_dt(u0, v0, w["cfl"]), rk=ldsv.SSPRK3)
+    u, v = torch.empty_like(u0), torch.empty_like(v0)
+    s.fv_step(prm, u0, v0, nsteps=steps, out=(u, v))
+    torch.cuda.synchronize()
+    ref = (u.clone(), v.clone())
+    eager = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        s.fv_step(prm, u0, v0, nsteps=steps, out=(u, v))
+        torch.cuda.synchronize()
+        eager.append(time.perf_counter() - t0)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        s.fv_step(prm, u0, v0, nsteps=steps, out=(u, v))
+    torch.cuda.synchronize()
+    graph, same = [], True
+    for _ in range(repeats):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        graph.append(time.perf_counter() - t0)
+        same = same and torch.equal(u, ref[0]) and torch.equal(v, ref[1])
+    return {"workload": "burgers64 (64^2, FP64, collocated, SSP-RK3, 200 steps)",
+            "us_per_step_eager": 1e6 * statistics.median(eager) / steps,
+            "us_per_step_graph": 1e6 * statistics.median(graph) / steps,
+            "graph_replays_match_eager": bool(same)}
+
+
+def streaming_block(steps=10, warmup=2):
+    """The plain step at a shape whose state does not fit the 256 MB
+    last-level cache: 1024^2 x 128 trajectories (the fine grid of the shear
+    configuration, 537 MB per field), FP32, RK4 with a projection per
+    sub-step.  Throughput, then per-class event-timed launch durations and
+    the dominant class against the HBM roofline."""
+    import torch
+    from paper_2507_01975_amd import ldsv
+    n, B = 1024, 128
+    s = ldsv.Solver(n, n, B)
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=0)
+    prm = ldsv.params(nu=2e-4, dt=0.1 * 2 * math.pi / n)
+    for _ in range(warmup):
+        s.fv_step(prm, u, v, out=(u, v))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.fv_step(prm, u, v, out=(u, v))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.timer_enable(True)
+    for _ in range(steps):
+        s.fv_step(prm, u, v, out=(u, v))
+    torch.cuda.synchronize()
+    cls = {c: s.timer_read(c) for c in range(4)}
+    s.timer_enable(False)
+    cells = n * n * B
+    dom = max(cls, key=lambda c: cls[c][0])
+    avg_s = cls[dom][0] * 1e-3 / cls[dom][1]
+    per_class = {}
+    for c in cls:
+        a = cls[c][0] * 1e-3 / cls[c][1]
+        per_class[CLASS_NAMES[c]] = {"avg_launch_us": a * 1e6,
+                                     "GB_per_s": STAGE_BYTES[c] * cells / a / 1e9}
+    s.close()
+    return {"workload": "1024^2 x 128 trajectories, FP32, RK4 + projection per sub-step",
+            "cell_steps_per_s": cells * steps / t, "ms_per_step": 1e3 * t / steps,
+            "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom],
+                         "achieved": STAGE_BYTES[dom] * cells / avg_s / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": STAGE_BYTES[dom] * cells / avg_s / 1e9 / HBM_PEAK_GBS},
+            "classes": per_class}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +247,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-corr", action="store_true",
                     help="skip the corr>=0.9 comparison (training + resolution sweep, ~2 min)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the streaming-shape (1024^2 x 128) and Burgers latency records")
     ap.add_argument("--learned-only", action="store_true",
                     help="profiling aid: time only the learned 64^2 step and print its record")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -241,6 +334,11 @@ def main():
     if not a.no_learned:
         log("learned step")
         line["learned"] = learned_block(max(10, a.steps // 4), 3)
+    if not a.no_extra:
+        log("streaming shape 1024^2 x 128")
+        line["streaming"] = streaming_block()
+        log("burgers64 latency")
+        line["burgers64"] = burgers_block()
     if not a.no_corr:
         log("corr>=0.9 comparison: learned coarse vs plain FV resolution sweep")
         from paper_2507_01975_amd import train as T

@@ -365,10 +365,11 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
                (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
                h->log2nx, B, rows, idx, idy);
   LDSV_LAUNCHED();
-  // pass 2: 8 columns (fewer when the column does not fit) within
-  // kColE * kColBlock values and 64 KB of LDS
+  // pass 2: 8 columns (fewer for long columns) within kColE * kColBlock
+  // values
+  // (at most 32 KB of LDS per block, so that four blocks share a CU)
   int cols = 8;
-  while (cols > 1 && ((size_t)cols * ny > (size_t)kColE * kColBlock || (size_t)cols * ny * cs > 65536))
+  while (cols > 1 && ((size_t)cols * ny > (size_t)kColE * kColBlock || (size_t)cols * ny * cs > 32768))
     cols >>= 1;
   if (cols > nx) cols = nx;
   LDSV_REQUIRE((size_t)cols * ny <= (size_t)kColE * kColBlock && (size_t)cols * ny * cs <= 65536,
