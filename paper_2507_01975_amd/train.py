@@ -234,7 +234,7 @@ def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi):
 
 
 def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, test_batch=4,
-                train_fine_steps=10000, warmup_fine=4000, horizon=600, iters=600, unroll=16,
+                train_fine_steps=10000, warmup_fine=4000, horizon=600, iters=1500, unroll=16,
                 windows=4, lr=1e-4, speed_batch=64, speed_steps=40, progress=None,
                 seeds=(100, 200)):
     """The forced-flow measurement: train the 64^2 learned solver on labels
