@@ -39,8 +39,16 @@ def conv3x3_circular(x, w, b):
     return F.conv2d(xp, w, b)
 
 
+NCOEF = 64  # output channels 0..63: the 4 x 16 raw stencil values
+
+
 def cnn_forward(x, weights, biases, bf16=False, return_acts=False):
-    """x: [B, 2, Ny, Nx].  Returns [B, 66, Ny, Nx] (and the activations)."""
+    """x: [B, 2, Ny, Nx].  Returns [B, 66, Ny, Nx] (and the activations).
+
+    bf16=True emulates the storage precision of a BF16 network: inputs,
+    weights and every stored activation are rounded to bf16, and so are the
+    64 stencil-coefficient outputs (they are stored like activations); the
+    two temporal-correction outputs stay at full precision."""
     h = round_bf16(x) if bf16 else x
     acts = [h]
     nl = len(weights)
@@ -51,6 +59,8 @@ def cnn_forward(x, weights, biases, bf16=False, return_acts=False):
             h = gelu(h)
             if bf16:
                 h = round_bf16(h)
+        elif bf16:
+            h = torch.cat([round_bf16(h[:, :NCOEF]), h[:, NCOEF:]], dim=1)
         acts.append(h)
     return (h, acts) if return_acts else h
 

@@ -92,7 +92,8 @@ int check_params(const ldsv_handle* h, const ldsv_params* p) {
 // (state-sized planes) instead of the shared stage buffer.
 int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs, const void* su,
              const void* sv, void* du, void* dv, const float* tcu, const float* tcv, size_t tcbs,
-             hipStream_t st, void* keep = nullptr) {
+             hipStream_t st, void* keep = nullptr, const uint16_t* coef16 = nullptr,
+             size_t cbs16 = 0) {
   const size_t sbk = h->nstate * h->esize;
   auto ku = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s) * sbk : h->ws_u; };
   auto kv = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s + 1) * sbk : h->ws_v; };
@@ -101,6 +102,8 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
   StageArgs a;
   a.coef = coef;
   a.coef_bstride = cbs;
+  a.coef16 = coef16;
+  a.coef16_bstride = cbs16;
   if (p->rk == LDSV_RK4) {
     const double eps[4] = {0.5 * dt, 0.5 * dt, dt, dt / 6.0};
     for (int s = 0; s < 4; ++s) {
@@ -183,6 +186,13 @@ int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, 
                        const void* su, const void* sv, void* du, void* dv, const float* tcu,
                        const float* tcv, size_t tcbs, hipStream_t st) {
   return one_step(h, p, coef, cbs, su, sv, du, dv, tcu, tcv, tcbs, st);
+}
+
+// the same with the raw coefficients stored as bf16 planes
+int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* coef16,
+                         size_t cbs16, const void* su, const void* sv, void* du, void* dv,
+                         const float* tcu, const float* tcv, size_t tcbs, hipStream_t st) {
+  return one_step(h, p, nullptr, 0, su, sv, du, dv, tcu, tcv, tcbs, st, nullptr, coef16, cbs16);
 }
 
 // VJP of one RK4 step with a projection per sub-step (reverse sweep in

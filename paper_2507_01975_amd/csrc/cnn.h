@@ -5,8 +5,14 @@
 
 int ldsv_ensure_learned(ldsv_handle* h);
 int ldsv_check_net(const ldsv_net* net);
+// forward through all layers.  Output either as float planes [B][66][Ny][Nx]
+// in `out` (coefficient channels rounded to bf16 values), or, when coef16 is
+// given and the grid is tiled (sides multiples of 16), as bf16 coefficient
+// planes [B][64][Ny][Nx] in coef16 and float correction planes [B][2][Ny][Nx]
+// in tc.  Returns in *bf16_out whether the second form was written.
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
-                    float* out, float* const* zpre, hipStream_t st);
+                    float* out, float* const* zpre, hipStream_t st, uint16_t* coef16 = nullptr,
+                    float* tc = nullptr, bool* bf16_out = nullptr);
 int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                              const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
                              hipStream_t st);

@@ -111,12 +111,16 @@ int ldsv_ensure_learned(ldsv_handle* h) {
                "the learned path needs an F32 MAC grid");
   if (h->netout) return LDSV_OK;
   const size_t P = h->nstate;
-  const size_t bytes = 5 * P * kC * sizeof(uint16_t) + P * LDSV_NOUT * sizeof(float);
+  const size_t bytes = 5 * P * kC * sizeof(uint16_t) + P * LDSV_NOUT * sizeof(float) +
+                       P * LDSV_NCOEF * sizeof(uint16_t) +
+                       P * (LDSV_NOUT - LDSV_NCOEF) * sizeof(float);
   void* vblk = nullptr;
   LDSV_TRY(ldsv_alloc(h, &vblk, bytes, "learned workspace"));
   char* blk = (char*)vblk;
   for (int l = 0; l < 5; ++l) h->act[l] = (uint16_t*)(blk + (size_t)l * P * kC * sizeof(uint16_t));
   h->netout = (float*)(blk + 5 * P * kC * sizeof(uint16_t));
+  h->coef16 = (uint16_t*)(h->netout + P * LDSV_NOUT);
+  h->tcbuf = (float*)(h->coef16 + P * LDSV_NCOEF);
   return LDSV_OK;
 }
 
@@ -133,7 +137,8 @@ int ldsv_check_net(const ldsv_net* net) {
 // forward through all layers; zpre (nullable): 5 float NHWC pre-activation
 // buffers for the backward pass
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
-                    float* out, float* const* zpre, hipStream_t st) {
+                    float* out, float* const* zpre, hipStream_t st, uint16_t* coef16, float* tc,
+                    bool* bf16_out) {
   PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
   const int nblk_first = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
   {
@@ -157,12 +162,15 @@ int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const f
     LDSV_LAUNCHED();
   }
   if (tiled)
-    LDSV_TRY(ldsv_launch_conv_tile(h, 5, 1, h->act[4], net->w[5], net->b[5], LDSV_NOUT, nullptr,
-                                   nullptr, out, st));
+    LDSV_TRY(coef16 ? ldsv_launch_conv_tile(h, 5, 3, h->act[4], net->w[5], net->b[5], LDSV_NOUT,
+                                            coef16, nullptr, tc, st)
+                    : ldsv_launch_conv_tile(h, 5, 1, h->act[4], net->w[5], net->b[5], LDSV_NOUT,
+                                            nullptr, nullptr, out, st));
   else
     LDSV_TLAUNCH(h, 4, (k_conv3x3_mfma<5, 1, 64>), dim3(nblk), dim3(kBlock), 0, st, h->act[4],
                  net->w[5], net->b[5], LDSV_NOUT, pm, (uint16_t*)nullptr, (float*)nullptr, out);
   LDSV_LAUNCHED();
+  if (bf16_out) *bf16_out = tiled && coef16;
   return LDSV_OK;
 }
 
@@ -194,6 +202,7 @@ int ldsv_launch_conv_tile(ldsv_handle* h, int mt, int epi, const uint16_t* X, co
   if (mt == 4 && epi == 0 && cout == kC) LDSV_CONV_DMA(0)
   else if (mt == 4 && epi == 2 && cout == kC) LDSV_CONV_DMA(2)
   else if (mt == 5 && epi == 1) LDSV_CONV_TILE(5, 1, 16)
+  else if (mt == 5 && epi == 3) LDSV_CONV_TILE(5, 3, 16)
   else {
     ldsv_set_error("conv tile: unsupported configuration");
     return LDSV_EINVAL;

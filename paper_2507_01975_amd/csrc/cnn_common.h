@@ -32,6 +32,12 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(pack_bf16x2(f, 0.0f) & 0xffffu);
 }
 
+// the float value of f rounded to bf16 (the storage precision of the
+// network's stencil-coefficient outputs)
+__device__ __forceinline__ float round_to_bf16(float f) {
+  return __uint_as_float(((uint32_t)f32_to_bf16(f)) << 16);
+}
+
 // erfc(x) for x >= 0 by the Chebyshev-fitted form of Press et al.,
 // Numerical Recipes (sec. 6.2, erfcc): t exp(-x^2 + P(t)), t = 1/(1 + x/2),
 // fractional error below 1.2e-7 in exact arithmetic; in float32 the error is
@@ -82,7 +88,10 @@ struct PixMap {
 
 // MT: output-channel tiles of 16.  CIN: input channels (multiple of 32).
 // EPI 0: z = acc + bias -> gelu -> bf16 NHWC [P][64] (and z float NHWC if zout)
-// EPI 1: z = acc + bias -> float planar [B][cout][H][W]
+// EPI 1: z = acc + bias -> float planar [B][cout][H][W], channels below
+//        LDSV_NCOEF rounded to bf16 values (the coefficient storage precision)
+// EPI 3 (tiled kernel only): channels below LDSV_NCOEF -> bf16 planar Y,
+//        the rest -> float planar out_planar
 // EPI 2: g = acc * gelu'(zin[p][c]) -> bf16 NHWC [P][64] (data gradient)
 template <int MT, int EPI, int CIN>
 __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restrict__ X,
@@ -180,7 +189,9 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restr
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int c = c0 + i;
-          if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i] + bias[c];
+          const float z = acc[t][m][i] + bias[c];
+          if (c < cout)
+            out_planar[((size_t)b * cout + c) * hw + r] = c < LDSV_NCOEF ? round_to_bf16(z) : z;
         }
       }
     }
@@ -361,11 +372,27 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
           if (EPI == 0 && zio)
             *reinterpret_cast<float4*>(zio + p * kC + c0) =
                 float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
-        } else {
+        } else if (EPI == 1) {
+          // all 66 channels as float planes, the 64 stencil coefficients
+          // rounded to bf16 values
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = c0 + i;
-            if (c < cout) out_planar[((size_t)b * cout + c) * hw + r] = acc[t][m][i];
+            const float z = acc[t][m][i];
+            if (c < cout)
+              out_planar[((size_t)b * cout + c) * hw + r] = c < LDSV_NCOEF ? round_to_bf16(z) : z;
+          }
+        } else {
+          // EPI 3: the 64 stencil coefficients as bf16 planes [B][64][H][W]
+          // (Y), the 2 correction channels as float planes [B][2][H][W]
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = c0 + i;
+            const float z = acc[t][m][i];
+            if (c < LDSV_NCOEF)
+              Y[((size_t)b * LDSV_NCOEF + c) * hw + r] = f32_to_bf16(z);
+            else if (c < cout)
+              out_planar[((size_t)b * (LDSV_NOUT - LDSV_NCOEF) + (c - LDSV_NCOEF)) * hw + r] = z;
           }
         }
       }

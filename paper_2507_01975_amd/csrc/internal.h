@@ -105,6 +105,8 @@ struct ldsv_handle {
   uint16_t* act[6] = {nullptr};  // bf16 activations [B][Ny][Nx][64] (input of layer l+1)
   float* pre[5] = {nullptr};     // unused unless backward: pre-activation cache
   float* netout = nullptr;       // [B][66][Ny][Nx]
+  uint16_t* coef16 = nullptr;    // bf16 stencil coefficients [B][64][Ny][Nx] (inference)
+  float* tcbuf = nullptr;        // temporal correction [B][2][Ny][Nx] (inference)
   float* gnet = nullptr;         // [B][66][Ny][Nx] gradient of network output
   float* gact = nullptr;         // [B][Ny][Nx][64] float gradient buffers
   float* gact2 = nullptr;

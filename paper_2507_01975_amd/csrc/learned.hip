@@ -18,6 +18,9 @@ int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const f
 int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
                        const void* su, const void* sv, void* du, void* dv, const float* tcu,
                        const float* tcv, size_t tcbs, hipStream_t st);
+int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* coef16,
+                         size_t cbs16, const void* su, const void* sv, void* du, void* dv,
+                         const float* tcu, const float* tcv, size_t tcbs, hipStream_t st);
 
 namespace {
 
@@ -58,14 +61,29 @@ __global__ void k_select(float* cu, float* cv, const float* fu, const float* fv,
       if (bad[b]) counts[b] += 1;
 }
 
+// The network's 64 stencil-coefficient outputs are stored in bf16 (like its
+// activations): as bf16 planes when nothing asks for the float output (half
+// the bytes the four stage kernels read), else as bf16-rounded values in the
+// float output.  Both forms give the same step.
 int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, const float* u_in,
                  const float* v_in, float* u_out, float* v_out, int step_index, float* net_out,
                  hipStream_t st) {
-  float* out = net_out ? net_out : h->netout;
-  LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st));
   const size_t N = h->ncell;
-  const size_t bs = (size_t)LDSV_NOUT * N;
   const bool tc = prm->k_c > 0 && (step_index % prm->k_c) == 0;
+  bool packed = false;
+  if (!net_out) {
+    LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st, h->coef16, h->tcbuf,
+                             &packed));
+    if (packed) {
+      const size_t ts = (size_t)(LDSV_NOUT - LDSV_NCOEF) * N;
+      return ldsv_internal_step16(h, prm, h->coef16, (size_t)LDSV_NCOEF * N, u_in, v_in, u_out,
+                                  v_out, tc ? h->tcbuf : nullptr, tc ? h->tcbuf + N : nullptr, ts,
+                                  st);
+    }
+  }
+  float* out = net_out ? net_out : h->netout;
+  if (net_out) LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st));
+  const size_t bs = (size_t)LDSV_NOUT * N;
   return ldsv_internal_step(h, prm, out, bs, u_in, v_in, u_out, v_out,
                             tc ? out + (size_t)LDSV_NCOEF * N : nullptr,
                             tc ? out + (size_t)(LDSV_NCOEF + 1) * N : nullptr, bs, st);

@@ -21,6 +21,8 @@ struct StageArgs {
   void* oaccv = nullptr;
   const float* coef = nullptr;  // raw learned stencil values, planar, nullable
   size_t coef_bstride = 0;      // elements between trajectories
+  const uint16_t* coef16 = nullptr;  // the same as bf16 planes (used when set)
+  size_t coef16_bstride = 0;
   const float* tcu = nullptr;   // temporal correction added to out, nullable
   const float* tcv = nullptr;
   size_t tc_bstride = 0;

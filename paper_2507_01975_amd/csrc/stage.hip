@@ -64,21 +64,29 @@ struct StagePtrs {
   T* oaccv;
   const float* coef;
   size_t cbs;
+  const uint16_t* coef16;
+  size_t cbs16;
   const float* tcu;
   const float* tcv;
   size_t tcbs;
 };
 
+__device__ __forceinline__ float coef_value(const float* p) { return *p; }
+__device__ __forceinline__ float coef_value(const uint16_t* p) {
+  return __uint_as_float(((uint32_t)*p) << 16);  // bf16 -> float, exact
+}
+
 // learned interpolation at a face owned by global cell (gi, gj), kind K;
-// q(a, b) is the tile value at along offset a, across offset b
-template <typename T, bool ALONG_X, int W>
-__device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const float* cb,
+// q(a, b) is the tile value at along offset a, across offset b; the raw
+// coefficients are float or bf16 planes (CT)
+template <typename T, bool ALONG_X, int W, typename CT>
+__device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const CT* cb,
                                           int kind, size_t plane, size_t off) {
   T r[16];
   T m = 0;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    r[s] = (T)cb[(size_t)(16 * kind + s) * plane + off];
+    r[s] = (T)coef_value(cb + (size_t)(16 * kind + s) * plane + off);
     m += r[s];
   }
   m *= (T)(1.0 / 16.0);
@@ -93,7 +101,8 @@ __device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const
   return acc + (T)0.5 * (q0 + q1);
 }
 
-template <typename T, bool LEARNED, int TX, int TY>
+// COEF: 0 plain stencil, 1 float raw coefficients, 2 bf16 raw coefficients
+template <typename T, int COEF, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny) {
   constexpr int W = TX + 2 * kH, Hh = TY + 2 * kH;
@@ -174,7 +183,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   const bool visc = ph.mask & LDSV_VISCOSITY;
   const T nu = ph.nu;
   const T i24dx = ph.i24dx, i24dy = ph.i24dy;
-  const float* cbase = LEARNED ? p.coef + (size_t)b * p.cbs : nullptr;
+  const float* cbf = COEF == 1 ? p.coef + (size_t)b * p.cbs : nullptr;
+  const uint16_t* cbh = COEF == 2 ? p.coef16 + (size_t)b * p.cbs16 : nullptr;
 
   // x-faces: owners i in [i0-1, i0+TX-1], rows j in [j0, j0+TY-1]
   constexpr int kXF = TY * (TX + 1);
@@ -189,11 +199,16 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       const T ubar = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
       const T ubar_e = (T)0.5 * (su[lj - 1][li + 1] + su[lj][li + 1]);
       T uf, vf;
-      if (LEARNED) {
+      if constexpr (COEF != 0) {
         const int gi = (i0 - 1 + c + nx) & (nx - 1);
         const size_t off = (size_t)(j0 + r) * nx + gi;
-        uf = learned_face<T, true, W>(su, lj, li, cbase, 0, plane, off);
-        vf = learned_face<T, true, W>(sv, lj, li, cbase, 2, plane, off);
+        if constexpr (COEF == 1) {
+          uf = learned_face<T, true, W>(su, lj, li, cbf, 0, plane, off);
+          vf = learned_face<T, true, W>(sv, lj, li, cbf, 2, plane, off);
+        } else {
+          uf = learned_face<T, true, W>(su, lj, li, cbh, 0, plane, off);
+          vf = learned_face<T, true, W>(sv, lj, li, cbh, 2, plane, off);
+        }
       } else {
         uf = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
         vf = (T)0.5 * (sv[lj][li] + sv[lj][li + 1]);
@@ -221,11 +236,16 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       const T vbar_n = (T)0.5 * (sv[lj + 1][li - 1] + sv[lj + 1][li]);
       const T vbar_c = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
       T uf, vf;
-      if (LEARNED) {
+      if constexpr (COEF != 0) {
         const int gj = (j0 - 1 + r + ny) & (ny - 1);
         const size_t off = (size_t)gj * nx + (i0 + c);
-        uf = learned_face<T, false, W>(su, lj, li, cbase, 1, plane, off);
-        vf = learned_face<T, false, W>(sv, lj, li, cbase, 3, plane, off);
+        if constexpr (COEF == 1) {
+          uf = learned_face<T, false, W>(su, lj, li, cbf, 1, plane, off);
+          vf = learned_face<T, false, W>(sv, lj, li, cbf, 3, plane, off);
+        } else {
+          uf = learned_face<T, false, W>(su, lj, li, cbh, 1, plane, off);
+          vf = learned_face<T, false, W>(sv, lj, li, cbh, 3, plane, off);
+        }
       } else {
         uf = (T)0.5 * (su[lj][li] + su[lj + 1][li]);
         vf = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
@@ -402,6 +422,8 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   p.oaccv = (T*)a.oaccv;
   p.coef = a.coef;
   p.cbs = a.coef_bstride;
+  p.coef16 = a.coef16;
+  p.cbs16 = a.coef16_bstride;
   p.tcu = a.tcu;
   p.tcv = a.tcv;
   p.tcbs = a.tc_bstride;
@@ -434,12 +456,15 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   dim3 grid((nx / TX) * (ny / TY), h->g.batch);
 #define LDSV_STAGE_CASE(tx, ty)                                                                   \
   if (TX == tx && TY == ty) {                                                                     \
-    if (a.coef)                                                                                   \
-      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, true, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, \
+    if (a.coef16)                                                                                 \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 2, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
+                   ny);                                                                           \
+    else if (a.coef)                                                                              \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 1, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
     else                                                                                          \
-      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, false, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb,   \
-                   nx, ny);                                                                       \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
+                   ny);                                                                           \
   }
   LDSV_STAGE_CASE(64, 16)
   else LDSV_STAGE_CASE(32, 16) else LDSV_STAGE_CASE(16, 16) else LDSV_STAGE_CASE(8, 16)
