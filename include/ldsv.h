@@ -174,7 +174,10 @@ LDSV_API int ldsv_project_bwd(ldsv_handle* h, void* gu, void* gv, void* stream);
 
 /* ---- a12: the coefficient network (Sec. 3.4) ----
  * out: float [B][66][Ny][Nx] (64 raw stencil values, then TC_u, TC_v).
- * F32/MAC grids only. */
+ * A BF16 network: inputs, weights and activations are rounded to bf16
+ * (round to nearest even) with FP32 accumulation, and the 64 raw stencil
+ * values are returned rounded to bf16 values (their storage precision in the
+ * learned step); TC_u, TC_v are FP32.  F32/MAC grids only. */
 LDSV_API int ldsv_cnn_forward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                      float* out, void* stream);
 
@@ -188,7 +191,9 @@ LDSV_API int ldsv_cnn_activation(ldsv_handle* h, int layer, uint16_t* dst, void*
  * and, when step_index % k_c == 0, adds the temporal correction before the
  * last projection: u_k = P(FV(u_{k-1}) + TC).  step_index is k, the index
  * of the output state.  net_out (nullable): receives the network output
- * [B][66][Ny][Nx]. */
+ * [B][66][Ny][Nx] as ldsv_cnn_forward writes it.  Without net_out the
+ * stencil values stay in bf16 planes inside the handle (half the bytes for
+ * the stage kernels); the step is the same bit for bit. */
 LDSV_API int ldsv_learned_fv_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
                          const float* u_in, const float* v_in, float* u_out, float* v_out,
                          int step_index, float* net_out, void* stream);
