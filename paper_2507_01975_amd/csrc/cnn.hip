@@ -31,9 +31,13 @@
 namespace {
 using namespace cnnk;
 
+// pixel tiles of 16 per wavefront in layer 1: two keep the accumulators
+// small enough for 4+ wavefronts per SIMD, which the GELU-bound epilogue needs
+constexpr int kFirstTiles = 2;
+
 // layer 1: 2 -> 64 as one K = 32 step of the same MFMA (K = 18 real
 // entries: tap-major, channel-minor, as the weights are stored, zero-padded).
-// Wavefront w owns pixels 64w..64w+63 (4 tiles of 16) and all 64 channels:
+// Wavefront w owns kFirstTiles tiles of 16 pixels and all 64 channels:
 // lane l gathers the 8 K entries 8(l/16)..+7 of pixel l%16 of each tile
 // (bf16-rounded u, v of the taps), holds the matching 8 weights of 4 channel
 // tiles, and the epilogue is the one of the other layers.
@@ -47,9 +51,9 @@ __global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__
   const int wave = threadIdx.x >> 6;
   const int col = lane & 15;
   const int kq = lane >> 4;
-  const int pbase = (blockIdx.x * (kBlock / 64) + wave) * 64;
+  const int pbase = (blockIdx.x * (kBlock / 64) + wave) * (kFirstTiles * 16);
   bf16x8 afrag[4];
-  f32x4 acc[4][4];
+  f32x4 acc[kFirstTiles][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int co = m * 16 + col;
@@ -62,10 +66,10 @@ __global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__
 #pragma unroll
     for (int i = 0; i < 4; ++i) b0[i] = b1[m * 16 + kq * 4 + i];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t][m] = b0;
+    for (int t = 0; t < kFirstTiles; ++t) acc[t][m] = b0;
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < kFirstTiles; ++t) {
     int p = pbase + t * 16 + col;
     p = p < pm.total ? p : pm.total - 1;
     bf16x8 bfrag;
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__
       acc[t][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag[m], bfrag, acc[t][m], 0, 0, 0);
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < kFirstTiles; ++t) {
     const int p = pbase + t * 16 + col;
     if (p >= pm.total) continue;
 #pragma unroll
@@ -140,7 +144,8 @@ int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const f
                     float* out, float* const* zpre, hipStream_t st, uint16_t* coef16, float* tc,
                     bool* bf16_out) {
   PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
-  const int nblk_first = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
+  const int first_pix = (kBlock / 64) * kFirstTiles * 16;
+  const int nblk_first = (int)((h->nstate + first_pix - 1) / first_pix);
   {
     LDSV_TLAUNCH(h, 5, k_conv_first, dim3(nblk_first), dim3(kBlock), 0, st, u, v, net->w[0],
                        net->b[0], pm, h->act[0], zpre ? zpre[0] : nullptr);
