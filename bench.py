@@ -23,6 +23,8 @@ The line also carries
   last-level cache) with its own roofline record;
 * burgers64: microseconds per step of the FP64 Burgers configuration,
   eager and as a captured HIP graph;
+* training: one Adam iteration of the 128^2 learned solver unrolled 32 steps
+  through the hand-written adjoint (checkpoints every 8);
 * corr: the accuracy-matched comparison of the metric on forced Kolmogorov
   flow: the learned 64^2 solver is trained (Adam through the hand-written
   adjoint) on labels from 1024^2 plain FV down-sampled 16x; on held-out seeds
@@ -238,6 +240,36 @@ def streaming_block(steps=10, warmup=2):
             "classes": per_class}
 
 
+def training_block(iters=5):
+    """One training iteration of the decaying-flow configuration: the 128^2
+    learned solver, batch 8, unrolled 32 steps with checkpoints every 8,
+    forward + hand-written backward + Adam (labels: a plain-FV rollout of the
+    same batch stands in for the down-sampled fine solution)."""
+    import torch
+    import synthetic_inputs as si
+    from paper_2507_01975_amd import ldsv, train as T
+    w = si.WORKLOADS["decaying128_train"]
+    n, B, unroll = w["nx"], w["batch"], w["unroll"]
+    s = ldsv.Solver(n, n, B)
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"], k_c=1, fallback_enable=0)
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=300)
+    tu, tv = s.rollout(prm, u, v, unroll + 8)
+    lu, lv = torch.cat([u[None], tu]), torch.cat([v[None], tv])
+    net = T.init_network(seed=0)
+    T.train(s, net, (lu, lv), prm, iters=2, unroll=unroll,
+            checkpoint_every=w["checkpoint_every"], log_every=10 ** 9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T.train(s, net, (lu, lv), prm, iters=iters, unroll=unroll,
+            checkpoint_every=w["checkpoint_every"], log_every=10 ** 9)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / iters
+    s.close()
+    return {"workload": "decaying128_train (128^2, batch 8, unroll 32, checkpoints every 8, "
+                        "Adam)", "ms_per_iteration": 1e3 * t,
+            "learned_steps_per_s": B * unroll / t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +371,8 @@ def main():
         line["streaming"] = streaming_block()
         log("burgers64 latency")
         line["burgers64"] = burgers_block()
+        log("training iteration 128^2")
+        line["training"] = training_block()
     if not a.no_corr:
         log("corr>=0.9 comparison: learned coarse vs plain FV resolution sweep")
         from paper_2507_01975_amd import train as T
