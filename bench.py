@@ -17,7 +17,10 @@ The line also carries
   between launches), its algorithmic bytes per launch, achieved GB/s against
   8 TB/s;
 * cpu_baseline: the FP64 CPU oracle timed on this host on a bounded sample
-  of the same workload (the full batch, as many steps as fit in ~10 s);
+  of the same workload (the full batch, as many steps as fit in ~10 s), and
+  the GPU step's error against it;
+* fp64_errors: the learned step, the network output and the 200-step Burgers
+  run against the FP64 oracle;
 * learned: the learned step (64^2, batch 64, BF16 CNN on MFMA);
 * streaming: the plain step at 1024^2 x 128 (a state far larger than the
   last-level cache) with its own roofline record;
@@ -81,9 +84,17 @@ def measured_traffic(kernel):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def cpu_baseline(w, u0, v0, budget_s=10.0):
+def _rel_l2(a, b):
+    a = a.double().cpu()
+    b = b.double().cpu()
+    return float((a - b).norm() / b.norm().clamp_min(1e-300))
+
+
+def cpu_baseline(w, u0, v0, u1_gpu, v1_gpu, budget_s=10.0):
     """The oracle as it stands on a bounded sample of the same workload: all
-    16 trajectories at 512^2, RK4 steps until about budget_s of CPU time."""
+    16 trajectories at 512^2, RK4 steps until about budget_s of CPU time.
+    The oracle's first step also gives the GPU step's error against FP64
+    (same initial state)."""
     import torch
     from oracle import fv, timestep
     cores = len(os.sched_getaffinity(0))
@@ -92,17 +103,67 @@ def cpu_baseline(w, u0, v0, budget_s=10.0):
     v = v0.double().cpu()
     prm = fv.grid_params(w["nx"], w["ny"], nu=w["nu"], dt=w["dt"])
     steps = 0
+    err = None
     t0 = time.perf_counter()
     while True:
         u, v = timestep.fv_step(u, v, prm)
         steps += 1
+        if steps == 1:
+            t_err = time.perf_counter()
+            err = max(_rel_l2(u1_gpu, u), _rel_l2(v1_gpu, v))
+            t0 += time.perf_counter() - t_err
         t = time.perf_counter() - t0
         if t >= budget_s:
             break
     cells = w["nx"] * w["ny"] * u.shape[0] * steps
     return {"value": cells / t, "unit": "cell-steps/s", "cores": torch.get_num_threads(),
             "kind": "oracle", "sample": "%d RK4 steps of all 16 trajectories of the 512^2 "
-            "workload (%.1f s, FP64 torch CPU)" % (steps, t)}
+            "workload (%.1f s, FP64 torch CPU)" % (steps, t),
+            "gpu_step_rel_l2_vs_fp64": err}
+
+
+def fp64_errors():
+    """Errors of the other results against the FP64 oracle (the oracle is run
+    here as the checker, outside every timed region): the learned step of the
+    forced-flow workload (trajectory 0 of the batch of 64, bench network),
+    its network output, and 200 FP64 Burgers steps."""
+    import torch
+    import synthetic_inputs as si
+    from oracle import cnn as ocnn, fv as ofv, ic as oic, learned as olearned
+    from oracle import timestep as ots
+    from paper_2507_01975_amd import ldsv
+    out = {}
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    s = ldsv.Solver(n, n, B)
+    ws, bs = si.cnn_weights(0, ocnn.LAYERS)
+    net = ldsv.NetParams([torch.tensor(x) for x in ws], [torch.tensor(x) for x in bs])
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
+    kw = dict(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"], forcing_k=w["forcing_k"],
+              drag=w["drag"])
+    uo, vo, no = s.learned_fv_step(ldsv.params(k_c=1, **kw), net, u, v, 1, want_net_out=True)
+    prm = ofv.grid_params(n, n, k_c=1, **kw)
+    wb = [x.double().cpu() for x in net.bf16_weights()]
+    bb = [x.double().cpu() for x in net.b]
+    u0, v0 = u[:1].double().cpu(), v[:1].double().cpu()
+    eu, ev, eo = olearned.learned_fv_step(u0, v0, prm, wb, bb, 1, bf16=False)
+    out["learned_step_rel_l2_vs_fp64"] = max(_rel_l2(uo[:1], eu), _rel_l2(vo[:1], ev))
+    out["network_output_rel_l2_vs_fp64"] = _rel_l2(no[:1], eo)
+    s.close()
+    wb_ = si.WORKLOADS["burgers64"]
+    nb = wb_["nx"]
+    s = ldsv.Solver(nb, nb, 1, dtype=torch.float64, layout=ldsv.COLLOCATED)
+    gu, gv = s.init_state(ldsv.IC_FOURIER_MODES, seed=0)
+    dt = s.cfl_dt(gu, gv, wb_["cfl"])
+    gu, gv = s.fv_step(ldsv.params(nu=wb_["nu"], dt=dt, rk=ldsv.SSPRK3), gu, gv,
+                       nsteps=wb_["steps"])
+    bu, bv = oic.fourier_modes(1, nb, nb, 2 * math.pi, 2 * math.pi, seed=0)
+    bprm = ofv.grid_params(nb, nb, nu=wb_["nu"], rk=ots.SSPRK3, layout=ots.COLLOCATED)
+    bprm["dt"] = dt
+    bu, bv = ots.fv_step(bu, bv, bprm, nsteps=wb_["steps"])
+    out["burgers64_200_steps_fp64_rel_l2"] = max(_rel_l2(gu, bu), _rel_l2(gv, bv))
+    s.close()
+    return out
 
 
 def learned_block(steps, warmup):
@@ -315,6 +376,8 @@ def main():
     u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=0)
     u0, v0 = u.clone(), v.clone()
     prm = ldsv.params(nu=w["nu"], dt=w["dt"])
+    # one step from the initial state, kept for the error against FP64
+    u1, v1 = s.fv_step(prm, u0, v0)
     for _ in range(a.warmup):
         s.fv_step(prm, u, v, out=(u, v))
     torch.cuda.synchronize()
@@ -382,7 +445,9 @@ def main():
             line["corr"] = {"status": "failed: %r" % (e,)}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(w, u0, v0)
+        line["cpu_baseline"] = cpu_baseline(w, u0, v0, u1, v1)
+        log("errors against the FP64 oracle")
+        line["fp64_errors"] = fp64_errors()
     print(json.dumps(line), flush=True)
 
 
