@@ -31,6 +31,24 @@ Coefficient tensors are [B, 64, Ny, Nx]: channel 16*K + s for kind K:
 Each is the east (K0, K2) or north (K1, K3) face of the momentum control
 volume of the owning index (i, j).  Flux differences therefore telescope and
 the scheme conserves momentum whatever the coefficients are.
+
+Flux block (Sec. 3.4, Eqs. 5-8): every face value is O_P + O_L + O_F.  Besides
+the physics kernels above (O_P) and the per-cell coefficients, ``ns_rhs``
+takes a ``flux`` record with the paper's spatially uniform learnable 5x4
+kernels and the frequency-operator fields:
+  wi [4, 20]  uniform learnable interpolation kernel per kind (O_L^(i))
+  wd [4, 20]  uniform learnable derivative kernel per kind (O_L^(d)); the
+              weights are dimensionless, the face derivative gets
+              (1/h) sum_s wd[K, s] q_s with h the spacing along the normal
+  fi [B, 4, Ny, Nx]  field added to the interpolated value of kind K at the
+              face its cell owns (O_F^(i))
+  fd [B, 4, Ny, Nx]  field added to the face derivative of kind K (O_F^(d))
+The derivative kinds sit where the interpolation kinds do: K0 du/dx at the
+cell centre, K1 du/dy at the corner, K2 dv/dx at the corner, K3 dv/dy at the
+cell centre.  The uniform kernels cover the whole 5x4 window: footprint
+points 0..15 as above, then the four corners 16: (-1,-2), 17: (2,-2),
+18: (-1,2), 19: (2,2).  Any entry may be absent (None).  Each face value is
+still single-valued, so the residual stays conservative.
 """
 import math
 import torch
@@ -44,6 +62,7 @@ ALL_PHYSICS = 7
 FOOTPRINT = [(s % 4 - 1, s // 4 - 1) for s in range(12)] + [(0, -2), (1, -2), (0, 2), (1, 2)]
 NKIND = 4
 NPOINT = 16
+FOOTPRINT20 = FOOTPRINT + [(-1, -2), (2, -2), (-1, 2), (2, 2)]
 
 
 def plain_coefficients(dtype=torch.float64):
@@ -99,7 +118,49 @@ def deriv4_y(q, dy):
     return (sy(q, -1) - 27.0 * q + 27.0 * sy(q, 1) - sy(q, 2)) / (24.0 * dy)
 
 
-def ns_rhs(u, v, prm, coef=None):
+def uniform_x(q, w):
+    """Spatially uniform 5x4 kernel w [20] along x: sum_s w[s] q[j+b, i+a]."""
+    out = 0.0
+    for s, (a, b) in enumerate(FOOTPRINT20):
+        out = out + w[s] * sx(sy(q, b), a)
+    return out
+
+
+def uniform_y(q, w):
+    """The transpose kernel along y: sum_s w[s] q[j+a, i+b]."""
+    out = 0.0
+    for s, (a, b) in enumerate(FOOTPRINT20):
+        out = out + w[s] * sy(sx(q, b), a)
+    return out
+
+
+def _flux_interp(q, flux, kind, along_x):
+    """O_L^(i) + O_F^(i) part of the interpolated value of kind K (0 if absent)."""
+    out = 0.0
+    if flux is None:
+        return out
+    if flux.get("wi") is not None:
+        w = flux["wi"][kind]
+        out = out + (uniform_x(q, w) if along_x else uniform_y(q, w))
+    if flux.get("fi") is not None:
+        out = out + flux["fi"][:, kind]
+    return out
+
+
+def _flux_deriv(q, flux, kind, along_x, h):
+    """O_L^(d) + O_F^(d) part of the face derivative of kind K (0 if absent)."""
+    out = 0.0
+    if flux is None:
+        return out
+    if flux.get("wd") is not None:
+        w = flux["wd"][kind]
+        out = out + (uniform_x(q, w) if along_x else uniform_y(q, w)) / h
+    if flux.get("fd") is not None:
+        out = out + flux["fd"][:, kind]
+    return out
+
+
+def ns_rhs(u, v, prm, coef=None, flux=None):
     """Residual R(u) of the incompressible momentum equations without the
     pressure term, on the MAC grid (Eq. 4; App. B.2 S1-S5; App. C.1 S26).
 
@@ -116,6 +177,8 @@ def ns_rhs(u, v, prm, coef=None):
 
     prm keys: dx, dy, nu, forcing_amp, forcing_k, drag, mask.
     coef: None for the physics stencil, else a 64-vector or [B, 64, Ny, Nx].
+    flux: None, or the flux-block record (wi, wd, fi, fd) described above,
+    whose terms add to the face values.
     """
     dx, dy = prm["dx"], prm["dy"]
     mask = prm.get("mask", ALL_PHYSICS)
@@ -125,22 +188,22 @@ def ns_rhs(u, v, prm, coef=None):
     if mask & ADVECTION:
         # u momentum: east face at the cell centre, north face at the corner
         ubar_c = 0.5 * (u + sx(u, 1))
-        F = ubar_c * interp_x(u, c, 0)
+        F = ubar_c * (interp_x(u, c, 0) + _flux_interp(u, flux, 0, True))
         vbar_n = 0.5 * (sx(sy(v, 1), -1) + sy(v, 1))     # v[j+1, i-1], v[j+1, i]
-        G = vbar_n * interp_y(u, c, 1)
+        G = vbar_n * (interp_y(u, c, 1) + _flux_interp(u, flux, 1, False))
         ru = ru - (F - sx(F, -1)) / dx - (G - sy(G, -1)) / dy
         # v momentum: east face at the corner, north face at the cell centre
         ubar_e = 0.5 * (sx(sy(u, -1), 1) + sx(u, 1))     # u[j-1, i+1], u[j, i+1]
-        E = ubar_e * interp_x(v, c, 2)
+        E = ubar_e * (interp_x(v, c, 2) + _flux_interp(v, flux, 2, True))
         vbar_c = 0.5 * (v + sy(v, 1))
-        H = vbar_c * interp_y(v, c, 3)
+        H = vbar_c * (interp_y(v, c, 3) + _flux_interp(v, flux, 3, False))
         rv = rv - (E - sx(E, -1)) / dx - (H - sy(H, -1)) / dy
     if mask & VISCOSITY:
         nu = prm["nu"]
-        ux = deriv4_x(u, dx)
-        uy = deriv4_y(u, dy)
-        vx = deriv4_x(v, dx)
-        vy = deriv4_y(v, dy)
+        ux = deriv4_x(u, dx) + _flux_deriv(u, flux, 0, True, dx)
+        uy = deriv4_y(u, dy) + _flux_deriv(u, flux, 1, False, dy)
+        vx = deriv4_x(v, dx) + _flux_deriv(v, flux, 2, True, dx)
+        vy = deriv4_y(v, dy) + _flux_deriv(v, flux, 3, False, dy)
         ru = ru + nu * ((ux - sx(ux, -1)) / dx + (uy - sy(uy, -1)) / dy)
         rv = rv + nu * ((vx - sx(vx, -1)) / dx + (vy - sy(vy, -1)) / dy)
     if mask & FORCING:

@@ -86,3 +86,37 @@ WORKLOADS = {
                      ic="shear_layer", forcing_amp=0.0, forcing_k=0.0, drag=0.0,
                      dtype="f32", fine_n=1024),
 }
+
+
+def fno_weights(seed, width, layers, modes, n_in=2, n_out=4, out_scale=1e-2, dtype=np.float64):
+    """Random FNO parameters as real arrays: lift P_w [width, n_in], P_b;
+    per layer R_re, R_im [2 modes, modes, width, width] drawn with scale
+    1 / width^2, pointwise W [width, width] (out, in) with scale 1 / sqrt(width)
+    and b; projection Q_w [n_out, width] and Q_b scaled by out_scale (a small
+    initial correction)."""
+    g = rng(seed)
+    a = {"P_w": g.standard_normal((width, n_in)) / math.sqrt(n_in),
+         "P_b": g.standard_normal(width) * 0.01, "layers": []}
+    for _ in range(layers):
+        sc = 1.0 / (width * width)
+        a["layers"].append({
+            "R_re": g.standard_normal((2 * modes, modes, width, width)) * sc,
+            "R_im": g.standard_normal((2 * modes, modes, width, width)) * sc,
+            "W": g.standard_normal((width, width)) / math.sqrt(width),
+            "b": g.standard_normal(width) * 0.01})
+    a["Q_w"] = g.standard_normal((n_out, width)) / math.sqrt(width) * out_scale
+    a["Q_b"] = g.standard_normal(n_out) * 0.01 * out_scale
+
+    def cast(z):
+        return {k: ([cast(l) for l in v] if isinstance(v, list) else v.astype(dtype))
+                for k, v in z.items()}
+    return cast(a)
+
+
+def stencil_weights(seed, scale=1e-2, dtype=np.float64):
+    """Random uniform 5x4 kernels [4 kinds, 20 points], N(0, scale^2)."""
+    return (rng(seed).standard_normal((4, 20)) * scale).astype(dtype)
+
+
+# flux-block networks of the paper's hyper-parameter table: (layers, modes, width)
+FLUXBLOCK_FNO = {"forced": (6, 32, 16), "decaying": (4, 16, 8)}
