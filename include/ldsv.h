@@ -280,11 +280,87 @@ LDSV_API int ldsv_diagnostics(ldsv_handle* h, const void* u, const void* v, doub
 LDSV_API int ldsv_cfl_dt(ldsv_handle* h, const void* u, const void* v, double cfl, double* dt_host,
                 void* stream);
 
+/* ---- the paper's flux block (Sec. 3.4, Eqs. 5-8) ----
+ * Every interpolated face value and every face derivative of the momentum
+ * residual is O_P + O_L + O_F: the physics kernel (as in ldsv_fv_step), a
+ * spatially uniform learnable 5x4 kernel (O_L, Eqs. 6-7) and a per-cell
+ * field from a Fourier neural operator (O_F, Eq. 8).
+ *
+ * Uniform kernels `stencil_w`: float [2][4][20] (device).  Index m = 0
+ * interpolation, 1 derivative; kind K = 0: u along x (face at the cell
+ * centre), 1: u along y (corner), 2: v along x (corner), 3: v along y (cell
+ * centre), each the east or north face of the momentum volume of the cell
+ * that owns it.  Point s of the 5x4 window has offset a along the face
+ * normal and b across it: s = 0..11: a = s % 4 - 1, b = s / 4 - 1;
+ * 12: (0,-2), 13: (1,-2), 14: (0,2), 15: (1,2), 16: (-1,-2), 17: (2,-2),
+ * 18: (-1,2), 19: (2,2); along y the kernel is the transpose (q[j+a][i+b]).
+ * The interpolated value adds sum_s w[0][K][s] q(a, b) and the face
+ * derivative adds (1/h) sum_s w[1][K][s] q(a, b), h the spacing along the
+ * normal.  `fields`: float [B][8][Ny][Nx] (device, nullable = zero):
+ * channel K adds to the interpolated value of kind K, channel 4 + K to the
+ * face derivative of kind K, at the face the cell owns.  The residual stays
+ * conservative (every face value is single-valued).
+ *
+ * FNO (Li et al. 2021, the paper's frequency operator): v_0 = lift (u, v);
+ * L layers v <- GELU(K v + W v + b) with no GELU after the last; fields =
+ * proj v_L.  K keeps the modes k_y in [0, M) U [Ny - M, Ny), k_x < M of the
+ * real 2D transform, mixes channels per mode with complex weights and
+ * applies the real inverse transform (which reads only the real part of the
+ * k_x = 0 column).  Retained row r: k_y for k_y < M, k_y - Ny + 2M above.
+ * F32 MAC grids with Nx * Ny <= 16384 (one LDS transform per field). */
+typedef struct {
+  int width;             /* C: 8 or 16 */
+  int layers;            /* L >= 1 */
+  int modes;             /* M: 2M <= Ny and M <= Nx/2 */
+  const float* lift_w;   /* [C][2]: v_0 = lift_w (u, v) + lift_b */
+  const float* lift_b;   /* [C] */
+  const float* spec_w;   /* [L][C_in][C_out][2M][M] complex (re, im), 8-byte aligned */
+  const float* point_w;  /* [L][C_out][C_in] */
+  const float* point_b;  /* [L][C] */
+  const float* proj_w;   /* [4][C] */
+  const float* proj_b;   /* [4] */
+} ldsv_fno;
+
+typedef struct {
+  const float* stencil_w;  /* [2][4][20] uniform kernels (device) */
+  const ldsv_fno* fno[2];  /* frequency operators for m = interpolation,
+                              derivative (host structs of device pointers);
+                              NULL = absent (zero fields); when both are
+                              given they share width, layers and modes */
+} ldsv_fluxnet;
+
+/* ldsv_fno_forward: fields [B][8][Ny][Nx] = channels 0..3 from fno[0] and
+ * 4..7 from fno[1] (zeros for an absent operator) on (u, v). */
+LDSV_API int ldsv_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u,
+                              const float* v, float* fields, void* stream);
+/* ldsv_fluxblock_fv_step: nsteps RK4 steps (projection per sub-step) with
+ * the flux block's uniform kernels and FIXED fields (MAC, F32 or F64; the
+ * kernels and fields are FP32 in both).  In place allowed. */
+LDSV_API int ldsv_fluxblock_fv_step(ldsv_handle* h, const ldsv_params* prm,
+                                    const float* stencil_w, const float* fields,
+                                    const void* u_in, const void* v_in, void* u_out, void* v_out,
+                                    int nsteps, void* stream);
+/* ldsv_fluxblock_fv_step_bwd: VJP of one ldsv_fluxblock_fv_step: writes
+ * gu_in, gv_in and ACCUMULATES dL/dstencil_w into gstencil (float [160],
+ * nullable) and dL/dfields into gfields ([B][8][Ny][Nx], nullable).  The
+ * kernel gradient is reduced in a fixed order (deterministic). */
+LDSV_API int ldsv_fluxblock_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm,
+                                        const float* stencil_w, const float* fields,
+                                        const void* u_in, const void* v_in, const void* gu_out,
+                                        const void* gv_out, void* gu_in, void* gv_in,
+                                        float* gstencil, float* gfields, void* stream);
+/* ldsv_fluxblock_step: one step of the flux-block model, u_out = FV(u_in)
+ * with fields = FNO(u_in) (evaluated once, held over the four sub-steps).
+ * fields_out (nullable) receives the fields.  Not in place. */
+LDSV_API int ldsv_fluxblock_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,
+                                 const float* u_in, const float* v_in, float* u_out, float* v_out,
+                                 float* fields_out, void* stream);
+
 /* ---- measurement ----
  * Kernel classes timed by ldsv_timer_*: 0 RK stage (fused residual), 1 row
  * FFT + divergence, 2 column FFT + Poisson division, 3 inverse row FFT +
  * gradient correction, 4 convolution (MFMA), 5 first convolution layer,
- * 6 adjoint stage, 7 other.  While enabled, every launch of a class is
+ * 6 adjoint stage, 7 other, 8 FNO transforms, 9 FNO mode mixing.  While enabled, every launch of a class is
  * bracketed by HIP events on its stream.  ldsv_timer_read synchronises the
  * device and returns the summed duration (ms) and the launch count. */
 LDSV_API int ldsv_timer_enable(ldsv_handle* h, int on);

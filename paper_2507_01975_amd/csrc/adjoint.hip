@@ -21,6 +21,16 @@
 //   k_adj_gather  one thread per output cell: sums what every face whose
 //                 stencil touches the cell sends to it.
 //
+// Flux block (Sec. 3.4): the interpolation stencil is c_P + w_K over the
+// 5x4 window plus a field fi_K, the face derivative adds (1/h) sum w^d_K q
+// plus a field fd_K.  The faces then also send Fb * abar * w_K,s to the
+// points of the uniform kernel and -nu * Fb * w^d_K,s / h to the points of
+// the derivative kernel; the field gradients are dfi_K = Fb * abar and
+// dfd_K = -nu * Fb at the owner, and the uniform-kernel gradients are sums
+// over all faces, dw_K,s = sum Fb * abar * q_s and dw^d_K,s =
+// sum -nu * Fb * q_s / h, reduced per tile (k_adj_fb_wgrad) and then in a
+// fixed order over the tiles (k_fb_wreduce): deterministic.
+//
 // RK4 reverse sweep, with P the (symmetric) projection and u1..u3 the
 // recomputed projected stage states:
 //   A = P g;  S = A
@@ -53,13 +63,34 @@ struct Field {
 // scratch layout (per trajectory plane, 16 planes): P0..P3, Q0..Q3, V0..V3, M0..M3
 constexpr int kAdjPlanes = 16;
 
-template <typename T, bool LEARNED>
+// the 5x4 window of the uniform kernels (points 0..15 as in kAOffA/kBOffA,
+// then the four corners)
+__device__ __forceinline__ constexpr int a_off20(int s) {
+  return s < 12 ? s % 4 - 1 : (s < 16 ? (s & 1) : (s & 1 ? 2 : -1));
+}
+__device__ __forceinline__ constexpr int b_off20(int s) {
+  return s < 12 ? s / 4 - 1 : (s < 14 ? -2 : (s < 16 ? 2 : (s < 18 ? -2 : 2)));
+}
+
+struct AdjFB {
+  const float* w;   // [2][4][20]
+  const float* f;   // [B][8][Ny][Nx], nullable
+  size_t fbs;
+  float* gf;        // nullable
+  size_t gfbs;
+};
+
+// MODE: 0 physics stencil, 1 per-cell coefficients, 2 flux block
+
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, const T* __restrict__ vs,
                                                       const T* __restrict__ Au, const T* __restrict__ Av,
                                                       const T* __restrict__ Gu, const T* __restrict__ Gv,
                                                       double aA, double aG, const float* __restrict__ coef,
                                                       size_t cbs, float* __restrict__ gcoef, size_t gcbs,
-                                                      T* __restrict__ scr, AdjPhys ph, int nx, int ny) {
+                                                      AdjFB fb, T* __restrict__ scr, AdjPhys ph, int nx,
+                                                      int ny) {
+  constexpr bool LEARNED = MODE == 1;
   const size_t n = (size_t)nx * ny;
   const int b = blockIdx.y;
   const size_t off = (size_t)b * n;
@@ -135,6 +166,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
         face[1] = (T)0.5 * (U(i, j) + U(i, j + 1));
         face[2] = (T)0.5 * (V(i, j) + V(i + 1, j));
         face[3] = (T)0.5 * (V(i, j) + V(i, j + 1));
+        if constexpr (MODE == 2) {
+          const float* fo = fb.f ? fb.f + (size_t)b * fb.fbs : nullptr;
+#pragma unroll
+          for (int K = 0; K < 4; ++K) {
+            const Field<T>& F = (K < 2) ? U : V;
+            const bool along_x = (K == 0 || K == 2);
+            T acc = 0;
+#pragma unroll
+            for (int s = 0; s < 20; ++s) {
+              const T q = along_x ? F(i + a_off20(s), j + b_off20(s)) : F(i + b_off20(s), j + a_off20(s));
+              acc += (T)fb.w[20 * K + s] * q;
+            }
+            face[K] += acc;
+            if (fo) face[K] += (T)fo[(size_t)K * n + c];
+          }
+        }
       }
       P[0] = (T)0.5 * fxb * face[0];
       P[1] = (T)0.5 * fyb * face[1];
@@ -151,6 +198,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
       Vm[2] = -nu * exb * (T)(1.0 / 24.0) * idx;
       Vm[3] = -nu * eyb * (T)(1.0 / 24.0) * idy;
     }
+    if constexpr (MODE == 2) {
+      if (fb.gf) {
+        float* g = fb.gf + (size_t)b * fb.gfbs;
+        const T fbk[4] = {fxb, fyb, exb, eyb};
+#pragma unroll
+        for (int K = 0; K < 4; ++K) {
+          if (adv) g[(size_t)K * n + c] += (float)Q[K];
+          if (visc) g[(size_t)(4 + K) * n + c] += (float)(-nu * fbk[K]);
+        }
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       S[(size_t)k * n + c] = P[k];
@@ -161,9 +219,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
   }
 }
 
-template <typename T, bool LEARNED>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr,
                                                        const float* __restrict__ coef, size_t cbs,
+                                                       const float* __restrict__ fbw,
                                                        const T* __restrict__ Au, const T* __restrict__ Av,
                                                        const T* __restrict__ Gu, const T* __restrict__ Gv,
                                                        double aA, double aG,
@@ -173,6 +232,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
   const size_t n = (size_t)nx * ny;
   const int b = blockIdx.y;
   const size_t off = (size_t)b * n;
+  constexpr bool LEARNED = MODE == 1;
   const T* S = scr + (size_t)b * kAdjPlanes * n;
   const float* cb = LEARNED ? coef + (size_t)b * cbs : nullptr;
   const T wv[4] = {(T)1, (T)-27, (T)27, (T)-1};  // derivative weights for offsets -1..2
@@ -214,6 +274,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
       gv += (T)0.5 * (at(6, i, j) + at(6, i - 1, j));
       gv += (T)0.5 * (at(7, i, j) + at(7, i, j - 1));
     }
+    if constexpr (MODE == 2) {
+      // uniform kernels: owner o = p - offset sends w * Q (interpolation) and
+      // 24 w^d * V (derivative: V holds -nu Fb / (24 h))
+#pragma unroll
+      for (int s = 0; s < 20; ++s) {
+        const int a = a_off20(s), bb = b_off20(s);
+        gu += (T)fbw[s] * at(4, i - a, j - bb) + (T)fbw[20 + s] * at(5, i - bb, j - a);
+        gv += (T)fbw[40 + s] * at(6, i - a, j - bb) + (T)fbw[60 + s] * at(7, i - bb, j - a);
+        gu += (T)24 * ((T)fbw[80 + s] * at(8, i - a, j - bb) + (T)fbw[100 + s] * at(9, i - bb, j - a));
+        gv += (T)24 * ((T)fbw[120 + s] * at(10, i - a, j - bb) + (T)fbw[140 + s] * at(11, i - bb, j - a));
+      }
+    }
     // viscous face derivatives: owner o = p - m sends V * w_m to p
 #pragma unroll
     for (int m = -1; m <= 2; ++m) {
@@ -239,6 +311,78 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
   }
 }
 
+// Per-tile partial sums of the uniform-kernel gradients.  A tile is TX x TY
+// cells of one trajectory (TX * TY <= 256); thread w < 160 owns weight w =
+// (m, K, s) and sums M_K * q_s over the tile's cells, with M the
+// interpolation multiplier Q (m = 0) or the derivative multiplier 24 V
+// (m = 1).  part[tile][w] is written, never accumulated.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_fb_wgrad(const T* __restrict__ us,
+                                                         const T* __restrict__ vs,
+                                                         const T* __restrict__ scr,
+                                                         T* __restrict__ part, int nx, int ny, int TX,
+                                                         int TY) {
+  // (TY + 4) x (TX + 4) <= 544 for every TX in [4, 64] with TX * TY <= 256
+  constexpr int kHalo = 544;
+  __shared__ T su[kHalo];
+  __shared__ T sv[kHalo];
+  __shared__ T sm[8][256];
+  const size_t n = (size_t)nx * ny;
+  const int tilesx = nx / TX;
+  const int b = blockIdx.y;
+  const int i0 = (blockIdx.x % tilesx) * TX, j0 = (blockIdx.x / tilesx) * TY;
+  const T* u = us + (size_t)b * n;
+  const T* v = vs + (size_t)b * n;
+  const T* S = scr + (size_t)b * kAdjPlanes * n;
+  const int W = TX + 4, H = TY + 4;
+  for (int t = threadIdx.x; t < W * H; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    const size_t g = (size_t)((j0 - 2 + r + ny) & (ny - 1)) * nx + ((i0 - 2 + c + nx) & (nx - 1));
+    su[t] = u[g];
+    sv[t] = v[g];
+  }
+  for (int t = threadIdx.x; t < TX * TY; t += blockDim.x) {
+    const int r = t / TX, c = t - r * TX;
+    const size_t g = (size_t)(j0 + r) * nx + (i0 + c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sm[k][t] = S[(size_t)(4 + k) * n + g];
+      sm[4 + k][t] = (T)24 * S[(size_t)(8 + k) * n + g];
+    }
+  }
+  __syncthreads();
+  const int w = threadIdx.x;
+  if (w < 160) {
+    const int m = w / 80, K = (w / 20) & 3, s = w % 20;
+    const int a = a_off20(s), bb = b_off20(s);
+    const bool along_x = (K == 0 || K == 2);
+    const int dr = along_x ? bb : a, dc = along_x ? a : bb;
+    const T* F = (K < 2 ? su : sv) + (2 + dr) * W + 2 + dc;
+    const T* M = sm[4 * m + K];
+    T acc = 0;
+    for (int r = 0; r < TY; ++r)
+      for (int c = 0; c < TX; ++c) acc += M[r * TX + c] * F[r * W + c];
+    part[((size_t)b * gridDim.x + blockIdx.x) * 160 + w] = acc;
+  }
+}
+
+// gw[w] += sum over the tiles of part[tile][w], in a fixed order
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fb_wreduce(const T* __restrict__ part, int ntiles,
+                                                       float* __restrict__ gw) {
+  __shared__ T red[kBlock];
+  const int w = blockIdx.x;
+  T acc = 0;
+  for (int t = threadIdx.x; t < ntiles; t += kBlock) acc += part[(size_t)t * 160 + w];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gw[w] += (float)red[0];
+}
+
 template <typename T>
 __global__ void k_axpy2(T* yu, T* yv, const T* xu, const T* xv, T a, size_t n) {
   for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
@@ -248,31 +392,60 @@ __global__ void k_axpy2(T* yu, T* yv, const T* xu, const T* xv, T a, size_t n) {
   }
 }
 
+// tile of the uniform-kernel gradient reduction: TX = min(nx, 64) columns,
+// TY = min(ny, 256 / TX) rows
+inline void fb_wgrad_tile(int nx, int ny, int* tx, int* ty) {
+  *tx = nx < 64 ? nx : 64;
+  *ty = ny < 256 / *tx ? ny : 256 / *tx;
+}
+
 template <typename T>
 int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
               float* gcoef, size_t gcbs, const void* us, const void* vs, const void* Au,
               const void* Av, const void* Gu, const void* Gv, double aA, double aG,
-              const void* addu, const void* addv, void* ou, void* ov, hipStream_t st) {
+              const void* addu, const void* addv, void* ou, void* ov, hipStream_t st,
+              const FluxBlockArgs* fbp) {
   AdjPhys ph{prm->nu, prm->drag, h->g.lx / h->g.nx, h->g.ly / h->g.ny, prm->physics_mask};
   const int nx = h->g.nx, ny = h->g.ny;
   dim3 grid((unsigned)std::min<size_t>((h->ncell + kBlock - 1) / kBlock, 4096), h->g.batch);
   T* scr = (T*)h->adj_g;
-  if (coef) {
-    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, true>), grid, dim3(kBlock), 0, st, (const T*)us,
+  AdjFB fb{nullptr, nullptr, 0, nullptr, 0};
+  if (fbp) fb = AdjFB{fbp->w, fbp->f, fbp->fbs, fbp->gf, fbp->gfbs};
+  if (fbp && fbp->w) {
+    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 2>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
-                       aG, coef, cbs, gcoef, gcbs, scr, ph, nx, ny);
-    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, true>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
-                       cbs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA, aG,
-                       (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph, nx, ny);
-  } else {
-    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, false>), grid, dim3(kBlock), 0, st, (const T*)us,
+                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, fb, scr,
+                       ph, nx, ny);
+    if (fbp->gw) {
+      int tx, ty;
+      fb_wgrad_tile(nx, ny, &tx, &ty);
+      const int tiles = (nx / tx) * (ny / ty);
+      LDSV_TLAUNCH(h, 6, k_adj_fb_wgrad<T>, dim3(tiles, h->g.batch), dim3(kBlock), 0, st,
+                         (const T*)us, (const T*)vs, (const T*)scr, (T*)h->fb_part, nx, ny, tx, ty);
+      LDSV_TLAUNCH(h, 6, k_fb_wreduce<T>, dim3(160), dim3(kBlock), 0, st, (const T*)h->fb_part,
+                         tiles * h->g.batch, fbp->gw);
+    }
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 2>), grid, dim3(kBlock), 0, st, (const T*)scr,
+                       (const float*)nullptr, (size_t)0, fbp->w, (const T*)Au, (const T*)Av,
+                       (const T*)Gu, (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv,
+                       (T*)ou, (T*)ov, ph, nx, ny);
+  } else if (coef) {
+    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 1>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
-                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, scr, ph,
-                       nx, ny);
-    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, false>), grid, dim3(kBlock), 0, st, (const T*)scr,
-                       (const float*)nullptr, (size_t)0, (const T*)Au, (const T*)Av, (const T*)Gu,
+                       aG, coef, cbs, gcoef, gcbs, fb, scr, ph, nx, ny);
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 1>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
+                       cbs, (const float*)nullptr, (const T*)Au, (const T*)Av, (const T*)Gu,
                        (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph,
                        nx, ny);
+  } else {
+    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 0>), grid, dim3(kBlock), 0, st, (const T*)us,
+                       (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
+                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, fb, scr,
+                       ph, nx, ny);
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 0>), grid, dim3(kBlock), 0, st, (const T*)scr,
+                       (const float*)nullptr, (size_t)0, (const float*)nullptr, (const T*)Au,
+                       (const T*)Av, (const T*)Gu, (const T*)Gv, aA, aG, (const T*)addu,
+                       (const T*)addv, (T*)ou, (T*)ov, ph, nx, ny);
   }
   LDSV_LAUNCHED();
   return LDSV_OK;
@@ -281,6 +454,12 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
 }  // namespace
 
 int ldsv_ensure_adjoint(ldsv_handle* h) {
+  if (!h->fb_part) {
+    int tx, ty;
+    fb_wgrad_tile(h->g.nx, h->g.ny, &tx, &ty);
+    const size_t tiles = (size_t)(h->g.nx / tx) * (h->g.ny / ty) * h->g.batch;
+    LDSV_TRY(ldsv_alloc(h, &h->fb_part, tiles * 160 * h->esize, "flux-block gradient partials"));
+  }
   if (h->adj_g) return LDSV_OK;
   const size_t sb = h->nstate * h->esize;
   // 6 stage planes (u1..u3), A, S, W, G (2 planes each) and 16 scratch planes
@@ -296,12 +475,13 @@ int ldsv_ensure_adjoint(ldsv_handle* h) {
 int ldsv_launch_adj_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
                         float* gcoef, size_t gcbs, const void* us, const void* vs, const void* Au,
                         const void* Av, const void* Gu, const void* Gv, double aA, double aG,
-                        const void* addu, const void* addv, void* ou, void* ov, hipStream_t st) {
+                        const void* addu, const void* addv, void* ou, void* ov, hipStream_t st,
+                        const FluxBlockArgs* fb) {
   if (h->g.dtype == LDSV_F64)
     return adj_rhs_t<double>(h, prm, coef, cbs, gcoef, gcbs, us, vs, Au, Av, Gu, Gv, aA, aG, addu,
-                             addv, ou, ov, st);
+                             addv, ou, ov, st, fb);
   return adj_rhs_t<float>(h, prm, coef, cbs, gcoef, gcbs, us, vs, Au, Av, Gu, Gv, aA, aG, addu,
-                          addv, ou, ov, st);
+                          addv, ou, ov, st, fb);
 }
 
 int ldsv_launch_axpy2(ldsv_handle* h, void* yu, void* yv, const void* xu, const void* xv, double a,

@@ -93,7 +93,7 @@ int check_params(const ldsv_handle* h, const ldsv_params* p) {
 int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs, const void* su,
              const void* sv, void* du, void* dv, const float* tcu, const float* tcv, size_t tcbs,
              hipStream_t st, void* keep = nullptr, const uint16_t* coef16 = nullptr,
-             size_t cbs16 = 0) {
+             size_t cbs16 = 0, const FluxBlockArgs* fb = nullptr) {
   const size_t sbk = h->nstate * h->esize;
   auto ku = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s) * sbk : h->ws_u; };
   auto kv = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s + 1) * sbk : h->ws_v; };
@@ -104,6 +104,11 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
   a.coef_bstride = cbs;
   a.coef16 = coef16;
   a.coef16_bstride = cbs16;
+  if (fb) {
+    a.fbw = fb->w;
+    a.fbf = fb->f;
+    a.fb_bstride = fb->fbs;
+  }
   if (p->rk == LDSV_RK4) {
     const double eps[4] = {0.5 * dt, 0.5 * dt, dt, dt / 6.0};
     for (int s = 0; s < 4; ++s) {
@@ -195,11 +200,19 @@ int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* c
   return one_step(h, p, nullptr, 0, su, sv, du, dv, tcu, tcv, tcbs, st, nullptr, coef16, cbs16);
 }
 
+// the same with the flux block's uniform kernels and fields
+int ldsv_internal_step_fb(ldsv_handle* h, const ldsv_params* p, const FluxBlockArgs* fb,
+                          const void* su, const void* sv, void* du, void* dv, hipStream_t st) {
+  return one_step(h, p, nullptr, 0, su, sv, du, dv, nullptr, nullptr, 0, st, nullptr, nullptr, 0,
+                  fb);
+}
+
 // VJP of one RK4 step with a projection per sub-step (reverse sweep in
 // adjoint.hip's header comment)
 int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
                   float* gcoef, size_t gcbs, const void* su, const void* sv, const void* gu_out,
-                  const void* gv_out, void* gu_in, void* gv_in, hipStream_t st) {
+                  const void* gv_out, void* gu_in, void* gv_in, hipStream_t st,
+                  const FluxBlockArgs* fb) {
   LDSV_REQUIRE(h->g.layout == LDSV_MAC && prm->rk == LDSV_RK4, LDSV_EDTYPE,
                "adjoint: RK4 on the MAC layout only");
   LDSV_TRY(ldsv_ensure_adjoint(h));
@@ -211,7 +224,8 @@ int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, siz
   char* G = A + 6 * sb;
   const double dt = prm->dt;
   // forward recompute keeping u1, u2, u3 (the output goes to W, unused)
-  LDSV_TRY(one_step(h, prm, coef, cbs, su, sv, W, W + sb, nullptr, nullptr, 0, st, K));
+  LDSV_TRY(one_step(h, prm, coef, cbs, su, sv, W, W + sb, nullptr, nullptr, 0, st, K, nullptr, 0,
+                    fb));
   // A = P g, S = A
   LDSV_TRY(ldsv_launch_project(h, gu_out, gv_out, A, A + sb, nullptr, st));
   LDSV_HIP(hipMemcpyAsync(S, A, 2 * sb, hipMemcpyDeviceToDevice, st));
@@ -223,13 +237,13 @@ int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, siz
     LDSV_TRY(ldsv_launch_adj_rhs(h, prm, coef, cbs, gcoef, gcbs, K + 2 * s * sb,
                                  K + (2 * s + 1) * sb, A, A + sb, k ? G : nullptr,
                                  k ? G + sb : nullptr, aA[k], aG[k], nullptr, nullptr, W, W + sb,
-                                 st));
+                                 st, fb));
     LDSV_TRY(ldsv_launch_project(h, W, W + sb, G, G + sb, nullptr, st));
     LDSV_TRY(ldsv_launch_axpy2(h, S, S + sb, G, G + sb, 1.0, st));
   }
   // stage 1: dL/du0 = S + J(u0)^T (dt/6 A + dt/2 g1)
   return ldsv_launch_adj_rhs(h, prm, coef, cbs, gcoef, gcbs, su, sv, A, A + sb, G, G + sb,
-                             dt / 6.0, 0.5 * dt, S, S + sb, gu_in, gv_in, st);
+                             dt / 6.0, 0.5 * dt, S, S + sb, gu_in, gv_in, st, fb);
 }
 
 extern "C" {

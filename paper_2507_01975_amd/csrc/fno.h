@@ -1,0 +1,11 @@
+// Host-side interface of the flux block's FNO kernels.
+#pragma once
+
+#include "internal.h"
+
+// fields [B][8][Ny][Nx] = the two FNOs of net on (u, v); keep_pre keeps every
+// layer's pre-activation in the handle's FNO workspace for the backward
+int ldsv_launch_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u,
+                            const float* v, float* fields, bool keep_pre, hipStream_t st);
+// the handle's [B][8][Ny][Nx] field and field-gradient buffers
+int ldsv_ensure_fluxblock(ldsv_handle* h);

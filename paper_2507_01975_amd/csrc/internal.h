@@ -65,7 +65,7 @@ __device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
 // Optional per-kernel-class timing with HIP events recorded on the launch
 // stream around each launch (used by the benchmark to measure the dominant
 // kernel's average duration inside its timed region).
-constexpr int kTimerClasses = 8;
+constexpr int kTimerClasses = 10;
 struct KernelTimer {
   bool on = false;
   std::vector<hipEvent_t> ev[kTimerClasses];  // start/stop pairs
@@ -118,6 +118,13 @@ struct ldsv_handle {
   void* zpre_blk = nullptr;      // network backward workspace
   void* roll_blk = nullptr;      // rollout-backward checkpoints and segment states
   size_t roll_bytes = 0;
+  // flux-block workspace (Sec. 3.4 O_L + O_F): per-tile partial sums of the
+  // uniform-kernel gradient, the FNO fields of a step and the FNO buffers
+  void* fb_part = nullptr;       // [B x tiles][160] of the grid dtype
+  float* fb_fields = nullptr;    // [B][8][Ny][Nx]
+  float* fb_gfields = nullptr;   // [B][8][Ny][Nx] gradient of the fields
+  void* fno_blk = nullptr;       // FNO buffers (fno.hip), fno_bytes long
+  size_t fno_bytes = 0;
   size_t bytes = 0;
   std::vector<void*> allocs;     // base pointers of every device allocation owned
   KernelTimer timer;

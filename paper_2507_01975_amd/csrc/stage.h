@@ -26,7 +26,26 @@ struct StageArgs {
   const float* tcu = nullptr;   // temporal correction added to out, nullable
   const float* tcv = nullptr;
   size_t tc_bstride = 0;
+  // flux block (used when fbw is set): uniform kernels [2][4][20] (interp,
+  // deriv) and optional fields [B][8][Ny][Nx]
+  const float* fbw = nullptr;
+  const float* fbf = nullptr;
+  size_t fb_bstride = 0;
   double alpha = 0, beta = 0, delta = 0, eps = 0, gamma = 0, wacc = 0;
+};
+
+// Flux-block operands of a step (Sec. 3.4, Eqs. 5-8): uniform kernels
+// w [2][4][20] (interp, deriv; FP32, device) and per-cell fields
+// f [B][8][Ny][Nx] (FP32, nullable; batch stride fbs).  The adjoint
+// accumulates dL/dw into gw [160] and dL/df into gf (same layout, batch
+// stride gfbs); both nullable.
+struct FluxBlockArgs {
+  const float* w = nullptr;
+  const float* f = nullptr;
+  size_t fbs = 0;
+  float* gw = nullptr;
+  float* gf = nullptr;
+  size_t gfbs = 0;
 };
 
 int ldsv_launch_stage(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a,

@@ -13,6 +13,12 @@
 // Collocated (2D viscous Burgers, S25): flux form minus q*div with a
 // second-order linear-upwind advected value and compact viscous term.
 //
+// Flux-block mode (Sec. 3.4, Eqs. 5-8): each interpolated value and each
+// face derivative is O_P + O_L + O_F: the physics kernel, a spatially
+// uniform learnable 5x4 kernel of the kind (20 weights, derivative weights
+// scaled by 1/h) and a per-cell field of the kind added at the face the
+// cell owns.
+//
 // One workgroup owns a TX x TY tile of cells.  It stages the stage state
 // with a periodic halo of 2 cells in LDS, computes every face flux once
 // (each face belongs to exactly one cell: the east face of the x-fluxes and
@@ -50,6 +56,15 @@ struct CombT {
   int need_un, need_acc;
 };
 
+// the 5x4 window of the uniform kernels: points 0..15 as above, then the
+// four corners
+__device__ __forceinline__ constexpr int a_off20(int s) {
+  return s < 12 ? s % 4 - 1 : (s < 16 ? (s & 1) : (s & 1 ? 2 : -1));
+}
+__device__ __forceinline__ constexpr int b_off20(int s) {
+  return s < 12 ? s / 4 - 1 : (s < 14 ? -2 : (s < 16 ? 2 : (s < 18 ? -2 : 2)));
+}
+
 template <typename T>
 struct StagePtrs {
   const T* us;
@@ -69,6 +84,9 @@ struct StagePtrs {
   const float* tcu;
   const float* tcv;
   size_t tcbs;
+  const float* fbw;  // flux block: [interp, deriv][kind][20] uniform weights
+  const float* fbf;  // flux block: [B][8][Ny][Nx] fields (interp kinds, deriv kinds), nullable
+  size_t fbs;
 };
 
 __device__ __forceinline__ float coef_value(const float* p) { return *p; }
@@ -101,7 +119,24 @@ __device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const
   return acc + (T)0.5 * (q0 + q1);
 }
 
-// COEF: 0 plain stencil, 1 float raw coefficients, 2 bf16 raw coefficients
+// uniform 5x4 kernel w (20 weights) at the face owned by tile point (lj, li)
+template <typename T, bool ALONG_X, int W>
+__device__ __forceinline__ T uniform_face(const T (*S)[W], int lj, int li, const float* w) {
+  T acc = 0;
+#pragma unroll
+  for (int s = 0; s < 20; ++s) {
+    const T q = ALONG_X ? S[lj + b_off20(s)][li + a_off20(s)] : S[lj + a_off20(s)][li + b_off20(s)];
+    acc += (T)w[s] * q;
+  }
+  return acc;
+}
+
+__device__ __forceinline__ float fb_field(const float* f, size_t plane, int ch, size_t off) {
+  return f ? f[(size_t)ch * plane + off] : 0.f;
+}
+
+// COEF: 0 plain stencil, 1 float raw coefficients, 2 bf16 raw coefficients,
+// 3 flux block (uniform kernels and fields)
 template <typename T, int COEF, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny) {
@@ -185,6 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   const T i24dx = ph.i24dx, i24dy = ph.i24dy;
   const float* cbf = COEF == 1 ? p.coef + (size_t)b * p.cbs : nullptr;
   const uint16_t* cbh = COEF == 2 ? p.coef16 + (size_t)b * p.cbs16 : nullptr;
+  const float* fbf = COEF == 3 && p.fbf ? p.fbf + (size_t)b * p.fbs : nullptr;
 
   // x-faces: owners i in [i0-1, i0+TX-1], rows j in [j0, j0+TY-1]
   constexpr int kXF = TY * (TX + 1);
@@ -194,12 +230,18 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
     if (t >= kXF) break;
     const int r = t / (TX + 1), c = t - r * (TX + 1);
     const int li = c + 1, lj = r + kH;
+    [[maybe_unused]] const size_t xoff = (size_t)(j0 + r) * nx + ((i0 - 1 + c + nx) & (nx - 1));
     T fu = 0, fv = 0;
     if (adv) {
       const T ubar = (T)0.5 * (su[lj][li] + su[lj][li + 1]);
       const T ubar_e = (T)0.5 * (su[lj - 1][li + 1] + su[lj][li + 1]);
       T uf, vf;
-      if constexpr (COEF != 0) {
+      if constexpr (COEF == 3) {
+        uf = (T)0.5 * (su[lj][li] + su[lj][li + 1]) + uniform_face<T, true, W>(su, lj, li, p.fbw) +
+             (T)fb_field(fbf, plane, 0, xoff);
+        vf = (T)0.5 * (sv[lj][li] + sv[lj][li + 1]) +
+             uniform_face<T, true, W>(sv, lj, li, p.fbw + 40) + (T)fb_field(fbf, plane, 2, xoff);
+      } else if constexpr (COEF != 0) {
         const int gi = (i0 - 1 + c + nx) & (nx - 1);
         const size_t off = (size_t)(j0 + r) * nx + gi;
         if constexpr (COEF == 1) {
@@ -217,8 +259,19 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       fv = ubar_e * vf;
     }
     if (visc) {
-      fu -= nu * (su[lj][li - 1] - (T)27 * su[lj][li] + (T)27 * su[lj][li + 1] - su[lj][li + 2]) * i24dx;
-      fv -= nu * (sv[lj][li - 1] - (T)27 * sv[lj][li] + (T)27 * sv[lj][li + 1] - sv[lj][li + 2]) * i24dx;
+      if constexpr (COEF == 3) {
+        const T du = (su[lj][li - 1] - (T)27 * su[lj][li] + (T)27 * su[lj][li + 1] - su[lj][li + 2]) * i24dx +
+                     uniform_face<T, true, W>(su, lj, li, p.fbw + 80) * ph.idx +
+                     (T)fb_field(fbf, plane, 4, xoff);
+        const T dv = (sv[lj][li - 1] - (T)27 * sv[lj][li] + (T)27 * sv[lj][li + 1] - sv[lj][li + 2]) * i24dx +
+                     uniform_face<T, true, W>(sv, lj, li, p.fbw + 120) * ph.idx +
+                     (T)fb_field(fbf, plane, 6, xoff);
+        fu -= nu * du;
+        fv -= nu * dv;
+      } else {
+        fu -= nu * (su[lj][li - 1] - (T)27 * su[lj][li] + (T)27 * su[lj][li + 1] - su[lj][li + 2]) * i24dx;
+        fv -= nu * (sv[lj][li - 1] - (T)27 * sv[lj][li] + (T)27 * sv[lj][li + 1] - sv[lj][li + 2]) * i24dx;
+      }
     }
     fux[r][c] = fu;
     fvx[r][c] = fv;
@@ -231,12 +284,18 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
     if (t >= kYF) break;
     const int r = t / TX, c = t - r * TX;
     const int li = c + kH, lj = r + 1;
+    [[maybe_unused]] const size_t yoff = (size_t)((j0 - 1 + r + ny) & (ny - 1)) * nx + (i0 + c);
     T fu = 0, fv = 0;
     if (adv) {
       const T vbar_n = (T)0.5 * (sv[lj + 1][li - 1] + sv[lj + 1][li]);
       const T vbar_c = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]);
       T uf, vf;
-      if constexpr (COEF != 0) {
+      if constexpr (COEF == 3) {
+        uf = (T)0.5 * (su[lj][li] + su[lj + 1][li]) +
+             uniform_face<T, false, W>(su, lj, li, p.fbw + 20) + (T)fb_field(fbf, plane, 1, yoff);
+        vf = (T)0.5 * (sv[lj][li] + sv[lj + 1][li]) +
+             uniform_face<T, false, W>(sv, lj, li, p.fbw + 60) + (T)fb_field(fbf, plane, 3, yoff);
+      } else if constexpr (COEF != 0) {
         const int gj = (j0 - 1 + r + ny) & (ny - 1);
         const size_t off = (size_t)gj * nx + (i0 + c);
         if constexpr (COEF == 1) {
@@ -254,8 +313,19 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       fv = vbar_c * vf;
     }
     if (visc) {
-      fu -= nu * (su[lj - 1][li] - (T)27 * su[lj][li] + (T)27 * su[lj + 1][li] - su[lj + 2][li]) * i24dy;
-      fv -= nu * (sv[lj - 1][li] - (T)27 * sv[lj][li] + (T)27 * sv[lj + 1][li] - sv[lj + 2][li]) * i24dy;
+      if constexpr (COEF == 3) {
+        const T du = (su[lj - 1][li] - (T)27 * su[lj][li] + (T)27 * su[lj + 1][li] - su[lj + 2][li]) * i24dy +
+                     uniform_face<T, false, W>(su, lj, li, p.fbw + 100) * ph.idy +
+                     (T)fb_field(fbf, plane, 5, yoff);
+        const T dv = (sv[lj - 1][li] - (T)27 * sv[lj][li] + (T)27 * sv[lj + 1][li] - sv[lj + 2][li]) * i24dy +
+                     uniform_face<T, false, W>(sv, lj, li, p.fbw + 140) * ph.idy +
+                     (T)fb_field(fbf, plane, 7, yoff);
+        fu -= nu * du;
+        fv -= nu * dv;
+      } else {
+        fu -= nu * (su[lj - 1][li] - (T)27 * su[lj][li] + (T)27 * su[lj + 1][li] - su[lj + 2][li]) * i24dy;
+        fv -= nu * (sv[lj - 1][li] - (T)27 * sv[lj][li] + (T)27 * sv[lj + 1][li] - sv[lj + 2][li]) * i24dy;
+      }
     }
     fuy[r][c] = fu;
     fvy[r][c] = fv;
@@ -427,6 +497,9 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   p.tcu = a.tcu;
   p.tcv = a.tcv;
   p.tcbs = a.tc_bstride;
+  p.fbw = a.fbw;
+  p.fbf = a.fbf;
+  p.fbs = a.fb_bstride;
   const double dx = h->g.lx / h->g.nx, dy = h->g.ly / h->g.ny;
   PhysT<T> ph;
   ph.nu = (T)prm->nu;
@@ -456,7 +529,10 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   dim3 grid((nx / TX) * (ny / TY), h->g.batch);
 #define LDSV_STAGE_CASE(tx, ty)                                                                   \
   if (TX == tx && TY == ty) {                                                                     \
-    if (a.coef16)                                                                                 \
+    if (a.fbw)                                                                                    \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 3, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
+                   ny);                                                                           \
+    else if (a.coef16)                                                                            \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 2, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
     else if (a.coef)                                                                              \

@@ -67,6 +67,18 @@ class NetGrad(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p * NLAYERS), ("b", ctypes.c_void_p * NLAYERS)]
 
 
+class Fno(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("layers", ctypes.c_int), ("modes", ctypes.c_int),
+                ("lift_w", ctypes.c_void_p), ("lift_b", ctypes.c_void_p),
+                ("spec_w", ctypes.c_void_p), ("point_w", ctypes.c_void_p),
+                ("point_b", ctypes.c_void_p), ("proj_w", ctypes.c_void_p),
+                ("proj_b", ctypes.c_void_p)]
+
+
+class FluxNet(ctypes.Structure):
+    _fields_ = [("stencil_w", ctypes.c_void_p), ("fno", ctypes.POINTER(Fno) * 2)]
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
@@ -105,13 +117,20 @@ _SIGS = {
     "ldsv_pcc": ([_vp, _vp, _vp, _vp, _vp], _i),
     "ldsv_diagnostics": ([_vp, _vp, _vp, _vp, _vp], _i),
     "ldsv_cfl_dt": ([_vp, _vp, _vp, _d, ctypes.POINTER(_d), _vp], _i),
+    "ldsv_fno_forward": ([_vp, ctypes.POINTER(FluxNet), _vp, _vp, _vp, _vp], _i),
+    "ldsv_fluxblock_fv_step": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _i,
+                                _vp], _i),
+    "ldsv_fluxblock_fv_step_bwd": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _vp, _vp, _vp, _vp], _i),
+    "ldsv_fluxblock_step": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(FluxNet), _vp, _vp, _vp,
+                             _vp, _vp, _vp], _i),
     "ldsv_timer_enable": ([_vp, _i], _i),
     "ldsv_timer_read": ([_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i)], _i),
 }
 
 # kernel classes of ldsv_timer_read
 TIMER_STAGE, TIMER_ROWFFT, TIMER_COLSOLVE, TIMER_ROWIFFT, TIMER_CONV, TIMER_CONV0, TIMER_ADJ, \
-    TIMER_OTHER = range(8)
+    TIMER_OTHER, TIMER_FNO_FFT, TIMER_FNO_MIX = range(10)
 
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -341,6 +360,56 @@ class Solver:
                                      _stream()))
         return out
 
+    # ---- the paper's flux block (O_P + O_L + O_F)
+    def _fields(self, f, name="fields"):
+        if f is None:
+            return None
+        if not (f.is_cuda and f.dtype == torch.float32 and f.is_contiguous()
+                and tuple(f.shape) == (self.batch, 8, self.ny, self.nx)):
+            raise ValueError("%s must be float32 [B, 8, Ny, Nx] contiguous on cuda" % name)
+        return _ptr(f)
+
+    @staticmethod
+    def _stencil(w, name="stencil_w"):
+        if w is None:
+            return None
+        if not (w.is_cuda and w.dtype == torch.float32 and w.is_contiguous() and w.numel() == 160):
+            raise ValueError("%s must be float32 [2, 4, 20] contiguous on cuda" % name)
+        return _ptr(w)
+
+    def fno_forward(self, net, u, v):
+        out = torch.empty(self.batch, 8, self.ny, self.nx, dtype=torch.float32, device="cuda")
+        _check(_lib.ldsv_fno_forward(self._h, ctypes.byref(net.c), self._state(u),
+                                     self._state(v), _ptr(out), _stream()))
+        return out
+
+    def fluxblock_fv_step(self, prm, stencil_w, fields, u, v, nsteps=1, out=None):
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        _check(_lib.ldsv_fluxblock_fv_step(self._h, ctypes.byref(prm), self._stencil(stencil_w),
+                                           self._fields(fields), self._state(u), self._state(v),
+                                           self._state(uo), self._state(vo), nsteps, _stream()))
+        return uo, vo
+
+    def fluxblock_fv_step_bwd(self, prm, stencil_w, fields, u, v, gu_out, gv_out, gstencil=None,
+                              gfields=None):
+        gu, gv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_fluxblock_fv_step_bwd(
+            self._h, ctypes.byref(prm), self._stencil(stencil_w), self._fields(fields),
+            self._state(u), self._state(v), self._state(gu_out), self._state(gv_out), _ptr(gu),
+            _ptr(gv), self._stencil(gstencil, "gstencil"), self._fields(gfields, "gfields"),
+            _stream()))
+        return gu, gv
+
+    def fluxblock_step(self, prm, net, u, v, want_fields=False, out=None):
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        f = None
+        if want_fields:
+            f = torch.empty(self.batch, 8, self.ny, self.nx, dtype=torch.float32, device="cuda")
+        _check(_lib.ldsv_fluxblock_step(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                        self._state(u), self._state(v), self._state(uo),
+                                        self._state(vo), _ptr(f), _stream()))
+        return (uo, vo, f) if want_fields else (uo, vo)
+
     def timer_enable(self, on=True):
         _check(_lib.ldsv_timer_enable(self._h, 1 if on else 0))
 
@@ -412,3 +481,54 @@ class NetGradBuffers:
 def adam_step(w, g, m, v, t, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
     _check(_lib.ldsv_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), t, lr, b1, b2, eps,
                                _stream()))
+
+
+class FnoParams:
+    """Device copy of one FNO of the flux block (float32): lift_w [C, 2],
+    lift_b [C], spec_w [L, C_in, C_out, 2M, M, 2] (complex as re, im),
+    point_w [L, C_out, C_in], point_b [L, C], proj_w [4, C], proj_b [4]."""
+
+    def __init__(self, lift_w, lift_b, spec, point_w, point_b, proj_w, proj_b):
+        """spec: list over layers of complex [2M, M, C_in, C_out] tensors (the
+        retained-row, k_x, in, out order), or of (re, im) pairs of real ones."""
+        f32 = lambda t: torch.as_tensor(t).detach().to("cuda", torch.float32).contiguous()
+        self.lift_w, self.lift_b = f32(lift_w), f32(lift_b)
+        layers = []
+        for R in spec:
+            if isinstance(R, (tuple, list)):
+                re, im = (torch.as_tensor(x, dtype=torch.float64) for x in R)
+            else:
+                R = torch.as_tensor(R)
+                re, im = R.real.double(), R.imag.double()
+            z = torch.stack([re, im], dim=-1)                 # [2M, M, Ci, Co, 2]
+            layers.append(z.permute(2, 3, 0, 1, 4))           # [Ci, Co, 2M, M, 2]
+        self.spec_w = f32(torch.stack(layers))
+        self.point_w, self.point_b = f32(point_w), f32(point_b)
+        self.proj_w, self.proj_b = f32(proj_w), f32(proj_b)
+        L, C, _, two_m, M, _ = self.spec_w.shape
+        self.c = Fno(C, L, M, self.lift_w.data_ptr(), self.lift_b.data_ptr(),
+                     self.spec_w.data_ptr(), self.point_w.data_ptr(), self.point_b.data_ptr(),
+                     self.proj_w.data_ptr(), self.proj_b.data_ptr())
+
+    @classmethod
+    def from_arrays(cls, a):
+        """From the real arrays of synthetic_inputs.fno_weights."""
+        import numpy as np
+        return cls(a["P_w"], a["P_b"], [(l["R_re"], l["R_im"]) for l in a["layers"]],
+                   np.stack([l["W"] for l in a["layers"]]),
+                   np.stack([l["b"] for l in a["layers"]]), a["Q_w"], a["Q_b"])
+
+
+class FluxNetParams:
+    """The flux block's learnable parameters: uniform kernels stencil_w
+    [2, 4, 20] (interpolation, derivative) and the two FNOs (either may be
+    None)."""
+
+    def __init__(self, stencil_w, fno_i=None, fno_d=None):
+        self.stencil_w = torch.as_tensor(stencil_w).detach().to("cuda", torch.float32) \
+            .reshape(2, 4, 20).contiguous()
+        self.fno = [fno_i, fno_d]
+        self.c = FluxNet()
+        self.c.stencil_w = self.stencil_w.data_ptr()
+        for g, f in enumerate(self.fno):
+            self.c.fno[g] = ctypes.pointer(f.c) if f is not None else ctypes.POINTER(Fno)()

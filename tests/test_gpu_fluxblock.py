@@ -1,0 +1,174 @@
+"""GPU parity of the flux block (Sec. 3.4, Eqs. 5-8) through the C ABI
+against the FP64 oracle: the FV step with uniform 5x4 kernels and face
+fields, its adjoint (state, kernel and field gradients), the two FNOs and
+the model step.
+
+Tolerances: the FV step and its adjoint keep the plain step's bars (rel-L2
+1e-5 per FP32 step, 1e-12 in FP64; adjoint 1e-4 in FP32).  The FNO runs in
+FP32 through L layers of two 2D FFTs (O(log2 N) rounding steps each) and a
+C-term complex sum per mode: about L (2 log2 N + C) 2^-24 ~ 6 (24 + 16)
+6e-8 ~ 1.4e-5 relative; the bar is 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic_inputs as si
+from oracle import fluxblock, fno, fv, ic, timestep
+from tests.gpu_common import L, announce, cpu64, dev, need_gpu, oracle_prm, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(nu=0.01, dt=0.02, forcing_amp=1.0, forcing_k=4.0, drag=0.1)
+
+
+def _stencils(seed, scale=0.05):
+    w = np.stack([si.stencil_weights(seed, scale), si.stencil_weights(seed + 1, scale)])
+    return torch.tensor(w, dtype=torch.float32)                     # [2, 4, 20]
+
+
+def _fields(seed, b, n, m, scale=0.05):
+    return torch.tensor(si.random_field(seed, (b, 8, m, n), scale=scale), dtype=torch.float32)
+
+
+def _record(w32, f32):
+    w = w32.double()
+    f = f32.double() if f32 is not None else None
+    return {"wi": w[0], "wd": w[1], "fi": f[:, :4] if f is not None else None,
+            "fd": f[:, 4:] if f is not None else None}
+
+
+@pytest.mark.parametrize("nx,ny,b,dtype,tol", [
+    (64, 64, 2, torch.float32, 1e-5), (128, 32, 3, torch.float32, 1e-5),
+    (32, 32, 2, torch.float64, 1e-12)])
+def test_fluxblock_fv_step_matches_oracle(nx, ny, b, dtype, tol):
+    L_ = need_gpu()
+    announce("fluxblock fv step", nx, ny, b, dtype)
+    s = L_.Solver(nx, ny, b, dtype=dtype)
+    u0, v0 = ic.grf_peak(b, nx, ny, L, L, seed=5)
+    u = dev(u0, dtype)
+    v = dev(v0, dtype)
+    w = _stencils(7)
+    f = _fields(9, b, nx, ny)
+    prm = L_.params(**KW)
+    uo, vo = s.fluxblock_fv_step(prm, w.cuda(), f.cuda(), u, v, nsteps=2)
+    ref = timestep.fv_step(cpu64(u), cpu64(v), oracle_prm(nx, ny, **KW), nsteps=2,
+                           flux=_record(w, f))
+    assert rel_l2(uo, ref[0]) < tol and rel_l2(vo, ref[1]) < tol
+
+
+def test_empty_flux_block_is_the_plain_step():
+    """Zero kernels and fields leave the physics operator: the plain step's
+    result up to the different association of the viscous product (the flux
+    block forms nu * (D + learned), the plain path nu * D_sum / (24 h))."""
+    L_ = need_gpu()
+    announce("fluxblock zero")
+    n, b = 64, 2
+    s = L_.Solver(n, n, b)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=6)
+    u, v = dev(u0, torch.float32), dev(v0, torch.float32)
+    prm = L_.params(**KW)
+    w = torch.zeros(2, 4, 20, device="cuda")
+    f = torch.zeros(b, 8, n, n, device="cuda")
+    a = s.fluxblock_fv_step(prm, w, f, u, v)
+    p = s.fv_step(prm, u, v)
+    assert rel_l2(a[0], p[0]) < 1e-6 and rel_l2(a[1], p[1]) < 1e-6
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+def test_fluxblock_fv_step_bwd_matches_oracle_autograd(dtype, tol):
+    L_ = need_gpu()
+    announce("fluxblock fv step bwd", dtype)
+    n, b = 32, 2
+    s = L_.Solver(n, n, b, dtype=dtype)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=15)
+    u, v = dev(u0, dtype), dev(v0, dtype)
+    w = _stencils(17)
+    f = _fields(19, b, n, n)
+    g = torch.Generator().manual_seed(3)
+    gu_out = torch.randn(b, n, n, generator=g, dtype=torch.float64)
+    gv_out = torch.randn(b, n, n, generator=g, dtype=torch.float64)
+    prm = L_.params(**KW)
+    gw = torch.zeros(2, 4, 20, device="cuda")
+    gf = torch.zeros(b, 8, n, n, device="cuda")
+    gu, gv = s.fluxblock_fv_step_bwd(prm, w.cuda(), f.cuda(), u, v, dev(gu_out, dtype),
+                                     dev(gv_out, dtype), gstencil=gw, gfields=gf)
+    ua, va = cpu64(u).requires_grad_(True), cpu64(v).requires_grad_(True)
+    wr = w.double().requires_grad_(True)
+    fr = f.double().requires_grad_(True)
+    rec = {"wi": wr[0], "wd": wr[1], "fi": fr[:, :4], "fd": fr[:, 4:]}
+    x, y = timestep.fv_step(ua, va, oracle_prm(n, n, **KW), flux=rec)
+    ((gu_out * x).sum() + (gv_out * y).sum()).backward()
+    assert rel_l2(gu, ua.grad) < tol and rel_l2(gv, va.grad) < tol
+    # the kernel and field gradients are stored in float32 whatever the grid
+    # dtype: one rounding, 2^-24 relative
+    gtol = max(tol, 2e-7)
+    assert rel_l2(gw, wr.grad) < gtol
+    assert rel_l2(gf, fr.grad) < gtol
+
+
+def _fno_pair(seed, cfg, out_scale=0.05):
+    layers, modes, width = si.FLUXBLOCK_FNO[cfg]
+    a_i = si.fno_weights(seed, width, layers, modes, out_scale=out_scale)
+    a_d = si.fno_weights(seed + 1, width, layers, modes, out_scale=out_scale)
+    return a_i, a_d
+
+
+@pytest.mark.parametrize("cfg,n,b", [("forced", 64, 4), ("decaying", 128, 2)])
+def test_fno_forward_matches_oracle(cfg, n, b):
+    """Both FNOs at the paper's hyper-parameters (forced: 6 layers, 32 modes,
+    width 16 on 64^2; decaying: 4 layers, 16 modes, width 8 on 128^2); the
+    last layer is given O(1) weights so the fields are not small."""
+    L_ = need_gpu()
+    announce("fno forward", cfg, n, b)
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(21, cfg, out_scale=1.0)
+    net = L_.FluxNetParams(_stencils(23), L_.FnoParams.from_arrays(a_i),
+                           L_.FnoParams.from_arrays(a_d))
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=25)
+    u, v = dev(u0, torch.float32), dev(v0, torch.float32)
+    got = s.fno_forward(net, u, v)
+    x = torch.stack([cpu64(u), cpu64(v)], dim=1)
+    ref_i = fno.fno_forward(x, fno.from_arrays(a_i))
+    ref_d = fno.fno_forward(x, fno.from_arrays(a_d))
+    assert rel_l2(got[:, :4], ref_i) < 1e-4
+    assert rel_l2(got[:, 4:], ref_d) < 1e-4
+
+
+def test_fno_forward_one_operator_and_none():
+    """An absent operator gives zero fields; a present one is unaffected."""
+    L_ = need_gpu()
+    announce("fno forward absent")
+    n, b = 64, 2
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(31, "decaying", out_scale=1.0)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=33)
+    u, v = dev(u0, torch.float32), dev(v0, torch.float32)
+    only_d = L_.FluxNetParams(_stencils(1), None, L_.FnoParams.from_arrays(a_d))
+    got = s.fno_forward(only_d, u, v)
+    assert torch.count_nonzero(got[:, :4]).item() == 0
+    x = torch.stack([cpu64(u), cpu64(v)], dim=1)
+    assert rel_l2(got[:, 4:], fno.fno_forward(x, fno.from_arrays(a_d))) < 1e-4
+    none = L_.FluxNetParams(_stencils(1))
+    assert torch.count_nonzero(s.fno_forward(none, u, v)).item() == 0
+
+
+@pytest.mark.parametrize("cfg,n,b", [("forced", 64, 4), ("decaying", 128, 2)])
+def test_fluxblock_step_matches_oracle(cfg, n, b):
+    L_ = need_gpu()
+    announce("fluxblock step", cfg, n, b)
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(41, cfg)
+    w = _stencils(43)
+    net = L_.FluxNetParams(w, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=45)
+    u, v = dev(u0, torch.float32), dev(v0, torch.float32)
+    kw = KW if cfg == "forced" else dict(nu=1e-3, dt=0.0035)
+    prm = L_.params(**kw)
+    uo, vo, f = s.fluxblock_step(prm, net, u, v, want_fields=True)
+    params = {"wi": w[0].double(), "wd": w[1].double(), "fno_i": fno.from_arrays(a_i),
+              "fno_d": fno.from_arrays(a_d)}
+    ru, rv = fluxblock.fluxblock_step(cpu64(u), cpu64(v), oracle_prm(n, n, **kw), params)
+    assert rel_l2(uo, ru) < 1e-5 and rel_l2(vo, rv) < 1e-5
+    # the step used the fields it returned
+    a = s.fluxblock_fv_step(prm, net.stencil_w, f, u, v)
+    assert torch.equal(a[0], uo) and torch.equal(a[1], vo)
