@@ -126,7 +126,8 @@ def fp64_errors():
     """Errors of the other results against the FP64 oracle (the oracle is run
     here as the checker, outside every timed region): the learned step of the
     forced-flow workload (trajectory 0 of the batch of 64, bench network),
-    its network output, and 200 FP64 Burgers steps."""
+    its network output, the flux-block step of the same workload, and 200
+    FP64 Burgers steps."""
     import torch
     import synthetic_inputs as si
     from oracle import cnn as ocnn, fv as ofv, ic as oic, learned as olearned
@@ -149,6 +150,14 @@ def fp64_errors():
     eu, ev, eo = olearned.learned_fv_step(u0, v0, prm, wb, bb, 1, bf16=False)
     out["learned_step_rel_l2_vs_fp64"] = max(_rel_l2(uo[:1], eu), _rel_l2(vo[:1], ev))
     out["network_output_rel_l2_vs_fp64"] = _rel_l2(no[:1], eo)
+    # the flux-block model step of the same workload (trajectory 0)
+    from oracle import fluxblock as ofb, fno as ofno
+    fnet, (fw, a_i, a_d) = _fluxblock_net("forced", ldsv)
+    fu, fv_ = s.fluxblock_step(ldsv.params(**kw), fnet, u, v)
+    fparams = {"wi": torch.tensor(fw[0]), "wd": torch.tensor(fw[1]),
+               "fno_i": ofno.from_arrays(a_i), "fno_d": ofno.from_arrays(a_d)}
+    ru, rv = ofb.fluxblock_step(u0, v0, ofv.grid_params(n, n, **kw), fparams)
+    out["fluxblock_step_rel_l2_vs_fp64"] = max(_rel_l2(fu[:1], ru), _rel_l2(fv_[:1], rv))
     s.close()
     wb_ = si.WORKLOADS["burgers64"]
     nb = wb_["nx"]
@@ -211,6 +220,85 @@ def learned_block(steps, warmup):
         out["mfma_conv"] = {"tflops": flop / launches_per_step / (per_launch_ms * 1e-3) / 1e12,
                             "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}
         out["mfma_conv"]["frac"] = out["mfma_conv"]["tflops"] / BF16_PEAK_TFLOPS
+    return out
+
+
+def _fluxblock_net(cfg, ldsv, seed=0):
+    import numpy as np
+    import synthetic_inputs as si
+    layers, modes, width = si.FLUXBLOCK_FNO[cfg]
+    w = np.stack([si.stencil_weights(seed, 0.01), si.stencil_weights(seed + 1, 0.01)])
+    a_i = si.fno_weights(seed + 2, width, layers, modes)
+    a_d = si.fno_weights(seed + 3, width, layers, modes)
+    net = ldsv.FluxNetParams(w, ldsv.FnoParams.from_arrays(a_i), ldsv.FnoParams.from_arrays(a_d))
+    return net, (w, a_i, a_d)
+
+
+def fluxblock_block(steps, warmup):
+    """The paper's own flux block (uniform 5x4 kernels + two FNOs, Sec. 3.4)
+    as the learned model of the forced 64^2 configuration (batch 64, FNO: 6
+    layers, 32 modes, width 16): throughput and per-class kernel time, and
+    the HBM rate of the FNO transform kernels against their algorithmic
+    bytes (per layer: the activation read and written once, the retained
+    spectrum written and read once)."""
+    import torch
+    import synthetic_inputs as si
+    from paper_2507_01975_amd import ldsv
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    layers, modes, width = si.FLUXBLOCK_FNO["forced"]
+    s = ldsv.Solver(n, n, B)
+    net, _ = _fluxblock_net("forced", ldsv)
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
+    u2, v2 = torch.empty_like(u), torch.empty_like(v)
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                      forcing_k=w["forcing_k"], drag=w["drag"])
+
+    def run(k):
+        nonlocal u, v, u2, v2
+        for _ in range(k):
+            s.fluxblock_step(prm, net, u, v, out=(u2, v2))
+            u, v, u2, v2 = u2, v2, u, v
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.timer_enable(True)
+    run(steps)
+    torch.cuda.synchronize()
+    cls = {c: s.timer_read(c) for c in (ldsv.TIMER_STAGE, ldsv.TIMER_ROWFFT, ldsv.TIMER_COLSOLVE,
+                                        ldsv.TIMER_ROWIFFT, ldsv.TIMER_FNO_FFT,
+                                        ldsv.TIMER_FNO_MIX, ldsv.TIMER_OTHER)}
+    s.timer_enable(False)
+    diag = s.diagnostics(u, v).cpu()
+    cells = n * n * B
+    nm = 2 * modes * modes
+    G = 2
+    act = G * B * width * n * n * 4
+    spec = G * B * width * nm * 8
+    # spectral kernels per step: layer 0 reads (u, v) instead of an activation
+    fft_bytes = layers * (2 * spec + 2 * act) - act + 2 * B * n * n * 4
+    mix_bytes = layers * (2 * spec + G * width * width * nm * 8)
+    out = {"workload": "kolmogorov64 flux-block step (64^2, batch 64, uniform 5x4 kernels + "
+                       "2 FNOs of 6 layers, 32 modes, width 16)",
+           "cell_steps_per_s": cells * steps / t, "ms_per_step": 1e3 * t / steps,
+           "sim_time_per_s": w["dt"] * steps / t, "finite": bool((diag[:, 5] == 1).all()),
+           "classes_ms_per_step": {k: cls[c][0] / steps for k, c in (
+               ("stage", ldsv.TIMER_STAGE), ("project", ldsv.TIMER_COLSOLVE),
+               ("fno_fft", ldsv.TIMER_FNO_FFT), ("fno_mix", ldsv.TIMER_FNO_MIX),
+               ("fno_proj", ldsv.TIMER_OTHER))}}
+    if cls[ldsv.TIMER_FNO_FFT][1]:
+        tf = cls[ldsv.TIMER_FNO_FFT][0] * 1e-3 / steps
+        out["fno_fft_hbm"] = {"achieved": fft_bytes / tf / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": fft_bytes / tf / 1e9 / HBM_PEAK_GBS,
+                              "alg_bytes_per_step": fft_bytes}
+    if cls[ldsv.TIMER_FNO_MIX][1]:
+        tm = cls[ldsv.TIMER_FNO_MIX][0] * 1e-3 / steps
+        out["fno_mix_hbm"] = {"achieved": mix_bytes / tm / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": mix_bytes / tm / 1e9 / HBM_PEAK_GBS,
+                              "alg_bytes_per_step": mix_bytes}
     return out
 
 
@@ -366,7 +454,8 @@ def main():
         log("copy probe: %d MiB" % a.copy_probe_mib)
         del src, dst
     if a.learned_only:
-        print(json.dumps({"learned": learned_block(a.steps, a.warmup)}), flush=True)
+        print(json.dumps({"learned": learned_block(a.steps, a.warmup),
+                          "fluxblock": fluxblock_block(a.steps, a.warmup)}), flush=True)
         return
 
     w = si.WORKLOADS["decaying512"]
@@ -429,6 +518,8 @@ def main():
     if not a.no_learned:
         log("learned step")
         line["learned"] = learned_block(max(10, a.steps // 4), 3)
+        log("flux-block step")
+        line["fluxblock"] = fluxblock_block(max(10, a.steps // 4), 3)
     if not a.no_extra:
         log("streaming shape 1024^2 x 128")
         line["streaming"] = streaming_block()

@@ -329,6 +329,23 @@ typedef struct {
                               given they share width, layers and modes */
 } ldsv_fluxnet;
 
+/* Gradients of the flux block's parameters (float, same layouts as
+ * ldsv_fno / stencil_w), ACCUMULATED by the backward calls. */
+typedef struct {
+  float* lift_w;
+  float* lift_b;
+  float* spec_w;   /* d/dRe + i d/dIm of the loss for each complex weight */
+  float* point_w;
+  float* point_b;
+  float* proj_w;
+  float* proj_b;
+} ldsv_fno_grad;
+
+typedef struct {
+  float* stencil_w;          /* [2][4][20] */
+  ldsv_fno_grad* fno[2];     /* must be set where ldsv_fluxnet.fno[g] is */
+} ldsv_fluxnet_grad;
+
 /* ldsv_fno_forward: fields [B][8][Ny][Nx] = channels 0..3 from fno[0] and
  * 4..7 from fno[1] (zeros for an absent operator) on (u, v). */
 LDSV_API int ldsv_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u,
@@ -349,6 +366,22 @@ LDSV_API int ldsv_fluxblock_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm,
                                         const void* u_in, const void* v_in, const void* gu_out,
                                         const void* gv_out, void* gu_in, void* gv_in,
                                         float* gstencil, float* gfields, void* stream);
+/* ldsv_fno_backward: VJP of ldsv_fno_forward (the forward is recomputed
+ * with its activations kept): given gfields = dL/dfields, ACCUMULATES the
+ * FNO parameter gradients into grad->fno[g] and writes gu, gv = dL/d(u, v)
+ * (nullable together).  Parameter gradients are reduced in a fixed order
+ * (deterministic). */
+LDSV_API int ldsv_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u,
+                               const float* v, const float* gfields, float* gu, float* gv,
+                               const ldsv_fluxnet_grad* grad, void* stream);
+/* ldsv_fluxblock_step_bwd: VJP of ldsv_fluxblock_step: writes gu_in, gv_in
+ * (through the FV step and through the FNOs) and ACCUMULATES every
+ * parameter gradient into *grad. */
+LDSV_API int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm,
+                                     const ldsv_fluxnet* net, const float* u_in,
+                                     const float* v_in, const float* gu_out, const float* gv_out,
+                                     float* gu_in, float* gv_in, const ldsv_fluxnet_grad* grad,
+                                     void* stream);
 /* ldsv_fluxblock_step: one step of the flux-block model, u_out = FV(u_in)
  * with fields = FNO(u_in) (evaluated once, held over the four sub-steps).
  * fields_out (nullable) receives the fields.  Not in place. */

@@ -26,8 +26,8 @@
 //               complex field (the k_x = 0 column symmetrised, which is the
 //               real part a real inverse transform takes), inverse 2D FFT
 //               in LDS, then the pointwise term W v + b and GELU fused in
-//               the epilogue.  The first layer's pointwise term recomputes
-//               v_0 from (u, v).
+//               the epilogue (the first layer's transform kernel writes v_0
+//               for it).
 // and after the last layer k_fno_proj writes the 4 fields of each network
 // into the [B][8][Ny][Nx] field array (channels 4 g .. 4 g + 3; zeros for an
 // absent network).  Everything is FP32; the FFT is O(N log N) on the vector
@@ -64,6 +64,21 @@ __device__ __forceinline__ int retained_row(int ky, int ny, int M) {
   return -1;
 }
 
+// (channel pair, trajectory, network slice) of a transform workgroup of the
+// grid (C/2, B, nets), renumbered so that the pairs of one trajectory run
+// on one XCD: they all read that trajectory's input (every channel for the
+// pointwise term, or u and v), which then comes from that XCD's L2 once
+// instead of once per XCD
+__device__ __forceinline__ void pair_of_block(int& p, int& b, int& z) {
+  const int np = gridDim.x, nb = gridDim.y;
+  const int lid = blockIdx.x + np * (blockIdx.y + nb * blockIdx.z);
+  const int r = xcd_contiguous(lid, np * nb * gridDim.z);
+  p = r % np;
+  const int rest = r / np;
+  b = rest % nb;
+  z = rest / nb;
+}
+
 template <int E>
 __device__ __forceinline__ void load_twiddles(Cx<float>* Wx, Cx<float>* Wy, const Cx<float>* twx,
                                               const Cx<float>* twy, int nx, int ny) {
@@ -75,6 +90,7 @@ __device__ __forceinline__ void load_twiddles(Cx<float>* Wx, Cx<float>* Wy, cons
 template <int E, bool LIFT>
 __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict__ vin,
                                                         const float* __restrict__ vin2, FnoArgs a,
+                                                        float* __restrict__ v0out,
                                                         c32* __restrict__ X,
                                                         const Cx<float>* __restrict__ twx,
                                                         const Cx<float>* __restrict__ twy, int nx,
@@ -85,7 +101,8 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict_
   Cx<float>* Wx = A + nx * ny;
   Cx<float>* Wy = Wx + nx;
   load_twiddles<E>(Wx, Wy, twx, twy, nx, ny);
-  const int p = blockIdx.x, b = blockIdx.y, z = blockIdx.z;
+  int p, b, z;
+  pair_of_block(p, b, z);
   const int g = a.net[z];
   const int c0 = 2 * p, c1 = 2 * p + 1;
   const int n = nx * ny;
@@ -96,12 +113,16 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict_
     const float* lb = a.lift_b[g];
     const float w00 = lw[2 * c0], w01 = lw[2 * c0 + 1], w10 = lw[2 * c1], w11 = lw[2 * c1 + 1];
     const float b0 = lb[c0], b1 = lb[c1];
+    float* d0 = v0out + ((size_t)(z * B + b) * C + c0) * n;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int t = k * kFnoBlock + (int)threadIdx.x;
       if (t < n) {
         const float x0 = u[t], x1 = v[t];
-        A[t] = Cx<float>{w00 * x0 + w01 * x1 + b0, w10 * x0 + w11 * x1 + b1};
+        const Cx<float> q{w00 * x0 + w01 * x1 + b0, w10 * x0 + w11 * x1 + b1};
+        A[t] = q;
+        d0[t] = q.x;  // v_0 kept for the pointwise term and the backward
+        d0[n + t] = q.y;
       }
     }
   } else {
@@ -177,106 +198,137 @@ __global__ void __launch_bounds__(64 * C) k_fno_mix(const c32* __restrict__ X, F
   }
 }
 
-// inverse transform of output channels (2p, 2p+1) + pointwise term + GELU
-template <int E, bool LIFT, bool LAST>
-__global__ void __launch_bounds__(kFnoBlock) k_fno_inv(const c32* __restrict__ Y,
-                                                       const float* __restrict__ vin,
-                                                       const float* __restrict__ vin2, FnoArgs a,
+// inverse transform of output channels (2p, 2p+1) + pointwise term + GELU.
+// The weights of the pair are read once into registers; every spectrum
+// load of a thread is issued before the LDS stores, and the pointwise sum
+// over the C input channels is unrolled so its loads are in flight together.
+// MODE 0: forward layer, out = GELU(z) with z = K v + W v + b (z kept in
+// zout when given); 1: last forward layer, out = z; 2: backward, the pair
+// are input channels i: dv_i = (K^T dz)_i + sum_o W[o][i] dz_o, out =
+// dv_i GELU'(gpre_i) (the cotangent of the previous layer's pre-activation);
+// 3: backward of the first layer, out = dv_i.
+template <int E, int C, int MODE>
+__global__ void __launch_bounds__(kFnoBlock, E <= 4 ? 8 : 4) k_fno_inv(const c32* __restrict__ Y,
+                                                       const float* __restrict__ vin, FnoArgs a,
                                                        float* __restrict__ vout,
                                                        float* __restrict__ zout,
+                                                       const float* __restrict__ gpre,
                                                        const Cx<float>* __restrict__ twx,
                                                        const Cx<float>* __restrict__ twy, int nx,
-                                                       int ny, int log2nx, int log2ny, int C, int M,
+                                                       int ny, int log2nx, int log2ny, int M,
                                                        int B) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   Cx<float>* A = reinterpret_cast<Cx<float>*>(smem_raw);
   Cx<float>* Wx = A + nx * ny;
   Cx<float>* Wy = Wx + nx;
   load_twiddles<E>(Wx, Wy, twx, twy, nx, ny);
-  const int p = blockIdx.x, b = blockIdx.y, z = blockIdx.z;
+  int p, b, z;
+  pair_of_block(p, b, z);
   const int g = a.net[z];
   const int o0 = 2 * p, o1 = 2 * p + 1;
   const int n = nx * ny;
   const int nm = 2 * M * M;
   const c32* Y0 = Y + ((size_t)(z * B + b) * C + o0) * nm;
   const c32* Y1 = Y0 + nm;
+  // weights of the two outputs (and the lift for the first layer)
+  constexpr bool BWD = MODE >= 2;
+  // the pointwise weights of the pair in LDS (read back four at a time)
+  __shared__ __attribute__((aligned(16))) float sw[2][C];
+  if (threadIdx.x < 2 * C) {
+    const float* pw = a.point_w[g];
+    const int q = threadIdx.x >> (C == 16 ? 4 : 3), i = threadIdx.x & (C - 1);
+    const int oq = q ? o1 : o0;
+    sw[q][i] = BWD ? pw[i * C + oq] : pw[oq * C + i];
+  }
+  const float bo0 = BWD ? 0.f : a.point_b[g][o0], bo1 = BWD ? 0.f : a.point_b[g][o1];
+  // Hermitian extension: element (ky, kx) takes Y(r, kx) directly for
+  // 0 < kx < M, conj Y(r', nx - kx) at the mirrored row for kx > nx - M, and
+  // the symmetrised pair (Y(r, 0) + conj Y(r', 0)) / 2 in the k_x = 0 column
+  // groups of 4 elements per thread: their loads are in flight together
+  // without holding all E in registers
+  constexpr int kG = E < 4 ? E : 4;
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
+  for (int g0 = 0; g0 < E; g0 += kG) {
+  c32 ya0[kG], ya1[kG], yb0[kG], yb1[kG];
+#pragma unroll
+  for (int kk = 0; kk < kG; ++kk) {
+    const int k = g0 + kk;
     const int t = k * kFnoBlock + (int)threadIdx.x;
+    ya0[kk] = ya1[kk] = yb0[kk] = yb1[kk] = c32{0.f, 0.f};
     if (t < n) {
       const int ky = t >> log2nx, kx = t & (nx - 1);
-      Cx<float> zv{0.f, 0.f};
+      const int r = retained_row(ky, ny, M);
+      const int rm = retained_row((ny - ky) & (ny - 1), ny, M);
+      int ia = -1, ib = -1;
       if (kx == 0) {
-        // the real inverse transform reads the real part of the k_x = 0
-        // column after the row-direction inverse: symmetrise it
-        const int r1 = retained_row(ky, ny, M);
-        const int r2 = retained_row((ny - ky) & (ny - 1), ny, M);
-        c32 s0{0.f, 0.f}, s1{0.f, 0.f};
-        if (r1 >= 0) {
-          s0 = Y0[r1 * M];
-          s1 = Y1[r1 * M];
-        }
-        if (r2 >= 0) {
-          const c32 q0 = Y0[r2 * M], q1 = Y1[r2 * M];
-          s0.x += q0.x;
-          s0.y -= q0.y;
-          s1.x += q1.x;
-          s1.y -= q1.y;
-        }
-        zv = Cx<float>{0.5f * (s0.x - s1.y), 0.5f * (s0.y + s1.x)};
+        ia = r >= 0 ? r * M : -1;
+        ib = rm >= 0 ? rm * M : -1;
       } else if (kx < M) {
-        const int r = retained_row(ky, ny, M);
-        if (r >= 0) {
-          const c32 y0 = Y0[r * M + kx], y1 = Y1[r * M + kx];
-          zv = Cx<float>{y0.x - y1.y, y0.y + y1.x};
-        }
+        ia = r >= 0 ? r * M + kx : -1;
       } else if (kx > nx - M) {
-        const int r = retained_row((ny - ky) & (ny - 1), ny, M);
-        if (r >= 0) {
-          const c32 y0 = Y0[r * M + (nx - kx)], y1 = Y1[r * M + (nx - kx)];
-          zv = Cx<float>{y0.x + y1.y, y1.x - y0.y};
-        }
+        ib = rm >= 0 ? rm * M + (nx - kx) : -1;
       }
-      A[t] = zv;
+      if (ia >= 0) {
+        ya0[kk] = Y0[ia];
+        ya1[kk] = Y1[ia];
+      }
+      if (ib >= 0) {
+        yb0[kk] = Y0[ib];
+        yb1[kk] = Y1[ib];
+      }
     }
+  }
+#pragma unroll
+  for (int kk = 0; kk < kG; ++kk) {
+    const int t = (g0 + kk) * kFnoBlock + (int)threadIdx.x;
+    if (t < n) {
+      // s = ya + conj(yb) (one of the two is zero outside the k_x = 0 column)
+      const float h = (t & (nx - 1)) == 0 ? 0.5f : 1.0f;
+      const float s0x = h * (ya0[kk].x + yb0[kk].x), s0y = h * (ya0[kk].y - yb0[kk].y);
+      const float s1x = h * (ya1[kk].x + yb1[kk].x), s1y = h * (ya1[kk].y - yb1[kk].y);
+      A[t] = Cx<float>{s0x - s1y, s0y + s1x};
+    }
+  }
   }
   __syncthreads();
   lds_fft<float, E>(A, nx, log2nx, ny, nx, 1, +1, Wx);
   lds_fft<float, E>(A, ny, log2ny, nx, 1, nx, +1, Wy);
   const float sc = 1.0f / (float)n;
-  const float* pw = a.point_w[g];
-  const float* pb = a.point_b[g];
-  const float bo0 = pb[o0], bo1 = pb[o1];
   float* d0 = vout + ((size_t)(z * B + b) * C + o0) * n;
   float* e0 = zout ? zout + ((size_t)(z * B + b) * C + o0) * n : nullptr;
-#pragma unroll 2
   for (int k = 0; k < E; ++k) {
     const int t = k * kFnoBlock + (int)threadIdx.x;
     if (t >= n) break;
     float z0 = A[t].x * sc + bo0, z1 = A[t].y * sc + bo1;
-    if constexpr (LIFT) {
-      const float x0 = vin[(size_t)b * n + t], x1 = vin2[(size_t)b * n + t];
-      const float* lw = a.lift_w[g];
-      const float* lb = a.lift_b[g];
-      for (int i = 0; i < C; ++i) {
-        const float vi = lw[2 * i] * x0 + lw[2 * i + 1] * x1 + lb[i];
-        z0 += pw[o0 * C + i] * vi;
-        z1 += pw[o1 * C + i] * vi;
+    const float* src = vin + (size_t)(z * B + b) * C * n + t;
+#pragma unroll
+    for (int c0 = 0; c0 < C; c0 += 8) {
+      float vi[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) vi[i] = src[(size_t)(c0 + i) * n];
+#pragma unroll
+      for (int i = 0; i < 8; i += 4) {
+        const float4 a0 = *reinterpret_cast<const float4*>(&sw[0][c0 + i]);
+        const float4 a1 = *reinterpret_cast<const float4*>(&sw[1][c0 + i]);
+        z0 += a0.x * vi[i] + a0.y * vi[i + 1] + a0.z * vi[i + 2] + a0.w * vi[i + 3];
+        z1 += a1.x * vi[i] + a1.y * vi[i + 1] + a1.z * vi[i + 2] + a1.w * vi[i + 3];
       }
+    }
+    if constexpr (MODE == 0 || MODE == 1) {
+      if (e0) {
+        e0[t] = z0;
+        e0[n + t] = z1;
+      }
+      d0[t] = MODE == 1 ? z0 : cnnk::gelu_exact(z0);
+      d0[n + t] = MODE == 1 ? z1 : cnnk::gelu_exact(z1);
+    } else if constexpr (MODE == 2) {
+      const float* gp = gpre + ((size_t)(z * B + b) * C + o0) * n;
+      d0[t] = z0 * cnnk::gelu_grad(gp[t]);
+      d0[n + t] = z1 * cnnk::gelu_grad(gp[n + t]);
     } else {
-      const float* s = vin + (size_t)(z * B + b) * C * n + t;
-      for (int i = 0; i < C; ++i) {
-        const float vi = s[(size_t)i * n];
-        z0 += pw[o0 * C + i] * vi;
-        z1 += pw[o1 * C + i] * vi;
-      }
+      d0[t] = z0;
+      d0[n + t] = z1;
     }
-    if (e0) {
-      e0[t] = z0;
-      e0[n + t] = z1;
-    }
-    d0[t] = LAST ? z0 : cnnk::gelu_exact(z0);
-    d0[n + t] = LAST ? z1 : cnnk::gelu_exact(z1);
   }
 }
 
@@ -303,6 +355,222 @@ __global__ void __launch_bounds__(kBlock) k_fno_proj(const float* __restrict__ v
   }
 #pragma unroll
   for (int K = 0; K < 4; ++K) fields[((size_t)b * 8 + 4 * g + K) * n + t] = acc[K];
+}
+
+// ---------------------------------------------------------------- backward
+//
+// With the saved pre-activations z_l, spectra X_l = F(v_l) and v_0:
+//   dv_L = Q^T dF;  dQ = sum dF v_L^T;  db_Q = sum dF            (k_fno_proj_bwd)
+//   layer l = L-1 .. 0, dz_l the cotangent of z_l:
+//     dW_l = sum dz_l v_l^T, db_l = sum dz_l                     (k_fno_wgrad)
+//     dR_l(k)[i][o] = (w(k_x) / N) sum_b conj(X_l,i(k)) DZ_o(k)  (k_fno_dR)
+//        with DZ = F(dz_l) (k_fno_spec), w = 1 at k_x = 0 else 2:
+//        d/dRe + i d/dIm of the loss, the gradient convention of a real
+//        loss in a complex parameter that torch uses
+//     dv_l = K_l^T dz_l + W_l^T dz_l, where K^T is the spectral
+//        convolution with weights conj(R[i][o]) (k_fno_mix<CONJ_T>, then
+//        k_fno_inv in backward mode); dz_{l-1} = dv_l GELU'(z_{l-1})
+//   dP = sum dv_0 x^T, db_P = sum dv_0, dx = P^T dv_0 summed over the two
+//   networks                                                        (k_fno_lift_bwd)
+// Every parameter gradient is a sum over trajectories and pixels: each
+// block writes its partial sums (wave shuffles, then the waves in a fixed
+// order) and k_sum_partials adds them over the blocks in a fixed order, so
+// the result is deterministic.
+
+// sum of v over the block (blockDim == kBlock), returned to every thread of
+// wave 0's lane 0... written to dst[j] by thread j for j < NV
+template <int NV>
+__device__ __forceinline__ void block_sums(float (&v)[NV], float* __restrict__ dst) {
+  __shared__ float red[kBlock / 64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    float x = v[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[wave][j] = x;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < NV; j += blockDim.x) {
+    float acc = 0.f;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) acc += red[q][j];
+    dst[j] = acc;
+  }
+}
+
+// dv_L[c] = sum_K Q[K][c] dF_K; partials of dQ[K][c] = dF_K v_L[c] and
+// db_Q[K] = dF_K: part[z][b][blk][4C + 4]
+template <int C>
+__global__ void __launch_bounds__(kBlock) k_fno_proj_bwd(const float* __restrict__ gfields,
+                                                         const float* __restrict__ vL, FnoArgs a,
+                                                         float* __restrict__ dv,
+                                                         float* __restrict__ part, int n, int B) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int b = blockIdx.y, z = blockIdx.z, g = a.net[z];
+  const bool in = t < n;
+  float dF[4];
+#pragma unroll
+  for (int K = 0; K < 4; ++K) dF[K] = in ? gfields[((size_t)b * 8 + 4 * g + K) * n + t] : 0.f;
+  const float* qw = a.proj_w[g];
+  float prod[4 * C + 4];
+  const size_t base = (size_t)(z * B + b) * C * n;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float x = in ? vL[base + (size_t)c * n + t] : 0.f;
+    float d = 0.f;
+#pragma unroll
+    for (int K = 0; K < 4; ++K) {
+      d += qw[K * C + c] * dF[K];
+      prod[K * C + c] = dF[K] * x;
+    }
+    if (in) dv[base + (size_t)c * n + t] = d;
+  }
+#pragma unroll
+  for (int K = 0; K < 4; ++K) prod[4 * C + K] = dF[K];
+  block_sums<4 * C + 4>(prod, part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * (4 * C + 4));
+}
+
+// partials of dW[o][i] = sum dz_o v_i and db[o] = sum dz_o over the pixels of
+// one (network, trajectory): part[z][b][C C + C].  v_i = GELU(vpre_i) when
+// GELU_V (v_l for l >= 1 from the saved z_{l-1}), else vpre itself (v_0).
+// Block C*C: thread (o, i).
+template <int C, bool GELU_V>
+__global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ dz,
+                                                     const float* __restrict__ vpre,
+                                                     float* __restrict__ part, int n, int B) {
+  constexpr int kT = 64;          // pixels per tile
+  constexpr int kS = kT + 4;      // padded row (16-byte aligned, spreads banks)
+  __shared__ __attribute__((aligned(16))) float sdz[C][kS];
+  __shared__ __attribute__((aligned(16))) float sv[C][kS];
+  const int zb = blockIdx.x;      // z * B + b
+  const int o = threadIdx.x / C, i = threadIdx.x % C;
+  const float* d = dz + (size_t)zb * C * n;
+  const float* vp = vpre + (size_t)zb * C * n;
+  float acc = 0.f, accb = 0.f;
+  for (int p0 = 0; p0 < n; p0 += kT) {
+    for (int e = threadIdx.x; e < C * kT; e += C * C) {
+      const int c = e / kT, q = e - c * kT;
+      const float x = vp[(size_t)c * n + p0 + q];
+      sdz[c][q] = d[(size_t)c * n + p0 + q];
+      sv[c][q] = GELU_V ? cnnk::gelu_exact(x) : x;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < kT; q += 4) {
+      const float4 dd = *reinterpret_cast<const float4*>(&sdz[o][q]);
+      const float4 vv = *reinterpret_cast<const float4*>(&sv[i][q]);
+      acc += dd.x * vv.x + dd.y * vv.y + dd.z * vv.z + dd.w * vv.w;
+      accb += dd.x + dd.y + dd.z + dd.w;
+    }
+    __syncthreads();
+  }
+  float* dst = part + (size_t)zb * (C * C + C);
+  dst[o * C + i] = acc;
+  if (i == 0) dst[C * C + o] = accb;
+}
+
+// partial spectral weight gradients over the trajectories of b-group
+// blockIdx.y: part[z][group][i][o][m] (complex, scaled by w(k_x) / N).
+// Block 64 x C: lane = mode, wave = output channel o; the X_l tile of each
+// trajectory streams through LDS as in k_fno_mix.
+template <int C>
+__global__ void __launch_bounds__(64 * C) k_fno_dR(const c32* __restrict__ Xl,
+                                                   const c32* __restrict__ DZ, c32* __restrict__ part,
+                                                   int B, int nm, int M, int bpg, float inv_n) {
+  __shared__ c32 xs[2][C][64];
+  const int lane = threadIdx.x & 63;
+  const int o = threadIdx.x >> 6;
+  const int m = blockIdx.x * 64 + lane;
+  const int z = blockIdx.z;
+  c32 acc[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) acc[i] = c32{0.f, 0.f};
+  const int b0 = blockIdx.y * bpg;
+  const int b1 = min(B, b0 + bpg);
+  for (int b = b0; b < b1; ++b) {
+    const int buf = (b - b0) & 1;
+    {
+      const int i = threadIdx.x >> 6;
+      xs[buf][i][lane] = m < nm ? Xl[((size_t)(z * B + b) * C + i) * nm + m] : c32{0.f, 0.f};
+    }
+    const c32 d = m < nm ? DZ[((size_t)(z * B + b) * C + o) * nm + m] : c32{0.f, 0.f};
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const c32 x = xs[buf][i][lane];
+      // conj(x) d
+      acc[i].x += x.x * d.x + x.y * d.y;
+      acc[i].y += x.x * d.y - x.y * d.x;
+    }
+  }
+  if (m < nm) {
+    const float sc = ((m % M) == 0 ? 1.f : 2.f) * inv_n;
+    c32* dst = part + ((size_t)z * gridDim.y + blockIdx.y) * C * C * nm;
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+      dst[((size_t)i * C + o) * nm + m] = c32{sc * acc[i].x, sc * acc[i].y};
+  }
+}
+
+// dx = sum over the networks of P^T dv_0 (written or added to gu, gv) and
+// partials of dP[c][j] = dv_0,c x_j, db_P[c] = dv_0,c: part[z][b][blk][3C]
+template <int C>
+__global__ void __launch_bounds__(kBlock) k_fno_lift_bwd(const float* __restrict__ dv0,
+                                                         const float* __restrict__ u,
+                                                         const float* __restrict__ v, FnoArgs a,
+                                                         int nnet, float* __restrict__ gu,
+                                                         float* __restrict__ gv, int accumulate,
+                                                         float* __restrict__ part, int n, int B) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int b = blockIdx.y;
+  const bool in = t < n;
+  const float x0 = in ? u[(size_t)b * n + t] : 0.f;
+  const float x1 = in ? v[(size_t)b * n + t] : 0.f;
+  float g0 = 0.f, g1 = 0.f;
+  for (int z = 0; z < nnet; ++z) {
+    const float* lw = a.lift_w[a.net[z]];
+    const float* d = dv0 + (size_t)(z * B + b) * C * n;
+    float prod[3 * C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float dc = in ? d[(size_t)c * n + t] : 0.f;
+      g0 += lw[2 * c] * dc;
+      g1 += lw[2 * c + 1] * dc;
+      prod[2 * c] = dc * x0;
+      prod[2 * c + 1] = dc * x1;
+      prod[2 * C + c] = dc;
+    }
+    block_sums<3 * C>(prod, part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * (3 * C));
+    __syncthreads();  // block_sums' LDS is reused by the next network
+  }
+  if (in && gu) {
+    const size_t q = (size_t)b * n + t;
+    gu[q] = accumulate ? gu[q] + g0 : g0;
+    gv[q] = accumulate ? gv[q] + g1 : g1;
+  }
+}
+
+struct PartOut {
+  float* out[2];  // destination of network slice z (accumulated)
+};
+
+// out_z[j] += sum over blk of part[(z nblk + blk) stride + off + j], blk in order
+__global__ void __launch_bounds__(kBlock) k_sum_partials(const float* __restrict__ part, int nblk,
+                                                         size_t stride, int off, int len,
+                                                         PartOut po) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int z = blockIdx.z;
+  if (j >= len) return;
+  const float* p = part + (size_t)z * nblk * stride + off + j;
+  float acc = 0.f;
+  for (int k = 0; k < nblk; ++k) acc += p[(size_t)k * stride];
+  po.out[z][j] += acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_zero(float* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    p[i] = 0.f;
 }
 
 // ---------------------------------------------------------------- host
@@ -347,25 +615,72 @@ int check_fluxnet(const ldsv_handle* h, const ldsv_fluxnet* net, FnoShape* sh) {
   return LDSV_OK;
 }
 
-// buffers: v ping-pong (2 x nnet B C N floats), X and Y (nnet B C nm complex)
-// and, for the backward, the L pre-activations (nnet B C N floats each)
-int ensure_fno(ldsv_handle* h, const FnoShape& sh, bool keep_pre, float** v0, float** v1,
-               c32** X, c32** Y, float** pre) {
+// Workspace.  Inference: X, Y (nnet B C nm complex) and two activation
+// buffers va, vb (nnet B C N floats).  Kept for the backward (keep): the L
+// pre-activations z_l, the L forward spectra X_l and v_0.  Backward (bwd):
+// two cotangent buffers, the per-b-group partial sums of the spectral
+// weight gradient and the small per-block partial sums.
+constexpr int kDRGroups = 8;  // b-groups of the spectral weight gradient
+struct FnoWs {
+  c32 *X, *Y;
+  float *va, *vb;
+  float* pre;   // [L][act]
+  c32* xs;      // [L][spec]
+  float* v0;    // [act] (va's partner in inference)
+  float *da, *db;
+  float* part;  // spectral gradient partials [nnet][kDRGroups][C C nm] complex
+  float* small; // small partials
+  size_t act, spec, small_len;
+};
+
+size_t fno_small_len(const ldsv_handle* h, const FnoShape& sh) {
+  const size_t nblk = (h->ncell + kBlock - 1) / kBlock;
+  const size_t a = (size_t)sh.nnet * h->g.batch * nblk * (4 * sh.C + 4);      // projection
+  const size_t b = (size_t)sh.nnet * h->g.batch * (sh.C * sh.C + sh.C);       // pointwise
+  const size_t c = (size_t)sh.nnet * h->g.batch * nblk * 3 * sh.C;            // lift
+  return std::max(a, std::max(b, c));
+}
+
+int ensure_fno(ldsv_handle* h, const FnoShape& sh, int level, FnoWs* w) {
   const size_t act = (size_t)sh.nnet * h->g.batch * sh.C * h->ncell;
-  const size_t spec = (size_t)sh.nnet * h->g.batch * sh.C * 2 * sh.M * sh.M;
-  const size_t need = (2 * act) * sizeof(float) + 2 * spec * sizeof(c32) +
-                      (keep_pre ? (size_t)sh.L * act * sizeof(float) : 0);
+  const size_t nm = (size_t)2 * sh.M * sh.M;
+  const size_t spec = (size_t)sh.nnet * h->g.batch * sh.C * nm;
+  const size_t part = (size_t)sh.nnet * kDRGroups * sh.C * sh.C * nm * 2;
+  const size_t small = fno_small_len(h, sh);
+  size_t need = 2 * spec * sizeof(c32) + 2 * act * sizeof(float);
+  if (level >= 1) need += (size_t)sh.L * (act * sizeof(float) + spec * sizeof(c32)) + act * sizeof(float);
+  if (level >= 2) need += 2 * act * sizeof(float) + (part + small) * sizeof(float);
   if (need > h->fno_bytes) {
     // grown workspaces are kept (owned by the handle) until ldsv_destroy
     LDSV_TRY(ldsv_alloc(h, &h->fno_blk, need, "FNO workspace"));
     h->fno_bytes = need;
   }
   char* p = (char*)h->fno_blk;
-  *X = (c32*)p;
-  *Y = (c32*)(p + spec * sizeof(c32));
-  *v0 = (float*)(p + 2 * spec * sizeof(c32));
-  *v1 = *v0 + act;
-  *pre = keep_pre ? *v1 + act : nullptr;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += bytes;
+    return q;
+  };
+  *w = FnoWs{};
+  w->act = act;
+  w->spec = spec;
+  w->small_len = small;
+  w->X = (c32*)take(spec * sizeof(c32));
+  w->Y = (c32*)take(spec * sizeof(c32));
+  w->va = (float*)take(act * sizeof(float));
+  w->vb = (float*)take(act * sizeof(float));
+  w->v0 = w->vb;
+  if (level >= 1) {
+    w->pre = (float*)take((size_t)sh.L * act * sizeof(float));
+    w->xs = (c32*)take((size_t)sh.L * spec * sizeof(c32));
+    w->v0 = (float*)take(act * sizeof(float));
+  }
+  if (level >= 2) {
+    w->da = (float*)take(act * sizeof(float));
+    w->db = (float*)take(act * sizeof(float));
+    w->part = (float*)take(part * sizeof(float));
+    w->small = (float*)take(small * sizeof(float));
+  }
   return LDSV_OK;
 }
 
@@ -390,10 +705,15 @@ FnoArgs make_args(const ldsv_fluxnet* net, const FnoShape& sh, int layer) {
   return a;
 }
 
+// layer l reads v_l from v0 (l = 0) or the buffer layer l - 1 wrote, and
+// writes v_{l+1} to va (l even) or vb (l odd)
+inline float* fno_in(const FnoWs& w, int l) { return l == 0 ? w.v0 : (l % 2 ? w.va : w.vb); }
+inline float* fno_out(const FnoWs& w, int l) { return l % 2 ? w.vb : w.va; }
+
 template <int E>
 int fno_forward_e(ldsv_handle* h, const ldsv_fluxnet* net, const FnoShape& sh, const float* u,
-                  const float* v, float* fields, float* pre, float* va, float* vb, c32* X,
-                  c32* Y, hipStream_t st) {
+                  const float* v, float* fields, const FnoWs& w, hipStream_t st) {
+  c32* Y = w.Y;
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch, C = sh.C, M = sh.M;
   const size_t lds = ((size_t)nx * ny + nx + ny) * sizeof(Cx<float>);
   const dim3 gfft(C / 2, B, sh.nnet);
@@ -403,23 +723,25 @@ int fno_forward_e(ldsv_handle* h, const ldsv_fluxnet* net, const FnoShape& sh, c
   const dim3 gmix((nm + 63) / 64, (B + bpg - 1) / bpg, sh.nnet);
   const Cx<float>* twx = (const Cx<float>*)h->twx;
   const Cx<float>* twy = (const Cx<float>*)h->twy;
-  const size_t act = (size_t)sh.nnet * B * C * h->ncell;
-  float* cur = va;
-  float* nxt = vb;
   for (int l = 0; l < sh.L; ++l) {
     const FnoArgs a = make_args(net, sh, l);
     const bool first = l == 0, last = l == sh.L - 1;
-    float* zl = pre ? pre + (size_t)l * act : nullptr;
+    float* zl = w.pre ? w.pre + (size_t)l * w.act : nullptr;
+    c32* X = w.xs ? w.xs + (size_t)l * w.spec : w.X;
+    float* cur = fno_in(w, l);
+    float* nxt = fno_out(w, l);
     if (first) {
+      // v_0 = lift(u, v) is written to cur on the way
       auto k = k_fno_spec<E, true>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, u, v, a, X, twx, twy, nx, ny,
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, u, v, a, cur, X, twx, twy, nx, ny,
                    h->log2nx, h->log2ny, C, M, B);
     } else {
       auto k = k_fno_spec<E, false>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const float*)cur,
-                   (const float*)nullptr, a, X, twx, twy, nx, ny, h->log2nx, h->log2ny, C, M, B);
+                   (const float*)nullptr, a, (float*)nullptr, X, twx, twy, nx, ny, h->log2nx,
+                   h->log2ny, C, M, B);
     }
     if (C == 16)
       LDSV_TLAUNCH(h, 9, (k_fno_mix<16, false>), gmix, dim3(64 * 16), 0, st, (const c32*)X,
@@ -427,31 +749,177 @@ int fno_forward_e(ldsv_handle* h, const ldsv_fluxnet* net, const FnoShape& sh, c
     else
       LDSV_TLAUNCH(h, 9, (k_fno_mix<8, false>), gmix, dim3(64 * 8), 0, st, (const c32*)X, a,
                    Y, B, nm, bpg);
-    const float* in0 = first ? u : cur;
-    const float* in1 = first ? v : nullptr;
-#define LDSV_FNO_INV(LF, LS)                                                                     \
-  {                                                                                              \
-    auto k = k_fno_inv<E, LF, LS>;                                                               \
-    LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,     \
-                                 (int)lds));                                                     \
-    LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const c32*)Y, in0, in1, a, nxt, zl, \
-                 twx, twy, nx, ny, h->log2nx, h->log2ny, C, M, B);                               \
-  }
-    if (first && last) LDSV_FNO_INV(true, true)
-    else if (first) LDSV_FNO_INV(true, false)
-    else if (last) LDSV_FNO_INV(false, true)
-    else LDSV_FNO_INV(false, false)
-#undef LDSV_FNO_INV
-    std::swap(cur, nxt);
+    {
+      auto k = last ? (C == 16 ? k_fno_inv<E, 16, 1> : k_fno_inv<E, 8, 1>)
+                    : (C == 16 ? k_fno_inv<E, 16, 0> : k_fno_inv<E, 8, 0>);
+      LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const c32*)Y, (const float*)cur, a,
+                   nxt, zl, (const float*)nullptr, twx, twy, nx, ny, h->log2nx, h->log2ny, M, B);
+    }
   }
   const FnoArgs a = make_args(net, sh, 0);
   LDSV_TLAUNCH(h, 7, k_fno_proj, dim3((unsigned)((h->ncell + kBlock - 1) / kBlock), B, 2),
-               dim3(kBlock), 0, st, (const float*)cur, a, fields, (int)h->ncell, C, B);
+               dim3(kBlock), 0, st, (const float*)fno_out(w, sh.L - 1), a, fields, (int)h->ncell,
+               C, B);
   LDSV_LAUNCHED();
   return LDSV_OK;
 }
 
+int sum_partials(ldsv_handle* h, const FnoShape& sh, const FnoArgs& a, const float* part,
+                 int nblk, size_t stride, int off, int len, float* const outs[2],
+                 hipStream_t st) {
+  PartOut po{};
+  for (int z = 0; z < sh.nnet; ++z) po.out[z] = outs[a.net[z]];
+  LDSV_TLAUNCH(h, 7, k_sum_partials, dim3((len + kBlock - 1) / kBlock, 1, sh.nnet), dim3(kBlock),
+               0, st, part, nblk, stride, off, len, po);
+  return LDSV_OK;
+}
+
+template <int E, int C>
+int fno_backward_e(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr,
+                   const FnoShape& sh, const float* u, const float* v, const float* gfields,
+                   float* gu, float* gv, int accumulate, const FnoWs& w, hipStream_t st) {
+  const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch, M = sh.M;
+  const int n = (int)h->ncell;
+  const size_t lds = ((size_t)nx * ny + nx + ny) * sizeof(Cx<float>);
+  const dim3 gfft(C / 2, B, sh.nnet);
+  const int nm = 2 * M * M;
+  int bpg = B / 8;
+  if (bpg < 1) bpg = 1;
+  const dim3 gmix((nm + 63) / 64, (B + bpg - 1) / bpg, sh.nnet);
+  const int bpg_r = (B + kDRGroups - 1) / kDRGroups;
+  const int ngr = (B + bpg_r - 1) / bpg_r;
+  const Cx<float>* twx = (const Cx<float>*)h->twx;
+  const Cx<float>* twy = (const Cx<float>*)h->twy;
+  const int nblk = (n + kBlock - 1) / kBlock;
+  float* g_lift_w[2] = {nullptr, nullptr};
+  float* g_lift_b[2] = {nullptr, nullptr};
+  float* g_proj_w[2] = {nullptr, nullptr};
+  float* g_proj_b[2] = {nullptr, nullptr};
+  for (int g = 0; g < 2; ++g) {
+    if (!net->fno[g]) continue;
+    const ldsv_fno_grad* q = gr->fno[g];
+    g_lift_w[g] = q->lift_w;
+    g_lift_b[g] = q->lift_b;
+    g_proj_w[g] = q->proj_w;
+    g_proj_b[g] = q->proj_b;
+  }
+  // projection
+  const FnoArgs a0 = make_args(net, sh, 0);
+  float* dcur = w.da;
+  float* dnxt = w.db;
+  LDSV_TLAUNCH(h, 7, k_fno_proj_bwd<C>, dim3(nblk, B, sh.nnet), dim3(kBlock), 0, st, gfields,
+               (const float*)(w.pre + (size_t)(sh.L - 1) * w.act), a0, dcur, w.small, n, B);
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 4 * C + 4, 0, 4 * C, g_proj_w, st));
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 4 * C + 4, 4 * C, 4, g_proj_b, st));
+  for (int l = sh.L - 1; l >= 0; --l) {
+    const FnoArgs a = make_args(net, sh, l);
+    float* g_pw[2] = {nullptr, nullptr};
+    float* g_pb[2] = {nullptr, nullptr};
+    float* g_sw[2] = {nullptr, nullptr};
+    for (int g = 0; g < 2; ++g) {
+      if (!net->fno[g]) continue;
+      const ldsv_fno_grad* q = gr->fno[g];
+      g_pw[g] = q->point_w + (size_t)l * C * C;
+      g_pb[g] = q->point_b + (size_t)l * C;
+      g_sw[g] = q->spec_w + (size_t)l * C * C * nm * 2;
+    }
+    // pointwise weight and bias gradients (v_l from v_0 or GELU(z_{l-1}))
+    if (l == 0)
+      LDSV_TLAUNCH(h, 7, (k_fno_wgrad<C, false>), dim3(sh.nnet * B), dim3(C * C), 0, st,
+                   (const float*)dcur, (const float*)w.v0, w.small, n, B);
+    else
+      LDSV_TLAUNCH(h, 7, (k_fno_wgrad<C, true>), dim3(sh.nnet * B), dim3(C * C), 0, st,
+                   (const float*)dcur, (const float*)(w.pre + (size_t)(l - 1) * w.act), w.small, n,
+                   B);
+    LDSV_TRY(sum_partials(h, sh, a, w.small, B, C * C + C, 0, C * C, g_pw, st));
+    LDSV_TRY(sum_partials(h, sh, a, w.small, B, C * C + C, C * C, C, g_pb, st));
+    // DZ = F(dz_l) into X
+    {
+      auto k = k_fno_spec<E, false>;
+      LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const float*)dcur,
+                   (const float*)nullptr, a, (float*)nullptr, w.X, twx, twy, nx, ny, h->log2nx,
+                   h->log2ny, C, M, B);
+    }
+    // spectral weight gradient
+    LDSV_TLAUNCH(h, 9, k_fno_dR<C>, dim3((nm + 63) / 64, ngr, sh.nnet), dim3(64 * C), 0, st,
+                 (const c32*)(w.xs + (size_t)l * w.spec), (const c32*)w.X, (c32*)w.part, B, nm, M,
+                 bpg_r, 1.0f / (float)n);
+    LDSV_TRY(sum_partials(h, sh, a, w.part, ngr, (size_t)C * C * nm * 2, 0, C * C * nm * 2, g_sw,
+                          st));
+    // dv_l = K^T dz + W^T dz, then dz_{l-1} = dv_l GELU'(z_{l-1})
+    LDSV_TLAUNCH(h, 9, (k_fno_mix<C, true>), gmix, dim3(64 * C), 0, st, (const c32*)w.X, a, w.Y,
+                 B, nm, bpg);
+    {
+      auto k = l == 0 ? k_fno_inv<E, C, 3> : k_fno_inv<E, C, 2>;
+      LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const c32*)w.Y, (const float*)dcur,
+                   a, dnxt, (float*)nullptr,
+                   (const float*)(l > 0 ? w.pre + (size_t)(l - 1) * w.act : nullptr), twx, twy,
+                   nx, ny, h->log2nx, h->log2ny, M, B);
+    }
+    std::swap(dcur, dnxt);
+  }
+  // lift: dcur holds dv_0
+  LDSV_TLAUNCH(h, 7, k_fno_lift_bwd<C>, dim3(nblk, B), dim3(kBlock), 0, st, (const float*)dcur, u,
+               v, a0, sh.nnet, gu, gv, accumulate, w.small, n, B);
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 3 * C, 0, 2 * C, g_lift_w, st));
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 3 * C, 2 * C, C, g_lift_b, st));
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}
+
+int check_fluxnet_grad(const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr) {
+  LDSV_REQUIRE(gr, LDSV_EINVAL, "flux block: null gradient");
+  for (int g = 0; g < 2; ++g) {
+    if (!net->fno[g]) continue;
+    const ldsv_fno_grad* q = gr->fno[g];
+    LDSV_REQUIRE(q && q->lift_w && q->lift_b && q->spec_w && q->point_w && q->point_b &&
+                     q->proj_w && q->proj_b,
+                 LDSV_EINVAL, "flux block: null gradient buffer of fno[%d]", g);
+  }
+  return LDSV_OK;
+}
+
 }  // namespace
+
+// forward with the saved activations, then the backward from gfields:
+// accumulates the parameter gradients into gr; gu, gv (nullable) receive
+// (or, with accumulate, add) the input gradient
+int ldsv_launch_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr,
+                             const float* u, const float* v, const float* gfields, float* gu,
+                             float* gv, int accumulate, hipStream_t st) {
+  FnoShape sh;
+  LDSV_TRY(check_fluxnet(h, net, &sh));
+  if (sh.nnet == 0) {
+    if (gu && !accumulate) {
+      LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(h->nstate), dim3(kBlock), 0, st, gu, h->nstate);
+      LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(h->nstate), dim3(kBlock), 0, st, gv, h->nstate);
+      LDSV_LAUNCHED();
+    }
+    return LDSV_OK;
+  }
+  LDSV_TRY(check_fluxnet_grad(net, gr));
+  FnoWs w;
+  LDSV_TRY(ensure_fno(h, sh, 2, &w));
+  float* scratch_fields = nullptr;
+  LDSV_TRY(ldsv_ensure_fluxblock(h));
+  scratch_fields = h->fb_fields;
+  const bool small = h->ncell <= (size_t)4 * kFnoBlock;
+  if (small) LDSV_TRY(fno_forward_e<4>(h, net, sh, u, v, scratch_fields, w, st));
+  else LDSV_TRY(fno_forward_e<16>(h, net, sh, u, v, scratch_fields, w, st));
+  if (small && sh.C == 16)
+    return fno_backward_e<4, 16>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
+  if (small)
+    return fno_backward_e<4, 8>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
+  if (sh.C == 16)
+    return fno_backward_e<16, 16>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
+  return fno_backward_e<16, 8>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
+}
 
 int ldsv_launch_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u,
                             const float* v, float* fields, bool keep_pre, hipStream_t st) {
@@ -467,12 +935,10 @@ int ldsv_launch_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float
     LDSV_LAUNCHED();
     return LDSV_OK;
   }
-  float *va, *vb, *pre;
-  c32 *X, *Y;
-  LDSV_TRY(ensure_fno(h, sh, keep_pre, &va, &vb, &X, &Y, &pre));
-  if (h->ncell <= (size_t)4 * kFnoBlock)
-    return fno_forward_e<4>(h, net, sh, u, v, fields, pre, va, vb, X, Y, st);
-  return fno_forward_e<16>(h, net, sh, u, v, fields, pre, va, vb, X, Y, st);
+  FnoWs w;
+  LDSV_TRY(ensure_fno(h, sh, keep_pre ? 1 : 0, &w));
+  if (h->ncell <= (size_t)4 * kFnoBlock) return fno_forward_e<4>(h, net, sh, u, v, fields, w, st);
+  return fno_forward_e<16>(h, net, sh, u, v, fields, w, st);
 }
 
 int ldsv_ensure_fluxblock(ldsv_handle* h) {
@@ -532,6 +998,50 @@ int ldsv_fluxblock_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const flo
   fb.gfbs = (size_t)8 * h->ncell;
   return ldsv_step_bwd(h, prm, nullptr, 0, nullptr, 0, u_in, v_in, gu_out, gv_out, gu_in, gv_in,
                        (hipStream_t)stream, &fb);
+}
+
+int ldsv_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u, const float* v,
+                      const float* gfields, float* gu, float* gv, const ldsv_fluxnet_grad* grad,
+                      void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(net && u && v && gfields, LDSV_EINVAL, "fno_backward: null argument");
+  LDSV_REQUIRE((gu == nullptr) == (gv == nullptr), LDSV_EINVAL, "fno_backward: gu and gv together");
+  return ldsv_launch_fno_backward(h, net, grad, u, v, gfields, gu, gv, 0, (hipStream_t)stream);
+}
+
+int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,
+                            const float* u_in, const float* v_in, const float* gu_out,
+                            const float* gv_out, float* gu_in, float* gv_in,
+                            const ldsv_fluxnet_grad* grad, void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(prm && net && net->stencil_w && u_in && v_in && gu_out && gv_out && gu_in && gv_in &&
+                   grad,
+               LDSV_EINVAL, "fluxblock_step_bwd: null argument");
+  LDSV_REQUIRE(prm->rk == LDSV_RK4, LDSV_EDTYPE, "fluxblock_step_bwd: RK4");
+  FnoShape sh;
+  LDSV_TRY(check_fluxnet(h, net, &sh));
+  LDSV_TRY(check_fluxnet_grad(net, grad));
+  const hipStream_t st = (hipStream_t)stream;
+  LDSV_TRY(ldsv_ensure_fluxblock(h));
+  // the fields of the forward step, then the FV adjoint with their gradient
+  LDSV_TRY(ldsv_launch_fno_forward(h, net, u_in, v_in, h->fb_fields, false, st));
+  LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(8 * h->nstate), dim3(kBlock), 0, st, h->fb_gfields,
+               8 * h->nstate);
+  LDSV_LAUNCHED();
+  FluxBlockArgs fb;
+  fb.w = net->stencil_w;
+  fb.f = h->fb_fields;
+  fb.fbs = (size_t)8 * h->ncell;
+  fb.gw = grad->stencil_w;
+  fb.gf = h->fb_gfields;
+  fb.gfbs = (size_t)8 * h->ncell;
+  LDSV_TRY(ldsv_step_bwd(h, prm, nullptr, 0, nullptr, 0, u_in, v_in, gu_out, gv_out, gu_in, gv_in,
+                         st, &fb));
+  if (sh.nnet == 0) return LDSV_OK;
+  // the operators' gradients, their input gradient added to the state's
+  // (the forward is recomputed with its activations kept; it overwrites the
+  // field buffer, which the FV adjoint has finished reading)
+  return ldsv_launch_fno_backward(h, net, grad, u_in, v_in, h->fb_gfields, gu_in, gv_in, 1, st);
 }
 
 int ldsv_fluxblock_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,

@@ -79,6 +79,17 @@ class FluxNet(ctypes.Structure):
     _fields_ = [("stencil_w", ctypes.c_void_p), ("fno", ctypes.POINTER(Fno) * 2)]
 
 
+class FnoGrad(ctypes.Structure):
+    _fields_ = [("lift_w", ctypes.c_void_p), ("lift_b", ctypes.c_void_p),
+                ("spec_w", ctypes.c_void_p), ("point_w", ctypes.c_void_p),
+                ("point_b", ctypes.c_void_p), ("proj_w", ctypes.c_void_p),
+                ("proj_b", ctypes.c_void_p)]
+
+
+class FluxNetGrad(ctypes.Structure):
+    _fields_ = [("stencil_w", ctypes.c_void_p), ("fno", ctypes.POINTER(FnoGrad) * 2)]
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
@@ -124,6 +135,10 @@ _SIGS = {
                                     _vp, _vp, _vp, _vp, _vp], _i),
     "ldsv_fluxblock_step": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(FluxNet), _vp, _vp, _vp,
                              _vp, _vp, _vp], _i),
+    "ldsv_fno_backward": ([_vp, ctypes.POINTER(FluxNet), _vp, _vp, _vp, _vp, _vp,
+                           ctypes.POINTER(FluxNetGrad), _vp], _i),
+    "ldsv_fluxblock_step_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(FluxNet), _vp, _vp,
+                                 _vp, _vp, _vp, _vp, ctypes.POINTER(FluxNetGrad), _vp], _i),
     "ldsv_timer_enable": ([_vp, _i], _i),
     "ldsv_timer_read": ([_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i)], _i),
 }
@@ -410,6 +425,22 @@ class Solver:
                                         self._state(vo), _ptr(f), _stream()))
         return (uo, vo, f) if want_fields else (uo, vo)
 
+    def fno_backward(self, net, u, v, gfields, grad, want_input_grad=True):
+        gu = self.new_state() if want_input_grad else None
+        gv = self.new_state() if want_input_grad else None
+        _check(_lib.ldsv_fno_backward(self._h, ctypes.byref(net.c), self._state(u), self._state(v),
+                                      self._fields(gfields, "gfields"), _ptr(gu), _ptr(gv),
+                                      ctypes.byref(grad.c), _stream()))
+        return gu, gv
+
+    def fluxblock_step_bwd(self, prm, net, u, v, gu_out, gv_out, grad):
+        gu, gv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_fluxblock_step_bwd(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                            self._state(u), self._state(v), self._state(gu_out),
+                                            self._state(gv_out), _ptr(gu), _ptr(gv),
+                                            ctypes.byref(grad.c), _stream()))
+        return gu, gv
+
     def timer_enable(self, on=True):
         _check(_lib.ldsv_timer_enable(self._h, 1 if on else 0))
 
@@ -532,3 +563,40 @@ class FluxNetParams:
         self.c.stencil_w = self.stencil_w.data_ptr()
         for g, f in enumerate(self.fno):
             self.c.fno[g] = ctypes.pointer(f.c) if f is not None else ctypes.POINTER(Fno)()
+
+
+class FnoGradBuffers:
+    """Zeroed float32 gradient buffers with the layouts of a FnoParams."""
+
+    NAMES = ("lift_w", "lift_b", "spec_w", "point_w", "point_b", "proj_w", "proj_b")
+
+    def __init__(self, fno):
+        for k in self.NAMES:
+            setattr(self, k, torch.zeros_like(getattr(fno, k)))
+        self.c = FnoGrad(*[getattr(self, k).data_ptr() for k in self.NAMES])
+
+    def tensors(self):
+        return [getattr(self, k) for k in self.NAMES]
+
+    def spec_complex(self):
+        """spec_w as complex [L, 2M, M, C_in, C_out] (the oracle's R order)."""
+        return torch.view_as_complex(self.spec_w.contiguous()).permute(0, 3, 4, 1, 2)
+
+
+class FluxNetGradBuffers:
+    """Gradients of a FluxNetParams (accumulated by the backward calls)."""
+
+    def __init__(self, net):
+        self.stencil_w = torch.zeros_like(net.stencil_w)
+        self.fno = [FnoGradBuffers(f) if f is not None else None for f in net.fno]
+        self.c = FluxNetGrad()
+        self.c.stencil_w = self.stencil_w.data_ptr()
+        for g, f in enumerate(self.fno):
+            self.c.fno[g] = ctypes.pointer(f.c) if f is not None else ctypes.POINTER(FnoGrad)()
+
+    def zero_(self):
+        self.stencil_w.zero_()
+        for f in self.fno:
+            if f is not None:
+                for t in f.tensors():
+                    t.zero_()

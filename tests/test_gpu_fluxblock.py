@@ -172,3 +172,106 @@ def test_fluxblock_step_matches_oracle(cfg, n, b):
     # the step used the fields it returned
     a = s.fluxblock_fv_step(prm, net.stencil_w, f, u, v)
     assert torch.equal(a[0], uo) and torch.equal(a[1], vo)
+
+
+def _fno_grads_ref(x, a, gF):
+    """Oracle autograd of sum(gF * FNO(x)) in every parameter and in x."""
+    p = fno.from_arrays(a)
+    leaves = [p["P_w"], p["P_b"], p["Q_w"], p["Q_b"]]
+    for lay in p["layers"]:
+        leaves += [lay["R"], lay["W"], lay["b"]]
+    for t in leaves:
+        t.requires_grad_(True)
+    xr = x.clone().requires_grad_(True)
+    (gF * fno.fno_forward(xr, p)).sum().backward()
+    return p, xr.grad
+
+
+def _check_fno_grads(gb, p, tol):
+    assert rel_l2(gb.lift_w, p["P_w"].grad) < tol
+    assert rel_l2(gb.lift_b, p["P_b"].grad) < tol
+    assert rel_l2(gb.proj_w, p["Q_w"].grad) < tol
+    # the output bias of the derivative operator has an exactly zero gradient
+    # inside the step (a uniform offset of every face derivative cancels in
+    # the flux differences): compare on the scale of the projection weights
+    scale = max(p["Q_b"].grad.norm().item(), p["Q_w"].grad.norm().item())
+    assert (gb.proj_b.double().cpu() - p["Q_b"].grad).norm().item() < tol * scale
+    spec = gb.spec_complex()
+    for l, lay in enumerate(p["layers"]):
+        assert rel_l2(gb.point_w[l], lay["W"].grad) < tol, l
+        # (the last layer's bias feeds the projection linearly: the same
+        # exact zero for the derivative operator)
+        sc = max(lay["b"].grad.norm().item(), lay["W"].grad.norm().item())
+        assert (gb.point_b[l].double().cpu() - lay["b"].grad).norm().item() < tol * sc, l
+        r = spec[l].cpu()
+        ref = lay["R"].grad
+        err = ((r.to(torch.complex128) - ref).abs().norm() / ref.abs().norm()).item()
+        assert err < tol, (l, err)
+
+
+@pytest.mark.parametrize("cfg,n,b", [("forced", 64, 2), ("decaying", 128, 2)])
+def test_fno_backward_matches_oracle_autograd(cfg, n, b):
+    """Every FNO parameter gradient (the complex spectral weights in torch's
+    d/dRe + i d/dIm convention) and the input gradient, both operators."""
+    L_ = need_gpu()
+    announce("fno backward", cfg, n, b)
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(51, cfg, out_scale=1.0)
+    net = L_.FluxNetParams(_stencils(53), L_.FnoParams.from_arrays(a_i),
+                           L_.FnoParams.from_arrays(a_d))
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=55)
+    u, v = dev(u0, torch.float32), dev(v0, torch.float32)
+    gF = torch.tensor(si.random_field(57, (b, 8, n, n)), dtype=torch.float32)
+    gb = L_.FluxNetGradBuffers(net)
+    gu, gv = s.fno_backward(net, u, v, gF.cuda(), gb)
+    x = torch.stack([cpu64(u), cpu64(v)], dim=1)
+    p_i, gx_i = _fno_grads_ref(x, a_i, gF[:, :4].double())
+    p_d, gx_d = _fno_grads_ref(x, a_d, gF[:, 4:].double())
+    _check_fno_grads(gb.fno[0], p_i, 1e-4)
+    _check_fno_grads(gb.fno[1], p_d, 1e-4)
+    gx = gx_i + gx_d
+    assert rel_l2(gu, gx[:, 0]) < 1e-4 and rel_l2(gv, gx[:, 1]) < 1e-4
+    # deterministic: a second call accumulates exactly the same numbers
+    before = [t.clone() for f in gb.fno for t in f.tensors()]
+    gu2, gv2 = s.fno_backward(net, u, v, gF.cuda(), gb)
+    assert torch.equal(gu, gu2) and torch.equal(gv, gv2)
+    for t0, t1 in zip(before, [t for f in gb.fno for t in f.tensors()]):
+        assert torch.equal(2 * t0, t1)
+
+
+def test_fluxblock_step_bwd_matches_oracle_autograd():
+    """The gradient of the whole flux-block step: state, uniform kernels and
+    both FNOs (forced configuration at 64^2)."""
+    L_ = need_gpu()
+    announce("fluxblock step bwd")
+    n, b = 64, 2
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(61, "forced", out_scale=0.2)
+    w = _stencils(63)
+    net = L_.FluxNetParams(w, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=65)
+    u, v = dev(u0, torch.float32), dev(v0, torch.float32)
+    g = torch.Generator().manual_seed(67)
+    gu_out = torch.randn(b, n, n, generator=g, dtype=torch.float64)
+    gv_out = torch.randn(b, n, n, generator=g, dtype=torch.float64)
+    prm = L_.params(**KW)
+    gb = L_.FluxNetGradBuffers(net)
+    gu, gv = s.fluxblock_step_bwd(prm, net, u, v, dev(gu_out, torch.float32),
+                                  dev(gv_out, torch.float32), gb)
+    p_i, p_d = fno.from_arrays(a_i), fno.from_arrays(a_d)
+    leaves = []
+    for p in (p_i, p_d):
+        leaves += [p["P_w"], p["P_b"], p["Q_w"], p["Q_b"]]
+        for lay in p["layers"]:
+            leaves += [lay["R"], lay["W"], lay["b"]]
+    wr = w.double().requires_grad_(True)
+    for t in leaves:
+        t.requires_grad_(True)
+    ua, va = cpu64(u).requires_grad_(True), cpu64(v).requires_grad_(True)
+    params = {"wi": wr[0], "wd": wr[1], "fno_i": p_i, "fno_d": p_d}
+    x, y = fluxblock.fluxblock_step(ua, va, oracle_prm(n, n, **KW), params)
+    ((gu_out * x).sum() + (gv_out * y).sum()).backward()
+    assert rel_l2(gu, ua.grad) < 1e-4 and rel_l2(gv, va.grad) < 1e-4
+    assert rel_l2(gb.stencil_w, wr.grad) < 1e-4
+    _check_fno_grads(gb.fno[0], p_i, 1e-4)
+    _check_fno_grads(gb.fno[1], p_d, 1e-4)
