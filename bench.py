@@ -419,6 +419,34 @@ def training_block(iters=5):
             "learned_steps_per_s": B * unroll / t}
 
 
+def fluxblock_training_block(iters=3):
+    """One training iteration of the paper's flux-block model on the
+    decaying-flow configuration: 128^2, batch 8, FNOs of 4 layers, 16 modes,
+    width 8, unrolled 32 steps (states kept, step adjoint backwards, Adam on
+    every parameter); a plain-FV rollout stands in for the labels."""
+    import torch
+    import synthetic_inputs as si
+    from paper_2507_01975_amd import ldsv, train as T
+    w = si.WORKLOADS["decaying128_train"]
+    n, B, unroll = w["nx"], w["batch"], w["unroll"]
+    s = ldsv.Solver(n, n, B)
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"])
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=300)
+    tu, tv = s.rollout(prm, u, v, unroll + 8)
+    labels = (torch.cat([u[None], tu]), torch.cat([v[None], tv]))
+    net, _ = _fluxblock_net("decaying", ldsv)
+    T.train_fluxblock(s, net, labels, prm, iters=1, unroll=unroll, log_every=10 ** 9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T.train_fluxblock(s, net, labels, prm, iters=iters, unroll=unroll, log_every=10 ** 9)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / iters
+    s.close()
+    return {"workload": "decaying128_train with the flux-block model (128^2, batch 8, unroll 32, "
+                        "FNOs 4 layers / 16 modes / width 8, Adam)", "ms_per_iteration": 1e3 * t,
+            "learned_steps_per_s": B * unroll / t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,7 +483,8 @@ def main():
         del src, dst
     if a.learned_only:
         print(json.dumps({"learned": learned_block(a.steps, a.warmup),
-                          "fluxblock": fluxblock_block(a.steps, a.warmup)}), flush=True)
+                          "fluxblock": fluxblock_block(a.steps, a.warmup),
+                          "fluxblock_training": fluxblock_training_block()}), flush=True)
         return
 
     w = si.WORKLOADS["decaying512"]
@@ -527,6 +556,8 @@ def main():
         line["burgers64"] = burgers_block()
         log("training iteration 128^2")
         line["training"] = training_block()
+        log("flux-block training iteration 128^2")
+        line["fluxblock_training"] = fluxblock_training_block()
     if not a.no_corr:
         log("corr>=0.9 comparison: learned coarse vs plain FV resolution sweep")
         from paper_2507_01975_amd import train as T

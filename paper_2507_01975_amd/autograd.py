@@ -14,6 +14,11 @@ that the solver composes with other torch code:
     rollout(solver, prm, net, u0, v0, n, ...)    n learned steps with
                                                  checkpointing, grads to u0,
                                                  v0 and net's parameters
+    fluxblock_step(solver, prm, fnet, u, v)      one step of the paper's
+                                                 flux-block model (uniform
+                                                 kernels + FNOs), grads to
+                                                 u, v and every parameter
+                                                 tensor of the FluxNetParams
 
 The network parameters are the FP32 master tensors of a
 ``ldsv.NetParams`` (``net.master_w`` [Cout][3][3][Cin] and ``net.b``); give
@@ -124,6 +129,43 @@ class _Rollout(torch.autograd.Function):
                                           checkpoint_every=ctx.ce, first_index=ctx.first,
                                           g_traj=(gtu, gtv), want_input_grad=True)
         return (gu0, gv0, None, None, None, None, None, None) + tuple(_net_grads(dW))
+
+
+def _fluxblock_params(fnet):
+    out = [fnet.stencil_w]
+    for f in fnet.fno:
+        if f is not None:
+            out += [f.lift_w, f.lift_b, f.spec_w, f.point_w, f.point_b, f.proj_w, f.proj_b]
+    return out
+
+
+class _FluxBlockStep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, v, solver, prm, fnet, *params):
+        u, v = u.contiguous(), v.contiguous()
+        uo, vo = solver.fluxblock_step(prm, fnet, u, v)
+        ctx.solver, ctx.prm, ctx.fnet = solver, prm, fnet
+        ctx.save_for_backward(u, v)
+        return uo, vo
+
+    @staticmethod
+    def backward(ctx, gu, gv):
+        u, v = ctx.saved_tensors
+        gu = _zeros_if_none(gu, u)
+        gv = _zeros_if_none(gv, v)
+        gb = ldsv.FluxNetGradBuffers(ctx.fnet)
+        gui, gvi = ctx.solver.fluxblock_step_bwd(ctx.prm, ctx.fnet, u, v, gu, gv, gb)
+        grads = [gb.stencil_w]
+        for f in gb.fno:
+            if f is not None:
+                grads += f.tensors()
+        return (gui, gvi, None, None, None) + tuple(grads)
+
+
+def fluxblock_step(solver, prm, fnet, u, v):
+    """One step of the flux-block model; differentiable in u, v and the
+    FluxNetParams tensors (give them requires_grad)."""
+    return _FluxBlockStep.apply(u, v, solver, prm, fnet, *_fluxblock_params(fnet))
 
 
 def fv_step(solver, prm, u, v, coef=None):

@@ -9,10 +9,11 @@ int ldsv_launch_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float
                             const float* v, float* fields, bool keep_pre, hipStream_t st);
 // the handle's [B][8][Ny][Nx] field and field-gradient buffers
 int ldsv_ensure_fluxblock(ldsv_handle* h);
-// forward with the activations kept, then the backward from gfields
-// [B][8][Ny][Nx]: accumulates the parameter gradients into gr; gu, gv
-// (nullable) receive the input gradient, added to their contents when
-// accumulate is set
+// backward from gfields [B][8][Ny][Nx] (after a forward with the activations
+// kept, run here unless forward_kept says the last forward on this handle
+// kept them for the same net and input): accumulates the parameter
+// gradients into gr; gu, gv (nullable) receive the input gradient, added to
+// their contents when accumulate is set
 int ldsv_launch_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr,
                              const float* u, const float* v, const float* gfields, float* gu,
-                             float* gv, int accumulate, hipStream_t st);
+                             float* gv, int accumulate, hipStream_t st, bool forward_kept);

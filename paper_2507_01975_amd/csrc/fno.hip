@@ -431,10 +431,11 @@ __global__ void __launch_bounds__(kBlock) k_fno_proj_bwd(const float* __restrict
   block_sums<4 * C + 4>(prod, part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * (4 * C + 4));
 }
 
-// partials of dW[o][i] = sum dz_o v_i and db[o] = sum dz_o over the pixels of
-// one (network, trajectory): part[z][b][C C + C].  v_i = GELU(vpre_i) when
-// GELU_V (v_l for l >= 1 from the saved z_{l-1}), else vpre itself (v_0).
-// Block C*C: thread (o, i).
+// partials of dW[o][i] = sum dz_o v_i and db[o] = sum dz_o over a chunk of
+// kWChunk pixels of one (network, trajectory): part[z][b][chunk][C C + C].
+// v_i = GELU(vpre_i) when GELU_V (v_l for l >= 1 from the saved z_{l-1}),
+// else vpre itself (v_0).  Grid (chunks, nnet B); block C*C: thread (o, i).
+constexpr int kWChunk = 1024;
 template <int C, bool GELU_V>
 __global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ dz,
                                                      const float* __restrict__ vpre,
@@ -443,12 +444,13 @@ __global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ d
   constexpr int kS = kT + 4;      // padded row (16-byte aligned, spreads banks)
   __shared__ __attribute__((aligned(16))) float sdz[C][kS];
   __shared__ __attribute__((aligned(16))) float sv[C][kS];
-  const int zb = blockIdx.x;      // z * B + b
+  const int zb = blockIdx.y;      // z * B + b
   const int o = threadIdx.x / C, i = threadIdx.x % C;
   const float* d = dz + (size_t)zb * C * n;
   const float* vp = vpre + (size_t)zb * C * n;
   float acc = 0.f, accb = 0.f;
-  for (int p0 = 0; p0 < n; p0 += kT) {
+  const int pend = min(n, (int)(blockIdx.x + 1) * kWChunk);
+  for (int p0 = blockIdx.x * kWChunk; p0 < pend; p0 += kT) {
     for (int e = threadIdx.x; e < C * kT; e += C * C) {
       const int c = e / kT, q = e - c * kT;
       const float x = vp[(size_t)c * n + p0 + q];
@@ -465,7 +467,7 @@ __global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ d
     }
     __syncthreads();
   }
-  float* dst = part + (size_t)zb * (C * C + C);
+  float* dst = part + ((size_t)zb * gridDim.x + blockIdx.x) * (C * C + C);
   dst[o * C + i] = acc;
   if (i == 0) dst[C * C + o] = accb;
 }
@@ -555,7 +557,9 @@ struct PartOut {
   float* out[2];  // destination of network slice z (accumulated)
 };
 
-// out_z[j] += sum over blk of part[(z nblk + blk) stride + off + j], blk in order
+// out_z[j] += sum over blk of part[(z nblk + blk) stride + off + j]: eight
+// interleaved running sums (blk mod 8, so eight loads are in flight) added
+// in a fixed order at the end
 __global__ void __launch_bounds__(kBlock) k_sum_partials(const float* __restrict__ part, int nblk,
                                                          size_t stride, int off, int len,
                                                          PartOut po) {
@@ -563,9 +567,14 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const float* __restrict
   const int z = blockIdx.z;
   if (j >= len) return;
   const float* p = part + (size_t)z * nblk * stride + off + j;
-  float acc = 0.f;
-  for (int k = 0; k < nblk; ++k) acc += p[(size_t)k * stride];
-  po.out[z][j] += acc;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int k = 0;
+  for (; k + 8 <= nblk; k += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += p[(size_t)(k + q) * stride];
+  }
+  for (int q = 0; k < nblk; ++k, ++q) acc[q] += p[(size_t)k * stride];
+  po.out[z][j] += ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_zero(float* __restrict__ p, size_t n) {
@@ -636,7 +645,8 @@ struct FnoWs {
 size_t fno_small_len(const ldsv_handle* h, const FnoShape& sh) {
   const size_t nblk = (h->ncell + kBlock - 1) / kBlock;
   const size_t a = (size_t)sh.nnet * h->g.batch * nblk * (4 * sh.C + 4);      // projection
-  const size_t b = (size_t)sh.nnet * h->g.batch * (sh.C * sh.C + sh.C);       // pointwise
+  const size_t nch = (h->ncell + kWChunk - 1) / kWChunk;
+  const size_t b = (size_t)sh.nnet * h->g.batch * nch * (sh.C * sh.C + sh.C); // pointwise
   const size_t c = (size_t)sh.nnet * h->g.batch * nblk * 3 * sh.C;            // lift
   return std::max(a, std::max(b, c));
 }
@@ -826,15 +836,16 @@ int fno_backward_e(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_g
       g_sw[g] = q->spec_w + (size_t)l * C * C * nm * 2;
     }
     // pointwise weight and bias gradients (v_l from v_0 or GELU(z_{l-1}))
+    const int nch = (n + kWChunk - 1) / kWChunk;
     if (l == 0)
-      LDSV_TLAUNCH(h, 7, (k_fno_wgrad<C, false>), dim3(sh.nnet * B), dim3(C * C), 0, st,
+      LDSV_TLAUNCH(h, 7, (k_fno_wgrad<C, false>), dim3(nch, sh.nnet * B), dim3(C * C), 0, st,
                    (const float*)dcur, (const float*)w.v0, w.small, n, B);
     else
-      LDSV_TLAUNCH(h, 7, (k_fno_wgrad<C, true>), dim3(sh.nnet * B), dim3(C * C), 0, st,
+      LDSV_TLAUNCH(h, 7, (k_fno_wgrad<C, true>), dim3(nch, sh.nnet * B), dim3(C * C), 0, st,
                    (const float*)dcur, (const float*)(w.pre + (size_t)(l - 1) * w.act), w.small, n,
                    B);
-    LDSV_TRY(sum_partials(h, sh, a, w.small, B, C * C + C, 0, C * C, g_pw, st));
-    LDSV_TRY(sum_partials(h, sh, a, w.small, B, C * C + C, C * C, C, g_pb, st));
+    LDSV_TRY(sum_partials(h, sh, a, w.small, B * nch, C * C + C, 0, C * C, g_pw, st));
+    LDSV_TRY(sum_partials(h, sh, a, w.small, B * nch, C * C + C, C * C, C, g_pb, st));
     // DZ = F(dz_l) into X
     {
       auto k = k_fno_spec<E, false>;
@@ -892,7 +903,7 @@ int check_fluxnet_grad(const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr) {
 // (or, with accumulate, add) the input gradient
 int ldsv_launch_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr,
                              const float* u, const float* v, const float* gfields, float* gu,
-                             float* gv, int accumulate, hipStream_t st) {
+                             float* gv, int accumulate, hipStream_t st, bool forward_kept) {
   FnoShape sh;
   LDSV_TRY(check_fluxnet(h, net, &sh));
   if (sh.nnet == 0) {
@@ -906,12 +917,12 @@ int ldsv_launch_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv
   LDSV_TRY(check_fluxnet_grad(net, gr));
   FnoWs w;
   LDSV_TRY(ensure_fno(h, sh, 2, &w));
-  float* scratch_fields = nullptr;
-  LDSV_TRY(ldsv_ensure_fluxblock(h));
-  scratch_fields = h->fb_fields;
   const bool small = h->ncell <= (size_t)4 * kFnoBlock;
-  if (small) LDSV_TRY(fno_forward_e<4>(h, net, sh, u, v, scratch_fields, w, st));
-  else LDSV_TRY(fno_forward_e<16>(h, net, sh, u, v, scratch_fields, w, st));
+  if (!forward_kept) {
+    LDSV_TRY(ldsv_ensure_fluxblock(h));
+    if (small) LDSV_TRY(fno_forward_e<4>(h, net, sh, u, v, h->fb_fields, w, st));
+    else LDSV_TRY(fno_forward_e<16>(h, net, sh, u, v, h->fb_fields, w, st));
+  }
   if (small && sh.C == 16)
     return fno_backward_e<4, 16>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
   if (small)
@@ -936,7 +947,9 @@ int ldsv_launch_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float
     return LDSV_OK;
   }
   FnoWs w;
-  LDSV_TRY(ensure_fno(h, sh, keep_pre ? 1 : 0, &w));
+  // a forward that keeps its activations sizes the workspace for the
+  // backward as well, so the backward that follows does not move them
+  LDSV_TRY(ensure_fno(h, sh, keep_pre ? 2 : 0, &w));
   if (h->ncell <= (size_t)4 * kFnoBlock) return fno_forward_e<4>(h, net, sh, u, v, fields, w, st);
   return fno_forward_e<16>(h, net, sh, u, v, fields, w, st);
 }
@@ -1006,7 +1019,8 @@ int ldsv_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u, c
   LDSV_TRY(ldsv_check_handle(h));
   LDSV_REQUIRE(net && u && v && gfields, LDSV_EINVAL, "fno_backward: null argument");
   LDSV_REQUIRE((gu == nullptr) == (gv == nullptr), LDSV_EINVAL, "fno_backward: gu and gv together");
-  return ldsv_launch_fno_backward(h, net, grad, u, v, gfields, gu, gv, 0, (hipStream_t)stream);
+  return ldsv_launch_fno_backward(h, net, grad, u, v, gfields, gu, gv, 0, (hipStream_t)stream,
+                                  false);
 }
 
 int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,
@@ -1023,8 +1037,9 @@ int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_f
   LDSV_TRY(check_fluxnet_grad(net, grad));
   const hipStream_t st = (hipStream_t)stream;
   LDSV_TRY(ldsv_ensure_fluxblock(h));
-  // the fields of the forward step, then the FV adjoint with their gradient
-  LDSV_TRY(ldsv_launch_fno_forward(h, net, u_in, v_in, h->fb_fields, false, st));
+  // the fields of the forward step (activations kept for the FNO backward),
+  // then the FV adjoint with their gradient
+  LDSV_TRY(ldsv_launch_fno_forward(h, net, u_in, v_in, h->fb_fields, true, st));
   LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(8 * h->nstate), dim3(kBlock), 0, st, h->fb_gfields,
                8 * h->nstate);
   LDSV_LAUNCHED();
@@ -1039,9 +1054,8 @@ int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_f
                          st, &fb));
   if (sh.nnet == 0) return LDSV_OK;
   // the operators' gradients, their input gradient added to the state's
-  // (the forward is recomputed with its activations kept; it overwrites the
-  // field buffer, which the FV adjoint has finished reading)
-  return ldsv_launch_fno_backward(h, net, grad, u_in, v_in, h->fb_gfields, gu_in, gv_in, 1, st);
+  return ldsv_launch_fno_backward(h, net, grad, u_in, v_in, h->fb_gfields, gu_in, gv_in, 1, st,
+                                  true);
 }
 
 int ldsv_fluxblock_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,

@@ -335,7 +335,14 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch;
   const T idx = (T)(nx / h->g.lx), idy = (T)(ny / h->g.ly);
   const size_t cs = sizeof(Cx<T>);
-  if ((size_t)nx * ny <= (size_t)16 * kOneBlock && (size_t)nx * ny * cs <= 131072) {
+  // one workgroup per trajectory pair holds the whole field in LDS: the
+  // fastest path when the grid is small (one HBM round trip), but at 16
+  // elements per thread (128^2) a workgroup takes ~50 us of transform
+  // latency, so it pays only when the pairs alone fill the chip; otherwise
+  // the three passes below spread the work over many more workgroups
+  const bool one_block = (size_t)nx * ny <= (size_t)4 * kOneBlock ||
+                         ((size_t)nx * ny <= (size_t)16 * kOneBlock && h->npairs >= 256);
+  if (one_block && (size_t)nx * ny * cs <= 131072) {
     // u*, v* are read only by the cells that write u, v at the same index
     // after all reads of neighbours are done (the divergence is formed
     // before the first barrier), so in-place calls are safe here as well

@@ -129,6 +129,69 @@ def train(solver, net, labels, prm, iters, unroll=32, checkpoint_every=8, lr=1e-
     return hist
 
 
+def fluxblock_param_tensors(net):
+    """The flux block's trainable tensors: the uniform kernels, then each
+    present FNO's lift, spectral, pointwise and projection tensors."""
+    out = [net.stencil_w]
+    for f in net.fno:
+        if f is not None:
+            out += [f.lift_w, f.lift_b, f.spec_w, f.point_w, f.point_b, f.proj_w, f.proj_b]
+    return out
+
+
+def fluxblock_grad_tensors(grads):
+    out = [grads.stencil_w]
+    for f in grads.fno:
+        if f is not None:
+            out += f.tensors()
+    return out
+
+
+def train_fluxblock(solver, net, labels, prm, iters, unroll=8, lr=1e-4, seed=0, progress=None,
+                    log_every=10):
+    """Adam on the unrolled rollout MSE of the flux-block model (the paper's
+    own learnable flux block, Sec. 3.4, trained on the Eq. 13 loss).
+    labels: (lu, lv) [T+1, B, n, n].  Each iteration unrolls `unroll` steps
+    from a random labels[t0], keeping the states, then runs the step adjoint
+    (ldsv_fluxblock_step_bwd) backwards through them with the loss gradient
+    of every state added on the way.  Returns the loss history."""
+    lu, lv = labels
+    T = lu.shape[0] - 1
+    g = torch.Generator().manual_seed(seed)
+    params = fluxblock_param_tensors(net)
+    grads = ldsv.FluxNetGradBuffers(net)
+    gts = fluxblock_grad_tensors(grads)
+    m = [torch.zeros_like(p) for p in params]
+    v2 = [torch.zeros_like(p) for p in params]
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hist = []
+    t_start = time.perf_counter()
+    for it in range(iters):
+        t0 = int(torch.randint(0, T - unroll + 1, (1,), generator=g))
+        states = [(lu[t0].contiguous(), lv[t0].contiguous())]
+        for k in range(unroll):
+            states.append(solver.fluxblock_step(prm, net, *states[-1]))
+        grads.zero_()
+        loss.zero_()
+        gu = gv = None
+        for k in range(unroll, 0, -1):
+            mu, mv = solver.mse_grad(states[k][0], states[k][1], lu[t0 + k], lv[t0 + k],
+                                     scale=1.0 / unroll, loss=loss)
+            if gu is not None:
+                mu += gu
+                mv += gv
+            gu, gv = solver.fluxblock_step_bwd(prm, net, states[k - 1][0], states[k - 1][1],
+                                               mu, mv, grads)
+        for p, gp, mm, vv in zip(params, gts, m, v2):
+            ldsv.adam_step(p, gp, mm, vv, it + 1, lr)
+        if (it + 1) % log_every == 0 or it == 0:
+            l = loss.item() / unroll
+            hist.append((it + 1, l))
+            if progress:
+                progress("iter %d loss %.6e (%.1f s)" % (it + 1, l, time.perf_counter() - t_start))
+    return hist
+
+
 def vorticity_pcc_series(solver, traj, labels):
     """PCC of corner vorticity per snapshot and trajectory: [T, B]."""
     tu, tv = traj

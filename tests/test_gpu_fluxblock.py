@@ -275,3 +275,58 @@ def test_fluxblock_step_bwd_matches_oracle_autograd():
     assert rel_l2(gb.stencil_w, wr.grad) < 1e-4
     _check_fno_grads(gb.fno[0], p_i, 1e-4)
     _check_fno_grads(gb.fno[1], p_d, 1e-4)
+
+
+def test_fluxblock_autograd_function_is_the_adjoint():
+    L_ = need_gpu()
+    from paper_2507_01975_amd import autograd as A
+    announce("fluxblock autograd")
+    n, b = 64, 2
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(71, "decaying", out_scale=0.2)
+    net = L_.FluxNetParams(_stencils(73), L_.FnoParams.from_arrays(a_i),
+                           L_.FnoParams.from_arrays(a_d))
+    params = A._fluxblock_params(net)
+    for p in params:
+        p.requires_grad_(True)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=75)
+    u = dev(u0, torch.float32).requires_grad_(True)
+    v = dev(v0, torch.float32).requires_grad_(True)
+    prm = L_.params(**KW)
+    wu, wv = (torch.randn(b, n, n, generator=torch.Generator().manual_seed(77)).cuda()
+              for _ in range(2))
+    uo, vo = A.fluxblock_step(s, prm, net, u, v)
+    ((wu * uo).sum() + (wv * vo).sum()).backward()
+    gb = L_.FluxNetGradBuffers(net)
+    gu, gv = s.fluxblock_step_bwd(prm, net, u.detach(), v.detach(), wu, wv, gb)
+    assert torch.equal(u.grad, gu) and torch.equal(v.grad, gv)
+    ref = [gb.stencil_w] + [t for f in gb.fno for t in f.tensors()]
+    for p, r in zip(params, ref):
+        assert torch.equal(p.grad, r)
+
+
+def test_train_fluxblock_reduces_the_loss():
+    """Teacher-student: labels from the same model with perturbed uniform
+    kernels; a few Adam iterations of the unrolled loss bring the student's
+    kernels toward the teacher's (the gradient itself is pinned above)."""
+    L_ = need_gpu()
+    from paper_2507_01975_amd import train as T
+    announce("fluxblock training")
+    n, b, steps = 64, 4, 10
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(81, "decaying", out_scale=0.1)
+    w = _stencils(83, scale=0.01)
+    teacher = L_.FluxNetParams(w + torch.tensor(si.random_field(85, (2, 4, 20), scale=0.02),
+                                                dtype=torch.float32),
+                               L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    student = L_.FluxNetParams(w, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    prm = L_.params(nu=1e-3, dt=0.02)
+    u, v = s.init_state(L_.IC_GRF_PEAK, seed=87)
+    lu, lv = [u], [v]
+    for _ in range(steps):
+        u, v = s.fluxblock_step(prm, teacher, u, v)
+        lu.append(u)
+        lv.append(v)
+    labels = (torch.stack(lu), torch.stack(lv))
+    hist = T.train_fluxblock(s, student, labels, prm, iters=12, unroll=4, lr=3e-3, log_every=1)
+    assert hist[-1][1] < 0.5 * hist[0][1], hist
