@@ -299,6 +299,31 @@ def fluxblock_block(steps, warmup):
         out["fno_mix_hbm"] = {"achieved": mix_bytes / tm / 1e9, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": mix_bytes / tm / 1e9 / HBM_PEAK_GBS,
                               "alg_bytes_per_step": mix_bytes}
+    # the complete model: the same flux block plus the temporal correction
+    # block every k_c = 4 steps (FNO over the 4 states since the last
+    # correction: 4 layers, 32 modes, width 8)
+    kc = 4
+    tc = ldsv.FnoParams.from_arrays(si.fno_weights(9, 8, 4, 32, n_in=2 * kc, n_out=2))
+    prm_tc = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                         forcing_k=w["forcing_k"], drag=w["drag"], k_c=kc)
+    hu = [u.clone() for _ in range(kc + 1)]
+    hv = [v.clone() for _ in range(kc + 1)]
+
+    def run_tc(k0, k):
+        for j in range(k0, k0 + k):
+            i = j % (kc + 1)
+            src = [(i - kc + q) % (kc + 1) for q in range(kc)]
+            s.fluxblock_tc_step(prm_tc, net, tc, [hu[q] for q in src], [hv[q] for q in src], j,
+                                out=(hu[i], hv[i]))
+    run_tc(kc, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_tc(kc + warmup, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["complete_model"] = {"k_c": kc, "tc_fno": "4 layers, 32 modes, width 8",
+                             "ms_per_step": 1e3 * t / steps,
+                             "cell_steps_per_s": cells * steps / t}
     return out
 
 

@@ -301,7 +301,7 @@ LDSV_API int ldsv_cfl_dt(ldsv_handle* h, const void* u, const void* v, double cf
  * face derivative of kind K, at the face the cell owns.  The residual stays
  * conservative (every face value is single-valued).
  *
- * FNO (Li et al. 2021, the paper's frequency operator): v_0 = lift (u, v);
+ * FNO (Li et al. 2021, the paper's frequency operator): v_0 = lift x;
  * L layers v <- GELU(K v + W v + b) with no GELU after the last; fields =
  * proj v_L.  K keeps the modes k_y in [0, M) U [Ny - M, Ny), k_x < M of the
  * real 2D transform, mixes channels per mode with complex weights and
@@ -312,13 +312,17 @@ typedef struct {
   int width;             /* C: 8 or 16 */
   int layers;            /* L >= 1 */
   int modes;             /* M: 2M <= Ny and M <= Nx/2 */
-  const float* lift_w;   /* [C][2]: v_0 = lift_w (u, v) + lift_b */
+  int n_in;              /* input planes: 2 (u, v) for the flux block, 2 k_c for the
+                            temporal correction */
+  int n_out;             /* output channels: 4 for the flux block, 2 for the
+                            temporal correction */
+  const float* lift_w;   /* [C][n_in]: v_0 = lift_w x + lift_b */
   const float* lift_b;   /* [C] */
   const float* spec_w;   /* [L][C_in][C_out][2M][M] complex (re, im), 8-byte aligned */
   const float* point_w;  /* [L][C_out][C_in] */
   const float* point_b;  /* [L][C] */
-  const float* proj_w;   /* [4][C] */
-  const float* proj_b;   /* [4] */
+  const float* proj_w;   /* [n_out][C] */
+  const float* proj_b;   /* [n_out] */
 } ldsv_fno;
 
 typedef struct {
@@ -382,6 +386,33 @@ LDSV_API int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm,
                                      const float* v_in, const float* gu_out, const float* gv_out,
                                      float* gu_in, float* gv_in, const ldsv_fluxnet_grad* grad,
                                      void* stream);
+/* ---- the paper's temporal correction block (Eq. 2; Sec. 3.5) ----
+ * ldsv_fluxblock_tc_step: one step of the complete model.  u_k = FV(u_{k-1})
+ * with the flux block (fields from net's FNOs on u_{k-1}); when step_index
+ * (= k) is a multiple of prm->k_c and tc is given, the correction
+ * TC = tc(u_{k-k_c}, v_{k-k_c}, ..., u_{k-1}, v_{k-1}) (an FNO with
+ * n_in = 2 k_c planes, oldest state first, and n_out = 2) is added before
+ * the last projection, u_k = P(FV(u_{k-1}) + TC).  hist_u, hist_v: HOST
+ * arrays of k_c DEVICE pointers to the states u_{k-k_c} .. u_{k-1} (the last
+ * one is the step's input; the others are read only when the correction is
+ * applied).  Not in place. */
+LDSV_API int ldsv_fluxblock_tc_step(ldsv_handle* h, const ldsv_params* prm,
+                                    const ldsv_fluxnet* net, const ldsv_fno* tc,
+                                    const float* const* hist_u, const float* const* hist_v,
+                                    int step_index, float* u_out, float* v_out, void* stream);
+/* ldsv_fluxblock_tc_step_bwd: VJP of ldsv_fluxblock_tc_step: given gu_out,
+ * gv_out = dL/du_k, ACCUMULATES dL/d(history state j) into ghist_u[j],
+ * ghist_v[j] (host arrays of k_c device pointers, same order as hist_u),
+ * the flux-block parameter gradients into *grad and the correction's into
+ * *gtc (nullable when tc is). */
+LDSV_API int ldsv_fluxblock_tc_step_bwd(ldsv_handle* h, const ldsv_params* prm,
+                                        const ldsv_fluxnet* net, const ldsv_fno* tc,
+                                        const float* const* hist_u, const float* const* hist_v,
+                                        int step_index, const float* gu_out, const float* gv_out,
+                                        float* const* ghist_u, float* const* ghist_v,
+                                        const ldsv_fluxnet_grad* grad, const ldsv_fno_grad* gtc,
+                                        void* stream);
+
 /* ldsv_fluxblock_step: one step of the flux-block model, u_out = FV(u_in)
  * with fields = FNO(u_in) (evaluated once, held over the four sub-steps).
  * fields_out (nullable) receives the fields.  Not in place. */

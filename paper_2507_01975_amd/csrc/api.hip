@@ -200,11 +200,13 @@ int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* c
   return one_step(h, p, nullptr, 0, su, sv, du, dv, tcu, tcv, tcbs, st, nullptr, coef16, cbs16);
 }
 
-// the same with the flux block's uniform kernels and fields
+// the same with the flux block's uniform kernels and fields, and an
+// optional temporal correction (tcu, tcv, batch stride tcbs) added before
+// the last projection
 int ldsv_internal_step_fb(ldsv_handle* h, const ldsv_params* p, const FluxBlockArgs* fb,
-                          const void* su, const void* sv, void* du, void* dv, hipStream_t st) {
-  return one_step(h, p, nullptr, 0, su, sv, du, dv, nullptr, nullptr, 0, st, nullptr, nullptr, 0,
-                  fb);
+                          const void* su, const void* sv, void* du, void* dv, hipStream_t st,
+                          const float* tcu, const float* tcv, size_t tcbs) {
+  return one_step(h, p, nullptr, 0, su, sv, du, dv, tcu, tcv, tcbs, st, nullptr, nullptr, 0, fb);
 }
 
 // VJP of one RK4 step with a projection per sub-step (reverse sweep in

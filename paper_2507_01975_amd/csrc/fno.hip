@@ -44,6 +44,7 @@
 namespace {
 
 constexpr int kFnoBlock = 1024;
+constexpr int kMaxIn = 16;  // input planes of one FNO (two per state of a history)
 using c32 = Cx<float>;
 
 struct FnoArgs {
@@ -56,6 +57,11 @@ struct FnoArgs {
   const float* proj_b[2];
   int net[2];                // network run by grid.z slice z
   int slot[2];               // grid.z slice of network g, -1 if absent
+  int nin, nout;             // input planes (2 per state) and output channels
+  const float* xin[kMaxIn];  // input planes, each [B][Ny][Nx]
+  float* out;                // output channel c of network g, trajectory b at
+  size_t out_cs, out_bs;     //   out + (out_ch[g] + c) out_cs + b out_bs
+  int out_ch[2];
 };
 
 __device__ __forceinline__ int retained_row(int ky, int ny, int M) {
@@ -107,22 +113,37 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict_
   const int c0 = 2 * p, c1 = 2 * p + 1;
   const int n = nx * ny;
   if constexpr (LIFT) {
-    const float* u = vin + (size_t)b * n;
-    const float* v = vin2 + (size_t)b * n;
     const float* lw = a.lift_w[g];
     const float* lb = a.lift_b[g];
-    const float w00 = lw[2 * c0], w01 = lw[2 * c0 + 1], w10 = lw[2 * c1], w11 = lw[2 * c1 + 1];
+    const int nin = a.nin;
     const float b0 = lb[c0], b1 = lb[c1];
     float* d0 = v0out + ((size_t)(z * B + b) * C + c0) * n;
+    float q0[E], q1[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      q0[k] = b0;
+      q1[k] = b1;
+    }
+    for (int j = 0; j < nin; ++j) {
+      const float* x = a.xin[j] + (size_t)b * n;
+      const float w0 = lw[c0 * nin + j], w1 = lw[c1 * nin + j];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int t = k * kFnoBlock + (int)threadIdx.x;
+        if (t < n) {
+          const float xv = x[t];
+          q0[k] += w0 * xv;
+          q1[k] += w1 * xv;
+        }
+      }
+    }
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int t = k * kFnoBlock + (int)threadIdx.x;
       if (t < n) {
-        const float x0 = u[t], x1 = v[t];
-        const Cx<float> q{w00 * x0 + w01 * x1 + b0, w10 * x0 + w11 * x1 + b1};
-        A[t] = q;
-        d0[t] = q.x;  // v_0 kept for the pointwise term and the backward
-        d0[n + t] = q.y;
+        A[t] = Cx<float>{q0[k], q1[k]};
+        d0[t] = q0[k];  // v_0 kept for the pointwise term and the backward
+        d0[n + t] = q1[k];
       }
     }
   } else {
@@ -332,29 +353,32 @@ __global__ void __launch_bounds__(kFnoBlock, E <= 4 ? 8 : 4) k_fno_inv(const c32
   }
 }
 
-// fields[b][4 g + K] = Q_g v_L + b_Q (zeros for an absent network)
+// output channel K of network g = Q_g v_L + b_Q (zeros for an absent
+// network), K < nout <= 4
 __global__ void __launch_bounds__(kBlock) k_fno_proj(const float* __restrict__ vL, FnoArgs a,
-                                                     float* __restrict__ fields, int n, int C,
-                                                     int B) {
+                                                     int n, int C, int B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int b = blockIdx.y, g = blockIdx.z;
   if (t >= n) return;
   const int z = a.slot[g];
+  const int nout = a.nout;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   if (z >= 0) {
     const float* qw = a.proj_w[g];
     const float* qb = a.proj_b[g];
     const float* s = vL + (size_t)(z * B + b) * C * n + t;
 #pragma unroll
-    for (int K = 0; K < 4; ++K) acc[K] = qb[K];
+    for (int K = 0; K < 4; ++K) acc[K] = K < nout ? qb[K] : 0.f;
     for (int c = 0; c < C; ++c) {
       const float vc = s[(size_t)c * n];
 #pragma unroll
-      for (int K = 0; K < 4; ++K) acc[K] += qw[K * C + c] * vc;
+      for (int K = 0; K < 4; ++K)
+        if (K < nout) acc[K] += qw[K * C + c] * vc;
     }
   }
 #pragma unroll
-  for (int K = 0; K < 4; ++K) fields[((size_t)b * 8 + 4 * g + K) * n + t] = acc[K];
+  for (int K = 0; K < 4; ++K)
+    if (K < nout) a.out[(size_t)(a.out_ch[g] + K) * a.out_cs + (size_t)b * a.out_bs + t] = acc[K];
 }
 
 // ---------------------------------------------------------------- backward
@@ -380,9 +404,11 @@ __global__ void __launch_bounds__(kBlock) k_fno_proj(const float* __restrict__ v
 // sum of v over the block (blockDim == kBlock), returned to every thread of
 // wave 0's lane 0... written to dst[j] by thread j for j < NV
 template <int NV>
-__device__ __forceinline__ void block_sums(float (&v)[NV], float* __restrict__ dst) {
+__device__ __forceinline__ void block_sums(float (&v)[NV], float* __restrict__ dst,
+                                           int stride = 1) {
   __shared__ float red[kBlock / 64][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();  // a previous call's readers are done with red
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     float x = v[j];
@@ -395,40 +421,43 @@ __device__ __forceinline__ void block_sums(float (&v)[NV], float* __restrict__ d
     float acc = 0.f;
 #pragma unroll
     for (int q = 0; q < kBlock / 64; ++q) acc += red[q][j];
-    dst[j] = acc;
+    dst[(size_t)j * stride] = acc;
   }
 }
 
-// dv_L[c] = sum_K Q[K][c] dF_K; partials of dQ[K][c] = dF_K v_L[c] and
-// db_Q[K] = dF_K: part[z][b][blk][4C + 4]
-template <int C>
-__global__ void __launch_bounds__(kBlock) k_fno_proj_bwd(const float* __restrict__ gfields,
+// dv_L[c] = sum_K Q[K][c] dF_K with dF the output cotangent (addressed like
+// the output, base gout); partials of dQ[K][c] = dF_K v_L[c] and
+// db_Q[K] = dF_K: part[z][b][blk][NOUT C + NOUT]
+template <int C, int NOUT>
+__global__ void __launch_bounds__(kBlock) k_fno_proj_bwd(const float* __restrict__ gout,
                                                          const float* __restrict__ vL, FnoArgs a,
                                                          float* __restrict__ dv,
                                                          float* __restrict__ part, int n, int B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int b = blockIdx.y, z = blockIdx.z, g = a.net[z];
   const bool in = t < n;
-  float dF[4];
+  float dF[NOUT];
 #pragma unroll
-  for (int K = 0; K < 4; ++K) dF[K] = in ? gfields[((size_t)b * 8 + 4 * g + K) * n + t] : 0.f;
+  for (int K = 0; K < NOUT; ++K)
+    dF[K] = in ? gout[(size_t)(a.out_ch[g] + K) * a.out_cs + (size_t)b * a.out_bs + t] : 0.f;
   const float* qw = a.proj_w[g];
-  float prod[4 * C + 4];
+  float prod[NOUT * C + NOUT];
   const size_t base = (size_t)(z * B + b) * C * n;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const float x = in ? vL[base + (size_t)c * n + t] : 0.f;
     float d = 0.f;
 #pragma unroll
-    for (int K = 0; K < 4; ++K) {
+    for (int K = 0; K < NOUT; ++K) {
       d += qw[K * C + c] * dF[K];
       prod[K * C + c] = dF[K] * x;
     }
     if (in) dv[base + (size_t)c * n + t] = d;
   }
 #pragma unroll
-  for (int K = 0; K < 4; ++K) prod[4 * C + K] = dF[K];
-  block_sums<4 * C + 4>(prod, part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * (4 * C + 4));
+  for (int K = 0; K < NOUT; ++K) prod[NOUT * C + K] = dF[K];
+  block_sums<NOUT * C + NOUT>(
+      prod, part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * (NOUT * C + NOUT));
 }
 
 // partials of dW[o][i] = sum dz_o v_i and db[o] = sum dz_o over a chunk of
@@ -515,41 +544,54 @@ __global__ void __launch_bounds__(64 * C) k_fno_dR(const c32* __restrict__ Xl,
   }
 }
 
-// dx = sum over the networks of P^T dv_0 (written or added to gu, gv) and
-// partials of dP[c][j] = dv_0,c x_j, db_P[c] = dv_0,c: part[z][b][blk][3C]
+struct GradIn {
+  float* gx[kMaxIn];  // cotangents of the input planes (all null: not wanted)
+};
+
+// dx_j = sum over the networks of (P^T dv_0)_j (written or added to gx[j])
+// and partials of dP[c][j] = dv_0,c x_j, db_P[c] = dv_0,c:
+// part[z][b][blk][(nin + 1) C], dP in the [C][nin] order of the weights
 template <int C>
 __global__ void __launch_bounds__(kBlock) k_fno_lift_bwd(const float* __restrict__ dv0,
-                                                         const float* __restrict__ u,
-                                                         const float* __restrict__ v, FnoArgs a,
-                                                         int nnet, float* __restrict__ gu,
-                                                         float* __restrict__ gv, int accumulate,
-                                                         float* __restrict__ part, int n, int B) {
+                                                         FnoArgs a, int nnet, GradIn gi,
+                                                         int accumulate, float* __restrict__ part,
+                                                         int n, int B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int b = blockIdx.y;
   const bool in = t < n;
-  const float x0 = in ? u[(size_t)b * n + t] : 0.f;
-  const float x1 = in ? v[(size_t)b * n + t] : 0.f;
-  float g0 = 0.f, g1 = 0.f;
+  const int nin = a.nin;
+  const size_t q = (size_t)b * n + t;
+  float gx[kMaxIn];
+#pragma unroll
+  for (int j = 0; j < kMaxIn; ++j) gx[j] = 0.f;
   for (int z = 0; z < nnet; ++z) {
     const float* lw = a.lift_w[a.net[z]];
     const float* d = dv0 + (size_t)(z * B + b) * C * n;
-    float prod[3 * C];
+    float dc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const float dc = in ? d[(size_t)c * n + t] : 0.f;
-      g0 += lw[2 * c] * dc;
-      g1 += lw[2 * c + 1] * dc;
-      prod[2 * c] = dc * x0;
-      prod[2 * c + 1] = dc * x1;
-      prod[2 * C + c] = dc;
+    for (int c = 0; c < C; ++c) dc[c] = in ? d[(size_t)c * n + t] : 0.f;
+    float* dst = part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * ((nin + 1) * C);
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) {
+      if (j >= nin) break;
+      const float xj = in ? a.xin[j][q] : 0.f;
+      float prod[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        gx[j] += lw[c * nin + j] * dc[c];
+        prod[c] = dc[c] * xj;
+      }
+      block_sums<C>(prod, dst + j, nin);
     }
-    block_sums<3 * C>(prod, part + (((size_t)z * B + b) * gridDim.x + blockIdx.x) * (3 * C));
-    __syncthreads();  // block_sums' LDS is reused by the next network
+    block_sums<C>(dc, dst + nin * C);
   }
-  if (in && gu) {
-    const size_t q = (size_t)b * n + t;
-    gu[q] = accumulate ? gu[q] + g0 : g0;
-    gv[q] = accumulate ? gv[q] + g1 : g1;
+  if (in && gi.gx[0]) {
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j) {
+      if (j >= nin) break;
+      float* o = gi.gx[j];
+      o[q] = accumulate ? o[q] + gx[j] : gx[j];
+    }
   }
 }
 
@@ -588,14 +630,27 @@ struct FnoShape {
   int C, L, M, nnet;
 };
 
-int check_fluxnet(const ldsv_handle* h, const ldsv_fluxnet* net, FnoShape* sh) {
-  LDSV_REQUIRE(net, LDSV_EINVAL, "flux block: null network");
+// One or two FNOs run side by side (grid.z = network) on the same input
+// planes, each writing nout output channels: the flux block's pair (inputs
+// u, v; 4 fields each) or the temporal correction (inputs the history
+// states; 2 channels).
+struct FnoGroup {
+  const ldsv_fno* f[2];
+  int ngrid;                 // networks the output covers (absent ones write zeros)
+  int nin, nout;
+  const float* xin[kMaxIn];
+  float* out;
+  size_t out_cs, out_bs;
+  int out_ch[2];
+};
+
+int check_group(const ldsv_handle* h, const FnoGroup& G, FnoShape* sh) {
   LDSV_REQUIRE(h->g.dtype == LDSV_F32 && h->g.layout == LDSV_MAC, LDSV_EDTYPE,
                "flux block: the FNO needs an F32 MAC grid");
   sh->nnet = 0;
   sh->C = sh->L = sh->M = 0;
-  for (int g = 0; g < 2; ++g) {
-    const ldsv_fno* f = net->fno[g];
+  for (int g = 0; g < G.ngrid; ++g) {
+    const ldsv_fno* f = G.f[g];
     if (!f) continue;
     LDSV_REQUIRE(f->width == 8 || f->width == 16, LDSV_EINVAL, "fno[%d]: width %d (8 or 16)", g,
                  f->width);
@@ -604,6 +659,9 @@ int check_fluxnet(const ldsv_handle* h, const ldsv_fluxnet* net, FnoShape* sh) {
     LDSV_REQUIRE(f->modes >= 1 && 2 * f->modes <= h->g.ny && 2 * f->modes <= h->g.nx,
                  LDSV_EINVAL, "fno[%d]: modes %d needs 2 modes <= Ny and modes <= Nx/2", g,
                  f->modes);
+    LDSV_REQUIRE(f->n_in == G.nin && f->n_out == G.nout, LDSV_EINVAL,
+                 "fno[%d]: %d inputs and %d outputs where this call needs %d and %d", g, f->n_in,
+                 f->n_out, G.nin, G.nout);
     LDSV_REQUIRE(f->lift_w && f->lift_b && f->spec_w && f->point_w && f->point_b && f->proj_w &&
                      f->proj_b,
                  LDSV_EINVAL, "fno[%d]: null parameter", g);
@@ -618,6 +676,9 @@ int check_fluxnet(const ldsv_handle* h, const ldsv_fluxnet* net, FnoShape* sh) {
     sh->M = f->modes;
     sh->nnet++;
   }
+  LDSV_REQUIRE(G.nin >= 1 && G.nin <= kMaxIn && G.nout >= 1 && G.nout <= 4, LDSV_EINVAL,
+               "fno: %d inputs (1..%d) and %d outputs (1..4)", G.nin, kMaxIn, G.nout);
+  for (int j = 0; j < G.nin; ++j) LDSV_REQUIRE(G.xin[j], LDSV_EINVAL, "fno: null input plane %d", j);
   LDSV_REQUIRE((size_t)h->ncell <= (size_t)16 * kFnoBlock &&
                    (size_t)h->ncell * sizeof(Cx<float>) <= 131072,
                LDSV_ESHAPE, "fno: the grid must fit one LDS transform (Nx Ny <= 16384)");
@@ -644,10 +705,10 @@ struct FnoWs {
 
 size_t fno_small_len(const ldsv_handle* h, const FnoShape& sh) {
   const size_t nblk = (h->ncell + kBlock - 1) / kBlock;
-  const size_t a = (size_t)sh.nnet * h->g.batch * nblk * (4 * sh.C + 4);      // projection
+  const size_t a = (size_t)sh.nnet * h->g.batch * nblk * (4 * sh.C + 4);       // projection
   const size_t nch = (h->ncell + kWChunk - 1) / kWChunk;
-  const size_t b = (size_t)sh.nnet * h->g.batch * nch * (sh.C * sh.C + sh.C); // pointwise
-  const size_t c = (size_t)sh.nnet * h->g.batch * nblk * 3 * sh.C;            // lift
+  const size_t b = (size_t)sh.nnet * h->g.batch * nch * (sh.C * sh.C + sh.C);  // pointwise
+  const size_t c = (size_t)sh.nnet * h->g.batch * nblk * (kMaxIn + 1) * sh.C;  // lift
   return std::max(a, std::max(b, c));
 }
 
@@ -694,12 +755,13 @@ int ensure_fno(ldsv_handle* h, const FnoShape& sh, int level, FnoWs* w) {
   return LDSV_OK;
 }
 
-FnoArgs make_args(const ldsv_fluxnet* net, const FnoShape& sh, int layer) {
+FnoArgs make_args(const FnoGroup& G, const FnoShape& sh, int layer) {
   FnoArgs a{};
   int z = 0;
   for (int g = 0; g < 2; ++g) {
     a.slot[g] = -1;
-    const ldsv_fno* f = net->fno[g];
+    a.out_ch[g] = G.out_ch[g];
+    const ldsv_fno* f = g < G.ngrid ? G.f[g] : nullptr;
     if (!f) continue;
     a.lift_w[g] = f->lift_w;
     a.lift_b[g] = f->lift_b;
@@ -712,6 +774,12 @@ FnoArgs make_args(const ldsv_fluxnet* net, const FnoShape& sh, int layer) {
     a.slot[g] = z;
     a.net[z++] = g;
   }
+  a.nin = G.nin;
+  a.nout = G.nout;
+  for (int j = 0; j < G.nin; ++j) a.xin[j] = G.xin[j];
+  a.out = G.out;
+  a.out_cs = G.out_cs;
+  a.out_bs = G.out_bs;
   return a;
 }
 
@@ -721,8 +789,8 @@ inline float* fno_in(const FnoWs& w, int l) { return l == 0 ? w.v0 : (l % 2 ? w.
 inline float* fno_out(const FnoWs& w, int l) { return l % 2 ? w.vb : w.va; }
 
 template <int E>
-int fno_forward_e(ldsv_handle* h, const ldsv_fluxnet* net, const FnoShape& sh, const float* u,
-                  const float* v, float* fields, const FnoWs& w, hipStream_t st) {
+int fno_forward_e(ldsv_handle* h, const FnoGroup& G, const FnoShape& sh, const FnoWs& w,
+                  hipStream_t st) {
   c32* Y = w.Y;
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch, C = sh.C, M = sh.M;
   const size_t lds = ((size_t)nx * ny + nx + ny) * sizeof(Cx<float>);
@@ -734,18 +802,19 @@ int fno_forward_e(ldsv_handle* h, const ldsv_fluxnet* net, const FnoShape& sh, c
   const Cx<float>* twx = (const Cx<float>*)h->twx;
   const Cx<float>* twy = (const Cx<float>*)h->twy;
   for (int l = 0; l < sh.L; ++l) {
-    const FnoArgs a = make_args(net, sh, l);
+    const FnoArgs a = make_args(G, sh, l);
     const bool first = l == 0, last = l == sh.L - 1;
     float* zl = w.pre ? w.pre + (size_t)l * w.act : nullptr;
     c32* X = w.xs ? w.xs + (size_t)l * w.spec : w.X;
     float* cur = fno_in(w, l);
     float* nxt = fno_out(w, l);
     if (first) {
-      // v_0 = lift(u, v) is written to cur on the way
+      // v_0 = lift(inputs) is written to cur on the way
       auto k = k_fno_spec<E, true>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, u, v, a, cur, X, twx, twy, nx, ny,
-                   h->log2nx, h->log2ny, C, M, B);
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const float*)nullptr,
+                   (const float*)nullptr, a, cur, X, twx, twy, nx, ny, h->log2nx, h->log2ny, C, M,
+                   B);
     } else {
       auto k = k_fno_spec<E, false>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -768,10 +837,9 @@ int fno_forward_e(ldsv_handle* h, const ldsv_fluxnet* net, const FnoShape& sh, c
                    nxt, zl, (const float*)nullptr, twx, twy, nx, ny, h->log2nx, h->log2ny, M, B);
     }
   }
-  const FnoArgs a = make_args(net, sh, 0);
-  LDSV_TLAUNCH(h, 7, k_fno_proj, dim3((unsigned)((h->ncell + kBlock - 1) / kBlock), B, 2),
-               dim3(kBlock), 0, st, (const float*)fno_out(w, sh.L - 1), a, fields, (int)h->ncell,
-               C, B);
+  const FnoArgs a = make_args(G, sh, 0);
+  LDSV_TLAUNCH(h, 7, k_fno_proj, dim3((unsigned)((h->ncell + kBlock - 1) / kBlock), B, G.ngrid),
+               dim3(kBlock), 0, st, (const float*)fno_out(w, sh.L - 1), a, (int)h->ncell, C, B);
   LDSV_LAUNCHED();
   return LDSV_OK;
 }
@@ -787,9 +855,9 @@ int sum_partials(ldsv_handle* h, const FnoShape& sh, const FnoArgs& a, const flo
 }
 
 template <int E, int C>
-int fno_backward_e(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr,
-                   const FnoShape& sh, const float* u, const float* v, const float* gfields,
-                   float* gu, float* gv, int accumulate, const FnoWs& w, hipStream_t st) {
+int fno_backward_e(ldsv_handle* h, const FnoGroup& G, const ldsv_fno_grad* const gr[2],
+                   const FnoShape& sh, const float* gout, const GradIn& gi, int accumulate,
+                   const FnoWs& w, hipStream_t st) {
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch, M = sh.M;
   const int n = (int)h->ncell;
   const size_t lds = ((size_t)nx * ny + nx + ny) * sizeof(Cx<float>);
@@ -803,37 +871,42 @@ int fno_backward_e(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_g
   const Cx<float>* twx = (const Cx<float>*)h->twx;
   const Cx<float>* twy = (const Cx<float>*)h->twy;
   const int nblk = (n + kBlock - 1) / kBlock;
+  const int nin = G.nin, nout = G.nout;
   float* g_lift_w[2] = {nullptr, nullptr};
   float* g_lift_b[2] = {nullptr, nullptr};
   float* g_proj_w[2] = {nullptr, nullptr};
   float* g_proj_b[2] = {nullptr, nullptr};
-  for (int g = 0; g < 2; ++g) {
-    if (!net->fno[g]) continue;
-    const ldsv_fno_grad* q = gr->fno[g];
-    g_lift_w[g] = q->lift_w;
-    g_lift_b[g] = q->lift_b;
-    g_proj_w[g] = q->proj_w;
-    g_proj_b[g] = q->proj_b;
+  for (int g = 0; g < G.ngrid; ++g) {
+    if (!G.f[g]) continue;
+    g_lift_w[g] = gr[g]->lift_w;
+    g_lift_b[g] = gr[g]->lift_b;
+    g_proj_w[g] = gr[g]->proj_w;
+    g_proj_b[g] = gr[g]->proj_b;
   }
   // projection
-  const FnoArgs a0 = make_args(net, sh, 0);
+  const FnoArgs a0 = make_args(G, sh, 0);
   float* dcur = w.da;
   float* dnxt = w.db;
-  LDSV_TLAUNCH(h, 7, k_fno_proj_bwd<C>, dim3(nblk, B, sh.nnet), dim3(kBlock), 0, st, gfields,
-               (const float*)(w.pre + (size_t)(sh.L - 1) * w.act), a0, dcur, w.small, n, B);
-  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 4 * C + 4, 0, 4 * C, g_proj_w, st));
-  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 4 * C + 4, 4 * C, 4, g_proj_b, st));
+  const float* vL = w.pre + (size_t)(sh.L - 1) * w.act;
+  if (nout == 4)
+    LDSV_TLAUNCH(h, 7, (k_fno_proj_bwd<C, 4>), dim3(nblk, B, sh.nnet), dim3(kBlock), 0, st, gout,
+                 vL, a0, dcur, w.small, n, B);
+  else
+    LDSV_TLAUNCH(h, 7, (k_fno_proj_bwd<C, 2>), dim3(nblk, B, sh.nnet), dim3(kBlock), 0, st, gout,
+                 vL, a0, dcur, w.small, n, B);
+  const int pw_len = nout * C + nout;
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, pw_len, 0, nout * C, g_proj_w, st));
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, pw_len, nout * C, nout, g_proj_b, st));
   for (int l = sh.L - 1; l >= 0; --l) {
-    const FnoArgs a = make_args(net, sh, l);
+    const FnoArgs a = make_args(G, sh, l);
     float* g_pw[2] = {nullptr, nullptr};
     float* g_pb[2] = {nullptr, nullptr};
     float* g_sw[2] = {nullptr, nullptr};
-    for (int g = 0; g < 2; ++g) {
-      if (!net->fno[g]) continue;
-      const ldsv_fno_grad* q = gr->fno[g];
-      g_pw[g] = q->point_w + (size_t)l * C * C;
-      g_pb[g] = q->point_b + (size_t)l * C;
-      g_sw[g] = q->spec_w + (size_t)l * C * C * nm * 2;
+    for (int g = 0; g < G.ngrid; ++g) {
+      if (!G.f[g]) continue;
+      g_pw[g] = gr[g]->point_w + (size_t)l * C * C;
+      g_pb[g] = gr[g]->point_b + (size_t)l * C;
+      g_sw[g] = gr[g]->spec_w + (size_t)l * C * C * nm * 2;
     }
     // pointwise weight and bias gradients (v_l from v_0 or GELU(z_{l-1}))
     const int nch = (n + kWChunk - 1) / kWChunk;
@@ -876,24 +949,114 @@ int fno_backward_e(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_g
     std::swap(dcur, dnxt);
   }
   // lift: dcur holds dv_0
-  LDSV_TLAUNCH(h, 7, k_fno_lift_bwd<C>, dim3(nblk, B), dim3(kBlock), 0, st, (const float*)dcur, u,
-               v, a0, sh.nnet, gu, gv, accumulate, w.small, n, B);
-  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 3 * C, 0, 2 * C, g_lift_w, st));
-  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, 3 * C, 2 * C, C, g_lift_b, st));
+  LDSV_TLAUNCH(h, 7, k_fno_lift_bwd<C>, dim3(nblk, B), dim3(kBlock), 0, st, (const float*)dcur,
+               a0, sh.nnet, gi, accumulate, w.small, n, B);
+  const int lw_len = (nin + 1) * C;
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, lw_len, 0, nin * C, g_lift_w, st));
+  LDSV_TRY(sum_partials(h, sh, a0, w.small, B * nblk, lw_len, nin * C, C, g_lift_b, st));
   LDSV_LAUNCHED();
   return LDSV_OK;
 }
 
-int check_fluxnet_grad(const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr) {
-  LDSV_REQUIRE(gr, LDSV_EINVAL, "flux block: null gradient");
-  for (int g = 0; g < 2; ++g) {
-    if (!net->fno[g]) continue;
-    const ldsv_fno_grad* q = gr->fno[g];
+int check_grads(const FnoGroup& G, const ldsv_fno_grad* const gr[2]) {
+  for (int g = 0; g < G.ngrid; ++g) {
+    if (!G.f[g]) continue;
+    const ldsv_fno_grad* q = gr[g];
     LDSV_REQUIRE(q && q->lift_w && q->lift_b && q->spec_w && q->point_w && q->point_b &&
                      q->proj_w && q->proj_b,
-                 LDSV_EINVAL, "flux block: null gradient buffer of fno[%d]", g);
+                 LDSV_EINVAL, "fno[%d]: null gradient buffer", g);
   }
   return LDSV_OK;
+}
+
+// the flux block's pair: inputs (u, v), fields [B][8][Ny][Nx]
+FnoGroup flux_group(const ldsv_handle* h, const ldsv_fluxnet* net, const float* u, const float* v,
+                    float* fields) {
+  FnoGroup G{};
+  G.f[0] = net->fno[0];
+  G.f[1] = net->fno[1];
+  G.ngrid = 2;
+  G.nin = 2;
+  G.nout = 4;
+  G.xin[0] = u;
+  G.xin[1] = v;
+  G.out = fields;
+  G.out_cs = h->ncell;
+  G.out_bs = 8 * h->ncell;
+  G.out_ch[0] = 0;
+  G.out_ch[1] = 4;
+  return G;
+}
+
+// the temporal correction: inputs the k_c states (u, v) oldest first,
+// output (du, dv) as two [B][Ny][Nx] planes at out and out + B Ny Nx
+FnoGroup tc_group(const ldsv_handle* h, const ldsv_fno* tc, const float* const* hu,
+                  const float* const* hv, int kc, float* out) {
+  FnoGroup G{};
+  G.f[0] = tc;
+  G.f[1] = nullptr;
+  G.ngrid = 1;
+  G.nin = 2 * kc;
+  G.nout = 2;
+  for (int j = 0; j < kc && 2 * j + 1 < kMaxIn; ++j) {
+    G.xin[2 * j] = hu[j];
+    G.xin[2 * j + 1] = hv[j];
+  }
+  G.out = out;
+  G.out_cs = h->nstate;
+  G.out_bs = h->ncell;
+  return G;
+}
+
+int group_forward(ldsv_handle* h, const FnoGroup& G, bool keep_pre, hipStream_t st) {
+  FnoShape sh;
+  LDSV_TRY(check_group(h, G, &sh));
+  if (sh.nnet == 0) {
+    // no operator: zero outputs (a kernel, not a memset, so that the call
+    // can sit in a captured graph)
+    const FnoArgs a = make_args(G, sh, 0);
+    LDSV_TLAUNCH(h, 7, k_fno_proj, dim3((unsigned)((h->ncell + kBlock - 1) / kBlock), h->g.batch,
+                                        G.ngrid),
+                 dim3(kBlock), 0, st, (const float*)nullptr, a, (int)h->ncell, 0, h->g.batch);
+    LDSV_LAUNCHED();
+    return LDSV_OK;
+  }
+  FnoWs w;
+  // a forward that keeps its activations sizes the workspace for the
+  // backward as well, so the backward that follows does not move them
+  LDSV_TRY(ensure_fno(h, sh, keep_pre ? 2 : 0, &w));
+  if (h->ncell <= (size_t)4 * kFnoBlock) return fno_forward_e<4>(h, G, sh, w, st);
+  return fno_forward_e<16>(h, G, sh, w, st);
+}
+
+// backward of the group from gout (addressed like its output); when
+// forward_kept is false the forward is run first (its output goes to G.out)
+int group_backward(ldsv_handle* h, const FnoGroup& G, const ldsv_fno_grad* const gr[2],
+                   const float* gout, const GradIn& gi, int accumulate, bool forward_kept,
+                   hipStream_t st) {
+  FnoShape sh;
+  LDSV_TRY(check_group(h, G, &sh));
+  if (sh.nnet == 0) {
+    if (gi.gx[0] && !accumulate) {
+      for (int j = 0; j < G.nin; ++j)
+        LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(h->nstate), dim3(kBlock), 0, st, gi.gx[j],
+                     h->nstate);
+      LDSV_LAUNCHED();
+    }
+    return LDSV_OK;
+  }
+  LDSV_TRY(check_grads(G, gr));
+  FnoWs w;
+  LDSV_TRY(ensure_fno(h, sh, 2, &w));
+  const bool small = h->ncell <= (size_t)4 * kFnoBlock;
+  if (!forward_kept) {
+    if (small) LDSV_TRY(fno_forward_e<4>(h, G, sh, w, st));
+    else LDSV_TRY(fno_forward_e<16>(h, G, sh, w, st));
+  }
+  if (small && sh.C == 16) return fno_backward_e<4, 16>(h, G, gr, sh, gout, gi, accumulate, w, st);
+  if (small) return fno_backward_e<4, 8>(h, G, gr, sh, gout, gi, accumulate, w, st);
+  if (sh.C == 16) return fno_backward_e<16, 16>(h, G, gr, sh, gout, gi, accumulate, w, st);
+  return fno_backward_e<16, 8>(h, G, gr, sh, gout, gi, accumulate, w, st);
 }
 
 }  // namespace
@@ -904,67 +1067,67 @@ int check_fluxnet_grad(const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr) {
 int ldsv_launch_fno_backward(ldsv_handle* h, const ldsv_fluxnet* net, const ldsv_fluxnet_grad* gr,
                              const float* u, const float* v, const float* gfields, float* gu,
                              float* gv, int accumulate, hipStream_t st, bool forward_kept) {
-  FnoShape sh;
-  LDSV_TRY(check_fluxnet(h, net, &sh));
-  if (sh.nnet == 0) {
-    if (gu && !accumulate) {
-      LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(h->nstate), dim3(kBlock), 0, st, gu, h->nstate);
-      LDSV_TLAUNCH(h, 7, k_fill_zero, grid1d(h->nstate), dim3(kBlock), 0, st, gv, h->nstate);
-      LDSV_LAUNCHED();
-    }
-    return LDSV_OK;
-  }
-  LDSV_TRY(check_fluxnet_grad(net, gr));
-  FnoWs w;
-  LDSV_TRY(ensure_fno(h, sh, 2, &w));
-  const bool small = h->ncell <= (size_t)4 * kFnoBlock;
-  if (!forward_kept) {
-    LDSV_TRY(ldsv_ensure_fluxblock(h));
-    if (small) LDSV_TRY(fno_forward_e<4>(h, net, sh, u, v, h->fb_fields, w, st));
-    else LDSV_TRY(fno_forward_e<16>(h, net, sh, u, v, h->fb_fields, w, st));
-  }
-  if (small && sh.C == 16)
-    return fno_backward_e<4, 16>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
-  if (small)
-    return fno_backward_e<4, 8>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
-  if (sh.C == 16)
-    return fno_backward_e<16, 16>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
-  return fno_backward_e<16, 8>(h, net, gr, sh, u, v, gfields, gu, gv, accumulate, w, st);
+  LDSV_REQUIRE(net && gr, LDSV_EINVAL, "fno backward: null network or gradient");
+  LDSV_TRY(ldsv_ensure_fluxblock(h));
+  // a forward run here writes its fields into the handle's scratch field buffer
+  const FnoGroup G = flux_group(h, net, u, v, h->fb_fields);
+  const ldsv_fno_grad* grs[2] = {gr->fno[0], gr->fno[1]};
+  GradIn gi{};
+  gi.gx[0] = gu;
+  gi.gx[1] = gv;
+  return group_backward(h, G, grs, gfields, gi, accumulate, forward_kept, st);
 }
 
 int ldsv_launch_fno_forward(ldsv_handle* h, const ldsv_fluxnet* net, const float* u,
                             const float* v, float* fields, bool keep_pre, hipStream_t st) {
-  FnoShape sh;
-  LDSV_TRY(check_fluxnet(h, net, &sh));
-  if (sh.nnet == 0) {
-    // no frequency operator: zero fields (a kernel, not a memset, so that
-    // the call can sit in a captured graph)
-    const FnoArgs a = make_args(net, sh, 0);
-    LDSV_TLAUNCH(h, 7, k_fno_proj, dim3((unsigned)((h->ncell + kBlock - 1) / kBlock), h->g.batch, 2),
-                 dim3(kBlock), 0, st, (const float*)nullptr, a, fields, (int)h->ncell, 0,
-                 h->g.batch);
-    LDSV_LAUNCHED();
-    return LDSV_OK;
+  LDSV_REQUIRE(net, LDSV_EINVAL, "flux block: null network");
+  return group_forward(h, flux_group(h, net, u, v, fields), keep_pre, st);
+}
+
+int ldsv_launch_tc_forward(ldsv_handle* h, const ldsv_fno* tc, const float* const* hu,
+                           const float* const* hv, int kc, float* out, bool keep_pre,
+                           hipStream_t st) {
+  LDSV_REQUIRE(tc && hu && hv && kc >= 1 && 2 * kc <= kMaxIn, LDSV_EINVAL,
+               "temporal correction: null operator or history, or k_c = %d outside 1..%d", kc,
+               kMaxIn / 2);
+  return group_forward(h, tc_group(h, tc, hu, hv, kc, out), keep_pre, st);
+}
+
+int ldsv_launch_tc_backward(ldsv_handle* h, const ldsv_fno* tc, const ldsv_fno_grad* gtc,
+                            const float* const* hu, const float* const* hv, int kc,
+                            const float* gout, float* const* ghu, float* const* ghv,
+                            bool forward_kept, float* scratch_out, hipStream_t st) {
+  LDSV_REQUIRE(tc && gtc && hu && hv && ghu && ghv && kc >= 1 && 2 * kc <= kMaxIn, LDSV_EINVAL,
+               "temporal correction backward: null argument or k_c = %d outside 1..%d", kc,
+               kMaxIn / 2);
+  const FnoGroup G = tc_group(h, tc, hu, hv, kc, scratch_out);
+  const ldsv_fno_grad* grs[2] = {gtc, nullptr};
+  GradIn gi{};
+  for (int j = 0; j < kc; ++j) {
+    gi.gx[2 * j] = ghu[j];
+    gi.gx[2 * j + 1] = ghv[j];
   }
-  FnoWs w;
-  // a forward that keeps its activations sizes the workspace for the
-  // backward as well, so the backward that follows does not move them
-  LDSV_TRY(ensure_fno(h, sh, keep_pre ? 2 : 0, &w));
-  if (h->ncell <= (size_t)4 * kFnoBlock) return fno_forward_e<4>(h, net, sh, u, v, fields, w, st);
-  return fno_forward_e<16>(h, net, sh, u, v, fields, w, st);
+  return group_backward(h, G, grs, gout, gi, 1, forward_kept, st);
 }
 
 int ldsv_ensure_fluxblock(ldsv_handle* h) {
   if (h->fb_fields) return LDSV_OK;
   void* p = nullptr;
-  LDSV_TRY(ldsv_alloc(h, &p, (size_t)16 * h->nstate * sizeof(float), "flux-block fields"));
+  // fields and their gradient (8 planes each), the temporal correction and
+  // its gradient (2 each), a state-sized scratch pair (2)
+  LDSV_TRY(ldsv_alloc(h, &p, (size_t)22 * h->nstate * sizeof(float), "flux-block fields"));
   h->fb_fields = (float*)p;
   h->fb_gfields = h->fb_fields + 8 * h->nstate;
+  h->fb_tc = h->fb_gfields + 8 * h->nstate;
+  h->fb_gtc = h->fb_tc + 2 * h->nstate;
+  h->fb_tmp = h->fb_gtc + 2 * h->nstate;
   return LDSV_OK;
 }
 
 int ldsv_internal_step_fb(ldsv_handle* h, const ldsv_params* p, const FluxBlockArgs* fb,
-                          const void* su, const void* sv, void* du, void* dv, hipStream_t st);
+                          const void* su, const void* sv, void* du, void* dv, hipStream_t st,
+                          const float* tcu = nullptr, const float* tcv = nullptr,
+                          size_t tcbs = 0);
 
 extern "C" {
 
@@ -1032,11 +1195,15 @@ int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_f
                    grad,
                LDSV_EINVAL, "fluxblock_step_bwd: null argument");
   LDSV_REQUIRE(prm->rk == LDSV_RK4, LDSV_EDTYPE, "fluxblock_step_bwd: RK4");
-  FnoShape sh;
-  LDSV_TRY(check_fluxnet(h, net, &sh));
-  LDSV_TRY(check_fluxnet_grad(net, grad));
   const hipStream_t st = (hipStream_t)stream;
   LDSV_TRY(ldsv_ensure_fluxblock(h));
+  FnoShape sh;
+  {
+    const FnoGroup G = flux_group(h, net, u_in, v_in, h->fb_fields);
+    LDSV_TRY(check_group(h, G, &sh));
+    const ldsv_fno_grad* grs[2] = {grad->fno[0], grad->fno[1]};
+    LDSV_TRY(check_grads(G, grs));
+  }
   // the fields of the forward step (activations kept for the FNO backward),
   // then the FV adjoint with their gradient
   LDSV_TRY(ldsv_launch_fno_forward(h, net, u_in, v_in, h->fb_fields, true, st));
@@ -1056,6 +1223,68 @@ int ldsv_fluxblock_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_f
   // the operators' gradients, their input gradient added to the state's
   return ldsv_launch_fno_backward(h, net, grad, u_in, v_in, h->fb_gfields, gu_in, gv_in, 1, st,
                                   true);
+}
+
+int ldsv_fluxblock_tc_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,
+                           const ldsv_fno* tc, const float* const* hist_u,
+                           const float* const* hist_v, int step_index, float* u_out, float* v_out,
+                           void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(prm && net && net->stencil_w && hist_u && hist_v && u_out && v_out, LDSV_EINVAL,
+               "fluxblock_tc_step: null argument");
+  LDSV_REQUIRE(prm->rk == LDSV_RK4, LDSV_EDTYPE, "fluxblock_tc_step: RK4");
+  const int kc = prm->k_c;
+  LDSV_REQUIRE(kc >= 1 && 2 * kc <= kMaxIn, LDSV_EINVAL,
+               "fluxblock_tc_step: k_c = %d outside 1..%d", kc, kMaxIn / 2);
+  const float* u_in = hist_u[kc - 1];
+  const float* v_in = hist_v[kc - 1];
+  LDSV_REQUIRE(u_in && v_in, LDSV_EINVAL, "fluxblock_tc_step: null input state");
+  const hipStream_t st = (hipStream_t)stream;
+  LDSV_TRY(ldsv_ensure_fluxblock(h));
+  LDSV_TRY(ldsv_launch_fno_forward(h, net, u_in, v_in, h->fb_fields, false, st));
+  const bool apply = tc && step_index % kc == 0;
+  if (apply)
+    LDSV_TRY(ldsv_launch_tc_forward(h, tc, hist_u, hist_v, kc, h->fb_tc, false, st));
+  FluxBlockArgs fb;
+  fb.w = net->stencil_w;
+  fb.f = h->fb_fields;
+  fb.fbs = (size_t)8 * h->ncell;
+  return ldsv_internal_step_fb(h, prm, &fb, u_in, v_in, u_out, v_out, st,
+                               apply ? h->fb_tc : nullptr, apply ? h->fb_tc + h->nstate : nullptr,
+                               h->ncell);
+}
+
+int ldsv_fluxblock_tc_step_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,
+                               const ldsv_fno* tc, const float* const* hist_u,
+                               const float* const* hist_v, int step_index, const float* gu_out,
+                               const float* gv_out, float* const* ghist_u, float* const* ghist_v,
+                               const ldsv_fluxnet_grad* grad, const ldsv_fno_grad* gtc,
+                               void* stream) {
+  LDSV_TRY(ldsv_check_handle(h));
+  LDSV_REQUIRE(prm && net && hist_u && hist_v && gu_out && gv_out && ghist_u && ghist_v && grad,
+               LDSV_EINVAL, "fluxblock_tc_step_bwd: null argument");
+  const int kc = prm->k_c;
+  LDSV_REQUIRE(kc >= 1 && 2 * kc <= kMaxIn, LDSV_EINVAL,
+               "fluxblock_tc_step_bwd: k_c = %d outside 1..%d", kc, kMaxIn / 2);
+  const bool apply = tc && step_index % kc == 0;
+  LDSV_REQUIRE(!apply || gtc, LDSV_EINVAL, "fluxblock_tc_step_bwd: null correction gradient");
+  const hipStream_t st = (hipStream_t)stream;
+  LDSV_TRY(ldsv_ensure_fluxblock(h));
+  float* tu = h->fb_tmp;
+  float* tv = h->fb_tmp + h->nstate;
+  // through the FV step and the flux block into the last state (the
+  // correction does not change the step's Jacobian: it is added)
+  LDSV_TRY(ldsv_fluxblock_step_bwd(h, prm, net, hist_u[kc - 1], hist_v[kc - 1], gu_out, gv_out, tu,
+                                   tv, grad, stream));
+  LDSV_TRY(ldsv_launch_axpy2(h, ghist_u[kc - 1], ghist_v[kc - 1], tu, tv, 1.0, st));
+  if (!apply) return LDSV_OK;
+  // dL/dTC = P^T g = P g (the correction enters before the last projection)
+  float* gcu = h->fb_gtc;
+  float* gcv = h->fb_gtc + h->nstate;
+  LDSV_TRY(ldsv_launch_project(h, gu_out, gv_out, gcu, gcv, nullptr, st));
+  LDSV_TRY(ldsv_launch_tc_forward(h, tc, hist_u, hist_v, kc, h->fb_tc, true, st));
+  return ldsv_launch_tc_backward(h, tc, gtc, hist_u, hist_v, kc, gcu, ghist_u, ghist_v, true,
+                                 h->fb_tc, st);
 }
 
 int ldsv_fluxblock_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_fluxnet* net,

@@ -123,6 +123,9 @@ struct ldsv_handle {
   void* fb_part = nullptr;       // [B x tiles][160] of the grid dtype
   float* fb_fields = nullptr;    // [B][8][Ny][Nx]
   float* fb_gfields = nullptr;   // [B][8][Ny][Nx] gradient of the fields
+  float* fb_tc = nullptr;        // temporal correction: 2 planes [B][Ny][Nx]
+  float* fb_gtc = nullptr;       // its gradient
+  float* fb_tmp = nullptr;       // 2 state-sized scratch planes
   void* fno_blk = nullptr;       // FNO buffers (fno.hip), fno_bytes long
   size_t fno_bytes = 0;
   size_t bytes = 0;

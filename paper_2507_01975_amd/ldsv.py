@@ -69,7 +69,7 @@ class NetGrad(ctypes.Structure):
 
 class Fno(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int), ("layers", ctypes.c_int), ("modes", ctypes.c_int),
-                ("lift_w", ctypes.c_void_p), ("lift_b", ctypes.c_void_p),
+                ("n_in", ctypes.c_int), ("n_out", ctypes.c_int), ("lift_w", ctypes.c_void_p), ("lift_b", ctypes.c_void_p),
                 ("spec_w", ctypes.c_void_p), ("point_w", ctypes.c_void_p),
                 ("point_b", ctypes.c_void_p), ("proj_w", ctypes.c_void_p),
                 ("proj_b", ctypes.c_void_p)]
@@ -139,6 +139,14 @@ _SIGS = {
                            ctypes.POINTER(FluxNetGrad), _vp], _i),
     "ldsv_fluxblock_step_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(FluxNet), _vp, _vp,
                                  _vp, _vp, _vp, _vp, ctypes.POINTER(FluxNetGrad), _vp], _i),
+    "ldsv_fluxblock_tc_step": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(FluxNet),
+                                ctypes.POINTER(Fno), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i,
+                                _vp, _vp, _vp], _i),
+    "ldsv_fluxblock_tc_step_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(FluxNet),
+                                    ctypes.POINTER(Fno), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    _i, _vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(FluxNetGrad), ctypes.POINTER(FnoGrad), _vp],
+                                   _i),
     "ldsv_timer_enable": ([_vp, _i], _i),
     "ldsv_timer_read": ([_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i)], _i),
 }
@@ -441,6 +449,36 @@ class Solver:
                                             ctypes.byref(grad.c), _stream()))
         return gu, gv
 
+    def _hist(self, states, name):
+        for t in states:
+            self._state(t, name)
+        return (_vp * len(states))(*[t.data_ptr() for t in states])
+
+    def fluxblock_tc_step(self, prm, net, tc, hist_u, hist_v, step_index, out=None):
+        """One step of the complete model; hist_u/hist_v: the k_c = prm.k_c
+        states u_{k-k_c} .. u_{k-1} (oldest first)."""
+        if len(hist_u) != prm.k_c or len(hist_v) != prm.k_c:
+            raise ValueError("the history must hold k_c = %d states" % prm.k_c)
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        _check(_lib.ldsv_fluxblock_tc_step(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                           ctypes.byref(tc.c) if tc is not None else None,
+                                           self._hist(hist_u, "hist_u"),
+                                           self._hist(hist_v, "hist_v"), step_index,
+                                           self._state(uo), self._state(vo), _stream()))
+        return uo, vo
+
+    def fluxblock_tc_step_bwd(self, prm, net, tc, hist_u, hist_v, step_index, gu_out, gv_out,
+                              ghist_u, ghist_v, grad, gtc=None):
+        """Accumulates into ghist_u/ghist_v (lists like hist_u), grad and gtc."""
+        if not (len(hist_u) == len(hist_v) == len(ghist_u) == len(ghist_v) == prm.k_c):
+            raise ValueError("the history and its gradients must hold k_c = %d states" % prm.k_c)
+        _check(_lib.ldsv_fluxblock_tc_step_bwd(
+            self._h, ctypes.byref(prm), ctypes.byref(net.c),
+            ctypes.byref(tc.c) if tc is not None else None, self._hist(hist_u, "hist_u"),
+            self._hist(hist_v, "hist_v"), step_index, self._state(gu_out), self._state(gv_out),
+            self._hist(ghist_u, "ghist_u"), self._hist(ghist_v, "ghist_v"), ctypes.byref(grad.c),
+            ctypes.byref(gtc.c) if gtc is not None else None, _stream()))
+
     def timer_enable(self, on=True):
         _check(_lib.ldsv_timer_enable(self._h, 1 if on else 0))
 
@@ -515,9 +553,11 @@ def adam_step(w, g, m, v, t, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
 
 
 class FnoParams:
-    """Device copy of one FNO of the flux block (float32): lift_w [C, 2],
-    lift_b [C], spec_w [L, C_in, C_out, 2M, M, 2] (complex as re, im),
-    point_w [L, C_out, C_in], point_b [L, C], proj_w [4, C], proj_b [4]."""
+    """Device copy of one FNO (float32): lift_w [C, n_in], lift_b [C],
+    spec_w [L, C_in, C_out, 2M, M, 2] (complex as re, im), point_w
+    [L, C_out, C_in], point_b [L, C], proj_w [n_out, C], proj_b [n_out].
+    The flux block's operators take n_in = 2 (u, v) and n_out = 4; the
+    temporal correction n_in = 2 k_c and n_out = 2."""
 
     def __init__(self, lift_w, lift_b, spec, point_w, point_b, proj_w, proj_b):
         """spec: list over layers of complex [2M, M, C_in, C_out] tensors (the
@@ -537,7 +577,8 @@ class FnoParams:
         self.point_w, self.point_b = f32(point_w), f32(point_b)
         self.proj_w, self.proj_b = f32(proj_w), f32(proj_b)
         L, C, _, two_m, M, _ = self.spec_w.shape
-        self.c = Fno(C, L, M, self.lift_w.data_ptr(), self.lift_b.data_ptr(),
+        self.n_in, self.n_out = self.lift_w.shape[1], self.proj_w.shape[0]
+        self.c = Fno(C, L, M, self.n_in, self.n_out, self.lift_w.data_ptr(), self.lift_b.data_ptr(),
                      self.spec_w.data_ptr(), self.point_w.data_ptr(), self.point_b.data_ptr(),
                      self.proj_w.data_ptr(), self.proj_b.data_ptr())
 

@@ -147,20 +147,36 @@ def fluxblock_grad_tensors(grads):
     return out
 
 
+def _history(states, k, kc):
+    """The k_c states u_{k-k_c} .. u_{k-1} (padded with u_0 before the first
+    correction, where only the last one is read)."""
+    idx = [max(0, k - kc + j) for j in range(kc)]
+    return [states[i][0] for i in idx], [states[i][1] for i in idx]
+
+
 def train_fluxblock(solver, net, labels, prm, iters, unroll=8, lr=1e-4, seed=0, progress=None,
-                    log_every=10):
+                    log_every=10, tc=None):
     """Adam on the unrolled rollout MSE of the flux-block model (the paper's
-    own learnable flux block, Sec. 3.4, trained on the Eq. 13 loss).
+    own learnable flux block, Sec. 3.4, trained on the Eq. 13 loss), with the
+    temporal correction block when tc (an FnoParams with 2 prm.k_c inputs and
+    2 outputs) is given: Eq. 2 with the window start as time 0.
     labels: (lu, lv) [T+1, B, n, n].  Each iteration unrolls `unroll` steps
     from a random labels[t0], keeping the states, then runs the step adjoint
-    (ldsv_fluxblock_step_bwd) backwards through them with the loss gradient
-    of every state added on the way.  Returns the loss history."""
+    backwards through them with the loss gradient of every state added on
+    the way (a corrected step also sends gradient to the earlier states of
+    its history).  Returns the loss history."""
     lu, lv = labels
     T = lu.shape[0] - 1
+    kc = prm.k_c
     g = torch.Generator().manual_seed(seed)
     params = fluxblock_param_tensors(net)
     grads = ldsv.FluxNetGradBuffers(net)
     gts = fluxblock_grad_tensors(grads)
+    gtc = None
+    if tc is not None:
+        gtc = ldsv.FnoGradBuffers(tc)
+        params += [tc.lift_w, tc.lift_b, tc.spec_w, tc.point_w, tc.point_b, tc.proj_w, tc.proj_b]
+        gts += gtc.tensors()
     m = [torch.zeros_like(p) for p in params]
     v2 = [torch.zeros_like(p) for p in params]
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -169,19 +185,43 @@ def train_fluxblock(solver, net, labels, prm, iters, unroll=8, lr=1e-4, seed=0, 
     for it in range(iters):
         t0 = int(torch.randint(0, T - unroll + 1, (1,), generator=g))
         states = [(lu[t0].contiguous(), lv[t0].contiguous())]
-        for k in range(unroll):
-            states.append(solver.fluxblock_step(prm, net, *states[-1]))
+        for k in range(1, unroll + 1):
+            if tc is None:
+                states.append(solver.fluxblock_step(prm, net, *states[-1]))
+            else:
+                states.append(solver.fluxblock_tc_step(prm, net, tc, *_history(states, k, kc), k))
         grads.zero_()
+        if gtc is not None:
+            for t in gtc.tensors():
+                t.zero_()
         loss.zero_()
-        gu = gv = None
+        # cotangents of every state; complete for state k once steps > k are done
+        gs = [(torch.zeros_like(states[0][0]), torch.zeros_like(states[0][1]))
+              for _ in range(unroll + 1)]
         for k in range(unroll, 0, -1):
             mu, mv = solver.mse_grad(states[k][0], states[k][1], lu[t0 + k], lv[t0 + k],
                                      scale=1.0 / unroll, loss=loss)
-            if gu is not None:
-                mu += gu
-                mv += gv
-            gu, gv = solver.fluxblock_step_bwd(prm, net, states[k - 1][0], states[k - 1][1],
-                                               mu, mv, grads)
+            mu += gs[k][0]
+            mv += gs[k][1]
+            if tc is None:
+                gu, gv = solver.fluxblock_step_bwd(prm, net, states[k - 1][0], states[k - 1][1],
+                                                   mu, mv, grads)
+                gs[k - 1][0].add_(gu)
+                gs[k - 1][1].add_(gv)
+            else:
+                idx = [max(0, k - kc + j) for j in range(kc)]
+                hu, hv = _history(states, k, kc)
+                ghu, ghv = [], []
+                for j, i in enumerate(idx):
+                    # padded entries (before the first correction) are not read
+                    if j < kc - 1 and k % kc != 0:
+                        ghu.append(torch.zeros_like(mu))
+                        ghv.append(torch.zeros_like(mv))
+                    else:
+                        ghu.append(gs[i][0])
+                        ghv.append(gs[i][1])
+                solver.fluxblock_tc_step_bwd(prm, net, tc, hu, hv, k, mu, mv, ghu, ghv, grads,
+                                             gtc)
         for p, gp, mm, vv in zip(params, gts, m, v2):
             ldsv.adam_step(p, gp, mm, vv, it + 1, lr)
         if (it + 1) % log_every == 0 or it == 0:

@@ -330,3 +330,115 @@ def test_train_fluxblock_reduces_the_loss():
     labels = (torch.stack(lu), torch.stack(lv))
     hist = T.train_fluxblock(s, student, labels, prm, iters=12, unroll=4, lr=3e-3, log_every=1)
     assert hist[-1][1] < 0.5 * hist[0][1], hist
+
+
+def _tc_arrays(seed, kc, out_scale=0.1):
+    # the paper's temporal-correction FNO: 4 layers, 32 modes, width 8
+    return si.fno_weights(seed, 8, 4, 32, n_in=2 * kc, n_out=2, out_scale=out_scale)
+
+
+def test_complete_model_rollout_matches_oracle():
+    """Flux block + temporal correction every k_c = 2 steps (Eq. 2), forced
+    configuration at 64^2: every state of a 4-step rollout."""
+    L_ = need_gpu()
+    announce("complete model rollout")
+    n, b, kc, T = 64, 2, 2, 4
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(91, "forced")
+    w = _stencils(93)
+    a_tc = _tc_arrays(95, kc)
+    net = L_.FluxNetParams(w, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    tc = L_.FnoParams.from_arrays(a_tc)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=97)
+    prm = L_.params(k_c=kc, **KW)
+    hu, hv = [dev(u0, torch.float32)], [dev(v0, torch.float32)]
+    for k in range(1, T + 1):
+        pu = hu[-kc:] if len(hu) >= kc else [hu[0]] * (kc - len(hu)) + hu
+        pv = hv[-kc:] if len(hv) >= kc else [hv[0]] * (kc - len(hv)) + hv
+        u, v = s.fluxblock_tc_step(prm, net, tc, pu, pv, k)
+        hu.append(u)
+        hv.append(v)
+    params = {"wi": w[0].double(), "wd": w[1].double(), "fno_i": fno.from_arrays(a_i),
+              "fno_d": fno.from_arrays(a_d), "tc": fno.from_arrays(a_tc)}
+    ru, rv = fluxblock.model_rollout(cpu64(hu[0]), cpu64(hv[0]), oracle_prm(n, n, k_c=kc, **KW),
+                                     params, T)
+    for k in range(T):
+        assert rel_l2(hu[k + 1], ru[k]) < 1e-5 and rel_l2(hv[k + 1], rv[k]) < 1e-5, k
+
+
+def test_complete_model_step_bwd_matches_oracle_autograd():
+    """The adjoint of a corrected step (k = k_c = 2): gradients of both
+    history states, the flux block and the correction's FNO."""
+    L_ = need_gpu()
+    announce("complete model step bwd")
+    n, b, kc = 64, 2, 2
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(101, "decaying", out_scale=0.2)
+    w = _stencils(103)
+    a_tc = _tc_arrays(105, kc, out_scale=0.5)
+    net = L_.FluxNetParams(w, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    tc = L_.FnoParams.from_arrays(a_tc)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=107)
+    prm = L_.params(k_c=kc, **KW)
+    hu = [dev(u0, torch.float32)]
+    hv = [dev(v0, torch.float32)]
+    u1, v1 = s.fluxblock_step(prm, net, hu[0], hv[0])
+    hu.append(u1)
+    hv.append(v1)
+    g = torch.Generator().manual_seed(109)
+    gu_out = torch.randn(b, n, n, generator=g, dtype=torch.float64)
+    gv_out = torch.randn(b, n, n, generator=g, dtype=torch.float64)
+    gb = L_.FluxNetGradBuffers(net)
+    gtc = L_.FnoGradBuffers(tc)
+    ghu = [torch.zeros_like(x) for x in hu]
+    ghv = [torch.zeros_like(x) for x in hv]
+    s.fluxblock_tc_step_bwd(prm, net, tc, hu, hv, kc, dev(gu_out, torch.float32),
+                            dev(gv_out, torch.float32), ghu, ghv, gb, gtc)
+    p_i, p_d, p_tc = fno.from_arrays(a_i), fno.from_arrays(a_d), fno.from_arrays(a_tc)
+    leaves = []
+    for p in (p_i, p_d, p_tc):
+        leaves += [p["P_w"], p["P_b"], p["Q_w"], p["Q_b"]]
+        for lay in p["layers"]:
+            leaves += [lay["R"], lay["W"], lay["b"]]
+    for t in leaves:
+        t.requires_grad_(True)
+    wr = w.double().requires_grad_(True)
+    xs = [cpu64(t).requires_grad_(True) for t in hu + hv]
+    params = {"wi": wr[0], "wd": wr[1], "fno_i": p_i, "fno_d": p_d, "tc": p_tc}
+    x, y = fluxblock.model_step(xs[:2], xs[2:], oracle_prm(n, n, k_c=kc, **KW), params, kc)
+    ((gu_out * x).sum() + (gv_out * y).sum()).backward()
+    for j in range(2):
+        assert rel_l2(ghu[j], xs[j].grad) < 1e-4, j
+        assert rel_l2(ghv[j], xs[2 + j].grad) < 1e-4, j
+    assert rel_l2(gb.stencil_w, wr.grad) < 1e-4
+    _check_fno_grads(gb.fno[0], p_i, 1e-4)
+    _check_fno_grads(gb.fno[1], p_d, 1e-4)
+    _check_fno_grads(gtc, p_tc, 1e-4)
+
+
+def test_train_complete_model_reduces_the_loss():
+    """Teacher-student with the temporal correction: the student's
+    correction starts at zero output and learns the teacher's."""
+    L_ = need_gpu()
+    from paper_2507_01975_amd import train as T
+    announce("complete model training")
+    n, b, kc, steps = 64, 4, 2, 10
+    s = L_.Solver(n, n, b)
+    a_i, a_d = _fno_pair(111, "decaying", out_scale=0.1)
+    w = _stencils(113, scale=0.01)
+    net = L_.FluxNetParams(w, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    teacher_tc = L_.FnoParams.from_arrays(_tc_arrays(115, kc, out_scale=0.3))
+    student_tc = L_.FnoParams.from_arrays(_tc_arrays(115, kc, out_scale=0.0))
+    prm = L_.params(nu=1e-3, dt=0.02, k_c=kc)
+    u, v = s.init_state(L_.IC_GRF_PEAK, seed=117)
+    lu, lv = [u], [v]
+    for k in range(1, steps + 1):
+        hu = [lu[max(0, k - kc + j)] for j in range(kc)]
+        hv = [lv[max(0, k - kc + j)] for j in range(kc)]
+        u, v = s.fluxblock_tc_step(prm, net, teacher_tc, hu, hv, k)
+        lu.append(u)
+        lv.append(v)
+    labels = (torch.stack(lu), torch.stack(lv))
+    hist = T.train_fluxblock(s, net, labels, prm, iters=12, unroll=4, lr=3e-3, log_every=1,
+                             tc=student_tc)
+    assert hist[-1][1] < 0.5 * hist[0][1], hist

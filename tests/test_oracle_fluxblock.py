@@ -282,3 +282,73 @@ def test_flux_block_step_gradient_matches_finite_differences():
         # d/d(Re R) + i d/d(Im R), the convention the library's adjoint keeps
         got = getattr(R.grad[k], part).item()
         assert got == pytest.approx((lp - lm) / 2e-5, rel=1e-6, abs=1e-10), part
+
+
+def _tc_params(seed, kc, out_scale=0.05):
+    p = {"wi": torch.tensor(si.stencil_weights(seed, 0.02)),
+         "wd": torch.tensor(si.stencil_weights(seed + 1, 0.02)),
+         "fno_i": _net(seed + 2, out_scale=0.05), "fno_d": _net(seed + 3, out_scale=0.05)}
+    p["tc"] = fno.from_arrays(si.fno_weights(seed + 4, 4, 2, 2, n_in=2 * kc, n_out=2,
+                                             out_scale=out_scale))
+    return p
+
+
+def test_temporal_correction_only_at_multiples_of_kc_and_projected():
+    """Eq. 2: the correction enters at k = k_c, 2 k_c, ... only, and the
+    corrected state is divergence-free."""
+    from oracle import projection
+    kc, n = 3, 16
+    u0, v0, prm = _state(n, 2, seed=9)
+    prm = dict(prm, dt=0.02, k_c=kc)
+    p = _tc_params(40, kc)
+    with_tc = fluxblock.model_rollout(u0, v0, prm, p, 6)
+    no_tc = fluxblock.model_rollout(u0, v0, prm, dict(p, tc=None), 6)
+    for k in range(1, 7):
+        diff = (with_tc[0][k - 1] - no_tc[0][k - 1]).abs().max().item()
+        if k < kc:
+            assert diff == 0.0, k
+        if k == kc:
+            assert diff > 1e-6, k
+    div = projection.divergence(with_tc[0][kc - 1], with_tc[1][kc - 1], prm)
+    assert div.abs().max().item() < 1e-10
+
+
+def test_temporal_correction_reads_the_history_oldest_first():
+    """A correction whose lift reads only input plane 0 (and whose spectral
+    and pointwise layers are switched off) depends on u_{k-k_c} alone: the
+    planes are (u, v) per state, oldest first."""
+    kc, n = 2, 16
+    u0, v0, prm = _state(n, 1, seed=10)
+    prm = dict(prm, dt=0.02, k_c=kc)
+    p = _tc_params(50, kc, out_scale=1.0)
+    tc = p["tc"]
+    tc["P_w"] = torch.zeros_like(tc["P_w"])
+    tc["P_w"][:, 0] = 1.0
+    for lay in tc["layers"]:
+        lay["R"] = torch.zeros_like(lay["R"])
+    u1, v1 = fluxblock.fluxblock_step(u0, v0, prm, p)
+    base = fno.fno_forward(fluxblock.tc_input([u0, u1], [v0, v1]), tc)
+    # changing v_{k-2} or the later state leaves it; changing u_{k-2} does not
+    same = fno.fno_forward(fluxblock.tc_input([u0, 2 * u1], [v0 + 1, 3 * v1]), tc)
+    assert torch.allclose(base, same, atol=1e-14)
+    other = fno.fno_forward(fluxblock.tc_input([u0 + 0.5, u1], [v0, v1]), tc)
+    assert (other - base).abs().max().item() > 1e-6
+    # and the same function of u_{k-2} as a per-pixel evaluation
+    P_b, Q_w, Q_b = tc["P_b"], tc["Q_w"], tc["Q_b"]
+    h = u0[:, None] + P_b.view(1, -1, 1, 1)
+    nl = len(tc["layers"])
+    for li, lay in enumerate(tc["layers"]):
+        z = torch.einsum("oi,biyx->boyx", lay["W"], h) + lay["b"].view(1, -1, 1, 1)
+        h = cnn.gelu(z) if li < nl - 1 else z
+    ref = torch.einsum("ko,boyx->bkyx", Q_w, h) + Q_b.view(1, -1, 1, 1)
+    assert torch.allclose(base, ref, atol=1e-13)
+
+
+def test_temporal_correction_with_zero_output_is_the_flux_block_model():
+    kc = 2
+    u0, v0, prm = _state(16, 2, seed=11)
+    prm = dict(prm, dt=0.02, k_c=kc)
+    p = _tc_params(60, kc, out_scale=0.0)
+    a = fluxblock.model_rollout(u0, v0, prm, p, 4)
+    b = fluxblock.fluxblock_rollout(u0, v0, prm, p, 4)
+    assert torch.allclose(a[0], b[0], atol=1e-14) and torch.allclose(a[1], b[1], atol=1e-14)
