@@ -24,7 +24,10 @@ Every function follows the paper's definitions step by step in float64
 * ``fno``         the Fourier neural operator of the flux block's frequency
                   part (Sec. 3.4 Eq. 8; Li et al. 2021)
 * ``fluxblock``   the paper's flux block O_P + O_L + O_F (uniform learnable
-                  5x4 kernels and FNO fields, Sec. 3.4 Eqs. 5-8) in the step
+                  5x4 kernels and FNO fields, Sec. 3.4 Eqs. 5-8) in the step,
+                  and the temporal correction block (Eq. 2)
+* ``scalar``      the passive scalar of the shear-flow system, stepped with
+                  the velocity's RK4 stages
 * ``ic``          seeded initial conditions (App. C.1, S30-S31)
 * ``rng``         SplitMix64 and Box-Muller, from their published definitions
 * ``metrics``     down-sampling, vorticity, RMSE/MAE/MNAD/HCT/PCC (App. D.1,

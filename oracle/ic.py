@@ -152,6 +152,18 @@ def shear_layer(batch, nx, ny, lx, ly, seed, delta=1.0 / 30.0, pert=0.05, noise_
     return torch.stack(us), torch.stack(vs)
 
 
+def shear_scalar(batch, nx, ny, lx, ly, delta=1.0 / 30.0):
+    """The passive scalar aligned with the shear layers (our reading of the
+    shear-flow IC): s = (1 + prof(y)) / 2 at cell centres, with prof the
+    velocity's tanh profile (layers at L_y/4 and 3 L_y/4), so s runs from 0
+    to 1 across each layer."""
+    dy = ly / ny
+    yc = (torch.arange(ny, dtype=torch.float64) + 0.5) * dy
+    prof = torch.where(yc <= 0.5 * ly, torch.tanh((yc - 0.25 * ly) / delta),
+                       -torch.tanh((yc - 0.75 * ly) / delta))
+    return (0.5 * (1.0 + prof)).view(1, -1, 1).expand(batch, ny, nx).contiguous()
+
+
 def init_state(kind, batch, nx, ny, lx, ly, seed, **kw):
     if kind == FOURIER_MODES:
         return fourier_modes(batch, nx, ny, lx, ly, seed)
