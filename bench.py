@@ -327,6 +327,50 @@ def fluxblock_block(steps, warmup):
     return out
 
 
+def shear_scalar_block(steps=10, warmup=2):
+    """The shear-flow system with a passive scalar at the paper's fine
+    resolution (2048 x 1024 on [0, 8] x [0, 4], batch 8, FP32): the plain
+    DNS step of velocity and scalar together."""
+    import torch
+    import synthetic_inputs as si
+    from paper_2507_01975_amd import ldsv
+    w = si.WORKLOADS["shear_scalar"]
+    nx, ny, B = w["nx"], w["ny"], w["batch"]
+    s = ldsv.Solver(nx, ny, B, lx=w["lx"], ly=w["ly"])
+    u, v = s.init_state(ldsv.IC_SHEAR_LAYER, seed=1000, delta=w["delta"])
+    c = s.init_scalar(delta=w["delta"])
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"])
+    tot0 = c.double().sum().item()
+    s.fv_step_scalar(prm, w["diffusivity"], u, v, c, nsteps=warmup, out=(u, v, c))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.fv_step_scalar(prm, w["diffusivity"], u, v, c, nsteps=steps, out=(u, v, c))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.timer_enable(True)
+    s.fv_step_scalar(prm, w["diffusivity"], u, v, c, nsteps=steps, out=(u, v, c))
+    torch.cuda.synchronize()
+    sc_ms, sc_n = s.timer_read(ldsv.TIMER_OTHER)
+    st_ms, st_n = s.timer_read(ldsv.TIMER_STAGE)
+    s.timer_enable(False)
+    cells = nx * ny * B
+    # scalar stage: s_s, u_s, v_s, s_n, acc read, out and acc written (28 B/cell
+    # in the middle stages, averaged over the four like the velocity's)
+    sc_bytes = (16 + 28 + 28 + 24) / 4 * cells
+    out = {"workload": "shear_scalar fine DNS (2048 x 1024 on [0,8] x [0,4], batch 8, FP32, "
+                       "velocity + passive scalar, RK4 + projection per stage)",
+           "cell_steps_per_s": cells * steps / t, "ms_per_step": 1e3 * t / steps,
+           "scalar_total_rel_change": abs(c.double().sum().item() - tot0) / abs(tot0)}
+    if sc_n:
+        out["scalar_stage"] = {"avg_launch_us": 1e3 * sc_ms / sc_n,
+                               "achieved_GBs": sc_bytes / (sc_ms * 1e-3 / sc_n) / 1e9,
+                               "frac": sc_bytes / (sc_ms * 1e-3 / sc_n) / 1e9 / HBM_PEAK_GBS}
+    if st_n:
+        out["velocity_stage_avg_launch_us"] = 1e3 * st_ms / st_n
+    s.close()
+    return out
+
+
 def burgers_block(repeats=7):
     """The 2D viscous Burgers configuration (64^2, FP64, collocated, SSP-RK3,
     dt from CFL 0.5, 200 steps): microseconds per step, eager launches and a
@@ -579,6 +623,8 @@ def main():
         line["streaming"] = streaming_block()
         log("burgers64 latency")
         line["burgers64"] = burgers_block()
+        log("shear flow with a passive scalar, 2048 x 1024")
+        line["shear_scalar"] = shear_scalar_block()
         log("training iteration 128^2")
         line["training"] = training_block()
         log("flux-block training iteration 128^2")

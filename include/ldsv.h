@@ -420,6 +420,24 @@ LDSV_API int ldsv_fluxblock_step(ldsv_handle* h, const ldsv_params* prm, const l
                                  const float* u_in, const float* v_in, float* u_out, float* v_out,
                                  float* fields_out, void* stream);
 
+/* ---- shear flow with a passive scalar (the shear-flow equations of the
+ * appendix on the datasets) ----
+ * s at cell centres ([B][Ny][Nx], the grid's dtype), carried by the MAC
+ * velocity: ds/dt - D lap s = -u . grad s in flux form (face velocity times
+ * the midpoint average of s, fourth-order face derivative for the
+ * diffusion); the total of s is conserved.
+ * ldsv_fv_step_scalar: nsteps RK4 steps of the plain velocity (as
+ * ldsv_fv_step, projection per sub-step) and of s, whose stage residuals use
+ * the velocity's stage states.  MAC, RK4.  In place allowed. */
+LDSV_API int ldsv_fv_step_scalar(ldsv_handle* h, const ldsv_params* prm, double diffusivity,
+                                 const void* u_in, const void* v_in, const void* s_in,
+                                 void* u_out, void* v_out, void* s_out, int nsteps,
+                                 void* stream);
+/* ldsv_init_scalar: s = (1 + prof(y)) / 2 with prof the shear profile of
+ * ldsv_init_state's SHEAR_LAYER (layers at Ly/4 and 3Ly/4, thickness
+ * args->delta; NULL args: 1/30): the scalar aligned with the shear layers. */
+LDSV_API int ldsv_init_scalar(ldsv_handle* h, const ldsv_ic_args* args, void* s, void* stream);
+
 /* ---- measurement ----
  * Kernel classes timed by ldsv_timer_*: 0 RK stage (fused residual), 1 row
  * FFT + divergence, 2 column FFT + Poisson division, 3 inverse row FFT +

@@ -22,6 +22,10 @@ int ldsv_launch_downsample(ldsv_handle* h, int r, const float* uf, const float* 
                            float* vc, hipStream_t st);
 int ldsv_launch_vorticity(ldsv_handle* h, const void* u, const void* v, void* w, hipStream_t st);
 int ldsv_launch_pcc(ldsv_handle* h, const void* a, const void* b, double* out, hipStream_t st);
+int ldsv_launch_scalar_stage(ldsv_handle* h, const ldsv_params* prm, double diff, const void* us,
+                             const void* vs, const void* ss, const void* sn, const void* acc,
+                             void* out, void* oacc, double alpha, double beta, double delta,
+                             double eps, double gamma, double wacc, hipStream_t st);
 int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* lu,
                          const float* lv, double scale, float* gu, float* gv, double* loss,
                          hipStream_t st, int accumulate);
@@ -87,13 +91,22 @@ int check_params(const ldsv_handle* h, const ldsv_params* p) {
   return LDSV_OK;
 }
 
+// a passive scalar stepped with the velocity: s_in -> s_out (in place
+// allowed), diffusivity D
+struct ScalarStep {
+  const void* s_in;
+  void* s_out;
+  double diff;
+};
+
 // one time step src -> dst (dst may equal src).  keep (nullable, RK4/MAC):
 // the projected stage states u1, u2, u3 are written to keep[2s], keep[2s+1]
 // (state-sized planes) instead of the shared stage buffer.
 int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs, const void* su,
              const void* sv, void* du, void* dv, const float* tcu, const float* tcv, size_t tcbs,
              hipStream_t st, void* keep = nullptr, const uint16_t* coef16 = nullptr,
-             size_t cbs16 = 0, const FluxBlockArgs* fb = nullptr) {
+             size_t cbs16 = 0, const FluxBlockArgs* fb = nullptr,
+             const ScalarStep* sc = nullptr) {
   const size_t sbk = h->nstate * h->esize;
   auto ku = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s) * sbk : h->ws_u; };
   auto kv = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s + 1) * sbk : h->ws_v; };
@@ -129,6 +142,18 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
       a.tcu = (s == 3) ? tcu : nullptr;
       a.tcv = (s == 3) ? tcv : nullptr;
       a.tc_bstride = tcbs;
+      if (sc) {
+        // the scalar's stage reads the velocity stage state before this
+        // stage's projection overwrites it; its stage states ping-pong
+        const size_t sbs = h->nstate * h->esize;
+        char* sws = (char*)h->sc_ws;
+        const void* sin = (s == 0) ? sc->s_in : sws + ((s + 1) & 1) * sbs;
+        void* sout = (s == 3) ? sc->s_out : sws + (s & 1) * sbs;
+        void* sacc = sws + 2 * sbs;
+        LDSV_TRY(ldsv_launch_scalar_stage(h, p, sc->diff, a.us, a.vs, sin, sc->s_in, sacc, sout,
+                                          (s < 3) ? sacc : nullptr, a.alpha, a.beta, a.delta,
+                                          a.eps, a.gamma, a.wacc, st));
+      }
       if (mac) {
         a.ou = h->st_u;
         a.ov = h->st_v;
@@ -207,6 +232,16 @@ int ldsv_internal_step_fb(ldsv_handle* h, const ldsv_params* p, const FluxBlockA
                           const void* su, const void* sv, void* du, void* dv, hipStream_t st,
                           const float* tcu, const float* tcv, size_t tcbs) {
   return one_step(h, p, nullptr, 0, su, sv, du, dv, tcu, tcv, tcbs, st, nullptr, nullptr, 0, fb);
+}
+
+// a step of the velocity with a passive scalar
+int ldsv_internal_step_scalar(ldsv_handle* h, const ldsv_params* p, double diff, const void* su,
+                              const void* sv, const void* ss, void* du, void* dv, void* ds,
+                              hipStream_t st) {
+  if (!h->sc_ws) LDSV_TRY(ldsv_alloc(h, &h->sc_ws, 3 * h->nstate * h->esize, "scalar workspace"));
+  ScalarStep sc{ss, ds, diff};
+  return one_step(h, p, nullptr, 0, su, sv, du, dv, nullptr, nullptr, 0, st, nullptr, nullptr, 0,
+                  nullptr, &sc);
 }
 
 // VJP of one RK4 step with a projection per sub-step (reverse sweep in

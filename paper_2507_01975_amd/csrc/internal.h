@@ -126,6 +126,7 @@ struct ldsv_handle {
   float* fb_tc = nullptr;        // temporal correction: 2 planes [B][Ny][Nx]
   float* fb_gtc = nullptr;       // its gradient
   float* fb_tmp = nullptr;       // 2 state-sized scratch planes
+  void* sc_ws = nullptr;         // passive scalar: two stage states + accumulator
   void* fno_blk = nullptr;       // FNO buffers (fno.hip), fno_bytes long
   size_t fno_bytes = 0;
   size_t bytes = 0;

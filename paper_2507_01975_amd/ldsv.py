@@ -147,6 +147,9 @@ _SIGS = {
                                     _i, _vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                     ctypes.POINTER(FluxNetGrad), ctypes.POINTER(FnoGrad), _vp],
                                    _i),
+    "ldsv_fv_step_scalar": ([_vp, ctypes.POINTER(Params), _d, _vp, _vp, _vp, _vp, _vp, _vp, _i,
+                             _vp], _i),
+    "ldsv_init_scalar": ([_vp, ctypes.POINTER(ICArgs), _vp, _vp], _i),
     "ldsv_timer_enable": ([_vp, _i], _i),
     "ldsv_timer_read": ([_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i)], _i),
 }
@@ -382,6 +385,20 @@ class Solver:
         _check(_lib.ldsv_diagnostics(self._h, self._state(u), self._state(v), _ptr(out),
                                      _stream()))
         return out
+
+    # ---- shear flow with a passive scalar
+    def fv_step_scalar(self, prm, diffusivity, u, v, s, nsteps=1, out=None):
+        uo, vo, so = (self.new_state(), self.new_state(), self.new_state()) if out is None else out
+        _check(_lib.ldsv_fv_step_scalar(self._h, ctypes.byref(prm), diffusivity, self._state(u),
+                                        self._state(v), self._state(s), self._state(uo),
+                                        self._state(vo), self._state(so), nsteps, _stream()))
+        return uo, vo, so
+
+    def init_scalar(self, delta=1.0 / 30.0, s=None):
+        s = self.new_state() if s is None else s
+        ic = ICArgs(1.0, 1.0, delta, 0.05, 1e-3, 4.0)
+        _check(_lib.ldsv_init_scalar(self._h, ctypes.byref(ic), self._state(s), _stream()))
+        return s
 
     # ---- the paper's flux block (O_P + O_L + O_F)
     def _fields(self, f, name="fields"):

@@ -15,6 +15,9 @@ Workload records (sizes, physics parameters) follow the paper's flows
               dt = 16 * 4.38e-4, inference B = 64; fine reference 1024^2
 * decaying128_train  decaying NS, 128^2 learned, unroll 32, B = 8
 * shear128    shear layers, nu = 2e-4, learned 128^2 vs plain 1024^2, B = 128
+* shear_scalar  the shear-flow system with a passive scalar on [0, 8] x [0, 4]:
+              fine 2048 x 1024 (coarse 128 x 64), Re = 1000 (nu = 1e-3),
+              D = 1e-3, layer thickness w/5 = 0.1, dt = 0.1 dx, B = 8
 """
 import math
 
@@ -81,6 +84,10 @@ WORKLOADS = {
                               nu=1e-3, rk="rk4", dt=4 * 2.19e-4 * 2048 / 512, unroll=32,
                               checkpoint_every=8, ic="grf_peak", forcing_amp=0.0,
                               forcing_k=0.0, drag=0.0, dtype="f32", fine_n=512),
+    "shear_scalar": dict(layout="mac", nx=2048, ny=1024, lx=8.0, ly=4.0, batch=8, nu=1e-3,
+                         diffusivity=1e-3, rk="rk4", dt=0.1 * (8.0 / 2048), steps=20,
+                         ic="shear_layer", delta=0.1, forcing_amp=0.0, forcing_k=0.0, drag=0.0,
+                         dtype="f32", coarse_nx=128, coarse_ny=64),
     "shear128": dict(layout="mac", nx=128, ny=128, lx=TWO_PI, ly=TWO_PI, batch=128,
                      nu=2e-4, rk="rk4", dt=8 * 0.1 * (TWO_PI / 1024), steps=4096,
                      ic="shear_layer", forcing_amp=0.0, forcing_k=0.0, drag=0.0,
