@@ -15,11 +15,13 @@
 //   acc' = gamma acc + wacc R
 // with the velocity's stage coefficients and the velocity's stage state;
 // the RK loop launches it before each velocity stage (the projection of that
-// stage overwrites the velocity stage buffer).  One thread per cell; the 9
-// scalar values of the two face-derivative stencils and the four face
-// velocities come through L1/L2 (a wavefront covers 64 consecutive cells of
-// a row, so the x neighbours are the same lines and the y neighbours the
-// rows next to it).
+// stage overwrites the velocity stage buffer).  As the velocity's stage
+// kernel, one workgroup owns a TX x TY tile: the scalar with a 2-cell
+// periodic halo, the u column east of the tile and the v row north of it are
+// staged in LDS (all global loads of a thread in flight before the LDS
+// stores), every face flux is formed once, and the residual and the RK
+// combination stay in registers.  Tiles are renumbered XCD-contiguously so a
+// tile's halo lines are L2 hits.
 #include "internal.h"
 
 namespace {
@@ -35,50 +37,109 @@ struct ScalarComb {
   T alpha, beta, delta, eps, gamma, wacc;
 };
 
-template <typename T>
+constexpr int kSTX = 64, kSTY = 16, kSH = 2;
+
+template <typename T, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) k_stage_scalar(
     const T* __restrict__ us, const T* __restrict__ vs, const T* __restrict__ ss,
     const T* __restrict__ sn, const T* __restrict__ acc, T* __restrict__ out,
-    T* __restrict__ oacc, ScalarStagePhys<T> ph, ScalarComb<T> cb, int nx, int ny, int batch) {
-  const size_t n = (size_t)nx * ny;
-  const size_t total = n * batch;
-  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const size_t b0 = (g / n) * n;
-    const size_t c = g - b0;
-    const int i = (int)(c % nx), j = (int)(c / nx);
-    auto at = [&](const T* p, int ii, int jj) {
-      return p[b0 + (size_t)(jj & (ny - 1)) * nx + (ii & (nx - 1))];
-    };
-    const T s0 = ss[g];
-    T r = 0;
-    if (ph.mask & LDSV_ADVECTION) {
-      const T se = at(ss, i + 1, j), sw = at(ss, i - 1, j);
-      const T sN = at(ss, i, j + 1), sS = at(ss, i, j - 1);
-      const T fe = at(us, i + 1, j) * (T)0.5 * (s0 + se);
-      const T fw = us[g] * (T)0.5 * (sw + s0);
-      const T gn = at(vs, i, j + 1) * (T)0.5 * (s0 + sN);
-      const T gs = vs[g] * (T)0.5 * (sS + s0);
-      r = -(fe - fw) * ph.idx - (gn - gs) * ph.idy;
+    T* __restrict__ oacc, ScalarStagePhys<T> ph, ScalarComb<T> cb, int nx, int ny) {
+  constexpr int W = TX + 2 * kSH, H = TY + 2 * kSH;
+  constexpr int kS = W * H, kU = TY * (TX + 1), kV = (TY + 1) * TX;
+  constexpr int kSPer = (kS + kBlock - 1) / kBlock, kUPer = (kU + kBlock - 1) / kBlock,
+                kVPer = (kV + kBlock - 1) / kBlock;
+  constexpr int kCells = TX * TY, kCellPer = (kCells + kBlock - 1) / kBlock;
+  __shared__ T sl[H][W];
+  __shared__ T ul[TY][TX + 1];
+  __shared__ T vl[TY + 1][TX];
+  const int tilesx = nx / TX;
+  const int tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int b = tile / gridDim.x;
+  const int tp = tile - b * gridDim.x;
+  const int i0 = (tp % tilesx) * TX, j0 = (tp / tilesx) * TY;
+  const size_t boff = (size_t)b * nx * ny;
+  {
+    T ts[kSPer], tu[kUPer], tv[kVPer];
+#pragma unroll
+    for (int k = 0; k < kSPer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kS) {
+        const int r = t / W, c = t - r * W;
+        ts[k] = ss[boff + (size_t)((j0 - kSH + r + ny) & (ny - 1)) * nx + ((i0 - kSH + c + nx) & (nx - 1))];
+      }
     }
-    if (ph.mask & LDSV_VISCOSITY) {
-      const T sm2 = at(ss, i - 2, j), sm1 = at(ss, i - 1, j), sp1 = at(ss, i + 1, j),
-              sp2 = at(ss, i + 2, j);
-      const T tm2 = at(ss, i, j - 2), tm1 = at(ss, i, j - 1), tp1 = at(ss, i, j + 1),
-              tp2 = at(ss, i, j + 2);
-      const T de = (sm1 - (T)27 * s0 + (T)27 * sp1 - sp2) * ph.i24dx;
-      const T dw = (sm2 - (T)27 * sm1 + (T)27 * s0 - sp1) * ph.i24dx;
-      const T dn = (tm1 - (T)27 * s0 + (T)27 * tp1 - tp2) * ph.i24dy;
-      const T ds = (tm2 - (T)27 * tm1 + (T)27 * s0 - tp1) * ph.i24dy;
-      r += ph.diff * ((de - dw) * ph.idx + (dn - ds) * ph.idy);
+#pragma unroll
+    for (int k = 0; k < kUPer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kU) {
+        const int r = t / (TX + 1), c = t - r * (TX + 1);
+        tu[k] = us[boff + (size_t)(j0 + r) * nx + ((i0 + c) & (nx - 1))];
+      }
     }
-    T o = cb.beta * s0 + cb.eps * r;
-    if (cb.alpha != (T)0) o += cb.alpha * sn[g];
-    T a = 0;
-    if (cb.delta != (T)0 || cb.gamma != (T)0) a = acc[g];
-    o += cb.delta * a;
-    out[g] = o;
-    if (oacc) oacc[g] = cb.gamma * a + cb.wacc * r;
+#pragma unroll
+    for (int k = 0; k < kVPer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kV) {
+        const int r = t / TX, c = t - r * TX;
+        tv[k] = vs[boff + (size_t)((j0 + r) & (ny - 1)) * nx + (i0 + c)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSPer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kS) sl[t / W][t % W] = ts[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kUPer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kU) ul[t / (TX + 1)][t % (TX + 1)] = tu[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kVPer; ++k) {
+      const int t = k * kBlock + (int)threadIdx.x;
+      if (t < kV) vl[t / TX][t % TX] = tv[k];
+    }
+  }
+  // operands of the RK combination, loaded before the barrier
+  T pn[kCellPer], pa[kCellPer];
+  const bool need_n = cb.alpha != (T)0, need_a = cb.delta != (T)0 || cb.gamma != (T)0;
+#pragma unroll
+  for (int k = 0; k < kCellPer; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    pn[k] = pa[k] = (T)0;
+    if (t < kCells) {
+      const size_t g = boff + (size_t)(j0 + t / TX) * nx + (i0 + t % TX);
+      if (need_n) pn[k] = sn[g];
+      if (need_a) pa[k] = acc[g];
+    }
+  }
+  __syncthreads();
+  const bool adv = ph.mask & LDSV_ADVECTION, visc = ph.mask & LDSV_VISCOSITY;
+#pragma unroll
+  for (int k = 0; k < kCellPer; ++k) {
+    const int t = k * kBlock + (int)threadIdx.x;
+    if (t >= kCells) break;
+    const int r = t / TX, c = t - r * TX;
+    const int lj = r + kSH, li = c + kSH;
+    const T s0 = sl[lj][li];
+    T rr = 0;
+    if (adv) {
+      const T fe = ul[r][c + 1] * (T)0.5 * (s0 + sl[lj][li + 1]);
+      const T fw = ul[r][c] * (T)0.5 * (sl[lj][li - 1] + s0);
+      const T gn = vl[r + 1][c] * (T)0.5 * (s0 + sl[lj + 1][li]);
+      const T gs = vl[r][c] * (T)0.5 * (sl[lj - 1][li] + s0);
+      rr = -(fe - fw) * ph.idx - (gn - gs) * ph.idy;
+    }
+    if (visc) {
+      const T de = (sl[lj][li - 1] - (T)27 * s0 + (T)27 * sl[lj][li + 1] - sl[lj][li + 2]) * ph.i24dx;
+      const T dw = (sl[lj][li - 2] - (T)27 * sl[lj][li - 1] + (T)27 * s0 - sl[lj][li + 1]) * ph.i24dx;
+      const T dn = (sl[lj - 1][li] - (T)27 * s0 + (T)27 * sl[lj + 1][li] - sl[lj + 2][li]) * ph.i24dy;
+      const T ds = (sl[lj - 2][li] - (T)27 * sl[lj - 1][li] + (T)27 * s0 - sl[lj + 1][li]) * ph.i24dy;
+      rr += ph.diff * ((de - dw) * ph.idx + (dn - ds) * ph.idy);
+    }
+    const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
+    out[g] = cb.beta * s0 + cb.eps * rr + cb.alpha * pn[k] + cb.delta * pa[k];
+    if (oacc) oacc[g] = cb.gamma * pa[k] + cb.wacc * rr;
   }
 }
 
@@ -91,9 +152,17 @@ int launch_scalar_t(ldsv_handle* h, const ldsv_params* prm, double diff, const v
   ScalarStagePhys<T> ph{(T)(1.0 / dx), (T)(1.0 / dy), (T)(1.0 / (24.0 * dx)),
                         (T)(1.0 / (24.0 * dy)), (T)diff, prm->physics_mask};
   ScalarComb<T> cb{(T)alpha, (T)beta, (T)delta, (T)eps, (T)gamma, (T)wacc};
-  LDSV_TLAUNCH(h, 7, k_stage_scalar<T>, grid1d(h->nstate), dim3(kBlock), 0, st, (const T*)us,
-               (const T*)vs, (const T*)ss, (const T*)sn, (const T*)acc, (T*)out, (T*)oacc, ph, cb,
-               h->g.nx, h->g.ny, h->g.batch);
+  const int nx = h->g.nx, ny = h->g.ny;
+#define LDSV_SCALAR_CASE(tx, ty)                                                              \
+  if (nx >= tx && ny >= ty) {                                                                 \
+    dim3 grid((nx / tx) * (ny / ty), h->g.batch);                                             \
+    LDSV_TLAUNCH(h, 7, (k_stage_scalar<T, tx, ty>), grid, dim3(kBlock), 0, st, (const T*)us,  \
+                 (const T*)vs, (const T*)ss, (const T*)sn, (const T*)acc, (T*)out, (T*)oacc,  \
+                 ph, cb, nx, ny);                                                             \
+  }
+  LDSV_SCALAR_CASE(kSTX, kSTY)
+  else LDSV_SCALAR_CASE(32, 8) else LDSV_SCALAR_CASE(8, 8)
+#undef LDSV_SCALAR_CASE
   LDSV_LAUNCHED();
   return LDSV_OK;
 }

@@ -13,9 +13,11 @@ LX, LY = 8.0, 4.0
 KW = dict(nu=1e-3, dt=0.01)
 
 
+# tiles: 64 x 16 (128 x 64, 64 x 32), 32 x 8 (32 x 8), 8 x 8 (16 x 16)
 @pytest.mark.parametrize("nx,ny,b,dtype,tol", [
     (128, 64, 3, torch.float32, 1e-5), (64, 32, 2, torch.float32, 1e-5),
-    (64, 32, 2, torch.float64, 1e-12)])
+    (64, 32, 2, torch.float64, 1e-12), (32, 8, 2, torch.float64, 1e-12),
+    (16, 16, 1, torch.float64, 1e-12)])
 def test_scalar_step_matches_oracle(nx, ny, b, dtype, tol):
     L_ = need_gpu()
     announce("scalar step", nx, ny, b, dtype)
