@@ -529,6 +529,9 @@ def main():
                     help="skip the streaming-shape (1024^2 x 128) and Burgers latency records")
     ap.add_argument("--learned-only", action="store_true",
                     help="profiling aid: time only the learned 64^2 step and print its record")
+    ap.add_argument("--fluxblock-only", action="store_true",
+                    help="profiling aid: time only the flux-block model (64^2 step, complete "
+                    "model, 128^2 training iteration) and print its records")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="profiling aid: one device-to-device copy of this many MiB before the "
                     "timed loop, the known-size kernel that calibrates HBM byte counters")
@@ -551,8 +554,10 @@ def main():
         log("copy probe: %d MiB" % a.copy_probe_mib)
         del src, dst
     if a.learned_only:
-        print(json.dumps({"learned": learned_block(a.steps, a.warmup),
-                          "fluxblock": fluxblock_block(a.steps, a.warmup),
+        print(json.dumps({"learned": learned_block(a.steps, a.warmup)}), flush=True)
+        return
+    if a.fluxblock_only:
+        print(json.dumps({"fluxblock": fluxblock_block(a.steps, a.warmup),
                           "fluxblock_training": fluxblock_training_block()}), flush=True)
         return
 

@@ -8,7 +8,7 @@
 // synchronises, then every thread twiddles, transforms in registers and
 // stores its outputs, and the block synchronises again.  The buffer holds
 // `nrows` transforms of length n; element j of transform r lives at
-// buf[r * rs + j * es].  Threads walk the elements with the unit-stride
+// buf[r * rs + j * es] (rs and es powers of two).  Threads walk the elements with the unit-stride
 // index fastest (j when es == 1, r otherwise), so each wavefront reads and
 // writes consecutive LDS words.
 #pragma once
@@ -74,9 +74,10 @@ __device__ __forceinline__ void dft8(Cx<T>* x, int sign) {
 // kernels is comparable to their memory time.  Row transforms (es == 1) take
 // any nrows (the gradient pass transforms a halo row more).
 template <typename T, int R, int LR, int E>
-__device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int log2nrows, int rs,
-                                          int es, int log2ns, int sign,
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int log2nrows, int lrs,
+                                          int les, int log2ns, int sign,
                                           const Cx<T>* __restrict__ tw) {
+  const int es = 1 << les;
   constexpr int BPT = (E / R) > 0 ? (E / R) : 1;  // butterflies per thread
   const int lnb = log2n - LR;                      // log2 of butterflies per transform
   const int total = nrows << lnb;
@@ -96,7 +97,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int 
         row = t & ((1 << log2nrows) - 1);
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[q][r] = buf[row * rs + ((j + (r << lnb)) * es)];
+      for (int r = 0; r < R; ++r) x[q][r] = buf[(row << lrs) + ((j + (r << lnb)) << les)];
     }
   }
   __syncthreads();
@@ -125,7 +126,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int 
       else dft2(x[q]);
       const int d = ((j - k) << LR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[row * rs + (d + (r << log2ns)) * es] = x[q][r];
+      for (int r = 0; r < R; ++r) buf[(row << lrs) + ((d + (r << log2ns)) << les)] = x[q][r];
     }
   }
   __syncthreads();
@@ -142,19 +143,22 @@ __device__ __forceinline__ void lds_fft(Cx<T>* buf, int n, int log2n, int nrows,
                                         int sign, const Cx<T>* __restrict__ tw) {
   (void)n;
   const int log2nrows = es == 1 ? 0 : __builtin_ctz((unsigned)nrows);
+  // rs and es are powers of two: element addresses are shifts, not
+  // (quarter-rate) integer multiplies
+  const int lrs = __builtin_ctz((unsigned)rs), les = __builtin_ctz((unsigned)es);
   int log2ns = 0;
   int left = log2n;
   while (left > 0) {
     if (left >= 3 && left != 4) {
-      fft_stage<T, 8, 3, E>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
+      fft_stage<T, 8, 3, E>(buf, log2n, nrows, log2nrows, lrs, les, log2ns, sign, tw);
       log2ns += 3;
       left -= 3;
     } else if (left >= 2) {
-      fft_stage<T, 4, 2, E>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
+      fft_stage<T, 4, 2, E>(buf, log2n, nrows, log2nrows, lrs, les, log2ns, sign, tw);
       log2ns += 2;
       left -= 2;
     } else {
-      fft_stage<T, 2, 1, E>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
+      fft_stage<T, 2, 1, E>(buf, log2n, nrows, log2nrows, lrs, les, log2ns, sign, tw);
       log2ns += 1;
       left -= 1;
     }

@@ -113,18 +113,20 @@ def _fno_pair(seed, cfg, out_scale=0.05):
     return a_i, a_d
 
 
-@pytest.mark.parametrize("cfg,n,b", [("forced", 64, 4), ("decaying", 128, 2)])
-def test_fno_forward_matches_oracle(cfg, n, b):
+@pytest.mark.parametrize("cfg,n,b,ny", [("forced", 64, 4, 64), ("decaying", 128, 2, 128),
+                                         ("forced", 128, 2, 128), ("decaying", 64, 3, 32)])
+def test_fno_forward_matches_oracle(cfg, n, b, ny):
     """Both FNOs at the paper's hyper-parameters (forced: 6 layers, 32 modes,
-    width 16 on 64^2; decaying: 4 layers, 16 modes, width 8 on 128^2); the
+    width 16; decaying: 4 layers, 16 modes, width 8) on 64^2, 128^2 (16
+    values per thread in the transforms) and a non-square 64 x 32 grid; the
     last layer is given O(1) weights so the fields are not small."""
     L_ = need_gpu()
-    announce("fno forward", cfg, n, b)
-    s = L_.Solver(n, n, b)
+    announce("fno forward", cfg, n, ny, b)
+    s = L_.Solver(n, ny, b)
     a_i, a_d = _fno_pair(21, cfg, out_scale=1.0)
     net = L_.FluxNetParams(_stencils(23), L_.FnoParams.from_arrays(a_i),
                            L_.FnoParams.from_arrays(a_d))
-    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=25)
+    u0, v0 = ic.grf_peak(b, n, ny, L, L, seed=25)
     u, v = dev(u0, torch.float32), dev(v0, torch.float32)
     got = s.fno_forward(net, u, v)
     x = torch.stack([cpu64(u), cpu64(v)], dim=1)
