@@ -49,6 +49,13 @@ cell centre.  The uniform kernels cover the whole 5x4 window: footprint
 points 0..15 as above, then the four corners 16: (-1,-2), 17: (2,-2),
 18: (-1,2), 19: (2,2).  Any entry may be absent (None).  Each face value is
 still single-valued, so the residual stays conservative.
+
+Per-cell learned derivative stencils (the m = d operator in the per-cell
+form, Sec. 3.4): ``dcoef`` [B, 64, Ny, Nx] holds dimensionless weights w on
+the same 16-point footprint and kinds; the face derivative of kind K is
+(1/h) sum_s w[16K + s] q_s with h the spacing along the face normal, in
+place of the fourth-order kernel.  The learned module builds w from raw
+network values so that it differentiates linear fields exactly.
 """
 import math
 import torch
@@ -63,6 +70,16 @@ FOOTPRINT = [(s % 4 - 1, s // 4 - 1) for s in range(12)] + [(0, -2), (1, -2), (0
 NKIND = 4
 NPOINT = 16
 FOOTPRINT20 = FOOTPRINT + [(-1, -2), (2, -2), (-1, 2), (2, 2)]
+
+
+def plain_deriv_coefficients(dtype=torch.float64):
+    """The fourth-order derivative kernel (S6) as footprint weights, in units
+    of 1/h: [1, -27, 27, -1]/24 at a = -1..2 on the row b = 0 (points 4..7)."""
+    c = torch.zeros(NKIND * NPOINT, dtype=dtype)
+    for k in range(NKIND):
+        for s, w in zip(range(4, 8), (1.0, -27.0, 27.0, -1.0)):
+            c[16 * k + s] = w / 24.0
+    return c
 
 
 def plain_coefficients(dtype=torch.float64):
@@ -160,7 +177,15 @@ def _flux_deriv(q, flux, kind, along_x, h):
     return out
 
 
-def ns_rhs(u, v, prm, coef=None, flux=None):
+def _face_deriv(q, dcoef, kind, along_x, h):
+    """Face derivative of kind K: the fourth-order kernel, or the per-cell
+    learned weights dcoef (in units of 1/h) on the 16-point footprint."""
+    if dcoef is None:
+        return deriv4_x(q, h) if along_x else deriv4_y(q, h)
+    return (interp_x(q, dcoef, kind) if along_x else interp_y(q, dcoef, kind)) / h
+
+
+def ns_rhs(u, v, prm, coef=None, flux=None, dcoef=None):
     """Residual R(u) of the incompressible momentum equations without the
     pressure term, on the MAC grid (Eq. 4; App. B.2 S1-S5; App. C.1 S26).
 
@@ -179,6 +204,8 @@ def ns_rhs(u, v, prm, coef=None, flux=None):
     coef: None for the physics stencil, else a 64-vector or [B, 64, Ny, Nx].
     flux: None, or the flux-block record (wi, wd, fi, fd) described above,
     whose terms add to the face values.
+    dcoef: None for the fourth-order derivative, else per-cell derivative
+    weights [B, 64, Ny, Nx] (dimensionless, see the module header).
     """
     dx, dy = prm["dx"], prm["dy"]
     mask = prm.get("mask", ALL_PHYSICS)
@@ -200,10 +227,10 @@ def ns_rhs(u, v, prm, coef=None, flux=None):
         rv = rv - (E - sx(E, -1)) / dx - (H - sy(H, -1)) / dy
     if mask & VISCOSITY:
         nu = prm["nu"]
-        ux = deriv4_x(u, dx) + _flux_deriv(u, flux, 0, True, dx)
-        uy = deriv4_y(u, dy) + _flux_deriv(u, flux, 1, False, dy)
-        vx = deriv4_x(v, dx) + _flux_deriv(v, flux, 2, True, dx)
-        vy = deriv4_y(v, dy) + _flux_deriv(v, flux, 3, False, dy)
+        ux = _face_deriv(u, dcoef, 0, True, dx) + _flux_deriv(u, flux, 0, True, dx)
+        uy = _face_deriv(u, dcoef, 1, False, dy) + _flux_deriv(u, flux, 1, False, dy)
+        vx = _face_deriv(v, dcoef, 2, True, dx) + _flux_deriv(v, flux, 2, True, dx)
+        vy = _face_deriv(v, dcoef, 3, False, dy) + _flux_deriv(v, flux, 3, False, dy)
         ru = ru + nu * ((ux - sx(ux, -1)) / dx + (uy - sy(uy, -1)) / dy)
         rv = rv + nu * ((vx - sx(vx, -1)) / dx + (vy - sy(vy, -1)) / dy)
     if mask & FORCING:

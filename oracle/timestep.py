@@ -24,10 +24,10 @@ MAC = 0
 COLLOCATED = 1
 
 
-def rhs(u, v, prm, coef=None, flux=None):
+def rhs(u, v, prm, coef=None, flux=None, dcoef=None):
     if prm.get("layout", MAC) == COLLOCATED:
         return fv.burgers_rhs(u, v, prm)
-    return fv.ns_rhs(u, v, prm, coef, flux)
+    return fv.ns_rhs(u, v, prm, coef, flux, dcoef)
 
 
 def _proj(u, v, prm):
@@ -37,41 +37,42 @@ def _proj(u, v, prm):
     return pu, pv
 
 
-def rk4_step(u, v, prm, coef=None, flux=None):
+def rk4_step(u, v, prm, coef=None, flux=None, dcoef=None):
     dt = prm["dt"]
-    k1 = rhs(u, v, prm, coef, flux)
+    k1 = rhs(u, v, prm, coef, flux, dcoef)
     u1 = _proj(u + 0.5 * dt * k1[0], v + 0.5 * dt * k1[1], prm)
-    k2 = rhs(*u1, prm, coef, flux)
+    k2 = rhs(*u1, prm, coef, flux, dcoef)
     u2 = _proj(u + 0.5 * dt * k2[0], v + 0.5 * dt * k2[1], prm)
-    k3 = rhs(*u2, prm, coef, flux)
+    k3 = rhs(*u2, prm, coef, flux, dcoef)
     u3 = _proj(u + dt * k3[0], v + dt * k3[1], prm)
-    k4 = rhs(*u3, prm, coef, flux)
+    k4 = rhs(*u3, prm, coef, flux, dcoef)
     un = u + dt / 6.0 * (k1[0] + 2.0 * k2[0] + 2.0 * k3[0] + k4[0])
     vn = v + dt / 6.0 * (k1[1] + 2.0 * k2[1] + 2.0 * k3[1] + k4[1])
     return _proj(un, vn, prm)
 
 
-def ssprk3_step(u, v, prm, coef=None, flux=None):
+def ssprk3_step(u, v, prm, coef=None, flux=None, dcoef=None):
     dt = prm["dt"]
-    r = rhs(u, v, prm, coef, flux)
+    r = rhs(u, v, prm, coef, flux, dcoef)
     u1, v1 = u + dt * r[0], v + dt * r[1]
     u1, v1 = _proj(u1, v1, prm)
-    r = rhs(u1, v1, prm, coef, flux)
+    r = rhs(u1, v1, prm, coef, flux, dcoef)
     u2 = 0.75 * u + 0.25 * (u1 + dt * r[0])
     v2 = 0.75 * v + 0.25 * (v1 + dt * r[1])
     u2, v2 = _proj(u2, v2, prm)
-    r = rhs(u2, v2, prm, coef, flux)
+    r = rhs(u2, v2, prm, coef, flux, dcoef)
     un = u / 3.0 + 2.0 / 3.0 * (u2 + dt * r[0])
     vn = v / 3.0 + 2.0 / 3.0 * (v2 + dt * r[1])
     return _proj(un, vn, prm)
 
 
-def fv_step(u, v, prm, coef=None, nsteps=1, flux=None):
+def fv_step(u, v, prm, coef=None, nsteps=1, flux=None, dcoef=None):
     """The plain (or fixed-coefficient) FV module applied nsteps times; flux
-    is an optional flux-block record (see fv), held fixed over the steps."""
+    is an optional flux-block record and dcoef optional per-cell derivative
+    weights (see fv), both held fixed over the steps."""
     step = ssprk3_step if prm.get("rk", RK4) == SSPRK3 else rk4_step
     for _ in range(nsteps):
-        u, v = step(u, v, prm, coef, flux)
+        u, v = step(u, v, prm, coef, flux, dcoef)
     return u, v
 
 
