@@ -247,6 +247,58 @@ LDSV_API int ldsv_rollout_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv
                               float* gu0, float* gv0, const ldsv_net_grad* dW, double* loss_dev,
                               void* stream);
 
+/* ---- learned derivative stencils (Sec. 3.4: the m = d operator in per-cell
+ * form; each of m = i and m = d keeps its own parameters) ----
+ * dcoef: raw derivative values r, float [B][64][Ny][Nx] (channel 16K+s:
+ * kind K as for coef -- K0 du/dx at the cell centre, K1 du/dy at the corner,
+ * K2 dv/dx at the corner, K3 dv/dy at the cell centre -- footprint point s).
+ * Per kind and cell they become the weights
+ *   w = w_P + r - mean(r) - x (x . r)/16 - b (b . r)/24
+ * with x_s = a_s - 1/2 and b_s the footprint point's offsets along and
+ * across the face normal and w_P the fourth-order kernel [1,-27,27,-1]/24
+ * (zero sum, unit normal and zero across first moment: the exact normal
+ * derivative of every linear field), and the face derivative is
+ * (1/h) sum_s w_s q_s in place of the fourth-order kernel.  Both coef and
+ * dcoef are required (zeros give the physics stencils).  F32 MAC grids.
+ *
+ * ldsv_fv_step_d: the FV module with both coefficient sets (as ldsv_fv_step).
+ * ldsv_fv_step_d_bwd: its VJP for one RK4 step (as ldsv_fv_step_bwd);
+ *   ACCUMULATES dL/dr into gcoef and gdcoef (each nullable). */
+LDSV_API int ldsv_fv_step_d(ldsv_handle* h, const ldsv_params* prm, const float* coef,
+                            const float* dcoef, const void* u_in, const void* v_in, void* u_out,
+                            void* v_out, int nsteps, void* stream);
+LDSV_API int ldsv_fv_step_d_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef,
+                                const float* dcoef, const void* u_in, const void* v_in,
+                                const void* gu_out, const void* gv_out, void* gu_in, void* gv_in,
+                                float* gcoef, float* gdcoef, void* stream);
+/* The learned step with a second network dnet (the layer shapes of ldsv_net;
+ * its 64 first outputs are the raw derivative values, its two last outputs
+ * are not used) evaluated on u_{k-1} beside net: as ldsv_learned_fv_step,
+ * dnet_out (nullable) receiving dnet's output [B][66][Ny][Nx].  The _bwd,
+ * rollout and rollout_bwd forms are those of the coefficient network alone
+ * with dnet beside net and its parameter gradients ACCUMULATED into *dWd. */
+LDSV_API int ldsv_learned_d_fv_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                                    const ldsv_net* dnet, const float* u_in, const float* v_in,
+                                    float* u_out, float* v_out, int step_index, float* net_out,
+                                    float* dnet_out, void* stream);
+LDSV_API int ldsv_learned_d_fv_step_bwd(ldsv_handle* h, const ldsv_params* prm,
+                                        const ldsv_net* net, const ldsv_net* dnet,
+                                        const float* u_in, const float* v_in, int step_index,
+                                        const float* gu_out, const float* gv_out, float* gu_in,
+                                        float* gv_in, const ldsv_net_grad* dW,
+                                        const ldsv_net_grad* dWd, void* stream);
+LDSV_API int ldsv_rollout_d(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                            const ldsv_net* dnet, const void* u0, const void* v0, int nsteps,
+                            int save_every, int first_index, void* traj_u, void* traj_v,
+                            int* fallback_flags, void* stream);
+LDSV_API int ldsv_rollout_d_bwd(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
+                                const ldsv_net* dnet, const float* u0, const float* v0,
+                                int nsteps, int checkpoint_every, int first_index,
+                                const float* labels_u, const float* labels_v, double loss_scale,
+                                const float* g_traj_u, const float* g_traj_v, float* gu0,
+                                float* gv0, const ldsv_net_grad* dW, const ldsv_net_grad* dWd,
+                                double* loss_dev, void* stream);
+
 /* ---- a16: loss and optimiser (Eq. 13; App. D.3) ----
  * ldsv_mse_grad: loss contribution 0.5*(mean((u-lu)^2) + mean((v-lv)^2))
  * accumulated in FP64 into *loss_dev (device double, nullable), and the

@@ -31,6 +31,13 @@
 // sum -nu * Fb * q_s / h, reduced per tile (k_adj_fb_wgrad) and then in a
 // fixed order over the tiles (k_fb_wreduce): deterministic.
 //
+// Learned derivative stencils (per cell): the face derivative is
+// (1/h) sum_s w_s q_s with w = w_P + r - mean(r) - x (x.r)/16 - b (b.r)/24.
+// The face then sends -nu * Fb * w_s / h to every point s, and the raw
+// gradient is the same projection of g_s = -nu * Fb * q_s / h:
+// dr = g - mean(g) - x (x.g)/16 - b (b.g)/24.  The three moments of r per
+// kind and owner go through the scratch planes to the gather.
+//
 // RK4 reverse sweep, with P the (symmetric) projection and u1..u3 the
 // recomputed projected stage states:
 //   A = P g;  S = A
@@ -60,8 +67,15 @@ struct Field {
   }
 };
 
-// scratch layout (per trajectory plane, 16 planes): P0..P3, Q0..Q3, V0..V3, M0..M3
-constexpr int kAdjPlanes = 16;
+// scratch layout (per trajectory plane, 28 planes): P0..P3, Q0..Q3, V0..V3,
+// M0..M3, and for learned derivatives the moments mean(r), (x.r)/16 and
+// (b.r)/24 of each kind (planes 16..19, 20..23, 24..27)
+constexpr int kAdjPlanes = 28;
+
+// fourth-order derivative weight of footprint point s (units of 1/h)
+__device__ __forceinline__ constexpr double deriv4_w(int s) {
+  return s == 4 ? 1.0 / 24.0 : s == 5 ? -27.0 / 24.0 : s == 6 ? 27.0 / 24.0 : s == 7 ? -1.0 / 24.0 : 0.0;
+}
 
 // the 5x4 window of the uniform kernels (points 0..15 as in kAOffA/kBOffA,
 // then the four corners)
@@ -80,7 +94,8 @@ struct AdjFB {
   size_t gfbs;
 };
 
-// MODE: 0 physics stencil, 1 per-cell coefficients, 2 flux block
+// MODE: 0 physics stencil, 1 per-cell coefficients, 2 flux block, 3 per-cell
+// coefficients and per-cell derivative values
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, const T* __restrict__ vs,
@@ -88,9 +103,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
                                                       const T* __restrict__ Gu, const T* __restrict__ Gv,
                                                       double aA, double aG, const float* __restrict__ coef,
                                                       size_t cbs, float* __restrict__ gcoef, size_t gcbs,
-                                                      AdjFB fb, T* __restrict__ scr, AdjPhys ph, int nx,
-                                                      int ny) {
-  constexpr bool LEARNED = MODE == 1;
+                                                      const float* __restrict__ dcoef,
+                                                      float* __restrict__ gdcoef, AdjFB fb,
+                                                      T* __restrict__ scr, AdjPhys ph, int nx, int ny) {
+  constexpr bool LEARNED = MODE == 1 || MODE == 3;
   const size_t n = (size_t)nx * ny;
   const int b = blockIdx.y;
   const size_t off = (size_t)b * n;
@@ -198,6 +214,44 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
       Vm[2] = -nu * exb * (T)(1.0 / 24.0) * idx;
       Vm[3] = -nu * eyb * (T)(1.0 / 24.0) * idy;
     }
+    if constexpr (MODE == 3) {
+      const float* db = dcoef + (size_t)b * cbs;
+      float* gd = gdcoef ? gdcoef + (size_t)b * gcbs : nullptr;
+#pragma unroll
+      for (int K = 0; K < 4; ++K) {
+        const Field<T>& F = (K < 2) ? U : V;
+        const bool along_x = (K == 0 || K == 2);
+        T r[16], q[16];
+        T sr = 0, sxr = 0, sbr = 0, sq = 0, sxq = 0, sbq = 0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int a = a_off20(s), bb = b_off20(s);
+          const T x = (T)a - (T)0.5;
+          r[s] = (T)db[(size_t)(16 * K + s) * n + c];
+          q[s] = along_x ? F(i + a, j + bb) : F(i + bb, j + a);
+          sr += r[s];
+          sxr += x * r[s];
+          sbr += (T)bb * r[s];
+          sq += q[s];
+          sxq += x * q[s];
+          sbq += (T)bb * q[s];
+        }
+        S[(size_t)(16 + K) * n + c] = sr * (T)(1.0 / 16.0);
+        S[(size_t)(20 + K) * n + c] = sxr * (T)(1.0 / 16.0);
+        S[(size_t)(24 + K) * n + c] = sbr * (T)(1.0 / 24.0);
+        if (gd && visc) {
+          const T g24 = (T)24 * Vm[K];  // -nu Fb / h
+          sq *= (T)(1.0 / 16.0);
+          sxq *= (T)(1.0 / 16.0);
+          sbq *= (T)(1.0 / 24.0);
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const T x = (T)a_off20(s) - (T)0.5;
+            gd[(size_t)(16 * K + s) * n + c] += (float)(g24 * (q[s] - sq - x * sxq - (T)b_off20(s) * sbq));
+          }
+        }
+      }
+    }
     if constexpr (MODE == 2) {
       if (fb.gf) {
         float* g = fb.gf + (size_t)b * fb.gfbs;
@@ -222,6 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr,
                                                        const float* __restrict__ coef, size_t cbs,
+                                                       const float* __restrict__ dcoef,
                                                        const float* __restrict__ fbw,
                                                        const T* __restrict__ Au, const T* __restrict__ Av,
                                                        const T* __restrict__ Gu, const T* __restrict__ Gv,
@@ -232,9 +287,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
   const size_t n = (size_t)nx * ny;
   const int b = blockIdx.y;
   const size_t off = (size_t)b * n;
-  constexpr bool LEARNED = MODE == 1;
+  constexpr bool LEARNED = MODE == 1 || MODE == 3;
   const T* S = scr + (size_t)b * kAdjPlanes * n;
   const float* cb = LEARNED ? coef + (size_t)b * cbs : nullptr;
+  const float* db = MODE == 3 ? dcoef + (size_t)b * cbs : nullptr;
   const T wv[4] = {(T)1, (T)-27, (T)27, (T)-1};  // derivative weights for offsets -1..2
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
@@ -286,12 +342,31 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
         gv += (T)24 * ((T)fbw[120 + s] * at(10, i - a, j - bb) + (T)fbw[140 + s] * at(11, i - bb, j - a));
       }
     }
-    // viscous face derivatives: owner o = p - m sends V * w_m to p
+    if constexpr (MODE == 3) {
+      // learned face derivatives: owner o sends 24 V w_s (V = -nu Fb / (24 h))
+      // to its footprint point s, w rebuilt from o's raw values and moments
+      auto dw = [&](int K, int s, int ii, int jj) -> T {
+        const size_t o = cidx(ii, jj);
+        return (T)db[(size_t)(16 * K + s) * n + o] - S[(size_t)(16 + K) * n + o] -
+               ((T)a_off20(s) - (T)0.5) * S[(size_t)(20 + K) * n + o] -
+               (T)b_off20(s) * S[(size_t)(24 + K) * n + o] + (T)deriv4_w(s);
+      };
 #pragma unroll
-    for (int m = -1; m <= 2; ++m) {
-      const T w = wv[m + 1];
-      gu += w * (at(8, i - m, j) + at(9, i, j - m));
-      gv += w * (at(10, i - m, j) + at(11, i, j - m));
+      for (int s = 0; s < 16; ++s) {
+        const int a = a_off20(s), bb = b_off20(s);
+        gu += (T)24 * (dw(0, s, i - a, j - bb) * at(8, i - a, j - bb) +
+                       dw(1, s, i - bb, j - a) * at(9, i - bb, j - a));
+        gv += (T)24 * (dw(2, s, i - a, j - bb) * at(10, i - a, j - bb) +
+                       dw(3, s, i - bb, j - a) * at(11, i - bb, j - a));
+      }
+    } else {
+      // viscous face derivatives: owner o = p - m sends V * w_m to p
+#pragma unroll
+      for (int m = -1; m <= 2; ++m) {
+        const T w = wv[m + 1];
+        gu += w * (at(8, i - m, j) + at(9, i, j - m));
+        gv += w * (at(10, i - m, j) + at(11, i, j - m));
+      }
     }
     if (ph.mask & LDSV_FORCING) {
       T lu = (T)aA * Au[off + c], lv = (T)aA * Av[off + c];
@@ -404,7 +479,7 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
               float* gcoef, size_t gcbs, const void* us, const void* vs, const void* Au,
               const void* Av, const void* Gu, const void* Gv, double aA, double aG,
               const void* addu, const void* addv, void* ou, void* ov, hipStream_t st,
-              const FluxBlockArgs* fbp) {
+              const FluxBlockArgs* fbp, const DerivCoef* dc) {
   AdjPhys ph{prm->nu, prm->drag, h->g.lx / h->g.nx, h->g.ly / h->g.ny, prm->physics_mask};
   const int nx = h->g.nx, ny = h->g.ny;
   dim3 grid((unsigned)std::min<size_t>((h->ncell + kBlock - 1) / kBlock, 4096), h->g.batch);
@@ -414,8 +489,8 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
   if (fbp && fbp->w) {
     LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 2>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
-                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, fb, scr,
-                       ph, nx, ny);
+                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0,
+                       (const float*)nullptr, (float*)nullptr, fb, scr, ph, nx, ny);
     if (fbp->gw) {
       int tx, ty;
       fb_wgrad_tile(nx, ny, &tx, &ty);
@@ -426,24 +501,34 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
                          tiles * h->g.batch, fbp->gw);
     }
     LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 2>), grid, dim3(kBlock), 0, st, (const T*)scr,
-                       (const float*)nullptr, (size_t)0, fbp->w, (const T*)Au, (const T*)Av,
+                       (const float*)nullptr, (size_t)0, (const float*)nullptr, fbp->w, (const T*)Au, (const T*)Av,
+                       (const T*)Gu, (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv,
+                       (T*)ou, (T*)ov, ph, nx, ny);
+  } else if (coef && dc && dc->d) {
+    LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 3>), grid, dim3(kBlock), 0, st, (const T*)us,
+                       (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
+                       aG, coef, cbs, gcoef, gcbs, dc->d, dc->gd, fb, scr, ph, nx, ny);
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 3>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
+                       cbs, dc->d, (const float*)nullptr, (const T*)Au, (const T*)Av,
                        (const T*)Gu, (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv,
                        (T*)ou, (T*)ov, ph, nx, ny);
   } else if (coef) {
     LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 1>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
-                       aG, coef, cbs, gcoef, gcbs, fb, scr, ph, nx, ny);
+                       aG, coef, cbs, gcoef, gcbs, (const float*)nullptr, (float*)nullptr, fb,
+                       scr, ph, nx, ny);
     LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 1>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
-                       cbs, (const float*)nullptr, (const T*)Au, (const T*)Av, (const T*)Gu,
+                       cbs, (const float*)nullptr, (const float*)nullptr, (const T*)Au, (const T*)Av, (const T*)Gu,
                        (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph,
                        nx, ny);
   } else {
     LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 0>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
-                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0, fb, scr,
-                       ph, nx, ny);
+                       aG, (const float*)nullptr, (size_t)0, (float*)nullptr, (size_t)0,
+                       (const float*)nullptr, (float*)nullptr, fb, scr, ph, nx, ny);
     LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 0>), grid, dim3(kBlock), 0, st, (const T*)scr,
-                       (const float*)nullptr, (size_t)0, (const float*)nullptr, (const T*)Au,
+                       (const float*)nullptr, (size_t)0, (const float*)nullptr,
+                       (const float*)nullptr, (const T*)Au,
                        (const T*)Av, (const T*)Gu, (const T*)Gv, aA, aG, (const T*)addu,
                        (const T*)addv, (T*)ou, (T*)ov, ph, nx, ny);
   }
@@ -462,7 +547,7 @@ int ldsv_ensure_adjoint(ldsv_handle* h) {
   }
   if (h->adj_g) return LDSV_OK;
   const size_t sb = h->nstate * h->esize;
-  // 6 stage planes (u1..u3), A, S, W, G (2 planes each) and 16 scratch planes
+  // 6 stage planes (u1..u3), A, S, W, G (2 planes each) and the scratch planes
   void* blk = nullptr;
   LDSV_TRY(ldsv_alloc(h, &blk, (6 + 8 + kAdjPlanes) * sb, "adjoint workspace"));
   h->stage_keep = blk;
@@ -476,12 +561,12 @@ int ldsv_launch_adj_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coe
                         float* gcoef, size_t gcbs, const void* us, const void* vs, const void* Au,
                         const void* Av, const void* Gu, const void* Gv, double aA, double aG,
                         const void* addu, const void* addv, void* ou, void* ov, hipStream_t st,
-                        const FluxBlockArgs* fb) {
+                        const FluxBlockArgs* fb, const DerivCoef* dc) {
   if (h->g.dtype == LDSV_F64)
     return adj_rhs_t<double>(h, prm, coef, cbs, gcoef, gcbs, us, vs, Au, Av, Gu, Gv, aA, aG, addu,
-                             addv, ou, ov, st, fb);
+                             addv, ou, ov, st, fb, dc);
   return adj_rhs_t<float>(h, prm, coef, cbs, gcoef, gcbs, us, vs, Au, Av, Gu, Gv, aA, aG, addu,
-                          addv, ou, ov, st, fb);
+                          addv, ou, ov, st, fb, dc);
 }
 
 int ldsv_launch_axpy2(ldsv_handle* h, void* yu, void* yv, const void* xu, const void* xv, double a,

@@ -106,7 +106,7 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
              const void* sv, void* du, void* dv, const float* tcu, const float* tcv, size_t tcbs,
              hipStream_t st, void* keep = nullptr, const uint16_t* coef16 = nullptr,
              size_t cbs16 = 0, const FluxBlockArgs* fb = nullptr,
-             const ScalarStep* sc = nullptr) {
+             const ScalarStep* sc = nullptr, const DerivCoef* dc = nullptr) {
   const size_t sbk = h->nstate * h->esize;
   auto ku = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s) * sbk : h->ws_u; };
   auto kv = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s + 1) * sbk : h->ws_v; };
@@ -117,6 +117,10 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
   a.coef_bstride = cbs;
   a.coef16 = coef16;
   a.coef16_bstride = cbs16;
+  if (dc) {
+    a.dcoef = coef ? dc->d : nullptr;
+    a.dcoef16 = coef16 ? dc->d16 : nullptr;
+  }
   if (fb) {
     a.fbw = fb->w;
     a.fbf = fb->f;
@@ -225,6 +229,16 @@ int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* c
   return one_step(h, p, nullptr, 0, su, sv, du, dv, tcu, tcv, tcbs, st, nullptr, coef16, cbs16);
 }
 
+// the same with per-cell learned derivative values beside the coefficients
+// (float planes with coef, bf16 planes with coef16; the same strides)
+int ldsv_internal_step_d(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
+                         const uint16_t* coef16, size_t cbs16, const DerivCoef* dc,
+                         const void* su, const void* sv, void* du, void* dv, const float* tcu,
+                         const float* tcv, size_t tcbs, hipStream_t st) {
+  return one_step(h, p, coef16 ? nullptr : coef, coef16 ? 0 : cbs, su, sv, du, dv, tcu, tcv, tcbs,
+                  st, nullptr, coef16, cbs16, nullptr, nullptr, dc);
+}
+
 // the same with the flux block's uniform kernels and fields, and an
 // optional temporal correction (tcu, tcv, batch stride tcbs) added before
 // the last projection
@@ -249,7 +263,7 @@ int ldsv_internal_step_scalar(ldsv_handle* h, const ldsv_params* p, double diff,
 int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t cbs,
                   float* gcoef, size_t gcbs, const void* su, const void* sv, const void* gu_out,
                   const void* gv_out, void* gu_in, void* gv_in, hipStream_t st,
-                  const FluxBlockArgs* fb) {
+                  const FluxBlockArgs* fb, const DerivCoef* dc) {
   LDSV_REQUIRE(h->g.layout == LDSV_MAC && prm->rk == LDSV_RK4, LDSV_EDTYPE,
                "adjoint: RK4 on the MAC layout only");
   LDSV_TRY(ldsv_ensure_adjoint(h));
@@ -262,7 +276,7 @@ int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, siz
   const double dt = prm->dt;
   // forward recompute keeping u1, u2, u3 (the output goes to W, unused)
   LDSV_TRY(one_step(h, prm, coef, cbs, su, sv, W, W + sb, nullptr, nullptr, 0, st, K, nullptr, 0,
-                    fb));
+                    fb, nullptr, dc));
   // A = P g, S = A
   LDSV_TRY(ldsv_launch_project(h, gu_out, gv_out, A, A + sb, nullptr, st));
   LDSV_HIP(hipMemcpyAsync(S, A, 2 * sb, hipMemcpyDeviceToDevice, st));
@@ -274,13 +288,13 @@ int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, siz
     LDSV_TRY(ldsv_launch_adj_rhs(h, prm, coef, cbs, gcoef, gcbs, K + 2 * s * sb,
                                  K + (2 * s + 1) * sb, A, A + sb, k ? G : nullptr,
                                  k ? G + sb : nullptr, aA[k], aG[k], nullptr, nullptr, W, W + sb,
-                                 st, fb));
+                                 st, fb, dc));
     LDSV_TRY(ldsv_launch_project(h, W, W + sb, G, G + sb, nullptr, st));
     LDSV_TRY(ldsv_launch_axpy2(h, S, S + sb, G, G + sb, 1.0, st));
   }
   // stage 1: dL/du0 = S + J(u0)^T (dt/6 A + dt/2 g1)
   return ldsv_launch_adj_rhs(h, prm, coef, cbs, gcoef, gcbs, su, sv, A, A + sb, G, G + sb,
-                             dt / 6.0, 0.5 * dt, S, S + sb, gu_in, gv_in, st, fb);
+                             dt / 6.0, 0.5 * dt, S, S + sb, gu_in, gv_in, st, fb, dc);
 }
 
 extern "C" {

@@ -108,6 +108,12 @@ struct ldsv_handle {
   uint16_t* coef16 = nullptr;    // bf16 stencil coefficients [B][64][Ny][Nx] (inference)
   float* tcbuf = nullptr;        // temporal correction [B][2][Ny][Nx] (inference)
   float* gnet = nullptr;         // [B][66][Ny][Nx] gradient of network output
+  // the derivative-stencil network (allocated on first use): its output in
+  // the same two forms, its unused correction planes, its output gradient
+  float* dnetout = nullptr;      // [B][66][Ny][Nx]
+  uint16_t* dcoef16 = nullptr;   // [B][64][Ny][Nx]
+  float* dtcbuf = nullptr;       // [B][2][Ny][Nx]
+  float* gdnet = nullptr;        // [B][66][Ny][Nx]
   float* gact = nullptr;         // [B][Ny][Nx][64] float gradient buffers
   float* gact2 = nullptr;
   void* stage_keep = nullptr;    // forward stage states for the adjoint (4 x 2 x state)

@@ -23,6 +23,10 @@ struct StageArgs {
   size_t coef_bstride = 0;      // elements between trajectories
   const uint16_t* coef16 = nullptr;  // the same as bf16 planes (used when set)
   size_t coef16_bstride = 0;
+  // per-cell learned derivative values, raw, with the layout and batch
+  // stride of coef (dcoef) or coef16 (dcoef16); used only together with them
+  const float* dcoef = nullptr;
+  const uint16_t* dcoef16 = nullptr;
   const float* tcu = nullptr;   // temporal correction added to out, nullable
   const float* tcv = nullptr;
   size_t tc_bstride = 0;
@@ -46,6 +50,20 @@ struct FluxBlockArgs {
   float* gw = nullptr;
   float* gf = nullptr;
   size_t gfbs = 0;
+};
+
+// Per-cell learned derivative stencils (Sec. 3.4, the m = d operator in
+// per-cell form): raw values r [B][64][Ny][Nx] (channel 16K + s), float (d)
+// or bf16 planes (d16), with the batch stride of the interpolation
+// coefficients they accompany.  Per kind and cell the weights are
+//   w = w_P + r - mean(r) - x (x . r)/16 - b (b . r)/24
+// (x_s = a_s - 1/2 along the face normal, b_s across, w_P the fourth-order
+// kernel), and the face derivative is (1/h) sum_s w_s q_s.  The adjoint
+// accumulates dL/dr into gd (float, nullable, the gradient batch stride).
+struct DerivCoef {
+  const float* d = nullptr;
+  const uint16_t* d16 = nullptr;
+  float* gd = nullptr;
 };
 
 int ldsv_launch_stage(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a,

@@ -26,6 +26,8 @@
 // momentum is conserved), then forms R per cell and the RK combination in
 // registers.  HBM traffic per cell: one read of the stage state, the base
 // state and the accumulator as needed, one write of the outputs.
+#include <type_traits>
+
 #include "stage.h"
 
 namespace {
@@ -81,6 +83,8 @@ struct StagePtrs {
   size_t cbs;
   const uint16_t* coef16;
   size_t cbs16;
+  const float* dcoef;
+  const uint16_t* dcoef16;
   const float* tcu;
   const float* tcv;
   size_t tcbs;
@@ -119,6 +123,37 @@ __device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const
   return acc + (T)0.5 * (q0 + q1);
 }
 
+// learned face derivative (units of 1/h) at a face: the raw values r of kind
+// K projected onto zero sum, unit normal and zero across first moment around
+// the fourth-order kernel, w = w_P + r - mean(r) - x (x.r)/16 - b (b.r)/24,
+// applied to the 16 footprint values: sum r q - mean(r) sum q - (x.r)/16
+// sum x q - (b.r)/24 sum b q + the fourth-order part
+template <typename T, bool ALONG_X, int W, typename CT>
+__device__ __forceinline__ T learned_dface(const T (*S)[W], int lj, int li, const CT* cb, int kind,
+                                           size_t plane, size_t off) {
+  T rq = 0, sr = 0, sxr = 0, sbr = 0, sq = 0, sxq = 0, sbq = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const T r = (T)coef_value(cb + (size_t)(16 * kind + s) * plane + off);
+    const int a = a_off20(s), bb = b_off20(s);
+    const T q = ALONG_X ? S[lj + bb][li + a] : S[lj + a][li + bb];
+    const T x = (T)a - (T)0.5;
+    rq += r * q;
+    sr += r;
+    sxr += x * r;
+    sbr += (T)bb * r;
+    sq += q;
+    sxq += x * q;
+    sbq += (T)bb * q;
+  }
+  const T qm1 = ALONG_X ? S[lj][li - 1] : S[lj - 1][li];
+  const T q0 = S[lj][li];
+  const T q1 = ALONG_X ? S[lj][li + 1] : S[lj + 1][li];
+  const T q2 = ALONG_X ? S[lj][li + 2] : S[lj + 2][li];
+  return rq - sr * sq * (T)(1.0 / 16.0) - sxr * sxq * (T)(1.0 / 16.0) -
+         sbr * sbq * (T)(1.0 / 24.0) + (qm1 - (T)27 * q0 + (T)27 * q1 - q2) * (T)(1.0 / 24.0);
+}
+
 // uniform 5x4 kernel w (20 weights) at the face owned by tile point (lj, li)
 template <typename T, bool ALONG_X, int W>
 __device__ __forceinline__ T uniform_face(const T (*S)[W], int lj, int li, const float* w) {
@@ -136,7 +171,8 @@ __device__ __forceinline__ float fb_field(const float* f, size_t plane, int ch, 
 }
 
 // COEF: 0 plain stencil, 1 float raw coefficients, 2 bf16 raw coefficients,
-// 3 flux block (uniform kernels and fields)
+// 3 flux block (uniform kernels and fields), 4 and 5: as 1 and 2 plus the
+// learned derivative values in the same form
 template <typename T, int COEF, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny) {
@@ -218,8 +254,12 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   const bool visc = ph.mask & LDSV_VISCOSITY;
   const T nu = ph.nu;
   const T i24dx = ph.i24dx, i24dy = ph.i24dy;
-  const float* cbf = COEF == 1 ? p.coef + (size_t)b * p.cbs : nullptr;
-  const uint16_t* cbh = COEF == 2 ? p.coef16 + (size_t)b * p.cbs16 : nullptr;
+  constexpr int IC = COEF == 4 ? 1 : (COEF == 5 ? 2 : COEF);  // interpolation form
+  constexpr bool LD = COEF >= 4;                                 // learned derivatives
+  const float* cbf = IC == 1 ? p.coef + (size_t)b * p.cbs : nullptr;
+  const uint16_t* cbh = IC == 2 ? p.coef16 + (size_t)b * p.cbs16 : nullptr;
+  const float* dbf = COEF == 4 ? p.dcoef + (size_t)b * p.cbs : nullptr;
+  const uint16_t* dbh = COEF == 5 ? p.dcoef16 + (size_t)b * p.cbs16 : nullptr;
   const float* fbf = COEF == 3 && p.fbf ? p.fbf + (size_t)b * p.fbs : nullptr;
 
   // x-faces: owners i in [i0-1, i0+TX-1], rows j in [j0, j0+TY-1]
@@ -244,7 +284,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       } else if constexpr (COEF != 0) {
         const int gi = (i0 - 1 + c + nx) & (nx - 1);
         const size_t off = (size_t)(j0 + r) * nx + gi;
-        if constexpr (COEF == 1) {
+        if constexpr (IC == 1) {
           uf = learned_face<T, true, W>(su, lj, li, cbf, 0, plane, off);
           vf = learned_face<T, true, W>(sv, lj, li, cbf, 2, plane, off);
         } else {
@@ -268,6 +308,14 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
                      (T)fb_field(fbf, plane, 6, xoff);
         fu -= nu * du;
         fv -= nu * dv;
+      } else if constexpr (LD) {
+        if constexpr (COEF == 4) {
+          fu -= nu * learned_dface<T, true, W>(su, lj, li, dbf, 0, plane, xoff) * ph.idx;
+          fv -= nu * learned_dface<T, true, W>(sv, lj, li, dbf, 2, plane, xoff) * ph.idx;
+        } else {
+          fu -= nu * learned_dface<T, true, W>(su, lj, li, dbh, 0, plane, xoff) * ph.idx;
+          fv -= nu * learned_dface<T, true, W>(sv, lj, li, dbh, 2, plane, xoff) * ph.idx;
+        }
       } else {
         fu -= nu * (su[lj][li - 1] - (T)27 * su[lj][li] + (T)27 * su[lj][li + 1] - su[lj][li + 2]) * i24dx;
         fv -= nu * (sv[lj][li - 1] - (T)27 * sv[lj][li] + (T)27 * sv[lj][li + 1] - sv[lj][li + 2]) * i24dx;
@@ -298,7 +346,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       } else if constexpr (COEF != 0) {
         const int gj = (j0 - 1 + r + ny) & (ny - 1);
         const size_t off = (size_t)gj * nx + (i0 + c);
-        if constexpr (COEF == 1) {
+        if constexpr (IC == 1) {
           uf = learned_face<T, false, W>(su, lj, li, cbf, 1, plane, off);
           vf = learned_face<T, false, W>(sv, lj, li, cbf, 3, plane, off);
         } else {
@@ -322,6 +370,14 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
                      (T)fb_field(fbf, plane, 7, yoff);
         fu -= nu * du;
         fv -= nu * dv;
+      } else if constexpr (LD) {
+        if constexpr (COEF == 4) {
+          fu -= nu * learned_dface<T, false, W>(su, lj, li, dbf, 1, plane, yoff) * ph.idy;
+          fv -= nu * learned_dface<T, false, W>(sv, lj, li, dbf, 3, plane, yoff) * ph.idy;
+        } else {
+          fu -= nu * learned_dface<T, false, W>(su, lj, li, dbh, 1, plane, yoff) * ph.idy;
+          fv -= nu * learned_dface<T, false, W>(sv, lj, li, dbh, 3, plane, yoff) * ph.idy;
+        }
       } else {
         fu -= nu * (su[lj - 1][li] - (T)27 * su[lj][li] + (T)27 * su[lj + 1][li] - su[lj + 2][li]) * i24dy;
         fv -= nu * (sv[lj - 1][li] - (T)27 * sv[lj][li] + (T)27 * sv[lj + 1][li] - sv[lj + 2][li]) * i24dy;
@@ -477,6 +533,20 @@ __global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, PhysT<T> p
   }
 }
 
+// the learned-derivative stage modes exist for FP32 states only (the
+// learned path's precision)
+template <typename T, int COEF, int TX, int TY>
+int launch_learned_d(ldsv_handle* h, dim3 grid, hipStream_t st, const StagePtrs<T>& p,
+                     const PhysT<T>& ph, const CombT<T>& cb, int nx, int ny) {
+  if constexpr (std::is_same<T, float>::value) {
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, COEF, TX, TY>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny);
+    return LDSV_OK;
+  } else {
+    ldsv_set_error("stage: learned derivative stencils need FP32 states");
+    return LDSV_EDTYPE;
+  }
+}
+
 template <typename T>
 int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, hipStream_t st) {
   StagePtrs<T> p;
@@ -494,6 +564,8 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   p.cbs = a.coef_bstride;
   p.coef16 = a.coef16;
   p.cbs16 = a.coef16_bstride;
+  p.dcoef = a.dcoef;
+  p.dcoef16 = a.dcoef16;
   p.tcu = a.tcu;
   p.tcv = a.tcv;
   p.tcbs = a.tc_bstride;
@@ -532,9 +604,13 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
     if (a.fbw)                                                                                    \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 3, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
+    else if (a.coef16 && a.dcoef16)                                                               \
+      LDSV_TRY((launch_learned_d<T, 5, tx, ty>(h, grid, st, p, ph, cb, nx, ny)));                 \
     else if (a.coef16)                                                                            \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 2, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
+    else if (a.coef && a.dcoef)                                                                   \
+      LDSV_TRY((launch_learned_d<T, 4, tx, ty>(h, grid, st, p, ph, cb, nx, ny)));                 \
     else if (a.coef)                                                                              \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 1, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \

@@ -120,6 +120,19 @@ _SIGS = {
                                   _vp, _vp, _vp, _vp, ctypes.POINTER(NetGrad), _vp], _i),
     "ldsv_rollout_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), _vp, _vp, _i, _i, _i,
                           _vp, _vp, _d, _vp, _vp, _vp, _vp, ctypes.POINTER(NetGrad), _vp, _vp], _i),
+    "ldsv_fv_step_d": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp], _i),
+    "ldsv_fv_step_d_bwd": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _vp, _vp], _i),
+    "ldsv_learned_d_fv_step": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net),
+                                ctypes.POINTER(Net), _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp], _i),
+    "ldsv_learned_d_fv_step_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net),
+                                    ctypes.POINTER(Net), _vp, _vp, _i, _vp, _vp, _vp, _vp,
+                                    ctypes.POINTER(NetGrad), ctypes.POINTER(NetGrad), _vp], _i),
+    "ldsv_rollout_d": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), ctypes.POINTER(Net),
+                        _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "ldsv_rollout_d_bwd": ([_vp, ctypes.POINTER(Params), ctypes.POINTER(Net), ctypes.POINTER(Net),
+                            _vp, _vp, _i, _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp,
+                            ctypes.POINTER(NetGrad), ctypes.POINTER(NetGrad), _vp, _vp], _i),
     "ldsv_mse_grad": ([_vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp], _i),
     "ldsv_adam_step": ([_vp, _vp, _vp, _vp, _sz, _i, _d, _d, _d, _d, _vp], _i),
     "ldsv_to_bf16": ([_vp, _vp, _sz, _vp], _i),
@@ -350,6 +363,79 @@ class Solver:
                                      first_index, _ptr(lu), _ptr(lv), loss_scale, _ptr(gtu),
                                      _ptr(gtv), _ptr(gu), _ptr(gv), ctypes.byref(dW.c), _ptr(loss),
                                      _stream()))
+        return (gu, gv) if want_input_grad else None
+
+    # ---- learned derivative stencils (per cell; a second network dnet) ----
+
+    def fv_step_d(self, prm, u, v, coef, dcoef, nsteps=1, out=None):
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        _check(_lib.ldsv_fv_step_d(self._h, ctypes.byref(prm), self._coef(coef), self._coef(dcoef),
+                                   self._state(u), self._state(v), self._state(uo),
+                                   self._state(vo), nsteps, _stream()))
+        return uo, vo
+
+    def fv_step_d_bwd(self, prm, u, v, gu_out, gv_out, coef, dcoef, gcoef=None, gdcoef=None):
+        gu, gv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_fv_step_d_bwd(self._h, ctypes.byref(prm), self._coef(coef),
+                                       self._coef(dcoef), self._state(u), self._state(v),
+                                       self._state(gu_out), self._state(gv_out), _ptr(gu),
+                                       _ptr(gv), self._coef(gcoef), self._coef(gdcoef),
+                                       _stream()))
+        return gu, gv
+
+    def learned_d_fv_step(self, prm, net, dnet, u, v, step_index, want_net_out=False, out=None):
+        uo, vo = (self.new_state(), self.new_state()) if out is None else out
+        no = dno = None
+        if want_net_out:
+            no = torch.empty(self.batch, NOUT, self.ny, self.nx, dtype=torch.float32,
+                             device="cuda")
+            dno = torch.empty_like(no)
+        _check(_lib.ldsv_learned_d_fv_step(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                           ctypes.byref(dnet.c), self._state(u), self._state(v),
+                                           self._state(uo), self._state(vo), step_index, _ptr(no),
+                                           _ptr(dno), _stream()))
+        return (uo, vo, no, dno) if want_net_out else (uo, vo)
+
+    def learned_d_fv_step_bwd(self, prm, net, dnet, u, v, step_index, gu_out, gv_out, dW, dWd):
+        gu, gv = self.new_state(), self.new_state()
+        _check(_lib.ldsv_learned_d_fv_step_bwd(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                               ctypes.byref(dnet.c), self._state(u),
+                                               self._state(v), step_index, self._state(gu_out),
+                                               self._state(gv_out), _ptr(gu), _ptr(gv),
+                                               ctypes.byref(dW.c), ctypes.byref(dWd.c),
+                                               _stream()))
+        return gu, gv
+
+    def rollout_d(self, prm, net, dnet, u0, v0, nsteps, save_every=1, first_index=1,
+                  fallback_flags=None):
+        T = nsteps // save_every
+        tu = torch.empty(T, self.batch, self.ny, self.nx, dtype=self.dtype, device="cuda")
+        tv = torch.empty_like(tu)
+        _check(_lib.ldsv_rollout_d(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                   ctypes.byref(dnet.c), self._state(u0), self._state(v0), nsteps,
+                                   save_every, first_index, _ptr(tu), _ptr(tv),
+                                   _ptr(fallback_flags), _stream()))
+        return tu, tv
+
+    def rollout_d_bwd(self, prm, net, dnet, u0, v0, nsteps, dW, dWd, checkpoint_every=8,
+                      first_index=1, labels=None, loss_scale=1.0, g_traj=None,
+                      want_input_grad=False, loss=None):
+        lu = lv = gtu = gtv = None
+        if labels is not None:
+            lu, lv = labels
+            for t in (lu, lv):
+                if tuple(t.shape) != (nsteps, self.batch, self.ny, self.nx) or not t.is_contiguous():
+                    raise ValueError("labels must be contiguous [nsteps, B, Ny, Nx]")
+        if g_traj is not None:
+            gtu, gtv = g_traj
+        gu = self.new_state() if want_input_grad else None
+        gv = self.new_state() if want_input_grad else None
+        _check(_lib.ldsv_rollout_d_bwd(self._h, ctypes.byref(prm), ctypes.byref(net.c),
+                                       ctypes.byref(dnet.c), self._state(u0), self._state(v0),
+                                       nsteps, checkpoint_every, first_index, _ptr(lu), _ptr(lv),
+                                       loss_scale, _ptr(gtu), _ptr(gtv), _ptr(gu), _ptr(gv),
+                                       ctypes.byref(dW.c), ctypes.byref(dWd.c), _ptr(loss),
+                                       _stream()))
         return (gu, gv) if want_input_grad else None
 
     def mse_grad(self, u, v, lu, lv, scale=1.0, loss=None, want_grad=True):

@@ -96,17 +96,21 @@ class Adam:
 
 
 def train(solver, net, labels, prm, iters, unroll=32, checkpoint_every=8, lr=1e-4, seed=0,
-          batch_from=None, progress=None, log_every=10, windows=1):
+          batch_from=None, progress=None, log_every=10, windows=1, dnet=None):
     """Adam on the unrolled rollout MSE.  labels: (lu, lv) [T+1, B, n, n].
     Each iteration draws `windows` random start times t0 and unrolls `unroll`
     learned steps from labels[t0] for every trajectory of every window at
-    once; the solver's batch is windows * B.  Returns the loss history."""
+    once; the solver's batch is windows * B.  dnet: optional
+    derivative-stencil network trained beside net.  Returns the loss
+    history."""
     lu, lv = labels
     T = lu.shape[0] - 1
     assert solver.batch == windows * lu.shape[1], "solver batch must be windows * label batch"
     g = torch.Generator().manual_seed(seed)
     opt = Adam(net, lr=lr)
     dW = ldsv.NetGradBuffers(net)
+    dopt = Adam(dnet, lr=lr) if dnet is not None else None
+    dWd = ldsv.NetGradBuffers(dnet) if dnet is not None else None
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     hist = []
     t_start = time.perf_counter()
@@ -118,8 +122,16 @@ def train(solver, net, labels, prm, iters, unroll=32, checkpoint_every=8, lr=1e-
         yv = torch.cat([lv[t + 1:t + 1 + unroll] for t in t0s], dim=1).contiguous()
         dW.zero_()
         loss.zero_()
-        solver.rollout_bwd(prm, net, u0, v0, unroll, dW, checkpoint_every=checkpoint_every,
-                           first_index=1, labels=(yu, yv), loss_scale=1.0 / unroll, loss=loss)
+        if dnet is None:
+            solver.rollout_bwd(prm, net, u0, v0, unroll, dW, checkpoint_every=checkpoint_every,
+                               first_index=1, labels=(yu, yv), loss_scale=1.0 / unroll,
+                               loss=loss)
+        else:
+            dWd.zero_()
+            solver.rollout_d_bwd(prm, net, dnet, u0, v0, unroll, dW, dWd,
+                                 checkpoint_every=checkpoint_every, first_index=1,
+                                 labels=(yu, yv), loss_scale=1.0 / unroll, loss=loss)
+            dopt.step(dWd)
         opt.step(dW)
         if (it + 1) % log_every == 0 or it == 0:
             l = loss.item()
@@ -256,7 +268,7 @@ def first_drop(pcc, dt, threshold=0.9):
     return res
 
 
-def evaluate(solver, prm, labels, nsteps, net=None):
+def evaluate(solver, prm, labels, nsteps, net=None, dnet=None):
     """Rollout from labels[0] (plain FV if net is None) and compare with
     labels[1..nsteps]: returns dict with pcc [T, B], T_0.9 per trajectory,
     MSE per snapshot and wall time."""
@@ -269,8 +281,12 @@ def evaluate(solver, prm, labels, nsteps, net=None):
                         forcing_k=prm.forcing_k, drag=prm.drag, rk=prm.rk,
                         mask=prm.physics_mask, k_c=prm.k_c, fallback_enable=1)
     flags = torch.zeros(solver.batch, dtype=torch.int32, device="cuda")
-    tu, tv = solver.rollout(p, lu[0].contiguous(), lv[0].contiguous(), nsteps, 1, net=net,
-                            fallback_flags=flags if net is not None else None)
+    if dnet is not None:
+        tu, tv = solver.rollout_d(p, net, dnet, lu[0].contiguous(), lv[0].contiguous(), nsteps,
+                                  1, fallback_flags=flags)
+    else:
+        tu, tv = solver.rollout(p, lu[0].contiguous(), lv[0].contiguous(), nsteps, 1, net=net,
+                                fallback_flags=flags if net is not None else None)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ref = (lu[1:nsteps + 1], lv[1:nsteps + 1])
@@ -313,23 +329,27 @@ def plain_sweep_pcc(N, n, ic, labels, dt_coarse, phys, horizon, lx=2 * math.pi):
     return pcc, wall
 
 
-def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi):
+def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi, dnet=None):
     """(cell-steps/s, sim-time/s per trajectory, ms/step) of the plain or
-    learned step at N x N, batch B, on device-resident state."""
+    learned step (with the derivative-stencil network when dnet is given) at
+    N x N, batch B, on device-resident state."""
     s = ldsv.Solver(N, N, B, lx=lx, ly=lx)
     u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=7)
-    for k in range(warmup):
+
+    def one(k):
         if net is None:
             s.fv_step(prm, u, v, out=(u, v))
-        else:
+        elif dnet is None:
             s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+        else:
+            s.learned_d_fv_step(prm, net, dnet, u, v, k + 1, out=(u, v))
+
+    for k in range(warmup):
+        one(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        if net is None:
-            s.fv_step(prm, u, v, out=(u, v))
-        else:
-            s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
+        one(k)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     s.close()
