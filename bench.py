@@ -150,6 +150,14 @@ def fp64_errors():
     eu, ev, eo = olearned.learned_fv_step(u0, v0, prm, wb, bb, 1, bf16=False)
     out["learned_step_rel_l2_vs_fp64"] = max(_rel_l2(uo[:1], eu), _rel_l2(vo[:1], ev))
     out["network_output_rel_l2_vs_fp64"] = _rel_l2(no[:1], eo)
+    # with the derivative-stencil network beside it (trajectory 0)
+    dws, dbs = si.cnn_weights(1, ocnn.LAYERS)
+    dnet = ldsv.NetParams([torch.tensor(x) for x in dws], [torch.tensor(x) for x in dbs])
+    du, dv = s.learned_d_fv_step(ldsv.params(k_c=1, **kw), net, dnet, u, v, 1)
+    dwb = [x.double().cpu() for x in dnet.bf16_weights()]
+    dbb = [x.double().cpu() for x in dnet.b]
+    eu, ev, _ = olearned.learned_fv_step(u0, v0, prm, wb, bb, 1, bf16=False, dnet=(dwb, dbb))
+    out["learned_deriv_step_rel_l2_vs_fp64"] = max(_rel_l2(du[:1], eu), _rel_l2(dv[:1], ev))
     # the flux-block model step of the same workload (trajectory 0)
     from oracle import fluxblock as ofb, fno as ofno
     fnet, (fw, a_i, a_d) = _fluxblock_net("forced", ldsv)
@@ -220,6 +228,66 @@ def learned_block(steps, warmup):
         out["mfma_conv"] = {"tflops": flop / launches_per_step / (per_launch_ms * 1e-3) / 1e12,
                             "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}
         out["mfma_conv"]["frac"] = out["mfma_conv"]["tflops"] / BF16_PEAK_TFLOPS
+    return out
+
+
+def learned_deriv_block(steps, warmup):
+    """The learned step with per-cell learned derivative stencils (the m = d
+    operator in per-cell form, Sec. 3.4): a second network of the same shape
+    beside the coefficient network, on the forced 64^2 workload (batch 64).
+    The stage kernel then reads 64 BF16 interpolation and 64 BF16 derivative
+    values per cell: 256 B/cell on top of the plain stage's 34 B/cell (and
+    the correction's 8 B/cell in the last stage, 2 B/cell averaged)."""
+    import torch
+    import synthetic_inputs as si
+    from oracle import cnn as ocnn
+    from paper_2507_01975_amd import ldsv
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    s = ldsv.Solver(n, n, B)
+    nets = []
+    for seed in (0, 1):
+        ws, bs = si.cnn_weights(seed, ocnn.LAYERS)
+        nets.append(ldsv.NetParams([torch.tensor(x) for x in ws], [torch.tensor(x) for x in bs]))
+    net, dnet = nets
+    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
+    prm = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                      forcing_k=w["forcing_k"], drag=w["drag"], k_c=1)
+    for k in range(warmup):
+        s.learned_d_fv_step(prm, net, dnet, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.learned_d_fv_step(prm, net, dnet, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.timer_enable(True)
+    for k in range(steps):
+        s.learned_d_fv_step(prm, net, dnet, u, v, k + 1, out=(u, v))
+    torch.cuda.synchronize()
+    st_ms, st_n = s.timer_read(ldsv.TIMER_STAGE)
+    conv_ms, conv_n = s.timer_read(ldsv.TIMER_CONV)
+    s.timer_enable(False)
+    diag = s.diagnostics(u, v).cpu()
+    cells = n * n * B
+    out = {"workload": "kolmogorov64 learned step with learned derivative stencils (64^2, "
+                       "batch 64, two 6-layer 64-channel BF16 CNNs)",
+           "cell_steps_per_s": cells * steps / t, "ms_per_step": 1e3 * t / steps,
+           "sim_time_per_s": w["dt"] * steps / t, "finite": bool((diag[:, 5] == 1).all())}
+    if st_n:
+        alg = (34 + 256 + 2) * cells
+        us = 1e3 * st_ms / st_n
+        out["stage_hbm"] = {"kernel": "k_stage_mac<float, 5, ...> (fused residual + RK stage)", "avg_launch_us": us,
+                            "alg_bytes_per_launch": alg, "achieved": alg / (us * 1e-6) / 1e9,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        out["stage_hbm"]["frac"] = out["stage_hbm"]["achieved"] / HBM_PEAK_GBS
+    if conv_n:
+        flop = 2 * 2 * 9 * 64 * (64 * 4 + 66) * cells
+        per_launch_ms = conv_ms / conv_n
+        out["mfma_conv"] = {"tflops": flop / (conv_n / steps) / (per_launch_ms * 1e-3) / 1e12,
+                            "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}
+        out["mfma_conv"]["frac"] = out["mfma_conv"]["tflops"] / BF16_PEAK_TFLOPS
+    s.close()
     return out
 
 
@@ -554,7 +622,8 @@ def main():
         log("copy probe: %d MiB" % a.copy_probe_mib)
         del src, dst
     if a.learned_only:
-        print(json.dumps({"learned": learned_block(a.steps, a.warmup)}), flush=True)
+        print(json.dumps({"learned": learned_block(a.steps, a.warmup),
+                          "learned_deriv": learned_deriv_block(a.steps, a.warmup)}), flush=True)
         return
     if a.fluxblock_only:
         print(json.dumps({"fluxblock": fluxblock_block(a.steps, a.warmup),
@@ -621,6 +690,8 @@ def main():
     if not a.no_learned:
         log("learned step")
         line["learned"] = learned_block(max(10, a.steps // 4), 3)
+        log("learned step with learned derivative stencils")
+        line["learned_deriv"] = learned_deriv_block(max(10, a.steps // 4), 3)
         log("flux-block step")
         line["fluxblock"] = fluxblock_block(max(10, a.steps // 4), 3)
     if not a.no_extra:

@@ -589,15 +589,28 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   CombT<T> cb{(T)a.alpha, (T)a.beta, (T)a.delta, (T)a.eps, (T)a.gamma, (T)a.wacc,
               a.alpha != 0.0, a.delta != 0.0 || a.gamma != 0.0};
   const int nx = h->g.nx, ny = h->g.ny;
-  const int TX = nx < kMaxTX ? nx : kMaxTX;
   if (h->g.layout == LDSV_COLLOCATED) {
+    const int TX = nx < kMaxTX ? nx : kMaxTX;
     const int TYc = ny < kMaxTYc ? ny : kMaxTYc;
     dim3 gridc((nx / TX) * (ny / TYc), h->g.batch);
     LDSV_TLAUNCH(h, 0, k_stage_col<T>, gridc, dim3(kBlock), 0, st, p, ph, cb, nx, ny, TX, TYc);
     LDSV_LAUNCHED();
     return LDSV_OK;
   }
-  const int TY = ny < kMaxTY ? ny : kMaxTY;
+  // small grids: shrink the tile (64x16 -> 64x8 -> 32x8) until the launch
+  // has at least 1024 workgroups, about four waves per SIMD, so that the
+  // per-face coefficient loads have other waves to hide behind; each face
+  // flux is computed the same way whatever the tile, so the result does not
+  // depend on it
+  int TX = nx < kMaxTX ? nx : kMaxTX;
+  int TY = ny < kMaxTY ? ny : kMaxTY;
+  auto wgs = [&](int tx, int ty) { return (long)(nx / tx) * (ny / ty) * h->g.batch; };
+  while (wgs(TX, TY) < 1024 && (TY > 8 || TX > 32)) {
+    if (TY > 8)
+      TY = 8;
+    else
+      TX /= 2;
+  }
   dim3 grid((nx / TX) * (ny / TY), h->g.batch);
 #define LDSV_STAGE_CASE(tx, ty)                                                                   \
   if (TX == tx && TY == ty) {                                                                     \

@@ -253,3 +253,39 @@ def test_training_with_derivative_network_lowers_loss():
     first = hist[0][1]
     last = hist[-1][1]
     assert last < 0.8 * first, hist
+
+
+def test_kolmogorov64_full_size_learned_d_step():
+    """The two-network step at the benchmark's inference configuration (64^2,
+    batch 64, the forced-flow parameters and time step) in the launch
+    configuration the benchmark times (bf16 planes); trajectories 0, 31 and
+    63 against the oracle given the device's network outputs, and the
+    derivative network's output of trajectory 63 against the bf16-emulating
+    oracle network."""
+    L_ = need_gpu()
+    announce("kolmogorov64 learned_d step")
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    net, _, _ = _net(L_, seed=0, last_scale=1e-3)
+    dnet, dwb, dbb = _net(L_, seed=1, last_scale=1e-3)
+    s = L_.Solver(n, n, B)
+    gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=200)
+    kw = dict(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"], forcing_k=w["forcing_k"],
+              drag=w["drag"])
+    prm = L_.params(k_c=1, **kw)
+    uo, vo, no, dno = s.learned_d_fv_step(prm, net, dnet, gu, gv, 1, want_net_out=True)
+    pu, pv = s.learned_d_fv_step(prm, net, dnet, gu, gv, 1)
+    assert torch.equal(pu, uo) and torch.equal(pv, vo)
+    oprm = oracle_prm(n, n, k_c=1, **kw)
+    for b in (0, 31, B - 1):
+        u0, v0 = cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1])
+        out, dout = cpu64(no[b:b + 1]), cpu64(dno[b:b + 1])
+        eu, ev = timestep.fv_step(u0, v0, oprm, learned.constrain(out[:, :64]),
+                                  dcoef=learned.constrain_deriv(dout[:, :64]))
+        eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
+        assert rel_l2(uo[b:b + 1], eu) < 1e-5 and rel_l2(vo[b:b + 1], ev) < 1e-5, b
+    x = torch.stack([cpu64(gu[B - 1:B]), cpu64(gv[B - 1:B])], dim=1)
+    ref = cnn.cnn_forward(x, dwb, dbb, bf16=True)
+    assert rel_l2(dno[B - 1:B, :64], ref[:, :64]) < 5e-3
+    d = s.diagnostics(uo, vo).cpu()
+    assert (d[:, 5] == 1).all()
