@@ -92,15 +92,17 @@ def _net(L_, seed, last_scale=0.05):
     return net, wb, bb
 
 
-@pytest.mark.parametrize("n,b", [(32, 3), (64, 2)])
-def test_learned_d_step_matches_oracle(n, b):
+@pytest.mark.parametrize("n,ny,b", [(32, 32, 3), (64, 64, 2), (64, 32, 3), (8, 8, 1)])
+def test_learned_d_step_matches_oracle(n, ny, b):
+    """Square, non-square and an 8 x 8 grid (sides not multiples of 16: the
+    network's untiled path, float outputs)."""
     L_ = need_gpu()
-    announce("learned_d_step", n, b)
+    announce("learned_d_step", n, ny, b)
     net, wb, bb = _net(L_, seed=21)
     dnet, dwb, dbb = _net(L_, seed=22)
-    u, v = ic.grf_peak(b, n, n, L, L, seed=23)
+    u, v = ic.grf_peak(b, n, ny, L, L, seed=23)
     u, v = u.float().double(), v.float().double()
-    s = L_.Solver(n, n, b)
+    s = L_.Solver(n, ny, b)
     prm = L_.params(k_c=1, **KW)
     uo, vo, no, dno = s.learned_d_fv_step(prm, net, dnet, dev(u, torch.float32),
                                           dev(v, torch.float32), 1, want_net_out=True)
@@ -109,7 +111,7 @@ def test_learned_d_step_matches_oracle(n, b):
     assert torch.equal(up, uo) and torch.equal(vp, vo)
     # the FV step with the device's network outputs
     out, dout = cpu64(no), cpu64(dno)
-    oprm = oracle_prm(n, n, k_c=1, **KW)
+    oprm = oracle_prm(n, ny, k_c=1, **KW)
     eu, ev = timestep.fv_step(u, v, oprm, learned.constrain(out[:, :64]),
                               dcoef=learned.constrain_deriv(dout[:, :64]))
     eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
