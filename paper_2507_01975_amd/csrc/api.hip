@@ -59,6 +59,16 @@ int ldsv_check_handle(const ldsv_handle* h) {
   return LDSV_OK;
 }
 
+int ldsv_check_params(const ldsv_handle* h, const ldsv_params* p) {
+  LDSV_REQUIRE(p != nullptr, LDSV_EINVAL, "null params");
+  LDSV_REQUIRE(std::isfinite(p->dt) && std::isfinite(p->nu) && p->nu >= 0.0, LDSV_EINVAL,
+               "params: dt and nu must be finite, nu >= 0");
+  LDSV_REQUIRE(p->rk == LDSV_RK4 || p->rk == LDSV_SSPRK3, LDSV_EINVAL, "params: rk must be RK4 or SSPRK3");
+  LDSV_REQUIRE(p->physics_mask >= 0 && p->physics_mask <= 7, LDSV_EINVAL, "params: bad physics_mask");
+  (void)h;
+  return LDSV_OK;
+}
+
 namespace {
 
 int ilog2(int n) {
@@ -79,16 +89,6 @@ std::vector<Cx<T>> twiddles(int n) {
     t[m] = Cx<T>{(T)std::cos(a), (T)(-std::sin(a))};
   }
   return t;
-}
-
-int check_params(const ldsv_handle* h, const ldsv_params* p) {
-  LDSV_REQUIRE(p != nullptr, LDSV_EINVAL, "null params");
-  LDSV_REQUIRE(std::isfinite(p->dt) && std::isfinite(p->nu) && p->nu >= 0.0, LDSV_EINVAL,
-               "params: dt and nu must be finite, nu >= 0");
-  LDSV_REQUIRE(p->rk == LDSV_RK4 || p->rk == LDSV_SSPRK3, LDSV_EINVAL, "params: rk must be RK4 or SSPRK3");
-  LDSV_REQUIRE(p->physics_mask >= 0 && p->physics_mask <= 7, LDSV_EINVAL, "params: bad physics_mask");
-  (void)h;
-  return LDSV_OK;
 }
 
 // a passive scalar stepped with the velocity: s_in -> s_out (in place
@@ -437,7 +437,7 @@ int ldsv_init_state(ldsv_handle* h, int kind, uint64_t seed, const ldsv_ic_args*
 int ldsv_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coef, const void* u,
              const void* v, void* ru, void* rv, void* stream) {
   LDSV_TRY(ldsv_check_handle(h));
-  LDSV_TRY(check_params(h, prm));
+  LDSV_TRY(ldsv_check_params(h, prm));
   LDSV_REQUIRE(u && v && ru && rv, LDSV_EINVAL, "rhs: null array");
   LDSV_REQUIRE(!coef || (h->g.layout == LDSV_MAC), LDSV_EDTYPE,
                "rhs: learned coefficients need the MAC layout");
@@ -455,7 +455,7 @@ int ldsv_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coef, const vo
 int ldsv_fv_step(ldsv_handle* h, const ldsv_params* prm, const float* coef, const void* u_in,
                  const void* v_in, void* u_out, void* v_out, int nsteps, void* stream) {
   LDSV_TRY(ldsv_check_handle(h));
-  LDSV_TRY(check_params(h, prm));
+  LDSV_TRY(ldsv_check_params(h, prm));
   LDSV_REQUIRE(u_in && v_in && u_out && v_out, LDSV_EINVAL, "fv_step: null array");
   LDSV_REQUIRE(nsteps >= 1, LDSV_EINVAL, "fv_step: nsteps=%d", nsteps);
   LDSV_REQUIRE(!coef || (h->g.layout == LDSV_MAC), LDSV_EDTYPE,

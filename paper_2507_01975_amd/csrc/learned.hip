@@ -15,6 +15,7 @@
 int ldsv_launch_mse_grad(ldsv_handle* h, const float* u, const float* v, const float* lu,
                          const float* lv, double scale, float* gu, float* gv, double* loss,
                          hipStream_t st, int accumulate);
+int ldsv_check_params(const ldsv_handle* h, const ldsv_params* p);
 int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
                        const void* su, const void* sv, void* du, void* dv, const float* tcu,
                        const float* tcv, size_t tcbs, hipStream_t st);
@@ -444,10 +445,10 @@ int ldsv_fv_step_d(ldsv_handle* h, const ldsv_params* prm, const float* coef, co
   LDSV_TRY(ldsv_check_handle(h));
   LDSV_REQUIRE(prm && coef && dcoef && u_in && v_in && u_out && v_out, LDSV_EINVAL,
                "fv_step_d: null argument");
+  LDSV_TRY(ldsv_check_params(h, prm));
   LDSV_REQUIRE(nsteps >= 1, LDSV_EINVAL, "fv_step_d: nsteps=%d", nsteps);
   LDSV_REQUIRE(h->g.layout == LDSV_MAC && h->g.dtype == LDSV_F32, LDSV_EDTYPE,
                "fv_step_d: learned derivative stencils need an F32 MAC grid");
-  LDSV_REQUIRE(prm->rk == LDSV_RK4 || prm->rk == LDSV_SSPRK3, LDSV_EINVAL, "fv_step_d: bad rk");
   const hipStream_t st = (hipStream_t)stream;
   const size_t cbs = (size_t)LDSV_NCOEF * h->ncell;
   DerivCoef dc;
@@ -465,6 +466,7 @@ int ldsv_fv_step_d_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef
   LDSV_TRY(ldsv_check_handle(h));
   LDSV_REQUIRE(prm && coef && dcoef && u_in && v_in && gu_out && gv_out && gu_in && gv_in,
                LDSV_EINVAL, "fv_step_d_bwd: null argument");
+  LDSV_TRY(ldsv_check_params(h, prm));
   LDSV_REQUIRE(h->g.dtype == LDSV_F32, LDSV_EDTYPE, "fv_step_d_bwd: F32 grids only");
   const size_t cbs = (size_t)LDSV_NCOEF * h->ncell;
   DerivCoef dc;
@@ -483,8 +485,7 @@ int ldsv_learned_d_fv_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_ne
   LDSV_TRY(ldsv_check_net(dnet));
   LDSV_REQUIRE(prm && u_in && v_in && u_out && v_out, LDSV_EINVAL,
                "learned_d_fv_step: null argument");
-  LDSV_REQUIRE(prm->rk == LDSV_RK4 || prm->rk == LDSV_SSPRK3, LDSV_EINVAL,
-               "learned_d_fv_step: bad rk");
+  LDSV_TRY(ldsv_check_params(h, prm));
   LDSV_TRY(ldsv_ensure_learned(h));
   return learned_step(h, prm, net, u_in, v_in, u_out, v_out, step_index, net_out,
                       (hipStream_t)stream, dnet, dnet_out);
