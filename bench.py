@@ -122,6 +122,25 @@ def cpu_baseline(w, u0, v0, u1_gpu, v1_gpu, budget_s=10.0):
             "gpu_step_rel_l2_vs_fp64": err}
 
 
+def oracle_timed(call, cells_per_call, what, budget_s=2.0):
+    """The oracle as it stands, timed on the host's cores on a bounded sample
+    of a record's workload (for the records beside the headline one): `call`
+    runs one oracle step of the sample, repeated until about budget_s."""
+    import torch
+    torch.set_num_threads(len(os.sched_getaffinity(0)))
+    calls = 0
+    t0 = time.perf_counter()
+    while True:
+        call()
+        calls += 1
+        t = time.perf_counter() - t0
+        if t >= budget_s:
+            break
+    return {"value": cells_per_call * calls / t, "unit": "cell-steps/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "%d call(s) of %s (%.1f s, FP64 torch CPU)" % (calls, what, t)}
+
+
 def fp64_errors():
     """Errors of the other results against the FP64 oracle (the oracle is run
     here as the checker, outside every timed region): the learned step of the
@@ -228,6 +247,14 @@ def learned_block(steps, warmup):
         out["mfma_conv"] = {"tflops": flop / launches_per_step / (per_launch_ms * 1e-3) / 1e12,
                             "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}
         out["mfma_conv"]["frac"] = out["mfma_conv"]["tflops"] / BF16_PEAK_TFLOPS
+    from oracle import fv as ofv, learned as olearned
+    wb = [x.double().cpu() for x in net.bf16_weights()]
+    bb = [x.double().cpu() for x in net.b]
+    us, vs = u[:4].double().cpu(), v[:4].double().cpu()
+    oprm = ofv.grid_params(n, n, k_c=1, nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                           forcing_k=w["forcing_k"], drag=w["drag"])
+    out["cpu_oracle"] = oracle_timed(lambda: olearned.learned_fv_step(us, vs, oprm, wb, bb, 1),
+                                     n * n * 4, "one learned step of 4 of the 64 trajectories")
     return out
 
 
@@ -287,6 +314,15 @@ def learned_deriv_block(steps, warmup):
         out["mfma_conv"] = {"tflops": flop / (conv_n / steps) / (per_launch_ms * 1e-3) / 1e12,
                             "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}
         out["mfma_conv"]["frac"] = out["mfma_conv"]["tflops"] / BF16_PEAK_TFLOPS
+    from oracle import fv as ofv, learned as olearned
+    wts = [([x.double().cpu() for x in m.bf16_weights()], [x.double().cpu() for x in m.b])
+           for m in (net, dnet)]
+    us, vs = u[:4].double().cpu(), v[:4].double().cpu()
+    oprm = ofv.grid_params(n, n, k_c=1, nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                           forcing_k=w["forcing_k"], drag=w["drag"])
+    out["cpu_oracle"] = oracle_timed(
+        lambda: olearned.learned_fv_step(us, vs, oprm, wts[0][0], wts[0][1], 1, dnet=wts[1]),
+        n * n * 4, "one two-network learned step of 4 of the 64 trajectories")
     s.close()
     return out
 
@@ -316,7 +352,7 @@ def fluxblock_block(steps, warmup):
     n, B = w["nx"], w["batch"]
     layers, modes, width = si.FLUXBLOCK_FNO["forced"]
     s = ldsv.Solver(n, n, B)
-    net, _ = _fluxblock_net("forced", ldsv)
+    net, (fw, a_i, a_d) = _fluxblock_net("forced", ldsv)
     u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
     u2, v2 = torch.empty_like(u), torch.empty_like(v)
     prm = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
@@ -392,6 +428,14 @@ def fluxblock_block(steps, warmup):
     out["complete_model"] = {"k_c": kc, "tc_fno": "4 layers, 32 modes, width 8",
                              "ms_per_step": 1e3 * t / steps,
                              "cell_steps_per_s": cells * steps / t}
+    from oracle import fluxblock as ofb, fno as ofno, fv as ofv
+    fparams = {"wi": torch.tensor(fw[0]), "wd": torch.tensor(fw[1]),
+               "fno_i": ofno.from_arrays(a_i), "fno_d": ofno.from_arrays(a_d)}
+    us, vs = u[:4].double().cpu(), v[:4].double().cpu()
+    oprm = ofv.grid_params(n, n, nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                           forcing_k=w["forcing_k"], drag=w["drag"])
+    out["cpu_oracle"] = oracle_timed(lambda: ofb.fluxblock_step(us, vs, oprm, fparams),
+                                     n * n * 4, "one flux-block step of 4 of the 64 trajectories")
     return out
 
 
@@ -435,6 +479,13 @@ def shear_scalar_block(steps=10, warmup=2):
                                "frac": sc_bytes / (sc_ms * 1e-3 / sc_n) / 1e9 / HBM_PEAK_GBS}
     if st_n:
         out["velocity_stage_avg_launch_us"] = 1e3 * st_ms / st_n
+    from oracle import fv as ofv, scalar as oscalar
+    us, vs, cs = u[:1].double().cpu(), v[:1].double().cpu(), c[:1].double().cpu()
+    oprm = ofv.grid_params(nx, ny, lx=w["lx"], ly=w["ly"], nu=w["nu"], dt=w["dt"],
+                           diffusivity=w["diffusivity"])
+    out["cpu_oracle"] = oracle_timed(lambda: oscalar.fv_step_scalar(us, vs, cs, oprm),
+                                     nx * ny, "one step of velocity and scalar of 1 of the 8 "
+                                     "trajectories", budget_s=1.0)
     s.close()
     return out
 
@@ -476,7 +527,14 @@ def burgers_block(repeats=7):
         torch.cuda.synchronize()
         graph.append(time.perf_counter() - t0)
         same = same and torch.equal(u, ref[0]) and torch.equal(v, ref[1])
-    return {"workload": "burgers64 (64^2, FP64, collocated, SSP-RK3, 200 steps)",
+    from oracle import fv as ofv, timestep as ots
+    bu, bv = u0.double().cpu(), v0.double().cpu()
+    bprm = ofv.grid_params(n, n, nu=w["nu"], rk=ots.SSPRK3, layout=ots.COLLOCATED, dt=prm.dt)
+    orc = oracle_timed(lambda: ots.fv_step(bu, bv, bprm, nsteps=20), n * n * 20,
+                       "20 SSP-RK3 steps of the 64^2 state")
+    orc["us_per_step"] = 1e6 * n * n / orc["value"]
+    return {"cpu_oracle": orc,
+            "workload": "burgers64 (64^2, FP64, collocated, SSP-RK3, 200 steps)",
             "us_per_step_eager": 1e6 * statistics.median(eager) / steps,
             "us_per_step_graph": 1e6 * statistics.median(graph) / steps,
             "graph_replays_match_eager": bool(same)}
