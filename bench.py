@@ -122,6 +122,37 @@ def cpu_baseline(w, u0, v0, u1_gpu, v1_gpu, budget_s=10.0):
             "gpu_step_rel_l2_vs_fp64": err}
 
 
+def copy_reference(nbytes):
+    """Achieved rates of plain device-to-device copies (read + write) and
+    fills (write) measured with HIP events over 20 repeats after warm-up:
+    once with the dominant kernel's bytes per launch (the same working set,
+    which like the kernel's own data can stay in the 256 MB last-level
+    cache between repeats) and once with 1 GiB per buffer (beyond that
+    cache: HBM).  The practical ceilings for mixed read/write traffic,
+    reported beside the nominal 8 TB/s."""
+    import torch
+    out = {}
+    for key, n in (("same_bytes", max(1 << 20, int(nbytes // 8))), ("1GiB", 1 << 28)):
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        rec = {"bytes_moved_by_copy": 8 * n}
+        for name, fn, moved in (("copy_GBs", lambda: b.copy_(a), 8 * n),
+                                ("fill_GBs", lambda: b.fill_(2.0), 4 * n)):
+            for _ in range(3):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            rec[name] = moved / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+        out[key] = rec
+        del a, b
+    return out
+
+
 def oracle_timed(call, cells_per_call, what, budget_s=2.0):
     """The oracle as it stands, timed on the host's cores on a bounded sample
     of a record's workload (for the records beside the headline one): `call`
@@ -736,6 +767,8 @@ def main():
             "alg_bytes_per_launch": alg, "avg_launch_us": avg_s * 1e6,
             "classes_ms_per_step": {CLASS_NAMES[c]: cls[c][0] / a.steps for c in cls},
             "instrumented_ms_per_step": 1e3 * t_inst / a.steps}
+    roof["copy_reference"] = copy_reference(alg)
+    roof["frac_of_copy"] = achieved / roof["copy_reference"]["same_bytes"]["copy_GBs"]
     line = {"metric": "cell-steps/s + sim-time/s at corr>=0.9: learned coarse FV vs plain fine FV",
             "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "ms_per_step": 1e3 * t / a.steps, "higher_is_better": True,
