@@ -40,6 +40,20 @@ struct SpeedOrInf {
   }
 };
 
+// zero fill (a kernel rather than a memset node, so that a captured graph
+// of the training calls replays correctly)
+__global__ void k_zero(float* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+int launch_zero(ldsv_handle* h, float* p, size_t n, hipStream_t st) {
+  LDSV_TLAUNCH(h, 7, k_zero, grid1d(n), dim3(kBlock), 0, st, p, n);
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}
+
 __global__ void k_guard_flags(const double* maxspeed, int batch, double thr, int* bad, int* any) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int a = 0;
@@ -246,12 +260,12 @@ int learned_bwd_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net
   DerivCoef dc;
   if (dnet) {
     LDSV_TRY(ldsv_launch_cnn(h, dnet, u_in, v_in, h->dnetout, nullptr, st));
-    LDSV_HIP(hipMemsetAsync(h->gdnet, 0, h->nstate * LDSV_NOUT * sizeof(float), st));
+    LDSV_TRY(launch_zero(h, h->gdnet, h->nstate * LDSV_NOUT, st));
     dc.d = h->dnetout;
     dc.gd = h->gdnet;
   }
   LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st));
-  LDSV_HIP(hipMemsetAsync(h->gnet, 0, h->nstate * LDSV_NOUT * sizeof(float), st));
+  LDSV_TRY(launch_zero(h, h->gnet, h->nstate * LDSV_NOUT, st));
   // FV path: d/du_in and d/d(raw coefficients)
   LDSV_TRY(ldsv_step_bwd(h, prm, h->netout, bs, h->gnet, bs, u_in, v_in, gu_out, gv_out, gu_in,
                          gv_in, st, nullptr, dnet ? &dc : nullptr));
@@ -320,7 +334,7 @@ int rollout_bwd_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net
                           (float*)U(seg, 0), (float*)(U(seg, 0) + sb), first_index + k, nullptr, st, dnet));
   }
   LDSV_HIP(hipMemcpyAsync(U(ck, nseg), U(seg, 0), 2 * sb, hipMemcpyDeviceToDevice, st));
-  LDSV_HIP(hipMemsetAsync(ga, 0, 2 * sb, st));
+  LDSV_TRY(launch_zero(h, (float*)ga, 2 * h->nstate, st));
   char* g = ga;
   char* gn = gb;
   for (int s = nseg - 1; s >= 0; --s) {

@@ -250,3 +250,56 @@ def test_kolmogorov64_full_size_learned_step():
     assert rel_l2(no[B - 1:B], ref) < 5e-3
     d = s.diagnostics(uo, vo).cpu()
     assert (d[:, 5] == 1).all()
+
+
+def test_rollout_bwd_replays_as_a_captured_graph():
+    """The unrolled backward records no memset nodes, so it can be captured
+    in a HIP graph: three rounds of replays over two windows (new inputs
+    copied into the captured buffers, eager work and synchronisations
+    between replays) match the eager calls bit for bit."""
+    L_ = need_gpu()
+    announce("rollout_bwd graph capture")
+    n, b, unroll = 32, 2, 6
+    net, _, _ = _net(L_, seed=7, last_scale=0.05)
+    s = L_.Solver(n, n, b)
+    prm = L_.params(k_c=2, fallback_enable=0, **KW)
+    u, v = ic.grf_peak(b, n, n, L, L, seed=8)
+    u, v = dev(u, torch.float32), dev(v, torch.float32)
+    tu, tv = s.rollout(prm, u, v, unroll + 3)
+    lu, lv = torch.cat([u[None], tu]), torch.cat([v[None], tv])
+    dW = L_.NetGradBuffers(net)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    u0s, v0s = lu[0].clone(), lv[0].clone()
+    yus, yvs = lu[1:1 + unroll].clone(), lv[1:1 + unroll].clone()
+
+    def load(t0):
+        u0s.copy_(lu[t0])
+        v0s.copy_(lv[t0])
+        yus.copy_(lu[t0 + 1:t0 + 1 + unroll])
+        yvs.copy_(lv[t0 + 1:t0 + 1 + unroll])
+
+    def call():
+        dW.zero_()
+        loss.zero_()
+        s.rollout_bwd(prm, net, u0s, v0s, unroll, dW, checkpoint_every=4, first_index=1,
+                      labels=(yus, yvs), loss_scale=1.0 / unroll, loss=loss)
+
+    refs = []
+    for t0 in (0, 3):
+        load(t0)
+        call()
+        torch.cuda.synchronize()
+        refs.append(([x.clone() for x in dW.w + dW.b], loss.clone()))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        for k, t0 in enumerate((0, 3)):
+            load(t0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(loss, refs[k][1]), (t0, loss, refs[k][1])
+            for x, r in zip(dW.w + dW.b, refs[k][0]):
+                assert torch.equal(x, r)
