@@ -53,13 +53,26 @@ __global__ void k_dgrad_weights(const uint16_t* __restrict__ W, uint16_t* __rest
   }
 }
 
-// partial dW over the workgroup's pixel range; dz has CS channels, MT tiles
+// partial dW over the workgroup's pixel range; dz has CS channels, MT tiles.
+// Per 32-pixel chunk every thread holds its share of the chunk's operands in
+// registers (16-byte loads of 8 channels of one pixel; trip counts fixed at
+// compile time, all loads of a chunk in flight together), stores them
+// transposed into LDS, and issues the next chunk's loads before the current
+// chunk's MFMAs, so that their latency is hidden behind the matrix work.
+// Lanes walk the pixels fastest, so the transposing 2-byte LDS stores of a
+// wavefront fill consecutive halfwords of one or two rows (rows 8 apart sit
+// 32 banks apart): no bank conflicts.
 template <int MT, int CS>
 __global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ dz,
                                                   const uint16_t* __restrict__ x, PixMap pm,
                                                   int wgpix, float* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) uint16_t gT[MT * 16 * kTRow];
   __shared__ __attribute__((aligned(16))) uint16_t xT[kK * kTRow];
+  static_assert(MT * 16 <= CS, "the cotangent rows must exist");
+  constexpr int kGE = kChunk * (MT * 16 / 8);  // 16-byte cotangent groups per chunk
+  constexpr int kXE = kChunk * 9 * (kC / 8);   // 16-byte activation groups per chunk
+  static_assert(kXE % kBlock == 0, "chunk staging must tile the block");
+  constexpr int kGPer = (kGE + kBlock - 1) / kBlock, kXPer = kXE / kBlock;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
@@ -70,33 +83,55 @@ __global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ d
     for (int n = 0; n < 9; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int p_begin = blockIdx.x * wgpix;
   const int p_end = min(p_begin + wgpix, pm.total);
-  for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * MT * 16; e += blockDim.x) {
-      const int pl = e / (MT * 16), co = e % (MT * 16);
+  uint4 gv[kGPer];
+  uint4 xv[kXPer];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int k = 0; k < kGPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      const int pl = e % kChunk, cq = e / kChunk;
       const int p = p0 + pl;
-      uint16_t v = 0;
-      if (p < p_end && co < CS) v = dz[(size_t)p * CS + co];
-      gT[co * kTRow + pl] = v;
+      gv[k] = uint4{0u, 0u, 0u, 0u};
+      if (e < kGE && p < p_end)
+        gv[k] = *reinterpret_cast<const uint4*>(dz + (size_t)p * CS + cq * 8);
     }
-    for (int e = threadIdx.x; e < kChunk * 9 * (kC / 8); e += blockDim.x) {
-      const int pl = e / (9 * (kC / 8));
-      const int r = e - pl * (9 * (kC / 8));
+#pragma unroll
+    for (int k = 0; k < kXPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      const int pl = e % kChunk, r = e / kChunk;
       const int tap = r / (kC / 8), q = r % (kC / 8);
       const int p = p0 + pl;
-      uint4 v = {0u, 0u, 0u, 0u};
+      xv[k] = uint4{0u, 0u, 0u, 0u};
       if (p < p_end) {
         const int src = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
-        v = *reinterpret_cast<const uint4*>(x + (size_t)src * kC + q * 8);
+        xv[k] = *reinterpret_cast<const uint4*>(x + (size_t)src * kC + q * 8);
       }
-      const uint16_t h[8] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16),
-                             (uint16_t)(v.y & 0xffff), (uint16_t)(v.y >> 16),
-                             (uint16_t)(v.z & 0xffff), (uint16_t)(v.z >> 16),
-                             (uint16_t)(v.w & 0xffff), (uint16_t)(v.w >> 16)};
+    }
+  };
+  auto put8 = [](uint16_t* dst, const uint4 v) {
+    const uint16_t h[8] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16),
+                           (uint16_t)(v.y & 0xffff), (uint16_t)(v.y >> 16),
+                           (uint16_t)(v.z & 0xffff), (uint16_t)(v.z >> 16),
+                           (uint16_t)(v.w & 0xffff), (uint16_t)(v.w >> 16)};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) xT[(tap * kC + q * 8 + i) * kTRow + pl] = h[i];
+    for (int i = 0; i < 8; ++i) dst[i * kTRow] = h[i];
+  };
+  if (p_begin < p_end) load(p_begin);
+  for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
+    __syncthreads();  // the previous chunk's fragment reads are done
+#pragma unroll
+    for (int k = 0; k < kGPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      if (e < kGE) put8(gT + (e / kChunk) * 8 * kTRow + e % kChunk, gv[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kXPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      const int r = e / kChunk;  // tap * 8 + q: row block 8 r of xT
+      put8(xT + r * 8 * kTRow + e % kChunk, xv[k]);
     }
     __syncthreads();
+    if (p0 + kChunk < p_end) load(p0 + kChunk);  // in flight during the MFMAs below
     bf16x8 af[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -199,29 +234,55 @@ __global__ void __launch_bounds__(kBlock) k_wgrad_first(const uint16_t* __restri
                                                         int wgpix, float* __restrict__ partial) {
   __shared__ float sx[kChunk][18];
   __shared__ float sg[kChunk][kC];
+  // staging as in k_wgrad: registers first (compile-time trip counts), the
+  // next chunk's loads issued before the current chunk's products
+  constexpr int kSX = kChunk * 18, kSXPer = (kSX + kBlock - 1) / kBlock;
+  constexpr int kSG = kChunk * kC, kSGPer = kSG / kBlock;
+  static_assert(kSG % kBlock == 0, "chunk staging must tile the block");
   const int p_begin = blockIdx.x * wgpix;
   const int p_end = min(p_begin + wgpix, pm.total);
-  // thread owns outputs e = threadIdx.x + k * 256 (< 64 * 18 = 1152)
-  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * 18; e += blockDim.x) {
-      const int pl = e / 18, k = e % 18;
-      const int p = p0 + pl;
-      float val = 0.f;
-      if (p < p_end) {
-        const int tap = k / 2;
-        const int src = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
-        val = bf16_to_f32(f32_to_bf16((k & 1) ? v[src] : u[src]));
+  float xr[kSXPer];
+  uint16_t gr[kSGPer];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int k = 0; k < kSXPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      xr[k] = 0.f;
+      if (e < kSX) {
+        const int pl = e / 18, kk = e % 18;
+        const int p = p0 + pl;
+        if (p < p_end) {
+          const int tap = kk / 2;
+          const int src = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
+          xr[k] = bf16_to_f32(f32_to_bf16((kk & 1) ? v[src] : u[src]));
+        }
       }
-      sx[pl][k] = val;
     }
-    for (int e = threadIdx.x; e < kChunk * kC; e += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kSGPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
       const int pl = e / kC, c = e % kC;
       const int p = p0 + pl;
-      sg[pl][c] = (p < p_end) ? bf16_to_f32(dz1[(size_t)p * kC + c]) : 0.f;
+      gr[k] = (p < p_end) ? dz1[(size_t)p * kC + c] : (uint16_t)0;
+    }
+  };
+  // thread owns outputs e = threadIdx.x + k * 256 (< 64 * 18 = 1152)
+  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (p_begin < p_end) load(p_begin);
+  for (int p0 = p_begin; p0 < p_end; p0 += kChunk) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSXPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      if (e < kSX) sx[e / 18][e % 18] = xr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kSGPer; ++k) {
+      const int e = k * kBlock + (int)threadIdx.x;
+      sg[e / kC][e % kC] = bf16_to_f32(gr[k]);
     }
     __syncthreads();
+    if (p0 + kChunk < p_end) load(p0 + kChunk);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const int e = threadIdx.x + k * kBlock;
