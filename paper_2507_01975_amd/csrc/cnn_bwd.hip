@@ -155,24 +155,53 @@ __global__ void __launch_bounds__(kBlock) k_wgrad(const uint16_t* __restrict__ d
         out[(size_t)(m * 16 + kq * 4 + i) * kK + (wave * 9 + n) * 16 + col] = acc[m][n][i];
 }
 
-// dW[co][k] += sum over partials, in a fixed order (four interleaved
-// running sums, so that many loads of a thread are in flight, added
-// pairwise at the end); rows of partial = rows
-__global__ void k_partial_reduce(const float* __restrict__ partial, int nblk, int rows, int cout,
-                                 int ncol, float* __restrict__ dW) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cout * ncol; e += gridDim.x * blockDim.x) {
+// dW[co][k] += sum over partials, in a fixed order: S threads share each
+// output, thread s summing the partials s, s + S, ... eight at a time into
+// four interleaved running sums (eight loads in flight), and the S sums are
+// added in order through LDS; rows of partial = rows.  Outputs per
+// workgroup: kBlock / S.
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_partial_reduce(const float* __restrict__ partial,
+                                                           int nblk, int rows, int cout, int ncol,
+                                                           float* __restrict__ dW) {
+  constexpr int kO = kBlock / S;
+  __shared__ float red[S][kO];
+  const int o = threadIdx.x % kO, sp = threadIdx.x / kO;
+  const int e = blockIdx.x * kO + o;
+  float t = 0.f;
+  if (e < cout * ncol) {
     const int co = e / ncol, k = e % ncol;
     const size_t stride = (size_t)rows * ncol;
     const float* src = partial + (size_t)co * ncol + k;
-    float s[4] = {0.f, 0.f, 0.f, 0.f};
-    int b = 0;
-    for (; b + 8 <= nblk; b += 8) {
+    float a[4] = {0.f, 0.f, 0.f, 0.f};
+    int b = sp;
+    for (; b + 7 * S < nblk; b += 8 * S) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) s[i & 3] += src[(size_t)(b + i) * stride];
+      for (int i = 0; i < 8; ++i) a[i & 3] += src[(size_t)(b + i * S) * stride];
     }
-    for (; b < nblk; ++b) s[b & 3] += src[(size_t)b * stride];
-    dW[e] += (s[0] + s[1]) + (s[2] + s[3]);
+    for (; b < nblk; b += S) a[0] += src[(size_t)b * stride];
+    t = (a[0] + a[1]) + (a[2] + a[3]);
   }
+  red[sp][o] = t;
+  __syncthreads();
+  if (sp == 0 && e < cout * ncol) {
+    float r = 0.f;
+#pragma unroll
+    for (int q = 0; q < S; ++q) r += red[q][o];
+    dW[e] += r;
+  }
+}
+
+// launch the reduction of nblk partial blocks into cout x ncol outputs
+inline void launch_partial_reduce(ldsv_handle* h, hipStream_t st, const float* part, int nblk,
+                                  int rows, int cout, int ncol, float* dW) {
+  const int n = cout * ncol;
+  if (n >= 16384)
+    LDSV_TLAUNCH(h, 7, k_partial_reduce<4>, dim3((n + kBlock / 4 - 1) / (kBlock / 4)),
+                 dim3(kBlock), 0, st, part, nblk, rows, cout, ncol, dW);
+  else
+    LDSV_TLAUNCH(h, 7, k_partial_reduce<16>, dim3((n + kBlock / 16 - 1) / (kBlock / 16)),
+                 dim3(kBlock), 0, st, part, nblk, rows, cout, ncol, dW);
 }
 
 // bias gradient partials from the bf16 NHWC cotangent of a 64-channel layer:
@@ -364,16 +393,14 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   // layer 6: bias from the float cotangent, G = bf16 NHWC copy
   hipLaunchKernelGGL(k_bias_partial_planar, dim3(nbias, LDSV_NOUT), dim3(kBlock), 0, st, gout, hw,
                      (int)P, part);
-  hipLaunchKernelGGL(k_partial_reduce, dim3(1), dim3(128), 0, st, part, nbias, LDSV_NOUT,
-                     LDSV_NOUT, 1, dW->b[5]);
+  launch_partial_reduce(h, st, part, nbias, LDSV_NOUT, LDSV_NOUT, 1, dW->b[5]);
   hipLaunchKernelGGL(k_gout_to_nhwc, grid1d(P * 96), dim3(kBlock), 0, st, gout, G, hw, (int)P);
   LDSV_LAUNCHED();
   {
     LDSV_TLAUNCH(h, 4, (k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, wgpix,
                  part);
   }
-  LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)LDSV_NOUT * kK), dim3(kBlock), 0, st, part,
-                     nwg, 80, LDSV_NOUT, kK, dW->w[5]);
+  launch_partial_reduce(h, st, part, nwg, 80, LDSV_NOUT, kK, dW->w[5]);
   LDSV_TLAUNCH(h, 7, k_dgrad_weights, grid1d((size_t)kC * 9 * 96), dim3(kBlock), 0, st, net->w[5],
                      Wp, LDSV_NOUT, 96);
   LDSV_LAUNCHED();
@@ -387,12 +414,10 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   // layers 5..2 (index 4..1): dz is the cotangent of layer index li's pre-activation
   for (int li = 4; li >= 1; --li) {
     LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nbias), dim3(kBlock), 0, st, dz, (int)P, part);
-    LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nbias, kC, kC, 1,
-                 dW->b[li]);
+    launch_partial_reduce(h, st, part, nbias, kC, kC, 1, dW->b[li]);
     LDSV_TLAUNCH(h, 4, (k_wgrad<4, 64>), dim3(nwg), dim3(kBlock), 0, st, dz, h->act[li - 1], pm,
                  wgpix, part);
-    LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)kC * kK), dim3(kBlock), 0, st, part, nwg,
-                       64, kC, kK, dW->w[li]);
+    launch_partial_reduce(h, st, part, nwg, 64, kC, kK, dW->w[li]);
     LDSV_TLAUNCH(h, 7, k_dgrad_weights, grid1d((size_t)kC * 9 * 64), dim3(kBlock), 0, st,
                        net->w[li], Wp, kC, 64);
     if (h->g.nx % 16 == 0 && h->g.ny % 16 == 0)
@@ -407,10 +432,17 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   }
   // layer 1
   LDSV_TLAUNCH(h, 7, k_bias_partial, dim3(nbias), dim3(kBlock), 0, st, dz, (int)P, part);
-  LDSV_TLAUNCH(h, 7, k_partial_reduce, dim3(1), dim3(64), 0, st, part, nbias, kC, kC, 1, dW->b[0]);
-  LDSV_TLAUNCH(h, 7, k_wgrad_first, dim3(nwg), dim3(kBlock), 0, st, dz, u, v, pm, wgpix, part);
-  LDSV_TLAUNCH(h, 7, k_partial_reduce, grid1d((size_t)kC * 18), dim3(kBlock), 0, st, part, nwg,
-                     kC * 18, kC * 18, 1, dW->w[0]);
+  launch_partial_reduce(h, st, part, nbias, kC, kC, 1, dW->b[0]);
+  {
+    // its 1152 outputs are summed on the vector ALUs from LDS: four times
+    // the workgroups of the MFMA layers, each over a quarter of the pixels,
+    // so that more waves hide the LDS latency (the partials, nwg1 x 1152
+    // floats, fit the buffer sized for nwg x 80 x 576)
+    const int wgpix1 = wgpix / 4 > kChunk ? (wgpix / 4 + kChunk - 1) / kChunk * kChunk : kChunk;
+    const int nwg1 = (int)((P + wgpix1 - 1) / wgpix1);
+    LDSV_TLAUNCH(h, 7, k_wgrad_first, dim3(nwg1), dim3(kBlock), 0, st, dz, u, v, pm, wgpix1, part);
+    launch_partial_reduce(h, st, part, nwg1, kC * 18, kC * 18, 1, dW->w[0]);
+  }
   LDSV_LAUNCHED();
   if (gu && gv) {
     LDSV_TLAUNCH(h, 7, k_dgrad_first, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
