@@ -26,18 +26,39 @@ constexpr int kChunk = 32;        // pixels per MFMA K step in wgrad
 constexpr int kTRow = kChunk + 8; // padded LDS row of transposed operands
 constexpr int kK = 9 * kC;        // 576 = (tap, ci) columns of dW
 
-// gout planar float [B][66][H][W] -> bf16 NHWC [P][96] (channels 66..95 zero)
-__global__ void k_gout_to_nhwc(const float* __restrict__ g, uint16_t* __restrict__ G, int hw,
-                               int total) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)total * 96;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int p = (int)(e / 96), c = (int)(e % 96);
-    float v = 0.f;
-    if (c < LDSV_NOUT) {
-      const int b = p / hw, r = p - b * hw;
-      v = g[((size_t)b * LDSV_NOUT + c) * hw + r];
+// gout planar float [B][66][H][W] -> bf16 NHWC [P][96] (channels 66..95 zero),
+// transposed through LDS: a workgroup takes 64 consecutive pixels (one
+// trajectory's: the pixel count per trajectory is a power of two >= 64),
+// reads each channel row of them coalesced and writes each pixel's 96
+// channels as twelve 16-byte stores
+constexpr int kTP = 64;  // pixels per workgroup
+__global__ void __launch_bounds__(kBlock) k_gout_to_nhwc(const float* __restrict__ g,
+                                                         uint16_t* __restrict__ G, int hw,
+                                                         int total) {
+  __shared__ float t[LDSV_NOUT][kTP + 1];
+  const int p0 = blockIdx.x * kTP;
+  const int b = p0 / hw, r0 = p0 - b * hw;
+  const float* gb = g + (size_t)b * LDSV_NOUT * hw + r0;
+  for (int i = threadIdx.x; i < LDSV_NOUT * kTP; i += kBlock) {
+    const int c = i / kTP, px = i % kTP;
+    t[c][px] = (p0 + px < total) ? gb[(size_t)c * hw + px] : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTP * 12; i += kBlock) {
+    const int px = i / 12, cg = i % 12;
+    if (p0 + px >= total) continue;
+    uint16_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = cg * 8 + j;
+      h[j] = f32_to_bf16(c < LDSV_NOUT ? t[c][px] : 0.f);
     }
-    G[e] = f32_to_bf16(v);
+    uint4 v;
+    v.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+    v.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+    v.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+    v.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+    *reinterpret_cast<uint4*>(G + (size_t)(p0 + px) * 96 + cg * 8) = v;
   }
 }
 
@@ -394,7 +415,8 @@ int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u
   hipLaunchKernelGGL(k_bias_partial_planar, dim3(nbias, LDSV_NOUT), dim3(kBlock), 0, st, gout, hw,
                      (int)P, part);
   launch_partial_reduce(h, st, part, nbias, LDSV_NOUT, LDSV_NOUT, 1, dW->b[5]);
-  hipLaunchKernelGGL(k_gout_to_nhwc, grid1d(P * 96), dim3(kBlock), 0, st, gout, G, hw, (int)P);
+  hipLaunchKernelGGL(k_gout_to_nhwc, dim3((unsigned)((P + kTP - 1) / kTP)), dim3(kBlock), 0, st,
+                     gout, G, hw, (int)P);
   LDSV_LAUNCHED();
   {
     LDSV_TLAUNCH(h, 4, (k_wgrad<5, 96>), dim3(nwg), dim3(kBlock), 0, st, G, h->act[4], pm, wgpix,
