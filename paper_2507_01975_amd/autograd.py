@@ -104,6 +104,33 @@ class _LearnedStep(torch.autograd.Function):
         return (gui, gvi, None, None, None, None) + tuple(_net_grads(dW))
 
 
+class _LearnedDStep(torch.autograd.Function):
+    """The learned step with the derivative-stencil network beside the
+    coefficient network; parameters: net's, then dnet's."""
+
+    @staticmethod
+    def forward(ctx, u, v, solver, prm, net, dnet, step_index, *params):
+        u, v = u.contiguous(), v.contiguous()
+        net.refresh()
+        dnet.refresh()
+        uo, vo = solver.learned_d_fv_step(prm, net, dnet, u, v, step_index)
+        ctx.solver, ctx.prm, ctx.net, ctx.dnet, ctx.k = solver, prm, net, dnet, step_index
+        ctx.save_for_backward(u, v)
+        return uo, vo
+
+    @staticmethod
+    def backward(ctx, gu, gv):
+        u, v = ctx.saved_tensors
+        gu = _zeros_if_none(gu, u)
+        gv = _zeros_if_none(gv, v)
+        dW = ldsv.NetGradBuffers(ctx.net)
+        dWd = ldsv.NetGradBuffers(ctx.dnet)
+        gui, gvi = ctx.solver.learned_d_fv_step_bwd(ctx.prm, ctx.net, ctx.dnet, u, v, ctx.k, gu,
+                                                    gv, dW, dWd)
+        return (gui, gvi, None, None, None, None, None) + tuple(_net_grads(dW)) + \
+            tuple(_net_grads(dWd))
+
+
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, v0, solver, prm, net, nsteps, first_index, checkpoint_every, *params):
@@ -183,6 +210,13 @@ def learned_step(solver, prm, net, u, v, step_index):
     """One learned step producing u_{step_index}; differentiable in u, v and
     the network's master parameters."""
     return _LearnedStep.apply(u, v, solver, prm, net, step_index, *_net_params(net))
+
+
+def learned_d_step(solver, prm, net, dnet, u, v, step_index):
+    """One learned step with per-cell learned derivative stencils (dnet beside
+    net); differentiable in u, v and both networks' master parameters."""
+    return _LearnedDStep.apply(u, v, solver, prm, net, dnet, step_index, *_net_params(net),
+                               *_net_params(dnet))
 
 
 def rollout(solver, prm, net, u0, v0, nsteps, first_index=1, checkpoint_every=8):

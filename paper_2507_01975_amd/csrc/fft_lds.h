@@ -8,12 +8,22 @@
 // synchronises, then every thread twiddles, transforms in registers and
 // stores its outputs, and the block synchronises again.  The buffer holds
 // `nrows` transforms of length n; element j of transform r lives at
-// buf[r * rs + j * es] (rs and es powers of two).  Threads walk the elements with the unit-stride
+// buf[r * rs + j * es] (rs and es powers of two, or any values below 2^24
+// with PAD).  Threads walk the elements with the unit-stride
 // index fastest (j when es == 1, r otherwise), so each wavefront reads and
 // writes consecutive LDS words.
 #pragma once
 
 #include "internal.h"
+
+// Row padding (in elements) for a buffer of rows of n points whose rows are
+// transformed by lds_fft: with n / R butterflies per row a wavefront pass
+// spans several rows, and rows a power of two apart share LDS banks.  n / 8
+// extra elements per row put the rows of a pass n / 4 (FP32) or n / 2
+// (FP64) banks apart: no conflicts for n = 64 and for the 16-butterfly stage
+// of n = 128, at most two-way for n = 32; rows of 256 or more points fill a
+// pass on their own.
+__host__ __device__ inline int lds_row_pad(int n) { return (n >= 32 && n <= 128) ? n / 8 : 0; }
 
 template <typename T>
 __device__ __forceinline__ Cx<T> mul_i(Cx<T> a, int sign) {
@@ -71,13 +81,20 @@ __device__ __forceinline__ void dft8(Cx<T>* x, int sign) {
 // (nrows * n <= E * blockDim).  n, the stage sizes and, for strided
 // transforms (es != 1), nrows are powers of two passed as base-2 logarithms,
 // so index arithmetic is shifts and masks: the vector ALU time of these
-// kernels is comparable to their memory time.  Row transforms (es == 1) take
-// any nrows (the gradient pass transforms a halo row more).
-template <typename T, int R, int LR, int E>
-__device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int log2nrows, int lrs,
-                                          int les, int log2ns, int sign,
+// kernels is comparable to their memory time.  With PAD the row and element
+// strides rs and es are any values below 2^24 (24-bit multiplies), so that
+// a caller can pad the rows of its buffer: with short rows a wavefront
+// spans several rows, and rows a power of two apart fall into the same LDS
+// banks; without PAD they are powers of two (shifts).  Row transforms
+// (es == 1) take any nrows (the gradient pass transforms a halo row more).
+template <typename T, int R, int LR, int E, bool PAD>
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int log2nrows, int rs,
+                                          int es, int log2ns, int sign,
                                           const Cx<T>* __restrict__ tw) {
-  const int es = 1 << les;
+  const int lrs = PAD ? 0 : __builtin_ctz((unsigned)rs), les = PAD ? 0 : __builtin_ctz((unsigned)es);
+  auto at = [&](int row, int x) {
+    return PAD ? __umul24(row, rs) + __umul24(x, es) : (row << lrs) + (x << les);
+  };
   constexpr int BPT = (E / R) > 0 ? (E / R) : 1;  // butterflies per thread
   const int lnb = log2n - LR;                      // log2 of butterflies per transform
   const int total = nrows << lnb;
@@ -97,7 +114,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int 
         row = t & ((1 << log2nrows) - 1);
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[q][r] = buf[(row << lrs) + ((j + (r << lnb)) << les)];
+      for (int r = 0; r < R; ++r) x[q][r] = buf[at(row, j + (r << lnb))];
     }
   }
   __syncthreads();
@@ -126,7 +143,7 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int 
       else dft2(x[q]);
       const int d = ((j - k) << LR) + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(row << lrs) + ((d + (r << log2ns)) << les)] = x[q][r];
+      for (int r = 0; r < R; ++r) buf[at(row, d + (r << log2ns))] = x[q][r];
     }
   }
   __syncthreads();
@@ -138,27 +155,24 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int log2n, int nrows, int 
 // tw[m] = exp(-2 pi i m / n), a table the caller has copied into LDS (every
 // stage reads it, and a global-memory latency per stage would serialise the
 // transform).  The caller synchronises before the call.
-template <typename T, int E>
+template <typename T, int E, bool PAD = false>
 __device__ __forceinline__ void lds_fft(Cx<T>* buf, int n, int log2n, int nrows, int rs, int es,
                                         int sign, const Cx<T>* __restrict__ tw) {
   (void)n;
   const int log2nrows = es == 1 ? 0 : __builtin_ctz((unsigned)nrows);
-  // rs and es are powers of two: element addresses are shifts, not
-  // (quarter-rate) integer multiplies
-  const int lrs = __builtin_ctz((unsigned)rs), les = __builtin_ctz((unsigned)es);
   int log2ns = 0;
   int left = log2n;
   while (left > 0) {
     if (left >= 3 && left != 4) {
-      fft_stage<T, 8, 3, E>(buf, log2n, nrows, log2nrows, lrs, les, log2ns, sign, tw);
+      fft_stage<T, 8, 3, E, PAD>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
       log2ns += 3;
       left -= 3;
     } else if (left >= 2) {
-      fft_stage<T, 4, 2, E>(buf, log2n, nrows, log2nrows, lrs, les, log2ns, sign, tw);
+      fft_stage<T, 4, 2, E, PAD>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
       log2ns += 2;
       left -= 2;
     } else {
-      fft_stage<T, 2, 1, E>(buf, log2n, nrows, log2nrows, lrs, les, log2ns, sign, tw);
+      fft_stage<T, 2, 1, E, PAD>(buf, log2n, nrows, log2nrows, rs, es, log2ns, sign, tw);
       log2ns += 1;
       left -= 1;
     }

@@ -235,12 +235,14 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
                                                           const Cx<T>* __restrict__ twy,
                                                           const double* __restrict__ pinv, int nx,
                                                           int ny, int log2nx, int log2ny, int batch,
-                                                          T idx, T idy) {
+                                                          T idx, T idy, int ra) {
   constexpr bool kKeep = E <= 4;
   constexpr int KE = kKeep ? E : 1;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);  // element (i, j) at j * nx + i
-  Cx<T>* Wx = A + nx * ny;
+  // element (i, j) at j * ra + i: rows padded (ra >= nx) so that the rows a
+  // wavefront spans in the row transforms fall into different LDS banks
+  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
+  Cx<T>* Wx = A + ny * ra;
   Cx<T>* Wy = Wx + nx;
   for (int e = threadIdx.x; e < nx; e += blockDim.x) Wx[e] = twx[e];
   for (int e = threadIdx.x; e < ny; e += blockDim.x) Wy[e] = twy[e];
@@ -289,33 +291,34 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int t = (g + k) * kOneBlock + (int)threadIdx.x;
-      if (t < n) A[t] = Cx<T>{d0[k], d1[k]};
+      if (t < n) A[(t >> log2nx) * ra + (t & (nx - 1))] = Cx<T>{d0[k], d1[k]};
     }
   }
   __syncthreads();
-  lds_fft<T, E>(A, nx, log2nx, ny, nx, 1, -1, Wx);
-  lds_fft<T, E>(A, ny, log2ny, nx, 1, nx, -1, Wy);
+  lds_fft<T, E, true>(A, nx, log2nx, ny, ra, 1, -1, Wx);
+  lds_fft<T, E, true>(A, ny, log2ny, nx, 1, ra, -1, Wy);
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int t = k * kOneBlock + (int)threadIdx.x;
     if (t < n) {
       const double s = kKeep ? fac[k % KE] : pinv[t];
-      const Cx<T> v = A[t];
-      A[t] = Cx<T>{(T)((double)v.x * s), (T)((double)v.y * s)};
+      const int a = (t >> log2nx) * ra + (t & (nx - 1));
+      const Cx<T> v = A[a];
+      A[a] = Cx<T>{(T)((double)v.x * s), (T)((double)v.y * s)};
     }
   }
   __syncthreads();
-  lds_fft<T, E>(A, ny, log2ny, nx, 1, nx, +1, Wy);
-  lds_fft<T, E>(A, nx, log2nx, ny, nx, 1, +1, Wx);
+  lds_fft<T, E, true>(A, ny, log2ny, nx, 1, ra, +1, Wy);
+  lds_fft<T, E, true>(A, nx, log2nx, ny, ra, 1, +1, Wx);
 #pragma unroll 4
   for (int k = 0; k < E; ++k) {
     const int t = k * kOneBlock + (int)threadIdx.x;
     if (t >= n) break;
     const int j = t >> log2nx;
     const int i = t & (nx - 1);
-    const Cx<T> pc = A[t];
-    const Cx<T> pw = A[j * nx + ((i - 1) & (nx - 1))];
-    const Cx<T> ps = A[((j - 1) & (ny - 1)) * nx + i];
+    const Cx<T> pc = A[j * ra + i];
+    const Cx<T> pw = A[j * ra + ((i - 1) & (nx - 1))];
+    const Cx<T> ps = A[((j - 1) & (ny - 1)) * ra + i];
     const size_t c0 = (size_t)b0 * plane + t;
     uo[c0] = (kKeep ? cu0[k % KE] : us[c0]) - (pc.x - pw.x) * idx;
     vo[c0] = (kKeep ? cv0[k % KE] : vs[c0]) - (pc.x - ps.x) * idy;
@@ -346,14 +349,16 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
     // u*, v* are read only by the cells that write u, v at the same index
     // after all reads of neighbours are done (the divergence is formed
     // before the first barrier), so in-place calls are safe here as well
-    const size_t lds = ((size_t)nx * ny + nx + ny) * cs;
+    int ra = nx + lds_row_pad(nx);
+    if (((size_t)ny * ra + nx + ny) * cs > 163840) ra = nx;  // padding only within the LDS
+    const size_t lds = ((size_t)ny * ra + nx + ny) * cs;
     auto kern = (size_t)nx * ny <= (size_t)4 * kOneBlock ? k_project_lds<T, 4> : k_project_lds<T, 16>;
     LDSV_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
     LDSV_TLAUNCH(h, 2, kern, dim3(h->npairs), dim3(kOneBlock), lds, st, (const T*)us,
                  (const T*)vs, (T*)uo, (T*)vo, (T*)po, (const Cx<T>*)h->twx,
                  (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2nx, h->log2ny, B,
-                 idx, idy);
+                 idx, idy, ra);
     LDSV_LAUNCHED();
     return LDSV_OK;
   }

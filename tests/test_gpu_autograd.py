@@ -148,3 +148,33 @@ def test_rollout_function_matches_chained_steps():
     assert rel_l2(ru, cu) < 1e-6 and rel_l2(rv, cv) < 1e-6
     for a, c in zip(rp, cp):
         assert rel_l2(a, c) < 1e-5
+
+
+def test_learned_d_step_function_parameter_gradients():
+    """The two-network step as an autograd Function returns the numbers of the
+    step adjoint entry point bit for bit, for the state and both networks."""
+    L_ = need_gpu()
+    from paper_2507_01975_amd import autograd as A
+    announce("autograd learned_d step")
+    n, b = 32, 2
+    s = L_.Solver(n, n, b)
+    net = _net(L_, seed=41)
+    dnet = _net(L_, seed=42)
+    params = list(net.master_w) + list(net.b) + list(dnet.master_w) + list(dnet.b)
+    for p in params:
+        p.requires_grad_(True)
+    u0, v0 = ic.grf_peak(b, n, n, L, L, seed=43)
+    u = dev(u0, torch.float32).requires_grad_(True)
+    v = dev(v0, torch.float32).requires_grad_(True)
+    wu, wv = _weights(b, n, 44)
+    prm = L_.params(k_c=1, **KW)
+    uo, vo = A.learned_d_step(s, prm, net, dnet, u, v, 1)
+    ((wu.cuda() * uo).sum() + (wv.cuda() * vo).sum()).backward()
+    dW, dWd = L_.NetGradBuffers(net), L_.NetGradBuffers(dnet)
+    gu, gv = s.learned_d_fv_step_bwd(prm, net, dnet, u.detach(), v.detach(), 1, wu.cuda(),
+                                     wv.cuda(), dW, dWd)
+    assert torch.equal(u.grad, gu) and torch.equal(v.grad, gv)
+    for l in range(6):
+        assert torch.equal(net.master_w[l].grad, dW.w[l]), l
+        assert torch.equal(dnet.master_w[l].grad, dWd.w[l]), l
+        assert torch.equal(net.b[l].grad, dW.b[l]) and torch.equal(dnet.b[l].grad, dWd.b[l]), l
