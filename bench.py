@@ -686,6 +686,8 @@ def main():
                     help="skip the streaming-shape (1024^2 x 128) and Burgers latency records")
     ap.add_argument("--learned-only", action="store_true",
                     help="profiling aid: time only the learned 64^2 step and print its record")
+    ap.add_argument("--training-only", action="store_true",
+                    help="print only the training records (for kernel profiles)")
     ap.add_argument("--fluxblock-only", action="store_true",
                     help="profiling aid: time only the flux-block model (64^2 step, complete "
                     "model, 128^2 training iteration) and print its records")
@@ -713,6 +715,10 @@ def main():
     if a.learned_only:
         print(json.dumps({"learned": learned_block(a.steps, a.warmup),
                           "learned_deriv": learned_deriv_block(a.steps, a.warmup)}), flush=True)
+        return
+    if a.training_only:
+        print(json.dumps({"training": training_block(),
+                          "fluxblock_training": fluxblock_training_block()}), flush=True)
         return
     if a.fluxblock_only:
         print(json.dumps({"fluxblock": fluxblock_block(a.steps, a.warmup),
