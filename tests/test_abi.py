@@ -55,3 +55,19 @@ def test_create_rejects_bad_shapes_without_a_device():
     assert ldsv._lib.ldsv_fv_step(None, None, None, None, None, None, None, 1, None) == ldsv.EINVAL
     assert ldsv._lib.ldsv_adam_step(None, None, None, None, 0, 1, 1e-4, 0.9, 0.999, 1e-8,
                                     None) == ldsv.EINVAL
+
+
+def test_learned_derivative_entry_points_reject_bad_arguments_without_a_device():
+    # every entry point validates its handle and pointers before any HIP call
+    from paper_2507_01975_amd import ldsv
+    L = ldsv._lib
+    N = None
+    assert L.ldsv_fv_step_d(N, N, N, N, N, N, N, N, 1, N) == ldsv.EINVAL
+    assert L.ldsv_fv_step_d_bwd(*([N] * 13)) == ldsv.EINVAL
+    assert L.ldsv_learned_d_fv_step(N, N, N, N, N, N, N, N, 1, N, N, N) == ldsv.EINVAL
+    assert L.ldsv_learned_d_fv_step_bwd(N, N, N, N, N, N, 1, N, N, N, N, N, N, N) == ldsv.EINVAL
+    assert "derivative network" in ldsv.last_error()
+    assert L.ldsv_rollout_d(N, N, N, N, N, N, 1, 1, 1, N, N, N, N) == ldsv.EINVAL
+    assert "null network" in ldsv.last_error()
+    assert L.ldsv_rollout_d_bwd(N, N, N, N, N, N, 1, 1, 1, N, N, 1.0, N, N, N, N, N, N, N,
+                                N) == ldsv.EINVAL
