@@ -43,7 +43,21 @@
 
 namespace {
 
-constexpr int kFnoBlock = 1024;
+constexpr int kFnoBlock = 1024;  // largest transform workgroup
+// transform workgroup for E values per thread: 512 threads for E = 8, else
+// 1024.  Grids of up to 4096 cells run the forward transform with E = 8
+// (every radix-8 butterfly of a stage has its thread and four workgroups
+// share a CU: 9-11 % faster than E = 4) and the inverse, whose pointwise
+// term and GELU need more registers, with E = 4 (E = 8 at two workgroups
+// per CU was 18 % slower); larger grids use E = 16 for both.
+template <int E>
+__host__ __device__ constexpr int fno_block() {
+  return E == 8 ? 512 : kFnoBlock;
+}
+template <int E>
+constexpr int spec_e() {
+  return E == 4 ? 8 : E;
+}
 constexpr int kMaxIn = 16;  // input planes of one FNO (two per state of a history)
 using c32 = Cx<float>;
 
@@ -94,7 +108,7 @@ __device__ __forceinline__ void load_twiddles(Cx<float>* Wx, Cx<float>* Wy, cons
 
 // forward transform of channels (2p, 2p+1) of trajectory b, network slice z
 template <int E, bool LIFT>
-__global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict__ vin,
+__global__ void __launch_bounds__(fno_block<E>()) k_fno_spec(const float* __restrict__ vin,
                                                         const float* __restrict__ vin2, FnoArgs a,
                                                         float* __restrict__ v0out,
                                                         c32* __restrict__ X,
@@ -129,7 +143,7 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict_
       const float w0 = lw[c0 * nin + j], w1 = lw[c1 * nin + j];
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const int t = k * kFnoBlock + (int)threadIdx.x;
+        const int t = k * fno_block<E>() + (int)threadIdx.x;
         if (t < n) {
           const float xv = x[t];
           q0[k] += w0 * xv;
@@ -139,7 +153,7 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict_
     }
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const int t = k * kFnoBlock + (int)threadIdx.x;
+      const int t = k * fno_block<E>() + (int)threadIdx.x;
       if (t < n) {
         A[t] = Cx<float>{q0[k], q1[k]};
         d0[t] = q0[k];  // v_0 kept for the pointwise term and the backward
@@ -150,7 +164,7 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_spec(const float* __restrict_
     const float* s0 = vin + ((size_t)(z * B + b) * C + c0) * n;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const int t = k * kFnoBlock + (int)threadIdx.x;
+      const int t = k * fno_block<E>() + (int)threadIdx.x;
       if (t < n) A[t] = Cx<float>{s0[t], s0[n + t]};
     }
   }
@@ -229,7 +243,7 @@ __global__ void __launch_bounds__(64 * C) k_fno_mix(const c32* __restrict__ X, F
 // dv_i GELU'(gpre_i) (the cotangent of the previous layer's pre-activation);
 // 3: backward of the first layer, out = dv_i.
 template <int E, int C, int MODE>
-__global__ void __launch_bounds__(kFnoBlock, E <= 4 ? 8 : 4) k_fno_inv(const c32* __restrict__ Y,
+__global__ void __launch_bounds__(fno_block<E>(), E <= 4 ? 8 : 4) k_fno_inv(const c32* __restrict__ Y,
                                                        const float* __restrict__ vin, FnoArgs a,
                                                        float* __restrict__ vout,
                                                        float* __restrict__ zout,
@@ -274,7 +288,7 @@ __global__ void __launch_bounds__(kFnoBlock, E <= 4 ? 8 : 4) k_fno_inv(const c32
 #pragma unroll
   for (int kk = 0; kk < kG; ++kk) {
     const int k = g0 + kk;
-    const int t = k * kFnoBlock + (int)threadIdx.x;
+    const int t = k * fno_block<E>() + (int)threadIdx.x;
     ya0[kk] = ya1[kk] = yb0[kk] = yb1[kk] = c32{0.f, 0.f};
     if (t < n) {
       const int ky = t >> log2nx, kx = t & (nx - 1);
@@ -301,7 +315,7 @@ __global__ void __launch_bounds__(kFnoBlock, E <= 4 ? 8 : 4) k_fno_inv(const c32
   }
 #pragma unroll
   for (int kk = 0; kk < kG; ++kk) {
-    const int t = (g0 + kk) * kFnoBlock + (int)threadIdx.x;
+    const int t = (g0 + kk) * fno_block<E>() + (int)threadIdx.x;
     if (t < n) {
       // s = ya + conj(yb) (one of the two is zero outside the k_x = 0 column)
       const float h = (t & (nx - 1)) == 0 ? 0.5f : 1.0f;
@@ -318,7 +332,7 @@ __global__ void __launch_bounds__(kFnoBlock, E <= 4 ? 8 : 4) k_fno_inv(const c32
   float* d0 = vout + ((size_t)(z * B + b) * C + o0) * n;
   float* e0 = zout ? zout + ((size_t)(z * B + b) * C + o0) * n : nullptr;
   for (int k = 0; k < E; ++k) {
-    const int t = k * kFnoBlock + (int)threadIdx.x;
+    const int t = k * fno_block<E>() + (int)threadIdx.x;
     if (t >= n) break;
     float z0 = A[t].x * sc + bo0, z1 = A[t].y * sc + bo1;
     const float* src = vin + (size_t)(z * B + b) * C * n + t;
@@ -810,15 +824,15 @@ int fno_forward_e(ldsv_handle* h, const FnoGroup& G, const FnoShape& sh, const F
     float* nxt = fno_out(w, l);
     if (first) {
       // v_0 = lift(inputs) is written to cur on the way
-      auto k = k_fno_spec<E, true>;
+      auto k = k_fno_spec<spec_e<E>(), true>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const float*)nullptr,
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(fno_block<spec_e<E>()>()), lds, st, (const float*)nullptr,
                    (const float*)nullptr, a, cur, X, twx, twy, nx, ny, h->log2nx, h->log2ny, C, M,
                    B);
     } else {
-      auto k = k_fno_spec<E, false>;
+      auto k = k_fno_spec<spec_e<E>(), false>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const float*)cur,
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(fno_block<spec_e<E>()>()), lds, st, (const float*)cur,
                    (const float*)nullptr, a, (float*)nullptr, X, twx, twy, nx, ny, h->log2nx,
                    h->log2ny, C, M, B);
     }
@@ -833,7 +847,7 @@ int fno_forward_e(ldsv_handle* h, const FnoGroup& G, const FnoShape& sh, const F
                     : (C == 16 ? k_fno_inv<E, 16, 0> : k_fno_inv<E, 8, 0>);
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const c32*)Y, (const float*)cur, a,
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(fno_block<E>()), lds, st, (const c32*)Y, (const float*)cur, a,
                    nxt, zl, (const float*)nullptr, twx, twy, nx, ny, h->log2nx, h->log2ny, M, B);
     }
   }
@@ -921,10 +935,10 @@ int fno_backward_e(ldsv_handle* h, const FnoGroup& G, const ldsv_fno_grad* const
     LDSV_TRY(sum_partials(h, sh, a, w.small, B * nch, C * C + C, C * C, C, g_pb, st));
     // DZ = F(dz_l) into X
     {
-      auto k = k_fno_spec<E, false>;
+      auto k = k_fno_spec<spec_e<E>(), false>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const float*)dcur,
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(fno_block<spec_e<E>()>()), lds, st, (const float*)dcur,
                    (const float*)nullptr, a, (float*)nullptr, w.X, twx, twy, nx, ny, h->log2nx,
                    h->log2ny, C, M, B);
     }
@@ -941,7 +955,7 @@ int fno_backward_e(ldsv_handle* h, const FnoGroup& G, const ldsv_fno_grad* const
       auto k = l == 0 ? k_fno_inv<E, C, 3> : k_fno_inv<E, C, 2>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
-      LDSV_TLAUNCH(h, 8, k, gfft, dim3(kFnoBlock), lds, st, (const c32*)w.Y, (const float*)dcur,
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(fno_block<E>()), lds, st, (const c32*)w.Y, (const float*)dcur,
                    a, dnxt, (float*)nullptr,
                    (const float*)(l > 0 ? w.pre + (size_t)(l - 1) * w.act : nullptr), twx, twy,
                    nx, ny, h->log2nx, h->log2ny, M, B);
