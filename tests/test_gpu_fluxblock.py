@@ -444,3 +444,43 @@ def test_train_complete_model_reduces_the_loss():
     hist = T.train_fluxblock(s, net, labels, prm, iters=12, unroll=4, lr=3e-3, log_every=1,
                              tc=student_tc)
     assert hist[-1][1] < 0.5 * hist[0][1], hist
+
+
+def test_kolmogorov64_full_size_fluxblock_step_and_correction():
+    """The flux-block step at the benchmark's configuration (64^2, batch 64,
+    the forced-flow FNOs of 6 layers, 32 modes, width 16, the bench's
+    weights) in the launch configuration it times, trajectories 0, 31 and 63
+    against the oracle; then one step of the complete model with the
+    temporal correction (k_c = 4) on trajectories 0 and 63."""
+    L_ = need_gpu()
+    announce("kolmogorov64 flux-block step")
+    w = si.WORKLOADS["kolmogorov64"]
+    n, B = w["nx"], w["batch"]
+    layers, modes, width = si.FLUXBLOCK_FNO["forced"]
+    ws = np.stack([si.stencil_weights(0, 0.01), si.stencil_weights(1, 0.01)])
+    a_i = si.fno_weights(2, width, layers, modes)
+    a_d = si.fno_weights(3, width, layers, modes)
+    net = L_.FluxNetParams(ws, L_.FnoParams.from_arrays(a_i), L_.FnoParams.from_arrays(a_d))
+    s = L_.Solver(n, n, B)
+    gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=200)
+    kw = dict(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"], forcing_k=w["forcing_k"],
+              drag=w["drag"])
+    uo, vo = s.fluxblock_step(L_.params(**kw), net, gu, gv)
+    params = {"wi": torch.tensor(ws[0]), "wd": torch.tensor(ws[1]),
+              "fno_i": fno.from_arrays(a_i), "fno_d": fno.from_arrays(a_d)}
+    for b in (0, 31, B - 1):
+        ru, rv = fluxblock.fluxblock_step(cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1]),
+                                          oracle_prm(n, n, **kw), params)
+        assert rel_l2(uo[b:b + 1], ru) < 1e-5 and rel_l2(vo[b:b + 1], rv) < 1e-5, b
+    kc = 4
+    a_tc = si.fno_weights(9, 8, 4, 32, n_in=2 * kc, n_out=2)
+    tc = L_.FnoParams.from_arrays(a_tc)
+    hu = [gu, uo, gu, uo]
+    hv = [gv, vo, gv, vo]
+    cu, cv = s.fluxblock_tc_step(L_.params(k_c=kc, **kw), net, tc, hu, hv, kc)
+    params["tc"] = fno.from_arrays(a_tc)
+    for b in (0, B - 1):
+        ru, rv = fluxblock.model_step([cpu64(x[b:b + 1]) for x in hu],
+                                      [cpu64(x[b:b + 1]) for x in hv],
+                                      oracle_prm(n, n, k_c=kc, **kw), params, kc)
+        assert rel_l2(cu[b:b + 1], ru) < 1e-5 and rel_l2(cv[b:b + 1], rv) < 1e-5, b

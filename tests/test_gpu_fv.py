@@ -287,3 +287,21 @@ def test_projection_extreme_aspect_fp32(nx, ny):
     print("extreme-aspect projection tolerance %.3g" % tol)
     assert rel_l2(gu, eu) < tol and rel_l2(gv, ev) < tol
     assert rel_l2(p, ep) < 1e-5
+
+
+def test_streaming_full_size_step():
+    """One plain RK4 step at the streaming shape of the benchmark (1024^2,
+    batch 128, FP32; 537 MB per field) in the launch configuration it times;
+    trajectories 0 and 127 against the oracle."""
+    L_ = need_gpu()
+    announce("streaming 1024^2 x 128 step")
+    n, B = 1024, 128
+    s = L_.Solver(n, n, B)
+    gu, gv = s.init_state(L_.IC_GRF_PEAK, seed=0)
+    kw = dict(nu=2e-4, dt=0.1 * 2 * math.pi / n)
+    uo, vo = s.fv_step(L_.params(**kw), gu, gv)
+    for b in (0, B - 1):
+        u0, v0 = cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1])
+        eu, ev = timestep.fv_step(u0, v0, oracle_prm(n, n, **kw))
+        assert rel_l2(uo[b:b + 1], eu) < 1e-5 and rel_l2(vo[b:b + 1], ev) < 1e-5, b
+    s.close()

@@ -52,3 +52,26 @@ def test_scalar_init_and_in_place():
     ref = s.fv_step_scalar(prm, 1e-3, u, v, c, nsteps=2)
     s.fv_step_scalar(prm, 1e-3, u, v, c, nsteps=2, out=(u, v, c))
     assert torch.equal(u, ref[0]) and torch.equal(v, ref[1]) and torch.equal(c, ref[2])
+
+
+def test_shear_scalar_full_size_step():
+    """One step of velocity and passive scalar at the benchmark's fine
+    resolution (2048 x 1024 on [0, 8] x [0, 4], batch 8, FP32) in the launch
+    configuration it times; trajectories 0 and 7 against the oracle."""
+    import synthetic_inputs as si
+    L_ = need_gpu()
+    announce("shear_scalar full-size step")
+    w = si.WORKLOADS["shear_scalar"]
+    nx, ny, B = w["nx"], w["ny"], w["batch"]
+    s = L_.Solver(nx, ny, B, lx=w["lx"], ly=w["ly"])
+    u, v = s.init_state(L_.IC_SHEAR_LAYER, seed=1000, delta=w["delta"])
+    c = s.init_scalar(delta=w["delta"])
+    prm = L_.params(nu=w["nu"], dt=w["dt"])
+    uo, vo, co = s.fv_step_scalar(prm, w["diffusivity"], u, v, c)
+    oprm = oracle_prm(nx, ny, lx=w["lx"], ly=w["ly"], nu=w["nu"], dt=w["dt"],
+                      diffusivity=w["diffusivity"])
+    for b in (0, B - 1):
+        ru, rv, rc = scalar.fv_step_scalar(cpu64(u[b:b + 1]), cpu64(v[b:b + 1]),
+                                           cpu64(c[b:b + 1]), oprm)
+        e = (rel_l2(uo[b:b + 1], ru), rel_l2(vo[b:b + 1], rv), rel_l2(co[b:b + 1], rc))
+        assert max(e) < 1e-5, (b, e)
