@@ -174,7 +174,7 @@ def oracle_timed(call, cells_per_call, what, budget_s=2.0):
 
 def fp64_errors():
     """Errors of the other results against the FP64 oracle (the oracle is run
-    here as the checker, outside every timed region): the learned step of the
+    here as the reference, outside every timed region): the learned step of the
     forced-flow workload (trajectory 0 of the batch of 64, bench network),
     its network output, the flux-block step of the same workload, and 200
     FP64 Burgers steps."""
