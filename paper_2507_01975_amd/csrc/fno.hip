@@ -478,13 +478,14 @@ __global__ void __launch_bounds__(kBlock) k_fno_proj_bwd(const float* __restrict
 // kWChunk pixels of one (network, trajectory): part[z][b][chunk][C C + C].
 // v_i = GELU(vpre_i) when GELU_V (v_l for l >= 1 from the saved z_{l-1}),
 // else vpre itself (v_0).  Grid (chunks, nnet B); block C*C: thread (o, i).
-constexpr int kWChunk = 1024;
+constexpr int kWChunk = 256;
 template <int C, bool GELU_V>
 __global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ dz,
                                                      const float* __restrict__ vpre,
                                                      float* __restrict__ part, int n, int B) {
   constexpr int kT = 64;          // pixels per tile
   constexpr int kS = kT + 4;      // padded row (16-byte aligned, spreads banks)
+  constexpr int kPer = kT / C;    // tile values per thread and operand
   __shared__ __attribute__((aligned(16))) float sdz[C][kS];
   __shared__ __attribute__((aligned(16))) float sv[C][kS];
   const int zb = blockIdx.y;      // z * B + b
@@ -492,15 +493,32 @@ __global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ d
   const float* d = dz + (size_t)zb * C * n;
   const float* vp = vpre + (size_t)zb * C * n;
   float acc = 0.f, accb = 0.f;
+  const int pbeg = blockIdx.x * kWChunk;
   const int pend = min(n, (int)(blockIdx.x + 1) * kWChunk);
-  for (int p0 = blockIdx.x * kWChunk; p0 < pend; p0 += kT) {
-    for (int e = threadIdx.x; e < C * kT; e += C * C) {
-      const int c = e / kT, q = e - c * kT;
-      const float x = vp[(size_t)c * n + p0 + q];
-      sdz[c][q] = d[(size_t)c * n + p0 + q];
-      sv[c][q] = GELU_V ? cnnk::gelu_exact(x) : x;
+  // a tile's operands through registers (all loads in flight together), the
+  // next tile's loads issued before the current tile's products
+  float dv[kPer], xv[kPer];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = k * C * C + (int)threadIdx.x;
+      const int c = e / kT, q = e % kT;
+      dv[k] = d[(size_t)c * n + p0 + q];
+      xv[k] = vp[(size_t)c * n + p0 + q];
+    }
+  };
+  if (pbeg < pend) load(pbeg);
+  for (int p0 = pbeg; p0 < pend; p0 += kT) {
+    __syncthreads();  // the previous tile's products are done
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = k * C * C + (int)threadIdx.x;
+      const int c = e / kT, q = e % kT;
+      sdz[c][q] = dv[k];
+      sv[c][q] = GELU_V ? cnnk::gelu_exact(xv[k]) : xv[k];
     }
     __syncthreads();
+    if (p0 + kT < pend) load(p0 + kT);
 #pragma unroll 4
     for (int q = 0; q < kT; q += 4) {
       const float4 dd = *reinterpret_cast<const float4*>(&sdz[o][q]);
@@ -508,7 +526,6 @@ __global__ void __launch_bounds__(C * C) k_fno_wgrad(const float* __restrict__ d
       acc += dd.x * vv.x + dd.y * vv.y + dd.z * vv.z + dd.w * vv.w;
       accb += dd.x + dd.y + dd.z + dd.w;
     }
-    __syncthreads();
   }
   float* dst = part + ((size_t)zb * gridDim.x + blockIdx.x) * (C * C + C);
   dst[o * C + i] = acc;
@@ -616,21 +633,42 @@ struct PartOut {
 // out_z[j] += sum over blk of part[(z nblk + blk) stride + off + j]: eight
 // interleaved running sums (blk mod 8, so eight loads are in flight) added
 // in a fixed order at the end
+template <int S>
 __global__ void __launch_bounds__(kBlock) k_sum_partials(const float* __restrict__ part, int nblk,
                                                          size_t stride, int off, int len,
                                                          PartOut po) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
+  // S threads share an output (short outputs over many partials): thread s
+  // takes the partials s, s + S, ... eight at a time, the S sums are added
+  // in order through LDS
+  constexpr int kO = kBlock / S;
+  __shared__ float red[S][kO];
+  const int jo = threadIdx.x % kO, sp = threadIdx.x / kO;
+  const int j = blockIdx.x * kO + jo;
   const int z = blockIdx.z;
-  if (j >= len) return;
-  const float* p = part + (size_t)z * nblk * stride + off + j;
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int k = 0;
-  for (; k + 8 <= nblk; k += 8) {
+  float t = 0.f;
+  if (j < len) {
+    const float* p = part + (size_t)z * nblk * stride + off + j;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int k = sp;
+    for (; k + 7 * S < nblk; k += 8 * S) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] += p[(size_t)(k + q) * stride];
+      for (int q = 0; q < 8; ++q) acc[q] += p[(size_t)(k + q * S) * stride];
+    }
+    for (int q = 0; k < nblk; k += S, ++q) acc[q & 7] += p[(size_t)k * stride];
+    t = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
-  for (int q = 0; k < nblk; ++k, ++q) acc[q] += p[(size_t)k * stride];
-  po.out[z][j] += ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  if constexpr (S == 1) {
+    if (j < len) po.out[z][j] += t;
+  } else {
+    red[sp][jo] = t;
+    __syncthreads();
+    if (sp == 0 && j < len) {
+      float r = 0.f;
+#pragma unroll
+      for (int q = 0; q < S; ++q) r += red[q][jo];
+      po.out[z][j] += r;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_zero(float* __restrict__ p, size_t n) {
@@ -863,8 +901,12 @@ int sum_partials(ldsv_handle* h, const FnoShape& sh, const FnoArgs& a, const flo
                  hipStream_t st) {
   PartOut po{};
   for (int z = 0; z < sh.nnet; ++z) po.out[z] = outs[a.net[z]];
-  LDSV_TLAUNCH(h, 7, k_sum_partials, dim3((len + kBlock - 1) / kBlock, 1, sh.nnet), dim3(kBlock),
-               0, st, part, nblk, stride, off, len, po);
+  if (len <= 4096 && nblk >= 64)
+    LDSV_TLAUNCH(h, 7, k_sum_partials<16>, dim3((len + kBlock / 16 - 1) / (kBlock / 16), 1, sh.nnet),
+                 dim3(kBlock), 0, st, part, nblk, stride, off, len, po);
+  else
+    LDSV_TLAUNCH(h, 7, k_sum_partials<1>, dim3((len + kBlock - 1) / kBlock, 1, sh.nnet),
+                 dim3(kBlock), 0, st, part, nblk, stride, off, len, po);
   return LDSV_OK;
 }
 
