@@ -198,6 +198,18 @@ __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restr
   }
 }
 
+// Persistent loops: slot s = g + k G is the k-th tile of workgroup g (grid G).
+// Workgroups reach the 8 XCDs round-robin by id, so the slot is renumbered to
+// give XCD x = g % 8 the contiguous tile range [x T/8, (x+1) T/8): the tiles of one
+// image, whose halos overlap, are then in flight on one XCD at the same time
+// and the shared halo rows come from its L2 once.  A bijection of [0, T) (the
+// identity unless 8 divides both T and G).
+__device__ __forceinline__ int xcd_slot_tile(int s, int T, int G) {
+  if ((T & 7) || (G & 7)) return s;
+  const int g = s % G, k = s / G;
+  return (g & 7) * (T >> 3) + k * (G >> 3) + (g >> 3);
+}
+
 // The same convolution for grids whose sides are multiples of 16, as a
 // persistent kernel (used for the 66-output last layer; the 64-output layers
 // use k_conv3x3_dma below): a workgroup first stages the layer's whole weight
@@ -398,9 +410,11 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
       }
     }
   };
-  if ((int)blockIdx.x < ntiles) load_tile(blockIdx.x);
+  const int G = gridDim.x;
+  if ((int)blockIdx.x < ntiles) load_tile(xcd_slot_tile(blockIdx.x, ntiles, G));
   int prev = -1;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int s = blockIdx.x; s < ntiles; s += G) {
+    const int tile = xcd_slot_tile(s, ntiles, G);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kTPer; ++k) {
@@ -411,7 +425,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
       }
     }
     __syncthreads();
-    if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);
+    if (s + G < ntiles) load_tile(xcd_slot_tile(s + G, ntiles, G));
     if (grp == 1 && prev >= 0) epilogue(prev);
     mma();
     if (grp == 0) epilogue(tile);
@@ -553,16 +567,18 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
       }
     }
   };
+  const int G = gridDim.x;
   int sbuf = 0;
-  if ((int)blockIdx.x < ntiles) issue_tile(blockIdx.x, 0);
+  if ((int)blockIdx.x < ntiles) issue_tile(xcd_slot_tile(blockIdx.x, ntiles, G), 0);
   int prev = -1;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int s = blockIdx.x; s < ntiles; s += G) {
+    const int tile = xcd_slot_tile(s, ntiles, G);
     // this wavefront's loads of the current tile (and, the first time, of
     // the weights) have landed; after the barrier everyone's have, and every
     // wavefront is done reading the other buffer
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tile + (int)gridDim.x < ntiles) issue_tile(tile + gridDim.x, sbuf ^ 1);
+    if (s + G < ntiles) issue_tile(xcd_slot_tile(s + G, ntiles, G), sbuf ^ 1);
     if (grp == 1 && prev >= 0) epilogue(prev);
     mma(xbuf + sbuf * kDmaTile);
     if (grp == 0) epilogue(tile);
