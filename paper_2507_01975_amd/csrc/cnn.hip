@@ -154,8 +154,6 @@ int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const f
   const int nblk = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
   // 16 x 16 LDS tiles when both sides are multiples of 16
   const bool tiled = (h->g.nx % 16 == 0) && (h->g.ny % 16 == 0);
-  const int ntile = (int)(h->nstate / 256);
-  (void)ntile;
   for (int l = 1; l < 5; ++l) {
     if (tiled)
       LDSV_TRY(ldsv_launch_conv_tile(h, 4, 0, h->act[l - 1], net->w[l], net->b[l], kC, h->act[l],
