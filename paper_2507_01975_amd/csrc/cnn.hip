@@ -68,17 +68,23 @@ __global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__
 #pragma unroll
     for (int t = 0; t < kFirstTiles; ++t) acc[t][m] = b0;
   }
+  // the grid sides are powers of two: trajectory, row and column of a pixel
+  // by shifts and masks, once per pixel; the taps wrap periodically
+  const int hw = pm.H * pm.W;
+  const int lw = __builtin_ctz(pm.W), lhw = __builtin_ctz(hw);
 #pragma unroll
   for (int t = 0; t < kFirstTiles; ++t) {
     int p = pbase + t * 16 + col;
     p = p < pm.total ? p : pm.total - 1;
+    const int base = (p >> lhw) << lhw;
+    const int y = (p & (hw - 1)) >> lw, x = p & (pm.W - 1);
     bf16x8 bfrag;
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
       const int tap = (kq * 8 + e) / 2;
       float a = 0.f, b = 0.f;
       if (tap < 9) {
-        const int q = pm.shift(p, tap / 3 - 1, tap % 3 - 1);
+        const int q = base + ((y + tap / 3 - 1) & (pm.H - 1)) * pm.W + ((x + tap % 3 - 1) & (pm.W - 1));
         a = u[q];
         b = v[q];
       }
