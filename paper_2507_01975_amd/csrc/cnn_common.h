@@ -74,15 +74,16 @@ __device__ __forceinline__ float gelu_grad(float z) {
 }
 
 struct PixMap {
-  int H, W;
+  int H, W;   // powers of two
   int total;  // B * H * W
+  // pixel p moved by (dy, dx) with periodic wrap within its trajectory;
+  // trajectory, row and column by shifts and masks (no integer division)
   __device__ __forceinline__ int shift(int p, int dy, int dx) const {
     const int hw = H * W;
-    const int b = p / hw;
-    const int r = p - b * hw;
-    const int y = r / W;
-    const int x = r - y * W;
-    return b * hw + ((y + dy) & (H - 1)) * W + ((x + dx) & (W - 1));
+    const int lw = __builtin_ctz(W), lhw = __builtin_ctz(hw);
+    const int y = (p & (hw - 1)) >> lw;
+    const int x = p & (W - 1);
+    return ((p >> lhw) << lhw) + ((y + dy) & (H - 1)) * W + ((x + dx) & (W - 1));
   }
 };
 
