@@ -119,9 +119,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_faces(const T* __restrict__ us, 
   const T idx = (T)(1.0 / ph.dx), idy = (T)(1.0 / ph.dy);
   const T nu = (T)ph.nu;
   const bool adv = ph.mask & LDSV_ADVECTION, visc = ph.mask & LDSV_VISCOSITY;
+  const int lnx = __builtin_ctz(nx);  // nx is a power of two
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx), j = (int)(c / nx);
+    const int i = (int)c & (nx - 1), j = (int)c >> lnx;
     auto lam_u = [&](int a, int bb) {
       const size_t q = (size_t)((j + bb) & (ny - 1)) * nx + ((i + a) & (nx - 1));
       T l = cA * LA_u.p[q];
@@ -292,9 +293,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
   const float* cb = LEARNED ? coef + (size_t)b * cbs : nullptr;
   const float* db = MODE == 3 ? dcoef + (size_t)b * cbs : nullptr;
   const T wv[4] = {(T)1, (T)-27, (T)27, (T)-1};  // derivative weights for offsets -1..2
+  const int lnx = __builtin_ctz(nx);  // nx is a power of two
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx), j = (int)(c / nx);
+    const int i = (int)c & (nx - 1), j = (int)c >> lnx;
     auto at = [&](int plane, int ii, int jj) {
       return S[(size_t)plane * n + (size_t)(jj & (ny - 1)) * nx + (ii & (nx - 1))];
     };
