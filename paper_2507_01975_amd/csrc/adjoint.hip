@@ -294,8 +294,14 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
   const float* db = MODE == 3 ? dcoef + (size_t)b * cbs : nullptr;
   const T wv[4] = {(T)1, (T)-27, (T)27, (T)-1};  // derivative weights for offsets -1..2
   const int lnx = __builtin_ctz(nx);  // nx is a power of two
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (size_t)gridDim.x * blockDim.x) {
+  // learned modes: QS adjacent lanes per cell, lane q gathering footprint
+  // points 4q..4q+3 of every kind (4x the wavefronts in flight for the
+  // scattered coefficient loads); the partial sums are combined by two
+  // fixed xor-shuffle steps, so every lane of the cell holds the same total
+  constexpr int QS = LEARNED ? 4 : 1;
+  const int q = (int)threadIdx.x & (QS - 1);
+  for (size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / QS; c < n;
+       c += (size_t)gridDim.x * blockDim.x / QS) {
     const int i = (int)c & (nx - 1), j = (int)c >> lnx;
     auto at = [&](int plane, int ii, int jj) {
       return S[(size_t)plane * n + (size_t)(jj & (ny - 1)) * nx + (ii & (nx - 1))];
@@ -311,16 +317,24 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
       return (s == 5 || s == 6) ? (T)0.5 : (T)0;
     };
     T gu = 0, gv = 0;
-    // advecting-velocity parts
-    gu += at(0, i, j) + at(0, i - 1, j);          // P0: u(o), u(o+x)
-    gu += at(2, i - 1, j + 1) + at(2, i - 1, j);  // P2: u(o+x, o-y), u(o+x)
-    gv += at(1, i + 1, j - 1) + at(1, i, j - 1);  // P1: v(o-x+y), v(o+y)
-    gv += at(3, i, j) + at(3, i, j - 1);          // P3: v(o), v(o+y)
+    if (q == 0) {
+      // advecting-velocity parts
+      gu += at(0, i, j) + at(0, i - 1, j);          // P0: u(o), u(o+x)
+      gu += at(2, i - 1, j + 1) + at(2, i - 1, j);  // P2: u(o+x, o-y), u(o+x)
+      gv += at(1, i + 1, j - 1) + at(1, i, j - 1);  // P1: v(o-x+y), v(o+y)
+      gv += at(3, i, j) + at(3, i, j - 1);          // P3: v(o), v(o+y)
+    }
+    // footprint point 4q + k: a 4 x 3 block for q < 3 (offsets (k-1, q-1)),
+    // the points (0|1, -2) and (0|1, 2) for q = 3
+    const bool blk = q < 3;
+    auto pa = [&](int k) { return blk ? k - 1 : (k & 1); };
+    auto pb = [&](int k) { return blk ? q - 1 : (k < 2 ? -2 : 2); };
     // interpolation stencils
     if (LEARNED) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int a = kAOffA[s], bb = kBOffA[s];
+      for (int k = 0; k < 4; ++k) {
+        const int s = 4 * q + k;
+        const int a = pa(k), bb = pb(k);
         gu += coefv(0, s, i - a, j - bb) * at(4, i - a, j - bb);
         gu += coefv(1, s, i - bb, j - a) * at(5, i - bb, j - a);
         gv += coefv(2, s, i - a, j - bb) * at(6, i - a, j - bb);
@@ -347,21 +361,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
     if constexpr (MODE == 3) {
       // learned face derivatives: owner o sends 24 V w_s (V = -nu Fb / (24 h))
       // to its footprint point s, w rebuilt from o's raw values and moments
-      auto dw = [&](int K, int s, int ii, int jj) -> T {
+      auto dw = [&](int K, int s, int a, int bb, int ii, int jj) -> T {
         const size_t o = cidx(ii, jj);
         return (T)db[(size_t)(16 * K + s) * n + o] - S[(size_t)(16 + K) * n + o] -
-               ((T)a_off20(s) - (T)0.5) * S[(size_t)(20 + K) * n + o] -
-               (T)b_off20(s) * S[(size_t)(24 + K) * n + o] + (T)deriv4_w(s);
+               ((T)a - (T)0.5) * S[(size_t)(20 + K) * n + o] -
+               (T)bb * S[(size_t)(24 + K) * n + o] + (T)deriv4_w(s);
       };
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int a = a_off20(s), bb = b_off20(s);
-        gu += (T)24 * (dw(0, s, i - a, j - bb) * at(8, i - a, j - bb) +
-                       dw(1, s, i - bb, j - a) * at(9, i - bb, j - a));
-        gv += (T)24 * (dw(2, s, i - a, j - bb) * at(10, i - a, j - bb) +
-                       dw(3, s, i - bb, j - a) * at(11, i - bb, j - a));
+      for (int k = 0; k < 4; ++k) {
+        const int s = 4 * q + k;
+        const int a = pa(k), bb = pb(k);
+        gu += (T)24 * (dw(0, s, a, bb, i - a, j - bb) * at(8, i - a, j - bb) +
+                       dw(1, s, a, bb, i - bb, j - a) * at(9, i - bb, j - a));
+        gv += (T)24 * (dw(2, s, a, bb, i - a, j - bb) * at(10, i - a, j - bb) +
+                       dw(3, s, a, bb, i - bb, j - a) * at(11, i - bb, j - a));
       }
-    } else {
+    } else if (q == 0) {
       // viscous face derivatives: owner o = p - m sends V * w_m to p
 #pragma unroll
       for (int m = -1; m <= 2; ++m) {
@@ -369,6 +384,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(const T* __restrict__ scr
         gu += w * (at(8, i - m, j) + at(9, i, j - m));
         gv += w * (at(10, i - m, j) + at(11, i, j - m));
       }
+    }
+    if constexpr (QS > 1) {
+      gu += __shfl_xor(gu, 1);
+      gv += __shfl_xor(gv, 1);
+      gu += __shfl_xor(gu, 2);
+      gv += __shfl_xor(gv, 2);
+      if (q != 0) continue;
     }
     if (ph.mask & LDSV_FORCING) {
       T lu = (T)aA * Au[off + c], lv = (T)aA * Av[off + c];
@@ -485,6 +507,8 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
   AdjPhys ph{prm->nu, prm->drag, h->g.lx / h->g.nx, h->g.ly / h->g.ny, prm->physics_mask};
   const int nx = h->g.nx, ny = h->g.ny;
   dim3 grid((unsigned)std::min<size_t>((h->ncell + kBlock - 1) / kBlock, 4096), h->g.batch);
+  // the learned-mode gathers run 4 lanes per cell
+  dim3 grid4((unsigned)std::min<size_t>(4 * ((h->ncell + kBlock - 1) / kBlock), 4096), h->g.batch);
   T* scr = (T*)h->adj_g;
   AdjFB fb{nullptr, nullptr, 0, nullptr, 0};
   if (fbp) fb = AdjFB{fbp->w, fbp->f, fbp->fbs, fbp->gf, fbp->gfbs};
@@ -510,7 +534,7 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
     LDSV_TLAUNCH(h, 6, (k_adj_faces<T, 3>), grid, dim3(kBlock), 0, st, (const T*)us,
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
                        aG, coef, cbs, gcoef, gcbs, dc->d, dc->gd, fb, scr, ph, nx, ny);
-    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 3>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 3>), grid4, dim3(kBlock), 0, st, (const T*)scr, coef,
                        cbs, dc->d, (const float*)nullptr, (const T*)Au, (const T*)Av,
                        (const T*)Gu, (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv,
                        (T*)ou, (T*)ov, ph, nx, ny);
@@ -519,7 +543,7 @@ int adj_rhs_t(ldsv_handle* h, const ldsv_params* prm, const float* coef, size_t 
                        (const T*)vs, (const T*)Au, (const T*)Av, (const T*)Gu, (const T*)Gv, aA,
                        aG, coef, cbs, gcoef, gcbs, (const float*)nullptr, (float*)nullptr, fb,
                        scr, ph, nx, ny);
-    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 1>), grid, dim3(kBlock), 0, st, (const T*)scr, coef,
+    LDSV_TLAUNCH(h, 6, (k_adj_gather<T, 1>), grid4, dim3(kBlock), 0, st, (const T*)scr, coef,
                        cbs, (const float*)nullptr, (const float*)nullptr, (const T*)Au, (const T*)Av, (const T*)Gu,
                        (const T*)Gv, aA, aG, (const T*)addu, (const T*)addv, (T*)ou, (T*)ov, ph,
                        nx, ny);
