@@ -21,6 +21,7 @@
 //   k_rowifft_grad   inverse FFT along x for rows j-1..j+R-1, then
 //                    u = u* - (p - p[i-1])/dx, v = v* - (p - p[j-1])/dy
 #include "fft_lds.h"
+#include <algorithm>
 
 namespace {
 
@@ -367,7 +368,11 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   int rows = (kRowE * kBlock) / nx;
   if (rows < 1) rows = 1;
   if (rows > ny) rows = ny;
-  const int block1 = rows * nx / kRowE > kBlock ? kRow1MaxBlock : kBlock;
+  // small batches: fewer rows per block until the launch has a workgroup per
+  // CU, the block sized to the rows (whole wavefronts)
+  while (rows > 1 && (size_t)(ny / rows) * h->npairs < 256) rows >>= 1;
+  const int need1 = rows * nx / kRowE;
+  const int block1 = need1 > kBlock ? kRow1MaxBlock : std::max(64, (need1 + 63) / 64 * 64);
   LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * block1, LDSV_ESHAPE,
                "project: nx=%d too large for the LDS row transform", nx);
   size_t lds = ((size_t)rows * nx + nx) * cs;
@@ -384,6 +389,10 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   while (cols > 1 && ((size_t)cols * ny > (size_t)kColE * kColBlock || (size_t)cols * ny * cs > 32768))
     cols >>= 1;
   if (cols > nx) cols = nx;
+  // small batches: narrower column groups until the launch has a workgroup
+  // per CU (the XCD-contiguous numbering keeps neighbouring groups, which
+  // share row segments, on one L2)
+  while (cols > 2 && (size_t)(nx / cols) * h->npairs < 256) cols >>= 1;
   LDSV_REQUIRE((size_t)cols * ny <= (size_t)kColE * kColBlock && (size_t)cols * ny * cs <= 65536,
                LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
   // 8 values per thread where the block allows it: twice the wavefronts of
@@ -403,12 +412,17 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   int rows3 = 4096 / nx;
   if (rows3 < 1) rows3 = 1;
   if (rows3 > ny) rows3 = ny;
-  LDSV_REQUIRE((size_t)(rows3 + 1) * nx <= (size_t)kRowE3 * kRow3Block, LDSV_ESHAPE,
+  // small batches as in pass 1, down to 4 rows per block (the halo row at
+  // most a fifth of the block's transforms)
+  while (rows3 > 4 && (size_t)(ny / rows3) * h->npairs < 256) rows3 >>= 1;
+  const int need3 = (rows3 + 1) * nx / kRowE3;
+  const int block3 = std::min(kRow3Block, std::max(64, (need3 + 63) / 64 * 64));
+  LDSV_REQUIRE((size_t)(rows3 + 1) * nx <= (size_t)kRowE3 * block3, LDSV_ESHAPE,
                "project: nx=%d too large for the LDS row transform", nx);
   lds = ((size_t)(rows3 + 1) * nx + nx) * cs;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_rowifft_grad<T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows3, h->npairs), dim3(kRow3Block), lds, st,
+  LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows3, h->npairs), dim3(block3), lds, st,
                (const Cx<T>*)h->zspec, (const Cx<T>*)h->twx, (const T*)us, (const T*)vs, (T*)uo,
                (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows3, idx, idy);
   LDSV_LAUNCHED();
