@@ -413,10 +413,14 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   if (rows3 < 1) rows3 = 1;
   if (rows3 > ny) rows3 = ny;
   // small batches as in pass 1, down to 4 rows per block (the halo row at
-  // most a fifth of the block's transforms)
-  while (rows3 > 4 && (size_t)(ny / rows3) * h->npairs < 256) rows3 >>= 1;
-  const int need3 = (rows3 + 1) * nx / kRowE3;
-  const int block3 = std::min(kRow3Block, std::max(64, (need3 + 63) / 64 * 64));
+  // most a fifth of the block's transforms), the block then sized to them;
+  // launches that already have a workgroup per CU keep the full block
+  int block3 = kRow3Block;
+  if ((size_t)(ny / rows3) * h->npairs < 256) {
+    while (rows3 > 4 && (size_t)(ny / rows3) * h->npairs < 256) rows3 >>= 1;
+    const int need3 = (rows3 + 1) * nx / kRowE3;
+    block3 = std::min(kRow3Block, std::max(64, (need3 + 63) / 64 * 64));
+  }
   LDSV_REQUIRE((size_t)(rows3 + 1) * nx <= (size_t)kRowE3 * block3, LDSV_ESHAPE,
                "project: nx=%d too large for the LDS row transform", nx);
   lds = ((size_t)(rows3 + 1) * nx + nx) * cs;
