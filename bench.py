@@ -180,14 +180,14 @@ def fp64_errors():
     FP64 Burgers steps."""
     import torch
     import synthetic_inputs as si
-    from oracle import cnn as ocnn, fv as ofv, ic as oic, learned as olearned
+    from oracle import fv as ofv, ic as oic, learned as olearned
     from oracle import timestep as ots
     from paper_2507_01975_amd import ldsv
     out = {}
     w = si.WORKLOADS["kolmogorov64"]
     n, B = w["nx"], w["batch"]
     s = ldsv.Solver(n, n, B)
-    ws, bs = si.cnn_weights(0, ocnn.LAYERS)
+    ws, bs = si.cnn_weights(0, ldsv.LAYERS)
     net = ldsv.NetParams([torch.tensor(x) for x in ws], [torch.tensor(x) for x in bs])
     u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
     kw = dict(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"], forcing_k=w["forcing_k"],
@@ -201,7 +201,7 @@ def fp64_errors():
     out["learned_step_rel_l2_vs_fp64"] = max(_rel_l2(uo[:1], eu), _rel_l2(vo[:1], ev))
     out["network_output_rel_l2_vs_fp64"] = _rel_l2(no[:1], eo)
     # with the derivative-stencil network beside it (trajectory 0)
-    dws, dbs = si.cnn_weights(1, ocnn.LAYERS)
+    dws, dbs = si.cnn_weights(1, ldsv.LAYERS)
     dnet = ldsv.NetParams([torch.tensor(x) for x in dws], [torch.tensor(x) for x in dbs])
     du, dv = s.learned_d_fv_step(ldsv.params(k_c=1, **kw), net, dnet, u, v, 1)
     dwb = [x.double().cpu() for x in dnet.bf16_weights()]
@@ -236,12 +236,11 @@ def fp64_errors():
 def learned_block(steps, warmup):
     import torch
     import synthetic_inputs as si
-    from oracle import cnn as ocnn
     from paper_2507_01975_amd import ldsv
     w = si.WORKLOADS["kolmogorov64"]
     n, B = w["nx"], w["batch"]
     s = ldsv.Solver(n, n, B)
-    ws, bs = si.cnn_weights(0, ocnn.LAYERS)
+    ws, bs = si.cnn_weights(0, ldsv.LAYERS)
     net = ldsv.NetParams([torch.tensor(x) for x in ws], [torch.tensor(x) for x in bs])
     u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)
     prm = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
@@ -298,14 +297,13 @@ def learned_deriv_block(steps, warmup):
     the correction's 8 B/cell in the last stage, 2 B/cell averaged)."""
     import torch
     import synthetic_inputs as si
-    from oracle import cnn as ocnn
     from paper_2507_01975_amd import ldsv
     w = si.WORKLOADS["kolmogorov64"]
     n, B = w["nx"], w["batch"]
     s = ldsv.Solver(n, n, B)
     nets = []
     for seed in (0, 1):
-        ws, bs = si.cnn_weights(seed, ocnn.LAYERS)
+        ws, bs = si.cnn_weights(seed, ldsv.LAYERS)
         nets.append(ldsv.NetParams([torch.tensor(x) for x in ws], [torch.tensor(x) for x in bs]))
     net, dnet = nets
     u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=200)

@@ -10,7 +10,9 @@ divergence-free.  Collocated fields use the block mean.
 Vorticity at corners (i dx, j dy):
   w[j, i] = (v[j, i] - v[j, i-1]) / dx - (u[j, i] - u[j-1, i]) / dy.
 
-Metrics (App. D.1, S32-S36): RMSE, MAE, MNAD, PCC and HCT.  PCC is the
+Metrics (App. D.1, S32-S36): RMSE, MAE, MNAD, PCC and HCT.  Flow
+statistics of a state: kinetic energy 1/2 <u^2 + v^2> and enstrophy
+1/2 <w^2> (means over cells, per trajectory).  PCC is the
 centred Pearson correlation per snapshot; HCT sums dt over snapshots whose PCC
 exceeds a threshold (0.8 in the paper).
 """
@@ -31,6 +33,18 @@ def downsample_collocated(q, r):
 
 def vorticity(u, v, dx, dy):
     return (v - torch.roll(v, 1, dims=-1)) / dx - (u - torch.roll(u, 1, dims=-2)) / dy
+
+
+def energy(u, v):
+    """Kinetic energy per trajectory: 1/2 of the cell mean of u^2 + v^2."""
+    return 0.5 * (u * u + v * v).mean(dim=(-2, -1))
+
+
+def enstrophy(u, v, dx, dy):
+    """Enstrophy per trajectory: 1/2 of the cell mean of the squared corner
+    vorticity."""
+    w = vorticity(u, v, dx, dy)
+    return 0.5 * (w * w).mean(dim=(-2, -1))
 
 
 def pcc(a, b):

@@ -21,6 +21,9 @@ RK4, SSPRK3 = 0, 1
 ADVECTION, VISCOSITY, FORCING, ALL_PHYSICS = 1, 2, 4, 7
 IC_FOURIER_MODES, IC_GRF_PEAK, IC_TGV, IC_SHEAR_LAYER = 0, 1, 2, 3
 NCOEF, NOUT, NLAYERS = 64, 66, 6
+# (C_in, C_out) of the coefficient network's six 3x3 layers, as ldsv_net lays
+# them out: 2 -> 64 -> 64 -> 64 -> 64 -> 64 -> 66
+LAYERS = [(2, 64)] + [(64, 64)] * (NLAYERS - 2) + [(64, NOUT)]
 
 
 class LdsvError(RuntimeError):

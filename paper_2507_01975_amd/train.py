@@ -513,7 +513,7 @@ def init_network(seed=0, last_scale=1e-3):
     last_scale so that the learned correction starts small (Sec. 3.4: the
     learnable kernel starts from small random values)."""
     g = torch.Generator().manual_seed(seed)
-    layers = [(2, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 66)]
+    layers = ldsv.LAYERS
     ws, bs = [], []
     for li, (ci, co) in enumerate(layers):
         w = torch.randn(co, ci, 3, 3, generator=g) * math.sqrt(2.0 / (9 * ci))

@@ -20,6 +20,16 @@ def rel_l2(a, b):
     return ((a - b).norm() / b.norm().clamp_min(1e-300)).item()
 
 
+def assert_fields_close(got, ref, rel=1e-5, elem=1e-5, what=""):
+    """Relative L2 error <= rel, and every element within elem * max|ref|
+    (so that an error confined to a few cells, such as a tile seam, cannot
+    hide under the L2 norm of the whole field)."""
+    e = rel_l2(got, ref)
+    d = (got.double().cpu() - ref.double().cpu()).abs().max().item()
+    m = ref.double().abs().max().item()
+    assert e < rel and d <= elem * m, (what, e, d / max(m, 1e-300))
+
+
 def dev(x, dtype):
     return x.to("cuda", dtype).contiguous()
 

@@ -8,7 +8,7 @@ import torch
 
 import synthetic_inputs as si
 from oracle import cnn, fv, ic, learned, timestep
-from tests.gpu_common import L, announce, cpu64, dev, need_gpu, oracle_prm, rel_l2
+from tests.gpu_common import assert_fields_close, L, announce, cpu64, dev, need_gpu, oracle_prm, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -134,6 +134,93 @@ def test_rollout_equals_step_sequence():
     assert torch.equal(tu[0], pu) and torch.equal(tv[0], pv)
 
 
+@pytest.mark.parametrize("guard", [False, True])
+def test_rollout_matches_oracle(guard):
+    """ldsv_rollout of the coefficient network (Eq. 2 with k_c = 2: the
+    correction on even steps only) against the oracle: (1) each step from
+    the device's previous state with the device's network output, through
+    the oracle's FV step and correction schedule, to the FP32 step
+    tolerance; (2) the snapshots every 2 steps against the oracle's own
+    learned rollout (BF16-emulating network) over 6 steps.  With the guard
+    on (a bound it never reaches) the result is the same bit for bit."""
+    L_ = need_gpu()
+    announce("rollout vs oracle, guard", guard)
+    n, b, T, kc = 32, 3, 6, 2
+    net, wb, bb = _net(L_, seed=3, last_scale=0.05)
+    u, v = ic.grf_peak(b, n, n, L, L, seed=9)
+    u, v = u.float().double(), v.float().double()
+    s = L_.Solver(n, n, b)
+    gprm = dict(k_c=kc, fallback_enable=1 if guard else 0,
+                guard_threshold=1e3 if guard else 0.0, **KW)
+    prm = L_.params(**gprm)
+    flags = torch.zeros(b, dtype=torch.int32, device="cuda")
+    u0, v0 = dev(u, torch.float32), dev(v, torch.float32)
+    tu, tv = s.rollout(prm, u0, v0, nsteps=T, save_every=1, net=net,
+                       fallback_flags=flags if guard else None)
+    oprm = oracle_prm(n, n, k_c=kc, **KW)
+    from oracle.projection import project
+    prev_u, prev_v = u0, v0
+    for k in range(1, T + 1):
+        out = cpu64(s.cnn_forward(net, prev_u.contiguous(), prev_v.contiguous()))
+        eu, ev = timestep.fv_step(cpu64(prev_u), cpu64(prev_v), oprm,
+                                  learned.constrain(out[:, :64]))
+        if k % kc == 0:
+            eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
+        for bb_ in range(b):
+            assert rel_l2(tu[k - 1, bb_], eu[bb_]) < 1e-5, (k, bb_)
+            assert rel_l2(tv[k - 1, bb_], ev[bb_]) < 1e-5, (k, bb_)
+        prev_u, prev_v = tu[k - 1], tv[k - 1]
+    su, sv = s.rollout(prm, u0, v0, nsteps=T, save_every=2, net=net)
+    assert torch.equal(su, tu[1::2]) and torch.equal(sv, tv[1::2])
+    ou, ov = learned.learned_rollout(u, v, oprm, wb, bb, T, first_index=1, bf16=True)
+    errs = [max(rel_l2(su[t], ou[2 * t + 1]), rel_l2(sv[t], ov[2 * t + 1])) for t in range(T // 2)]
+    print("rollout rel-L2 vs the bf16-emulating oracle at steps 2, 4, 6:", errs)
+    # BF16 rounding flips of single network outputs (a few in 10^4, each one
+    # bf16 ulp of a coefficient) move a step by about 1e-5 relative; they
+    # compound over the steps
+    assert max(errs) < 3e-4, errs
+    if guard:
+        torch.cuda.synchronize()
+        assert flags.tolist() == [0] * b
+        p0 = L_.params(k_c=kc, fallback_enable=0, **KW)
+        nu_, nv_ = s.rollout(p0, u0, v0, nsteps=T, save_every=2, net=net)
+        assert torch.equal(nu_, su) and torch.equal(nv_, sv)
+
+
+def test_guard_fallback_matches_oracle_plain_step():
+    """A trajectory over the guard bound is recomputed with the plain FV step:
+    its state after the rollout equals the oracle's plain steps from the
+    same start, the others the oracle's learned steps given the device's
+    network output."""
+    L_ = need_gpu()
+    announce("guard vs oracle")
+    n, b = 32, 3
+    kw = dict(KW, dt=0.005)
+    net, _, _ = _net(L_, seed=4)
+    s = L_.Solver(n, n, b)
+    u0, v0 = s.init_state(L_.IC_GRF_PEAK, seed=7)
+    u0[2] *= 8.0
+    v0[2] *= 8.0
+    bound = 4.0 * float((u0[:2].abs() + v0[:2].abs()).max())
+    prm = L_.params(k_c=1, guard_threshold=bound, fallback_enable=1, **kw)
+    flags = torch.zeros(b, dtype=torch.int32, device="cuda")
+    tu, tv = s.rollout(prm, u0, v0, nsteps=2, save_every=1, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    assert flags.tolist() == [0, 0, 2]
+    oprm = oracle_prm(n, n, k_c=1, **kw)
+    pu, pv = timestep.fv_step(cpu64(u0[2:]), cpu64(v0[2:]), oprm, nsteps=2)
+    assert rel_l2(tu[1, 2], pu[0]) < 1e-5 and rel_l2(tv[1, 2], pv[0]) < 1e-5
+    from oracle.projection import project
+    cu, cv = u0[:2].contiguous(), v0[:2].contiguous()
+    s2 = L_.Solver(n, n, 2)
+    for k in range(2):
+        out = cpu64(s2.cnn_forward(net, cu, cv))
+        eu, ev = timestep.fv_step(cpu64(cu), cpu64(cv), oprm, learned.constrain(out[:, :64]))
+        eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
+        assert rel_l2(tu[k, :2], eu) < 1e-5 and rel_l2(tv[k, :2], ev) < 1e-5, k
+        cu, cv = tu[k, :2].contiguous(), tv[k, :2].contiguous()
+
+
 def test_guard_falls_back_to_plain_fv_for_the_failing_trajectory_only():
     L_ = need_gpu()
     announce("guard")
@@ -219,8 +306,8 @@ def test_bf16_conversion_rounds_to_nearest_even():
 def test_kolmogorov64_full_size_learned_step():
     """The learned step at the benchmark's inference configuration (64^2,
     batch 64, the forced-flow parameters and time step), in the launch
-    configuration the benchmark times; trajectories 0, 31 and 63 are checked
-    against the oracle given the device's network output, and the network
+    configuration the benchmark times; every trajectory is checked against
+    the oracle given the device's network output, and the network
     output of trajectory 63 against the bf16-emulating oracle network."""
     L_ = need_gpu()
     announce("kolmogorov64 learned step")
@@ -239,12 +326,13 @@ def test_kolmogorov64_full_size_learned_step():
     assert torch.equal(pu, uo) and torch.equal(pv, vo)
     oprm = oracle_prm(n, n, k_c=1, **kw)
     from oracle.projection import project
-    for b in (0, 31, B - 1):
-        u0, v0 = cpu64(gu[b:b + 1]), cpu64(gv[b:b + 1])
-        out = cpu64(no[b:b + 1])
-        eu, ev = timestep.fv_step(u0, v0, oprm, learned.constrain(out[:, :64]))
-        eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
-        assert rel_l2(uo[b:b + 1], eu) < 1e-5 and rel_l2(vo[b:b + 1], ev) < 1e-5, b
+    # every trajectory, in L2 and element by element
+    out = cpu64(no)
+    eu, ev = timestep.fv_step(cpu64(gu), cpu64(gv), oprm, learned.constrain(out[:, :64]))
+    eu, ev, _ = project(eu + out[:, 64], ev + out[:, 65], oprm)
+    for b in range(B):
+        assert_fields_close(uo[b], eu[b], what=("u", b))
+        assert_fields_close(vo[b], ev[b], what=("v", b))
     x = torch.stack([cpu64(gu[B - 1:B]), cpu64(gv[B - 1:B])], dim=1)
     ref = cnn.cnn_forward(x, wb, bb, bf16=True)
     assert rel_l2(no[B - 1:B], ref) < 5e-3

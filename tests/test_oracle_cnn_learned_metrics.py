@@ -187,3 +187,89 @@ def test_oracle_autograd_matches_central_differences():
               - loss(u - h * du, v - h * dv, coef - h * dc)) / (2 * h)
         ad = (ua.grad * du).sum() + (va.grad * dv).sum() + (ca.grad * dc).sum()
         assert abs(fd.item() - ad.item()) <= 1e-7 * abs(ad.item()) + 1e-9
+
+
+def test_cfl_dt_against_the_rule():
+    # dt = cfl * min(dx, dy) / max over cells and trajectories of |u| + |v|:
+    # u = A cos(2 pi i / 16) peaks at i = 0, v = B sin(2 pi j / 8) at j = 2,
+    # so the max is A + B on the second trajectory (scaled by 3)
+    nx, ny = 16, 8
+    prm = fv.grid_params(nx, ny, lx=2.0, ly=L)
+    i = torch.arange(nx, dtype=torch.float64).view(1, -1)
+    j = torch.arange(ny, dtype=torch.float64).view(-1, 1)
+    a, b = 0.7, 0.4
+    u = (a * torch.cos(2 * math.pi * i / nx)).expand(ny, nx)
+    v = (b * torch.sin(2 * math.pi * j / ny)).expand(ny, nx)
+    u = torch.stack([u, 3 * u])
+    v = torch.stack([v, 3 * v])
+    dt = timestep.cfl_dt(u, v, prm, 0.5)
+    assert dt == pytest.approx(0.5 * min(2.0 / nx, L / ny) / (3 * (a + b)), rel=1e-14)
+    # a single sign flip anywhere does not change |u| + |v|
+    assert timestep.cfl_dt(-u, v, prm, 0.5) == pytest.approx(dt, rel=1e-15)
+
+
+def test_mse_rmse_mae_against_written_out_sums():
+    g = torch.Generator().manual_seed(21)
+    pu, pv, lu, lv = (torch.randn(2, 3, 4, generator=g, dtype=torch.float64) for _ in range(4))
+    n = pu.numel()
+    su = sum((pu.flatten()[k].item() - lu.flatten()[k].item()) ** 2 for k in range(n))
+    sv = sum((pv.flatten()[k].item() - lv.flatten()[k].item()) ** 2 for k in range(n))
+    from oracle.optim import mse_loss
+    assert mse_loss(pu, pv, lu, lv).item() == pytest.approx(0.5 * (su / n + sv / n), rel=1e-14)
+    # its gradient is (pred - label) / n per component, the cotangent the
+    # rollout backward feeds the adjoint
+    a = pu.clone().requires_grad_(True)
+    mse_loss(a, pv, lu, lv).backward()
+    assert torch.allclose(a.grad, (pu - lu) / n, rtol=1e-14, atol=0)
+    # RMSE and MAE (S32, S33): written-out sums, a constant error, and the
+    # textbook inequality MAE <= RMSE
+    d = [pu.flatten()[k].item() - lu.flatten()[k].item() for k in range(n)]
+    assert metrics.rmse(pu, lu).item() == pytest.approx(math.sqrt(sum(x * x for x in d) / n),
+                                                        rel=1e-14)
+    assert metrics.mae(pu, lu).item() == pytest.approx(sum(abs(x) for x in d) / n, rel=1e-14)
+    assert metrics.mae(pu, lu).item() <= metrics.rmse(pu, lu).item()
+    c = torch.full_like(pu, -0.25)
+    assert metrics.rmse(lu + c, lu).item() == pytest.approx(0.25, rel=1e-14)
+    assert metrics.mae(lu + c, lu).item() == pytest.approx(0.25, rel=1e-14)
+    e = torch.tensor([3.0, -4.0], dtype=torch.float64)
+    z = torch.zeros(2, dtype=torch.float64)
+    assert metrics.rmse(e, z).item() == pytest.approx(math.sqrt(12.5), rel=1e-15)
+    assert metrics.mae(e, z).item() == pytest.approx(3.5, rel=1e-15)
+
+
+def test_energy_and_enstrophy_of_the_taylor_green_vortex():
+    # u = sin x cos y, v = -cos x sin y sampled on the MAC faces: the cell
+    # means of sin^2 cos^2 are exactly 1/4 on any grid of 4+ cells, so the
+    # energy is 1/4; the corner vorticity is 2 sin x sin y s with
+    # s = 2 sin(h/2)/h, so the enstrophy is s^2 / 2
+    for n in (8, 16):
+        h = L / n
+        u, v = ic.taylor_green(2, n, n, L, L)
+        assert torch.allclose(metrics.energy(u, v), torch.full((2,), 0.25, dtype=torch.float64),
+                              atol=1e-15)
+        s = 2 * math.sin(h / 2) / h
+        assert torch.allclose(metrics.enstrophy(u, v, h, h),
+                              torch.full((2,), s * s / 2, dtype=torch.float64), atol=1e-14)
+    # energy by Parseval on a random field
+    g = torch.Generator().manual_seed(22)
+    a = torch.randn(1, 8, 8, generator=g, dtype=torch.float64)
+    b = torch.randn(1, 8, 8, generator=g, dtype=torch.float64)
+    fa, fb = torch.fft.fft2(a), torch.fft.fft2(b)
+    par = 0.5 * ((fa.abs() ** 2).sum() + (fb.abs() ** 2).sum()) / 64 ** 2
+    assert metrics.energy(a, b).item() == pytest.approx(par.item(), rel=1e-13)
+
+
+def test_adam_bias_correction_over_several_steps():
+    # five steps with a constant gradient: m_t = g (1 - b1^t), v_t = g^2 (1 - b2^t),
+    # so every bias-corrected step is -lr g / (|g| + eps), written out
+    from oracle.optim import adam_step
+    g = torch.tensor([0.5, -2.0, 1e-4], dtype=torch.float64)
+    w = torch.tensor([1.0, 1.0, 1.0], dtype=torch.float64)
+    m = torch.zeros(3, dtype=torch.float64)
+    v = torch.zeros(3, dtype=torch.float64)
+    lr, b1, b2 = 1e-3, 0.9, 0.999
+    for t in range(1, 6):
+        w, m, v = adam_step(w, g, m, v, t, lr=lr, b1=b1, b2=b2)
+        assert torch.allclose(m, g * (1 - b1 ** t), rtol=1e-14, atol=0)
+        assert torch.allclose(v, g * g * (1 - b2 ** t), rtol=1e-13, atol=0)
+    assert torch.allclose(w, 1.0 - 5 * lr * g / (g.abs() + 1e-8), rtol=1e-12, atol=0)

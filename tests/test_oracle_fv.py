@@ -201,3 +201,76 @@ def test_upwind_direction():
     assert f[0, 3].item() == pytest.approx(-0.5 * 4 + 1.5 * 9)
     f = fv.upwind2_x(q, -a)
     assert f[0, 3].item() == pytest.approx(1.5 * 16 - 0.5 * 25)
+
+
+def test_upwind_direction_y():
+    # the mirror of the x test: b > 0 takes the value from below (j-1, j),
+    # b < 0 from above (j+1, j+2)
+    q = (torch.arange(8, dtype=torch.float64) ** 2).view(8, 1)
+    b = torch.ones_like(q)
+    f = fv.upwind2_y(q, b)
+    assert f[3, 0].item() == pytest.approx(-0.5 * 4 + 1.5 * 9)
+    f = fv.upwind2_y(q, -b)
+    assert f[3, 0].item() == pytest.approx(1.5 * 16 - 0.5 * 25)
+    # on a cubic profile the two biases differ: j^3 gives 36.5 from below and
+    # 33.5 from above at the face between rows 3 and 4
+    c = (torch.arange(8, dtype=torch.float64) ** 3).view(8, 1)
+    assert fv.upwind2_y(c, b)[3, 0].item() == pytest.approx(-0.5 * 8 + 1.5 * 27)
+    assert fv.upwind2_y(c, -b)[3, 0].item() == pytest.approx(1.5 * 64 - 0.5 * 125)
+
+
+def _upwind_face(q_m2, q_m1, q_p1, q_p2, a):
+    """Linear-upwind value at the face between m1 and p1 (written out)."""
+    return (-q_m2 + 3.0 * q_m1) / 2.0 if a > 0 else (3.0 * q_p1 - q_p2) / 2.0
+
+
+def test_burgers_residual_against_written_out_sums():
+    # every cell of a 6 x 5 random field, both components, by explicit
+    # index arithmetic: central advecting averages, linear-upwind advected
+    # values chosen by the sign of the face velocity, flux form minus q div,
+    # compact viscous differences (the collocated Burgers scheme)
+    g = torch.Generator().manual_seed(11)
+    ny, nx = 5, 6
+    u = torch.randn(1, ny, nx, generator=g, dtype=torch.float64)
+    v = torch.randn(1, ny, nx, generator=g, dtype=torch.float64)
+    nu = 0.03
+    prm = fv.grid_params(nx, ny, nu=nu)
+    dx, dy = prm["dx"], prm["dy"]
+    ru, rv = fv.burgers_rhs(u, v, prm)
+    U, V = u[0].tolist(), v[0].tolist()
+    for q, got in ((U, ru), (V, rv)):
+        for j in range(ny):
+            for i in range(nx):
+                def Q(jj, ii):
+                    return q[jj % ny][ii % nx]
+
+                def A(jj, ii):   # east-face advecting velocity of cell (ii, jj)
+                    return 0.5 * (U[jj % ny][ii % nx] + U[jj % ny][(ii + 1) % nx])
+
+                def B(jj, ii):   # north-face advecting velocity
+                    return 0.5 * (V[jj % ny][ii % nx] + V[(jj + 1) % ny][ii % nx])
+                ae, aw = A(j, i), A(j, i - 1)
+                bn, bs = B(j, i), B(j - 1, i)
+                qe = _upwind_face(Q(j, i - 1), Q(j, i), Q(j, i + 1), Q(j, i + 2), ae)
+                qw = _upwind_face(Q(j, i - 2), Q(j, i - 1), Q(j, i), Q(j, i + 1), aw)
+                qn = _upwind_face(Q(j - 1, i), Q(j, i), Q(j + 1, i), Q(j + 2, i), bn)
+                qs = _upwind_face(Q(j - 2, i), Q(j - 1, i), Q(j, i), Q(j + 1, i), bs)
+                r = -((ae * qe - aw * qw) / dx + (bn * qn - bs * qs) / dy)
+                r += Q(j, i) * ((ae - aw) / dx + (bn - bs) / dy)
+                r += nu * ((Q(j, i + 1) - 2 * Q(j, i) + Q(j, i - 1)) / dx ** 2
+                           + (Q(j + 1, i) - 2 * Q(j, i) + Q(j - 1, i)) / dy ** 2)
+                assert got[0, j, i].item() == pytest.approx(r, rel=1e-12, abs=1e-12), (j, i)
+
+
+def test_burgers_residual_commutes_with_transposition():
+    # swapping the axes maps (u, v)(x, y) to (v, u)(y, x); the residual of the
+    # swapped field is the swapped residual (a mirrored y bias breaks this)
+    g = torch.Generator().manual_seed(12)
+    n = 8
+    u = torch.randn(2, n, n, generator=g, dtype=torch.float64)
+    v = torch.randn(2, n, n, generator=g, dtype=torch.float64)
+    prm = fv.grid_params(n, n, nu=0.02)
+    ru, rv = fv.burgers_rhs(u, v, prm)
+    su, sv = fv.burgers_rhs(v.transpose(-1, -2), u.transpose(-1, -2), prm)
+    assert torch.allclose(su, rv.transpose(-1, -2), rtol=1e-13, atol=1e-13)
+    assert torch.allclose(sv, ru.transpose(-1, -2), rtol=1e-13, atol=1e-13)
