@@ -151,13 +151,16 @@ __global__ void k_mse_accum(const double* parts, int batch, double scale, double
   }
 }
 
-__global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, float b1, float b2,
-                       float c1, float c2, float lr, float eps) {
+// ob1 = 1 - b1 and ob2 = 1 - b2 come from the host in FP64 rounded once:
+// formed here from the FP32 betas they would carry the betas' own rounding
+// relative to their small difference (1 - 0.999f is 1.3e-5 away from 1e-3)
+__global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, float b1, float ob1,
+                       float b2, float ob2, float c1, float c2, float lr, float eps) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + ob1 * gi;
+    const float vi = b2 * v[i] + ob2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
@@ -273,7 +276,8 @@ extern "C" int ldsv_adam_step(float* w, const float* g, float* m, float* v, size
   const double c1 = 1.0 / (1.0 - pow(beta1, t));
   const double c2 = 1.0 / (1.0 - pow(beta2, t));
   hipLaunchKernelGGL(k_adam, grid1d(n), dim3(kBlock), 0, (hipStream_t)stream, w, g, m, v, n,
-                     (float)beta1, (float)beta2, (float)c1, (float)c2, (float)lr, (float)eps);
+                     (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2),
+                     (float)c1, (float)c2, (float)lr, (float)eps);
   LDSV_LAUNCHED();
   return LDSV_OK;
 }

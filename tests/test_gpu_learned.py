@@ -173,12 +173,24 @@ def test_rollout_matches_oracle(guard):
     su, sv = s.rollout(prm, u0, v0, nsteps=T, save_every=2, net=net)
     assert torch.equal(su, tu[1::2]) and torch.equal(sv, tv[1::2])
     ou, ov = learned.learned_rollout(u, v, oprm, wb, bb, T, first_index=1, bf16=True)
+    fu, fv_ = learned.learned_rollout(u, v, oprm, wb, bb, T, first_index=1, bf16=False)
     errs = [max(rel_l2(su[t], ou[2 * t + 1]), rel_l2(sv[t], ov[2 * t + 1])) for t in range(T // 2)]
-    print("rollout rel-L2 vs the bf16-emulating oracle at steps 2, 4, 6:", errs)
-    # BF16 rounding flips of single network outputs (a few in 10^4, each one
-    # bf16 ulp of a coefficient) move a step by about 1e-5 relative; they
-    # compound over the steps
-    assert max(errs) < 3e-4, errs
+    e64 = [max(rel_l2(su[t], fu[2 * t + 1]), rel_l2(sv[t], fv_[2 * t + 1])) for t in range(T // 2)]
+    spread = [max(rel_l2(ou[2 * t + 1], fu[2 * t + 1]), rel_l2(ov[2 * t + 1], fv_[2 * t + 1]))
+              for t in range(T // 2)]
+    print("rollout rel-L2 at steps 2, 4, 6: vs the bf16-emulating oracle", errs,
+          "vs the FP64 oracle", e64, "bf16 oracle vs FP64 oracle", spread)
+    # A rounding flip (one bf16 ulp) of a hidden activation moves the next
+    # layer's inputs by enough to flip others: the flips cascade through the
+    # five hidden layers, so the device's network output differs from the
+    # bf16-emulating oracle's by about as much as bf16 storage itself moves
+    # the output away from FP64 (a few 1e-3, bounded in test_cnn_forward).
+    # The rollout therefore differs from either oracle by about the oracle's
+    # own bf16-vs-FP64 spread: at most twice that spread, and within the
+    # BF16-network tolerance (2e-2) of the FP64 oracle.
+    for t in range(T // 2):
+        assert errs[t] < 2.0 * spread[t] + 1e-5, (errs, spread)
+        assert e64[t] < 2.0 * spread[t] + 1e-5 and e64[t] < 2e-2, (e64, spread)
     if guard:
         torch.cuda.synchronize()
         assert flags.tolist() == [0] * b
