@@ -164,6 +164,30 @@ LDSV_API int ldsv_fv_step(ldsv_handle* h, const ldsv_params* prm, const float* c
                  const void* u_in, const void* v_in, void* u_out, void* v_out,
                  int nsteps, void* stream);
 
+/* ---- ldsv_fv_step without a handle, allocating nothing ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * exactly what ldsv_fv_step computes on grid *g (the same kernels, arguments
+ * and layouts: coef nullable, in-place allowed, nsteps >= 1) but keeps every
+ * intermediate (RK stage states, accumulator, pre-projection state,
+ * spectrum, twiddle and Poisson-factor tables) in one fixed device array of
+ * LDSV_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends.  It makes no hipMalloc/hipFree call and calls no
+ * allocating library routine; the caller passes inputs and outputs only.
+ * Workspace need (each part rounded up to 256 bytes): twiddles
+ * (nx + ny) * 2 * esize, and for MAC grids the FP64 Poisson factors
+ * nx * ny * 8 plus the spectrum ceil(batch/2) * nx * ny * 2 * esize, then six
+ * state planes of batch * nx * ny * esize (esize 4 for LDSV_F32, 8 for
+ * LDSV_F64).  At 32 MiB this holds 128^2 x 64 or 256^2 x 16 FP32.  A larger
+ * grid is rejected with LDSV_ESHAPE before anything is enqueued.  The array is
+ * shared by every call on one device and keeps the last call's contents (the
+ * tables are rewritten by each call; nothing in it needs to start at zero):
+ * calls that overlap on one device, on any streams or threads, race. */
+#define LDSV_NOALLOC_SCRATCH_BYTES (32u << 20)
+LDSV_API int ldsv_fv_step_noalloc(const ldsv_grid* g, const ldsv_params* prm, const float* coef,
+                                  const void* u_in, const void* v_in, void* u_out, void* v_out,
+                                  int nsteps, void* stream);
+
 /* ---- a9-a11: pressure projection (App. B.3-B.4; S8-S14) ----
  * u <- u - G p with D G p = D u, solved by FFT with the compact-MAC
  * eigenvalues and a zero mean mode.  p_out (nullable): the potential p,

@@ -297,6 +297,49 @@ int ldsv_step_bwd(ldsv_handle* h, const ldsv_params* prm, const float* coef, siz
                              dt / 6.0, 0.5 * dt, S, S + sb, gu_in, gv_in, st, fb, dc);
 }
 
+int ldsv_check_grid(const ldsv_grid* g, const char* who) {
+  LDSV_REQUIRE(pow2_in_range(g->nx) && pow2_in_range(g->ny), LDSV_ESHAPE,
+               "%s: nx=%d ny=%d must be powers of two in [8, 4096]", who, g->nx, g->ny);
+  LDSV_REQUIRE(g->batch >= 1 && g->batch <= (1 << 20), LDSV_EINVAL, "%s: batch=%d", who,
+               g->batch);
+  LDSV_REQUIRE(g->dtype == LDSV_F32 || g->dtype == LDSV_F64, LDSV_EDTYPE, "%s: dtype=%d", who,
+               g->dtype);
+  LDSV_REQUIRE(g->layout == LDSV_COLLOCATED ||
+                   (g->nx <= (g->dtype == LDSV_F64 ? 1024 : 2048) &&
+                    g->ny <= (g->dtype == LDSV_F64 ? 1024 : 2048)),
+               LDSV_ESHAPE, "%s: MAC grids need nx, ny <= 2048 (FP32) or 1024 (FP64)", who);
+  LDSV_REQUIRE(g->layout == LDSV_MAC || g->layout == LDSV_COLLOCATED, LDSV_EINVAL,
+               "%s: layout=%d", who, g->layout);
+  LDSV_REQUIRE(g->lx > 0 && g->ly > 0 && std::isfinite(g->lx) && std::isfinite(g->ly), LDSV_EINVAL,
+               "%s: box lengths must be positive", who);
+  return LDSV_OK;
+}
+
+int ldsv_handle_shape(ldsv_handle* h, const ldsv_grid* g) {
+  h->g = *g;
+  LDSV_HIP(hipGetDevice(&h->device));
+  h->log2nx = ilog2(g->nx);
+  h->log2ny = ilog2(g->ny);
+  h->ncell = (size_t)g->nx * g->ny;
+  h->nstate = h->ncell * g->batch;
+  h->npairs = (g->batch + 1) / 2;
+  h->esize = (g->dtype == LDSV_F64) ? 8 : 4;
+  return LDSV_OK;
+}
+
+int ldsv_check_fv_step(const ldsv_handle* h, const ldsv_params* prm, const float* coef,
+                       const void* u_in, const void* v_in, const void* u_out,
+                       const void* v_out, int nsteps, const char* who) {
+  LDSV_TRY(ldsv_check_params(h, prm));
+  LDSV_REQUIRE(u_in && v_in && u_out && v_out, LDSV_EINVAL, "%s: null array", who);
+  LDSV_REQUIRE(nsteps >= 1, LDSV_EINVAL, "%s: nsteps=%d", who, nsteps);
+  LDSV_REQUIRE(!coef || (h->g.layout == LDSV_MAC), LDSV_EDTYPE,
+               "%s: learned coefficients need the MAC layout", who);
+  LDSV_REQUIRE(h->g.layout == LDSV_MAC || prm->rk == LDSV_SSPRK3, LDSV_EDTYPE,
+               "%s: the collocated layout integrates with SSPRK3", who);
+  return LDSV_OK;
+}
+
 extern "C" {
 
 int ldsv_version(void) { return 100; }
@@ -306,27 +349,13 @@ const char* ldsv_last_error(void) { return g_err; }
 int ldsv_create(ldsv_handle** out, const ldsv_grid* g) {
   LDSV_REQUIRE(out && g, LDSV_EINVAL, "create: null argument");
   *out = nullptr;
-  LDSV_REQUIRE(pow2_in_range(g->nx) && pow2_in_range(g->ny), LDSV_ESHAPE,
-               "create: nx=%d ny=%d must be powers of two in [8, 4096]", g->nx, g->ny);
-  LDSV_REQUIRE(g->batch >= 1 && g->batch <= (1 << 20), LDSV_EINVAL, "create: batch=%d", g->batch);
-  LDSV_REQUIRE(g->dtype == LDSV_F32 || g->dtype == LDSV_F64, LDSV_EDTYPE, "create: dtype=%d", g->dtype);
-  LDSV_REQUIRE(g->layout == LDSV_COLLOCATED ||
-                   (g->nx <= (g->dtype == LDSV_F64 ? 1024 : 2048) &&
-                    g->ny <= (g->dtype == LDSV_F64 ? 1024 : 2048)),
-               LDSV_ESHAPE, "create: MAC grids need nx, ny <= 2048 (FP32) or 1024 (FP64)");
-  LDSV_REQUIRE(g->layout == LDSV_MAC || g->layout == LDSV_COLLOCATED, LDSV_EINVAL,
-               "create: layout=%d", g->layout);
-  LDSV_REQUIRE(g->lx > 0 && g->ly > 0 && std::isfinite(g->lx) && std::isfinite(g->ly), LDSV_EINVAL,
-               "create: box lengths must be positive");
+  LDSV_TRY(ldsv_check_grid(g, "create"));
   ldsv_handle* h = new ldsv_handle();
-  h->g = *g;
-  LDSV_HIP(hipGetDevice(&h->device));
-  h->log2nx = ilog2(g->nx);
-  h->log2ny = ilog2(g->ny);
-  h->ncell = (size_t)g->nx * g->ny;
-  h->nstate = h->ncell * g->batch;
-  h->npairs = (g->batch + 1) / 2;
-  h->esize = (g->dtype == LDSV_F64) ? 8 : 4;
+  const int rc = ldsv_handle_shape(h, g);
+  if (rc != LDSV_OK) {
+    delete h;
+    return rc;
+  }
   const size_t sb = h->nstate * h->esize;
   char* blk = nullptr;
   hipError_t e = hipMalloc(&blk, 8 * sb);
@@ -455,13 +484,7 @@ int ldsv_rhs(ldsv_handle* h, const ldsv_params* prm, const float* coef, const vo
 int ldsv_fv_step(ldsv_handle* h, const ldsv_params* prm, const float* coef, const void* u_in,
                  const void* v_in, void* u_out, void* v_out, int nsteps, void* stream) {
   LDSV_TRY(ldsv_check_handle(h));
-  LDSV_TRY(ldsv_check_params(h, prm));
-  LDSV_REQUIRE(u_in && v_in && u_out && v_out, LDSV_EINVAL, "fv_step: null array");
-  LDSV_REQUIRE(nsteps >= 1, LDSV_EINVAL, "fv_step: nsteps=%d", nsteps);
-  LDSV_REQUIRE(!coef || (h->g.layout == LDSV_MAC), LDSV_EDTYPE,
-               "fv_step: learned coefficients need the MAC layout");
-  LDSV_REQUIRE(h->g.layout == LDSV_MAC || prm->rk == LDSV_SSPRK3, LDSV_EDTYPE,
-               "fv_step: the collocated layout integrates with SSPRK3");
+  LDSV_TRY(ldsv_check_fv_step(h, prm, coef, u_in, v_in, u_out, v_out, nsteps, "fv_step"));
   const hipStream_t st = (hipStream_t)stream;
   const size_t cbs = (size_t)LDSV_NCOEF * h->ncell;
   for (int k = 0; k < nsteps; ++k) {

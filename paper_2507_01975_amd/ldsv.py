@@ -107,6 +107,8 @@ _SIGS = {
     "ldsv_init_state": ([_vp, _i, ctypes.c_uint64, ctypes.POINTER(ICArgs), _vp, _vp, _vp], _i),
     "ldsv_rhs": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "ldsv_fv_step": ([_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _i, _vp], _i),
+    "ldsv_fv_step_noalloc": ([ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
+                              _vp, _i, _vp], _i),
     "ldsv_project": ([_vp, _vp, _vp, _vp, _vp], _i),
     "ldsv_project_bwd": ([_vp, _vp, _vp, _vp], _i),
     "ldsv_cnn_forward": ([_vp, ctypes.POINTER(Net), _vp, _vp, _vp, _vp], _i),
@@ -651,6 +653,34 @@ class NetGradBuffers:
     def zero_(self):
         for t in self.w + self.b:
             t.zero_()
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def fv_step_noalloc(prm, u, v, nsteps=1, coef=None, out=None, lx=2 * 3.141592653589793,
+                    ly=2 * 3.141592653589793, layout=MAC):
+    """ldsv_fv_step without a handle: the workspace is the library's fixed
+    device scratch array, nothing is allocated by the library (outputs are
+    allocated here only when `out` is None).  u, v: [B, Ny, Nx] float32 or
+    float64 cuda tensors."""
+    if u.dim() != 3 or u.shape != v.shape or u.dtype != v.dtype:
+        raise ValueError("u, v must be [B, Ny, Nx] tensors of one dtype")
+    b, ny, nx = u.shape
+    g = Grid(nx, ny, lx, ly, b, F64 if u.dtype == torch.float64 else F32, layout)
+    uo, vo = (torch.empty_like(u), torch.empty_like(v)) if out is None else out
+    for name, t in (("u", u), ("v", v), ("u_out", uo), ("v_out", vo)):
+        if not (t.is_cuda and t.dtype == u.dtype and t.is_contiguous()
+                and tuple(t.shape) == (b, ny, nx)):
+            raise ValueError("%s must be a contiguous %s cuda tensor of shape %s"
+                             % (name, u.dtype, (b, ny, nx)))
+    if coef is not None and not (coef.is_cuda and coef.dtype == torch.float32
+                                 and coef.is_contiguous()
+                                 and tuple(coef.shape) == (b, NCOEF, ny, nx)):
+        raise ValueError("coef must be float32 [B, 64, Ny, Nx] contiguous on cuda")
+    _check(_lib.ldsv_fv_step_noalloc(ctypes.byref(g), ctypes.byref(prm), _ptr(coef), _ptr(u),
+                                     _ptr(v), _ptr(uo), _ptr(vo), nsteps, _stream()))
+    return uo, vo
 
 
 def adam_step(w, g, m, v, t, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
