@@ -28,6 +28,9 @@ The line also carries
   eager and as a captured HIP graph;
 * training: one Adam iteration of the 128^2 learned solver unrolled 32 steps
   through the hand-written adjoint (checkpoints every 8);
+* corr_shear: the same comparison on the shear-layer flow (nu = 2e-4):
+  learned 128^2 against plain FV at 128, 256, 512 and the 1024^2 fine solve,
+  over 4096 coarse steps, throughput at batch 128;
 * corr: the accuracy-matched comparison of the metric on forced Kolmogorov
   flow: the learned 64^2 solver is trained (Adam through the hand-written
   adjoint) on labels from 1024^2 plain FV down-sampled 16x; on held-out seeds
@@ -116,10 +119,27 @@ def cpu_baseline(w, u0, v0, u1_gpu, v1_gpu, budget_s=10.0):
         if t >= budget_s:
             break
     cells = w["nx"] * w["ny"] * u.shape[0] * steps
-    return {"value": cells / t, "unit": "cell-steps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": "%d RK4 steps of all 16 trajectories of the 512^2 "
-            "workload (%.1f s, FP64 torch CPU)" % (steps, t),
-            "gpu_step_rel_l2_vs_fp64": err}
+    rec = {"value": cells / t, "unit": "cell-steps/s", "cores": torch.get_num_threads(),
+           "kind": "oracle", "sample": "%d RK4 steps of all 16 trajectories of the 512^2 "
+           "workload (%.1f s, FP64 torch CPU)" % (steps, t),
+           "gpu_step_rel_l2_vs_fp64": err}
+    # the same oracle on one thread, on one trajectory of the workload
+    torch.set_num_threads(1)
+    u1 = u0[:1].double().cpu()
+    v1 = v0[:1].double().cpu()
+    steps1 = 0
+    t0 = time.perf_counter()
+    while True:
+        u1, v1 = timestep.fv_step(u1, v1, prm)
+        steps1 += 1
+        t1 = time.perf_counter() - t0
+        if t1 >= budget_s / 3:
+            break
+    torch.set_num_threads(cores)
+    rec["one_thread"] = {"value": w["nx"] * w["ny"] * steps1 / t1, "unit": "cell-steps/s",
+                         "cores": 1, "sample": "%d RK4 steps of trajectory 0 of the 512^2 "
+                         "workload (%.1f s, FP64 torch CPU)" % (steps1, t1)}
+    return rec
 
 
 def copy_reference(nbytes):
@@ -807,6 +827,11 @@ def main():
             line["corr"] = T.corr_metric(progress=log)
         except Exception as e:  # report, do not lose the throughput line
             line["corr"] = {"status": "failed: %r" % (e,)}
+        log("corr>=0.9 comparison on shear flow: learned 128^2 vs plain FV up to 1024^2")
+        try:
+            line["corr_shear"] = T.corr_shear(progress=log)
+        except Exception as e:
+            line["corr_shear"] = {"status": "failed: %r" % (e,)}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(w, u0, v0, u1, v1)

@@ -27,12 +27,12 @@ def physics(w):
 
 
 def generate_labels(fine_n, coarse_n, batch, seed, nsteps, dt_fine, phys, warmup_steps=0,
-                    ic=ldsv.IC_GRF_PEAK, lx=2 * math.pi, progress=None, ic_resolutions=()):
+                    ic=ldsv.IC_GRF_PEAK, lx=2 * math.pi, progress=None, ic_resolutions=None):
     """Coarse labels [nsteps + 1, B, n, n] (u and v): the fine plain-FV
     solution down-sampled every r fine steps, r = fine_n / coarse_n.  With
-    ic_resolutions, also returns {N: (u, v)}: the state after the warm-up
-    down-sampled to N x N (the common initial condition of a resolution
-    sweep)."""
+    ic_resolutions (a sequence, possibly empty), returns ((u, v), ics) with
+    ics = {N: (u, v)}: the state after the warm-up down-sampled to N x N (the
+    common initial condition of a resolution sweep)."""
     r = fine_n // coarse_n
     fine = ldsv.Solver(fine_n, fine_n, batch, lx=lx, ly=lx)
     coarse = ldsv.Solver(coarse_n, coarse_n, batch, lx=lx, ly=lx)
@@ -49,7 +49,7 @@ def generate_labels(fine_n, coarse_n, batch, seed, nsteps, dt_fine, phys, warmup
                 torch.cuda.synchronize()
                 progress("warm-up %d/%d fine steps" % (done, warmup_steps))
     ics = {}
-    for N in ic_resolutions:
+    for N in ic_resolutions or ():
         if N == fine_n:
             ics[N] = (u.clone(), v.clone())
         else:
@@ -70,7 +70,7 @@ def generate_labels(fine_n, coarse_n, batch, seed, nsteps, dt_fine, phys, warmup
     torch.cuda.synchronize()
     fine.close()
     coarse.close()
-    if ic_resolutions:
+    if ic_resolutions is not None:
         return (lu, lv), ics
     return lu, lv
 
@@ -299,42 +299,61 @@ def evaluate(solver, prm, labels, nsteps, net=None, dnet=None):
             "fallbacks": flags.tolist() if net is not None else None}
 
 
-def plain_sweep_pcc(N, n, ic, labels, dt_coarse, phys, horizon, lx=2 * math.pi):
+def plain_sweep_pcc(N, n, ic, labels, dt_coarse, phys, horizon, lx=2 * math.pi, chunk=256):
     """Plain FV at N x N from ic (already at N), advanced N/n steps of dt
     dt_coarse * n / N per coarse step, down-sampled to n and compared with
     labels[1..horizon] by vorticity PCC: returns (pcc [T, B], wall seconds of
-    the rollout)."""
-    u0, v0 = ic
-    B = u0.shape[0]
+    the rollouts).  The rollout runs in chunks of `chunk` coarse steps, so
+    only a chunk of fine snapshots is held at a time."""
+    u, v = (t.contiguous() for t in ic)
+    B = u.shape[0]
     rN = N // n
     sN = ldsv.Solver(N, N, B, lx=lx, ly=lx)
     sn = ldsv.Solver(n, n, B, lx=lx, ly=lx)
     prm = ldsv.params(dt=dt_coarse / rN, **phys)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tu, tv = sN.rollout(prm, u0.contiguous(), v0.contiguous(), horizon * rN, save_every=rN)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    cu = torch.empty(horizon, B, n, n, device="cuda")
-    cv = torch.empty_like(cu)
-    for t in range(horizon):
-        if rN == 1:
-            cu[t], cv[t] = tu[t], tv[t]
-        else:
-            cu[t], cv[t] = sn.downsample(rN, tu[t].contiguous(), tv[t].contiguous())
     lu, lv = labels
-    pcc = vorticity_pcc_series(sn, (cu, cv), (lu[1:horizon + 1], lv[1:horizon + 1]))
+    pccs = []
+    wall = 0.0
+    for c0 in range(0, horizon, chunk):
+        k = min(chunk, horizon - c0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tu, tv = sN.rollout(prm, u, v, k * rN, save_every=rN)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        u, v = tu[-1].clone(), tv[-1].clone()
+        cu = torch.empty(k, B, n, n, device="cuda")
+        cv = torch.empty_like(cu)
+        for t in range(k):
+            if rN == 1:
+                cu[t], cv[t] = tu[t], tv[t]
+            else:
+                cu[t], cv[t] = sn.downsample(rN, tu[t].contiguous(), tv[t].contiguous())
+        del tu, tv
+        pccs.append(vorticity_pcc_series(sn, (cu, cv), (lu[c0 + 1:c0 + k + 1],
+                                                       lv[c0 + 1:c0 + k + 1])))
     sN.close()
     sn.close()
-    return pcc, wall
+    return torch.cat(pccs), wall
 
 
-def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi, dnet=None):
+def t09_summary(t09, horizon_s):
+    """Mean, spread and censoring of per-trajectory T_0.9 values (a
+    trajectory that never drops below 0.9 within the horizon is censored at
+    the horizon)."""
+    t = torch.tensor(t09, dtype=torch.float64)
+    return {"mean": float(t.mean()), "min": float(t.min()), "max": float(t.max()),
+            "std": float(t.std()) if t.numel() > 1 else 0.0,
+            "censored": int((t >= horizon_s - 1e-12).sum()), "per_trajectory": list(t09)}
+
+
+def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi, dnet=None,
+               ic=ldsv.IC_GRF_PEAK):
     """(cell-steps/s, sim-time/s per trajectory, ms/step) of the plain or
     learned step (with the derivative-stencil network when dnet is given) at
     N x N, batch B, on device-resident state."""
     s = ldsv.Solver(N, N, B, lx=lx, ly=lx)
-    u, v = s.init_state(ldsv.IC_GRF_PEAK, seed=7)
+    u, v = s.init_state(ic, seed=7)
 
     def one(k):
         if net is None:
@@ -356,8 +375,8 @@ def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi, dnet=None):
     return N * N * B * steps / t, prm.dt * steps / t, 1e3 * t / steps
 
 
-def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, test_batch=4,
-                train_fine_steps=10000, warmup_fine=4000, horizon=600, iters=1500, unroll=16,
+def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, test_batch=16,
+                train_fine_steps=10000, warmup_fine=4000, horizon=1200, iters=1500, unroll=16,
                 windows=4, lr=1e-4, speed_batch=64, speed_steps=40, progress=None,
                 seeds=(100, 200), fluxblock_iters=600, fluxblock_kc=4, deriv_iters=750):
     """The forced-flow measurement: train the 64^2 learned solver on labels
@@ -395,14 +414,16 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
     ev = evaluate(se, prm, lab_te, horizon, net=net)
     ev_plain = evaluate(se, prm, lab_te, horizon)
     se.close()
-    t09 = {"learned_%d" % n: sum(ev["t09"]) / test_batch}
-    t09["plain_%d" % n] = sum(ev_plain["t09"]) / test_batch
+    hs = horizon * dtc
+    spread = {"learned_%d" % n: t09_summary(ev["t09"], hs),
+              "plain_%d" % n: t09_summary(ev_plain["t09"], hs)}
     for N in sweep:
         if N == n:
             continue
         pcc, _ = plain_sweep_pcc(N, n, ics[N], lab_te, dtc, phys, horizon)
-        t09["plain_%d" % N] = sum(first_drop(pcc.cpu(), dtc)) / test_batch
-        log("plain %d: T_0.9 = %.3f" % (N, t09["plain_%d" % N]))
+        spread["plain_%d" % N] = t09_summary(first_drop(pcc.cpu(), dtc), hs)
+        log("plain %d: T_0.9 = %.3f" % (N, spread["plain_%d" % N]["mean"]))
+    t09 = {k: v["mean"] for k, v in spread.items()}
     target = t09["learned_%d" % n]
     match = None
     for N in sorted(sweep):
@@ -414,7 +435,8 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
     out = {"workload": "forced Kolmogorov flow, nu=1e-3, drag 0.1; learned %d^2 trained on %d^2 "
                        "plain FV down-sampled %dx (%d trajectories, %d fine steps each)"
                        % (n, fine_n, r, train_batch, train_fine_steps),
-           "horizon_s": horizon * dtc, "t09_s": t09, "test_trajectories": test_batch,
+           "horizon_s": horizon * dtc, "t09_s": t09, "t09_spread": spread,
+           "test_trajectories": test_batch,
            "training": {"iters": iters, "unroll": unroll, "windows_per_iter": windows,
                         "lr": lr, "seconds": t_train},
            "final_train_loss": hist[-1][1], "initial_train_loss": hist[0][1],
@@ -444,13 +466,14 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
         tu, tv = fluxblock_model_rollout(se, prm_fb, fnet, tc, lu[0], lv[0], horizon)
         pcc = vorticity_pcc_series(se, (tu, tv), (lu[1:horizon + 1], lv[1:horizon + 1]))
         se.close()
-        t09_fb = sum(first_drop(pcc.cpu(), dtc)) / test_batch
+        fb_spread = t09_summary(first_drop(pcc.cpu(), dtc), hs)
+        t09_fb = fb_spread["mean"]
         fb = {"model": "flux block (uniform 5x4 kernels + FNOs 6 layers / 32 modes / width 16) "
                        "+ temporal correction every %d steps (FNO 4 / 32 / 8)" % fluxblock_kc,
               "training": {"iters": fluxblock_iters, "unroll": unroll, "lr": lr,
                            "seconds": t_fb},
               "initial_train_loss": hist_fb[0][1], "final_train_loss": hist_fb[-1][1],
-              "t09_s": t09_fb}
+              "t09_s": t09_fb, "t09_spread": fb_spread}
         cs_f, st_f, ms_f = fluxblock_throughput(n, speed_batch, prm_fb, fnet, tc, speed_steps)
         fb["throughput"] = {"n": n, "batch": speed_batch, "cell_steps_per_s": cs_f,
                             "sim_time_per_s": st_f, "ms_per_step": ms_f}
@@ -480,13 +503,14 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
         se = ldsv.Solver(n, n, test_batch)
         ev_d = evaluate(se, prm, lab_te, horizon, net=net2, dnet=dnet)
         se.close()
-        t09_d = sum(ev_d["t09"]) / test_batch
+        d_spread = t09_summary(ev_d["t09"], hs)
+        t09_d = d_spread["mean"]
         dm = {"model": "per-cell learned interpolation and derivative stencils (two 6-layer "
                        "64-channel BF16 CNNs) + temporal correction every step",
               "training": {"iters": deriv_iters, "unroll": unroll, "windows_per_iter": windows,
                            "lr": lr, "seconds": t_d},
               "initial_train_loss": hist_d[0][1], "final_train_loss": hist_d[-1][1],
-              "t09_s": t09_d, "fallbacks": ev_d["fallbacks"],
+              "t09_s": t09_d, "t09_spread": d_spread, "fallbacks": ev_d["fallbacks"],
               "mse_at_horizon": ev_d["mse"][-1].item()}
         cs_d, st_d, ms_d = throughput(n, speed_batch, prm, speed_steps, net=net2, dnet=dnet)
         dm["throughput"] = {"n": n, "batch": speed_batch, "cell_steps_per_s": cs_d,
@@ -505,6 +529,96 @@ def corr_metric(fine_n=1024, n=64, sweep=(64, 128, 256, 512), train_batch=8, tes
         out["learned_deriv_model"] = dm
         log("learned-derivative model: T_0.9 = %.3f (%.1f s)" % (t09_d, time.perf_counter() - t0))
     log("corr metric done (%.1f s)" % (time.perf_counter() - t0))
+    return out
+
+
+def corr_shear(fine_n=1024, n=128, sweep=(128, 256, 512), train_batch=8, test_batch=16,
+               train_steps=2048, horizon=4096, iters=600, unroll=16, windows=2, lr=1e-4,
+               speed_batch=128, speed_steps=20, seeds=(1000, 0), progress=None):
+    """The shear-flow measurement: doubly periodic shear layers (nu = 2e-4),
+    the learned n^2 solver trained on fine plain FV down-sampled fine_n / n
+    times (train_batch trajectories from seed seeds[0], train_steps coarse
+    steps each), then on test_batch held-out trajectories (seed seeds[1])
+    the time until the vorticity PCC against the down-sampled fine solve
+    first drops below 0.9, for the learned solver and for plain FV at each
+    sweep resolution; the fine solve itself is the last candidate (its
+    correlation is 1 by construction).  Throughput of the learned step and
+    of the coarsest plain resolution that lasts as long, at speed_batch."""
+    log = progress or (lambda *a: None)
+    phys = dict(nu=2e-4)
+    lx = 2 * math.pi
+    dtf = 0.1 * lx / fine_n
+    r = fine_n // n
+    dtc = r * dtf
+    t0 = time.perf_counter()
+    lab_tr = generate_labels(fine_n, n, train_batch, seeds[0], train_steps, dtf, phys,
+                             ic=ldsv.IC_SHEAR_LAYER, progress=log)
+    lab_te, ics = generate_labels(fine_n, n, test_batch, seeds[1], horizon, dtf, phys,
+                                  ic=ldsv.IC_SHEAR_LAYER, progress=log,
+                                  ic_resolutions=tuple(N for N in sweep if N != n))
+    t_lab = time.perf_counter() - t0
+    log("shear labels ready (%.1f s)" % t_lab)
+    net = init_network(seed=0)
+    st = ldsv.Solver(n, n, train_batch * windows)
+    prm = ldsv.params(dt=dtc, k_c=1, fallback_enable=0, **phys)
+    t_tr0 = time.perf_counter()
+    hist = train(st, net, lab_tr, prm, iters=iters, unroll=unroll, checkpoint_every=8, lr=lr,
+                 progress=log, log_every=100, windows=windows)
+    st.close()
+    t_train = time.perf_counter() - t_tr0
+    log("shear model trained (%.1f s)" % (time.perf_counter() - t0))
+    se = ldsv.Solver(n, n, test_batch)
+    ev = evaluate(se, prm, lab_te, horizon, net=net)
+    ev_plain = evaluate(se, prm, lab_te, horizon)
+    se.close()
+    hs = horizon * dtc
+    spread = {"learned_%d" % n: t09_summary(ev["t09"], hs),
+              "plain_%d" % n: t09_summary(ev_plain["t09"], hs)}
+    for N in sweep:
+        if N == n:
+            continue
+        pcc, _ = plain_sweep_pcc(N, n, ics[N], lab_te, dtc, phys, horizon)
+        spread["plain_%d" % N] = t09_summary(first_drop(pcc.cpu(), dtc), hs)
+        log("shear plain %d: T_0.9 = %.3f" % (N, spread["plain_%d" % N]["mean"]))
+    t09 = {k: v["mean"] for k, v in spread.items()}
+    target = t09["learned_%d" % n]
+    match = fine_n
+    for N in sorted(sweep):
+        if t09["plain_%d" % N] >= target:
+            match = N
+            break
+    cs_l, st_l, ms_l = throughput(n, speed_batch, prm, speed_steps, net=net,
+                                  ic=ldsv.IC_SHEAR_LAYER)
+    pm = ldsv.params(dt=dtc * n / match, **phys)
+    cs_p, st_p, ms_p = throughput(match, speed_batch, pm, max(5, speed_steps * n // match),
+                                  ic=ldsv.IC_SHEAR_LAYER)
+    out = {"workload": "shear layers u = tanh((y - pi/2)/delta), -tanh((y - 3pi/2)/delta), "
+                       "delta = 1/30, v = 0.05 sin 2x + divergence-free noise (rms 1e-3), "
+                       "nu = 2e-4; learned %d^2 trained on %d^2 plain FV down-sampled %dx"
+                       % (n, fine_n, r),
+           "dt_fine": dtf, "dt_coarse": dtc, "horizon_steps": horizon, "horizon_s": hs,
+           "t09_s": t09, "t09_spread": spread, "test_trajectories": test_batch,
+           "test_trajectories_note": "%d held-out trajectories of the %d of the configuration "
+                                     "(the fine %d^2 reference of all %d would take minutes of "
+                                     "the bench); throughput is timed at batch %d"
+                                     % (test_batch, speed_batch, fine_n, speed_batch,
+                                        speed_batch),
+           "training": {"trajectories": train_batch, "coarse_steps": train_steps,
+                        "iters": iters, "unroll": unroll, "windows_per_iter": windows,
+                        "lr": lr, "seconds": t_train, "labels_seconds": t_lab},
+           "initial_train_loss": hist[0][1], "final_train_loss": hist[-1][1],
+           "fallbacks": ev["fallbacks"],
+           "mse_at_horizon": {"learned": ev["mse"][-1].item(),
+                              "plain_%d" % n: ev_plain["mse"][-1].item()},
+           "learned": {"n": n, "batch": speed_batch, "cell_steps_per_s": cs_l,
+                       "sim_time_per_s": st_l, "ms_per_step": ms_l},
+           "plain_match": {"n": match, "batch": speed_batch, "cell_steps_per_s": cs_p,
+                           "sim_time_per_s": st_p, "ms_per_step": ms_p,
+                           "note": ("the fine reference resolution itself" if match == fine_n
+                                    else "coarsest plain resolution with mean T_0.9 >= the "
+                                         "learned solver's")},
+           "sim_time_speedup_at_equal_corr": st_l / st_p}
+    log("shear corr done (%.1f s)" % (time.perf_counter() - t0))
     return out
 
 
