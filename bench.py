@@ -270,12 +270,24 @@ def learned_block(steps, warmup):
             s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
     except ldsv.LdsvError as e:
         return {"status": "unavailable: %s" % e}
+    # the rollout with its guard and plain-FV fallback on the device (the
+    # way the learned solver runs), one snapshot at the end
+    gprm = ldsv.params(nu=w["nu"], dt=w["dt"], forcing_amp=w["forcing_amp"],
+                       forcing_k=w["forcing_k"], drag=w["drag"], k_c=1, fallback_enable=1)
+    flags = torch.zeros(B, dtype=torch.int32, device="cuda")
+    s.rollout(gprm, u, v, warmup, save_every=warmup, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ru, rv = s.rollout(gprm, u, v, steps, save_every=steps, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # bare learned steps, for the guard's cost
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    t_bare = time.perf_counter() - t0
     # kernel durations from a second, instrumented pass (per-launch events
     # add several microseconds between launches, so the throughput above is
     # timed without them)
@@ -286,9 +298,12 @@ def learned_block(steps, warmup):
     conv_ms, conv_n = s.timer_read(ldsv.TIMER_CONV)
     s.timer_enable(False)
     cells = n * n * B
-    out = {"workload": "kolmogorov64 learned step (64^2, batch 64, 6-layer 64-channel BF16 CNN)",
+    out = {"workload": "kolmogorov64 learned rollout (64^2, batch 64, 6-layer 64-channel BF16 "
+                       "CNN, guard and plain-FV fallback on the device)",
            "cell_steps_per_s": cells * steps / t, "ms_per_step": 1e3 * t / steps,
-           "sim_time_per_s": w["dt"] * steps / t}
+           "sim_time_per_s": w["dt"] * steps / t,
+           "bare_steps_ms_per_step": 1e3 * t_bare / steps,
+           "guard_overhead": t / t_bare - 1.0, "fallbacks": int(flags.sum())}
     if conv_n:
         # layers 2..6 on MFMA: 2 * 9 * 64 * Cout FLOP per cell
         flop = 2 * 9 * 64 * (64 * 4 + 66) * cells

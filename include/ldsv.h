@@ -227,9 +227,13 @@ LDSV_API int ldsv_learned_fv_step(ldsv_handle* h, const ldsv_params* prm, const 
  * (t = 0 .. nsteps/save_every - 1) is the state after (t+1)*save_every steps,
  * into traj_u/traj_v [T][B][Ny][Nx].  fallback_flags (nullable, int [B]):
  * counts, per trajectory, learned steps that produced a non-finite state or
- * max|u| > guard_threshold and were redone with the plain FV step (when
- * fallback_enable), else the call returns LDSV_ENONFINITE.  The guard reads
- * one int per step back to the host. */
+ * max(|u| + |v|) >= guard_threshold and were redone with the plain FV step
+ * from the previous state (when fallback_enable), else the call returns
+ * LDSV_ENONFINITE.  The guard runs on the device (a detection kernel per
+ * step, the plain step launched for the flagged trajectories only): with
+ * fallback_enable the call reads nothing back and can be captured in a HIP
+ * graph; with the fallback disabled it synchronises once, at its end, to
+ * report a trip. */
 LDSV_API int ldsv_rollout(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
                  const void* u0, const void* v0, int nsteps, int save_every, int first_index,
                  void* traj_u, void* traj_v, int* fallback_flags, void* stream);

@@ -106,13 +106,15 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
              const void* sv, void* du, void* dv, const float* tcu, const float* tcv, size_t tcbs,
              hipStream_t st, void* keep = nullptr, const uint16_t* coef16 = nullptr,
              size_t cbs16 = 0, const FluxBlockArgs* fb = nullptr,
-             const ScalarStep* sc = nullptr, const DerivCoef* dc = nullptr) {
+             const ScalarStep* sc = nullptr, const DerivCoef* dc = nullptr,
+             const int* active = nullptr) {
   const size_t sbk = h->nstate * h->esize;
   auto ku = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s) * sbk : h->ws_u; };
   auto kv = [&](int s) -> void* { return keep ? (char*)keep + (size_t)(2 * s + 1) * sbk : h->ws_v; };
   const double dt = p->dt;
   const bool mac = h->g.layout == LDSV_MAC;
   StageArgs a;
+  a.active = active;
   a.coef = coef;
   a.coef_bstride = cbs;
   a.coef16 = coef16;
@@ -163,7 +165,7 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
         a.ov = h->st_v;
         LDSV_TRY(ldsv_launch_stage(h, p, a, st));
         LDSV_TRY(ldsv_launch_project(h, h->st_u, h->st_v, s == 3 ? du : ku(s),
-                                     s == 3 ? dv : kv(s), nullptr, st));
+                                     s == 3 ? dv : kv(s), nullptr, st, active));
       } else {
         // collocated RK4 without projection: stage outputs ping-pong
         LDSV_REQUIRE(false, LDSV_EDTYPE, "RK4 on the collocated layout is not provided; use SSPRK3");
@@ -196,7 +198,7 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
       a.ov = h->st_v;
       LDSV_TRY(ldsv_launch_stage(h, p, a, st));
       LDSV_TRY(ldsv_launch_project(h, h->st_u, h->st_v, s == 2 ? du : h->ws_u,
-                                   s == 2 ? dv : h->ws_v, nullptr, st));
+                                   s == 2 ? dv : h->ws_v, nullptr, st, active));
       cu = h->ws_u;
       cv = h->ws_v;
     } else {
@@ -220,6 +222,16 @@ int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, 
                        const void* su, const void* sv, void* du, void* dv, const float* tcu,
                        const float* tcv, size_t tcbs, hipStream_t st) {
   return one_step(h, p, coef, cbs, su, sv, du, dv, tcu, tcv, tcbs, st);
+}
+
+// the plain step for the trajectories whose `active` entry is nonzero (MAC):
+// the others' workgroups return at once and their outputs du, dv are left
+// as they were
+int ldsv_internal_step_masked(ldsv_handle* h, const ldsv_params* p, const void* su,
+                              const void* sv, void* du, void* dv, const int* active,
+                              hipStream_t st) {
+  return one_step(h, p, nullptr, 0, su, sv, du, dv, nullptr, nullptr, 0, st, nullptr, nullptr, 0,
+                  nullptr, nullptr, nullptr, active);
 }
 
 // the same with the raw coefficients stored as bf16 planes

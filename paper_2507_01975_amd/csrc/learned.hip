@@ -6,7 +6,7 @@
 // before its projection, u_k = P(u* + TC), which equals P(P(u*) + TC)
 // because P is a linear projector.  The rollout guards every learned step:
 // a trajectory whose new state is non-finite or exceeds the max-speed bound
-// is recomputed from u_{k-1} with the plain FV step.
+// is recomputed from u_{k-1} with the plain FV step, all on the device.
 #include "adjoint.h"
 #include "cnn.h"
 #include "reduce.h"
@@ -22,23 +22,18 @@ int ldsv_internal_step(ldsv_handle* h, const ldsv_params* p, const float* coef, 
 int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* coef16,
                          size_t cbs16, const void* su, const void* sv, void* du, void* dv,
                          const float* tcu, const float* tcv, size_t tcbs, hipStream_t st);
+int ldsv_internal_step_masked(ldsv_handle* h, const ldsv_params* p, const void* su,
+                              const void* sv, void* du, void* dv, const int* active,
+                              hipStream_t st);
+int ldsv_launch_guard_redo(ldsv_handle* h, const ldsv_params* prm, const float* cu,
+                           const float* cv, float* nu, float* nv, double thr, int redo,
+                           int* counts, int* any, hipStream_t st);
 int ldsv_internal_step_d(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
                          const uint16_t* coef16, size_t cbs16, const DerivCoef* dc,
                          const void* su, const void* sv, void* du, void* dv, const float* tcu,
                          const float* tcv, size_t tcbs, hipStream_t st);
 
 namespace {
-
-struct SpeedOrInf {
-  const float* u;
-  const float* v;
-  size_t n;
-  __device__ void operator()(int b, size_t i, double* out) const {
-    const float a = u[(size_t)b * n + i], c = v[(size_t)b * n + i];
-    const double s = (double)fabsf(a) + (double)fabsf(c);
-    out[0] = isfinite(s) ? s : 1.0e308;
-  }
-};
 
 // zero fill (a kernel rather than a memset node, so that a captured graph
 // of the training calls replays correctly)
@@ -54,30 +49,40 @@ int launch_zero(ldsv_handle* h, float* p, size_t n, hipStream_t st) {
   return LDSV_OK;
 }
 
-__global__ void k_guard_flags(const double* maxspeed, int batch, double thr, int* bad, int* any) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int a = 0;
-  for (int b = 0; b < batch; ++b) {
-    const int f = !(maxspeed[b] < thr);
-    bad[b] = f;
-    a |= f;
+// The rollout guard of one learned step, one workgroup per trajectory: the
+// largest |u| + |v| over the trajectory's cells (in FP64; a non-finite value
+// counts as infinite) against the bound thr.  Writes bad[b] (1: redo with
+// the plain step), adds it to counts[b] (nullable) and raises *any.
+constexpr int kGuardBlock = 256;
+__global__ void __launch_bounds__(kGuardBlock) k_guard_detect(const float* __restrict__ u,
+                                                              const float* __restrict__ v,
+                                                              size_t n, double thr, int* bad,
+                                                              int* counts, int* any) {
+  __shared__ double red[kGuardBlock / 64];
+  const int b = blockIdx.x;
+  const float* ub = u + (size_t)b * n;
+  const float* vb = v + (size_t)b * n;
+  double m = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += kGuardBlock) {
+    const double s = (double)fabsf(ub[i]) + (double)fabsf(vb[i]);
+    m = isfinite(s) ? fmax(m, s) : INFINITY;
   }
-  *any = a;
-}
-
-__global__ void k_select(float* cu, float* cv, const float* fu, const float* fv, const int* bad,
-                         int* counts, size_t n, int batch) {
-  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n * batch;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(g / n);
-    if (bad[b]) {
-      cu[g] = fu[g];
-      cv[g] = fv[g];
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kGuardBlock / 64; ++w) m = fmax(m, red[w]);
+    const int f = !(m < thr);
+    bad[b] = f;
+    if (f) {
+      if (counts) counts[b] += 1;
+      atomicOr(any, 1);
     }
   }
-  if (blockIdx.x == 0 && counts)
-    for (int b = threadIdx.x; b < batch; b += blockDim.x)
-      if (bad[b]) counts[b] += 1;
+}
+
+__global__ void k_zero_int(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 // The network's 64 stencil-coefficient outputs are stored in bf16 (like its
@@ -151,10 +156,13 @@ int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
                             tc ? out + (size_t)(LDSV_NCOEF + 1) * N : nullptr, bs, st);
 }
 
+// the guarded rollout's second state buffer (the learned steps ping-pong
+// between it and the handle's base state), per-trajectory flags and the
+// any-flag
 int ensure_rollout_buffers(ldsv_handle* h) {
   if (h->save_u) return LDSV_OK;
   const size_t sb = h->nstate * h->esize;
-  return ldsv_alloc(h, &h->save_u, 4 * sb + 64 * sizeof(int) + (size_t)h->g.batch * sizeof(int),
+  return ldsv_alloc(h, &h->save_u, 2 * sb + 64 * sizeof(int) + (size_t)h->g.batch * sizeof(int),
                     "rollout guard buffers");
 }
 
@@ -184,42 +192,53 @@ int rollout_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
   void* cv = h->base_v;
   LDSV_HIP(hipMemcpyAsync(cu, u0, sb, hipMemcpyDeviceToDevice, st));
   LDSV_HIP(hipMemcpyAsync(cv, v0, sb, hipMemcpyDeviceToDevice, st));
+  // The guard stays on the device: after every learned step the
+  // trajectories whose new state is non-finite or above the bound are
+  // flagged and (with fallback) recomputed with the plain FV step from the
+  // previous state, the others keeping their learned result.  No value is
+  // read back during the loop; with fallback disabled the any-flag is read
+  // once at the end of the call.
   const bool guard = net && (prm->fallback_enable || prm->guard_threshold > 0);
-  char* save = (char*)h->save_u;
-  int* bad = save ? (int*)(save + 4 * sb) : nullptr;
-  int* any = bad ? bad + h->g.batch : nullptr;
+  void* nu = nullptr;
+  void* nv = nullptr;
+  int* any = nullptr;
+  int* bad = nullptr;
+  if (guard) {
+    nu = h->save_u;
+    nv = (char*)h->save_u + sb;
+    any = (int*)((char*)h->save_u + 2 * sb);
+    bad = any + 64;
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, any, 1);
+    LDSV_LAUNCHED();
+  }
   const double thr = prm->guard_threshold > 0 ? prm->guard_threshold : 1.0e300;
   for (int k = 0; k < nsteps; ++k) {
     const int idx = first_index + k;
     if (net) {
       if (guard) {
-        LDSV_HIP(hipMemcpyAsync(save, cu, sb, hipMemcpyDeviceToDevice, st));
-        LDSV_HIP(hipMemcpyAsync(save + sb, cv, sb, hipMemcpyDeviceToDevice, st));
-      }
-      LDSV_TRY(learned_step(h, prm, net, (const float*)cu, (const float*)cv, (float*)cu,
-                            (float*)cv, idx, nullptr, st, dnet));
-      if (guard) {
-        LDSV_TRY((reduce_per_traj<kRedMax, 1>(h, SpeedOrInf{(const float*)cu, (const float*)cv, h->ncell},
-                                              h->ncell, h->g.batch, h->small, st)));
-        hipLaunchKernelGGL(k_guard_flags, dim3(1), dim3(64), 0, st, h->small, h->g.batch, thr, bad,
-                           any);
-        LDSV_LAUNCHED();
-        int any_h = 0;
-        LDSV_HIP(hipMemcpyAsync(&any_h, any, sizeof(int), hipMemcpyDeviceToHost, st));
-        LDSV_HIP(hipStreamSynchronize(st));
-        if (any_h) {
-          LDSV_REQUIRE(prm->fallback_enable, LDSV_ENONFINITE,
-                       "rollout: learned step %d left a trajectory non-finite or above the bound",
-                       idx);
-          // plain FV step from the saved state into the second save slot
-          LDSV_TRY(ldsv_internal_step(h, prm, nullptr, 0, save, save + sb, save + 2 * sb,
-                                      save + 3 * sb, nullptr, nullptr, 0, st));
-          hipLaunchKernelGGL(k_select, grid1d(h->nstate), dim3(kBlock), 0, st, (float*)cu,
-                             (float*)cv, (const float*)(save + 2 * sb),
-                             (const float*)(save + 3 * sb), bad, fallback_flags, h->ncell,
-                             h->g.batch);
+        LDSV_TRY(learned_step(h, prm, net, (const float*)cu, (const float*)cv, (float*)nu,
+                              (float*)nv, idx, nullptr, st, dnet));
+        // small grids: detection and redo in one launch; otherwise the
+        // detection kernel and the plain step masked to the flagged
+        // trajectories
+        const int rc = ldsv_launch_guard_redo(h, prm, (const float*)cu, (const float*)cv,
+                                              (float*)nu, (float*)nv, thr, prm->fallback_enable,
+                                              fallback_flags, any, st);
+        if (rc == LDSV_ESHAPE) {
+          hipLaunchKernelGGL(k_guard_detect, dim3(h->g.batch), dim3(kGuardBlock), 0, st,
+                             (const float*)nu, (const float*)nv, h->ncell, thr, bad,
+                             fallback_flags, any);
           LDSV_LAUNCHED();
+          if (prm->fallback_enable)
+            LDSV_TRY(ldsv_internal_step_masked(h, prm, cu, cv, nu, nv, bad, st));
+        } else {
+          LDSV_TRY(rc);
         }
+        std::swap(cu, nu);
+        std::swap(cv, nv);
+      } else {
+        LDSV_TRY(learned_step(h, prm, net, (const float*)cu, (const float*)cv, (float*)cu,
+                              (float*)cv, idx, nullptr, st, dnet));
       }
     } else {
       LDSV_TRY(ldsv_internal_step(h, prm, nullptr, 0, cu, cv, cu, cv, nullptr, nullptr, 0, st));
@@ -229,6 +248,13 @@ int rollout_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
       LDSV_HIP(hipMemcpyAsync((char*)traj_u + t * sb, cu, sb, hipMemcpyDeviceToDevice, st));
       LDSV_HIP(hipMemcpyAsync((char*)traj_v + t * sb, cv, sb, hipMemcpyDeviceToDevice, st));
     }
+  }
+  if (guard && !prm->fallback_enable) {
+    LDSV_HIP(hipMemcpyAsync(h->small_host, any, sizeof(int), hipMemcpyDeviceToHost, st));
+    LDSV_HIP(hipStreamSynchronize(st));
+    LDSV_REQUIRE(*(const int*)h->small_host == 0, LDSV_ENONFINITE,
+                 "rollout: a learned step left a trajectory non-finite or above the bound "
+                 "(fallback disabled)");
   }
   return LDSV_OK;
 }

@@ -25,6 +25,12 @@
 
 namespace {
 
+// the pair (b0, b0 + 1) has work when either of its trajectories is active
+// (no mask: every trajectory is)
+__device__ __forceinline__ bool pair_active(const int* active, int b0, int batch) {
+  return !active || active[b0] || (b0 + 1 < batch && active[b0 + 1]);
+}
+
 constexpr int kRowE = 4;       // elements per thread, pass 1
 constexpr int kRow1MaxBlock = 512;
 constexpr int kRowE3 = 8;      // pass 3, with its extra halo row
@@ -38,17 +44,21 @@ __global__ void __launch_bounds__(kRow1MaxBlock) k_div_rowfft(const T* __restric
                                                        Cx<T>* __restrict__ z,
                                                        const Cx<T>* __restrict__ twx, int nx,
                                                        int ny, int log2nx, int batch, int rows,
-                                                       T idx, T idy) {
+                                                       T idx, T idy, const int* active) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* W = A + rows * nx;  // twiddles, read by every stage
-  for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
   // row bands renumbered so one XCD walks consecutive bands (the halo row
   // of a band is the next band's first row)
   const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const int pair = band / gridDim.x;
   const int b0 = 2 * pair;
-  const bool has1 = (b0 + 1) < batch;
+  if (!pair_active(active, b0, batch)) return;
+  Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
+  Cx<T>* W = A + rows * nx;  // twiddles, read by every stage
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
+  // a masked-out trajectory of the pair contributes zeros, so that whatever
+  // its buffers hold cannot reach its partner through the packed transform
+  const bool has0 = !active || active[b0];
+  const bool has1 = (b0 + 1) < batch && (!active || active[b0 + 1]);
   const int j0 = (band - pair * gridDim.x) * rows;
   const size_t plane = (size_t)nx * ny;
   const T* u0 = us + (size_t)b0 * plane;
@@ -65,7 +75,8 @@ __global__ void __launch_bounds__(kRow1MaxBlock) k_div_rowfft(const T* __restric
       const int ip = (i + 1) & (nx - 1);
       const int jp = (j + 1) & (ny - 1);
       const size_t c = (size_t)j * nx + i;
-      const T d0 = (u0[(size_t)j * nx + ip] - u0[c]) * idx + (v0[(size_t)jp * nx + i] - v0[c]) * idy;
+      T d0 = 0;
+      if (has0) d0 = (u0[(size_t)j * nx + ip] - u0[c]) * idx + (v0[(size_t)jp * nx + i] - v0[c]) * idy;
       T d1 = 0;
       if (has1) d1 = (u1[(size_t)j * nx + ip] - u1[c]) * idx + (v1[(size_t)jp * nx + i] - v1[c]) * idy;
       A[t] = Cx<T>{d0, d1};
@@ -92,13 +103,13 @@ template <typename T>
 __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
                                                       const Cx<T>* __restrict__ twy,
                                                       const double* __restrict__ pinv, int nx,
-                                                      int ny, int log2ny, int log2cols) {
+                                                      int ny, int log2ny, int log2cols, int batch,
+                                                      const int* active) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int cols = 1 << log2cols;
   const int n = cols << log2ny;
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);  // element (column c, y) at y * cols + c
   Cx<T>* W = A + n;
-  for (int e = threadIdx.x; e < ny; e += blockDim.x) W[e] = twy[e];
   const int ncx = nx >> log2cols;
   int cx, pair;
   {
@@ -113,6 +124,8 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
       cx = lid - pair * ncx;
     }
   }
+  if (!pair_active(active, 2 * pair, batch)) return;
+  for (int e = threadIdx.x; e < ny; e += blockDim.x) W[e] = twy[e];
   const int x0 = cx << log2cols;
   Cx<T>* zp = z + (size_t)pair * nx * ny;
   {
@@ -156,18 +169,21 @@ __global__ void __launch_bounds__(kRow3Block) k_rowifft_grad(const Cx<T>* __rest
                                                          T* __restrict__ uo, T* __restrict__ vo,
                                                          T* __restrict__ po, int nx, int ny,
                                                          int log2nx, int batch, int rows, T idx,
-                                                         T idy) {
+                                                         T idy, const int* active) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int nr = rows + 1;
-  Cx<T>* P = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* W = P + nr * nx;
-  for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
   // row bands renumbered so one XCD walks consecutive bands (the halo row
   // of a band is the next band's first row)
   const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const int pair = band / gridDim.x;
   const int b0 = 2 * pair;
+  if (!pair_active(active, b0, batch)) return;
+  const bool w0 = !active || active[b0];
   const bool has1 = (b0 + 1) < batch;
+  const bool w1 = has1 && (!active || active[b0 + 1]);
+  Cx<T>* P = reinterpret_cast<Cx<T>*>(smem_raw);
+  Cx<T>* W = P + nr * nx;
+  for (int e = threadIdx.x; e < nx; e += blockDim.x) W[e] = twx[e];
   const int j0 = (band - pair * gridDim.x) * rows;
   const size_t plane = (size_t)nx * ny;
   const Cx<T>* zp = z + (size_t)pair * plane;
@@ -203,10 +219,12 @@ __global__ void __launch_bounds__(kRow3Block) k_rowifft_grad(const Cx<T>* __rest
     const Cx<T> pw = P[(r + 1) * nx + im];
     const Cx<T> ps = P[r * nx + i];
     const size_t c0 = (size_t)b0 * plane + (size_t)j * nx + i;
-    uo[c0] = us[c0] - (pc.x - pw.x) * idx;
-    vo[c0] = vs[c0] - (pc.x - ps.x) * idy;
-    if (po) po[c0] = pc.x;
-    if (has1) {
+    if (w0) {
+      uo[c0] = us[c0] - (pc.x - pw.x) * idx;
+      vo[c0] = vs[c0] - (pc.x - ps.x) * idy;
+      if (po) po[c0] = pc.x;
+    }
+    if (w1) {
       const size_t c1 = c0 + plane;
       uo[c1] = us[c1] - (pc.y - pw.y) * idx;
       vo[c1] = vs[c1] - (pc.y - ps.y) * idy;
@@ -236,10 +254,13 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
                                                           const Cx<T>* __restrict__ twy,
                                                           const double* __restrict__ pinv, int nx,
                                                           int ny, int log2nx, int log2ny, int batch,
-                                                          T idx, T idy, int ra) {
+                                                          T idx, T idy, int ra, const int* active) {
   constexpr bool kKeep = E <= 4;
   constexpr int KE = kKeep ? E : 1;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  if (!pair_active(active, 2 * (int)blockIdx.x, batch)) return;
+  const bool w0 = !active || active[2 * blockIdx.x];
+  const bool w1 = 2 * (int)blockIdx.x + 1 < batch && (!active || active[2 * blockIdx.x + 1]);
   // element (i, j) at j * ra + i: rows padded (ra >= nx) so that the rows a
   // wavefront spans in the row transforms fall into different LDS banks
   Cx<T>* A = reinterpret_cast<Cx<T>*>(smem_raw);
@@ -249,7 +270,6 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
   for (int e = threadIdx.x; e < ny; e += blockDim.x) Wy[e] = twy[e];
   const int pair = blockIdx.x;
   const int b0 = 2 * pair;
-  const bool has1 = (b0 + 1) < batch;
   const int n = nx * ny;
   const size_t plane = (size_t)n;
   const T* u0 = us + (size_t)b0 * plane;
@@ -273,9 +293,11 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
         const int ip = (i + 1) & (nx - 1);
         const int jp = (j + 1) & (ny - 1);
         const T a0 = u0[t], c0v = v0[t];
-        d0[k] = (u0[j * nx + ip] - a0) * idx + (v0[jp * nx + i] - c0v) * idy;
+        // a masked-out trajectory of the pair contributes zeros to the
+        // packed transform (and is not written)
+        if (w0) d0[k] = (u0[j * nx + ip] - a0) * idx + (v0[jp * nx + i] - c0v) * idy;
         T a1 = 0, c1v = 0;
-        if (has1) {
+        if (w1) {
           a1 = u0[plane + t];
           c1v = v0[plane + t];
           d1[k] = (u0[plane + j * nx + ip] - a1) * idx + (v0[plane + jp * nx + i] - c1v) * idy;
@@ -321,10 +343,12 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
     const Cx<T> pw = A[j * ra + ((i - 1) & (nx - 1))];
     const Cx<T> ps = A[((j - 1) & (ny - 1)) * ra + i];
     const size_t c0 = (size_t)b0 * plane + t;
-    uo[c0] = (kKeep ? cu0[k % KE] : us[c0]) - (pc.x - pw.x) * idx;
-    vo[c0] = (kKeep ? cv0[k % KE] : vs[c0]) - (pc.x - ps.x) * idy;
-    if (po) po[c0] = pc.x;
-    if (has1) {
+    if (w0) {
+      uo[c0] = (kKeep ? cu0[k % KE] : us[c0]) - (pc.x - pw.x) * idx;
+      vo[c0] = (kKeep ? cv0[k % KE] : vs[c0]) - (pc.x - ps.x) * idy;
+      if (po) po[c0] = pc.x;
+    }
+    if (w1) {
       const size_t c1 = c0 + plane;
       uo[c1] = (kKeep ? cu1[k % KE] : us[c1]) - (pc.y - pw.y) * idx;
       vo[c1] = (kKeep ? cv1[k % KE] : vs[c1]) - (pc.y - ps.y) * idy;
@@ -335,7 +359,7 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
 
 template <typename T>
 int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo, void* po,
-                 hipStream_t st) {
+                 hipStream_t st, const int* active) {
   const int nx = h->g.nx, ny = h->g.ny, B = h->g.batch;
   const T idx = (T)(nx / h->g.lx), idy = (T)(ny / h->g.ly);
   const size_t cs = sizeof(Cx<T>);
@@ -359,7 +383,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
     LDSV_TLAUNCH(h, 2, kern, dim3(h->npairs), dim3(kOneBlock), lds, st, (const T*)us,
                  (const T*)vs, (T*)uo, (T*)vo, (T*)po, (const Cx<T>*)h->twx,
                  (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2nx, h->log2ny, B,
-                 idx, idy, ra);
+                 idx, idy, ra, active);
     LDSV_LAUNCHED();
     return LDSV_OK;
   }
@@ -380,7 +404,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(block1), lds, st,
                (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
-               h->log2nx, B, rows, idx, idy);
+               h->log2nx, B, rows, idx, idy, active);
   LDSV_LAUNCHED();
   // pass 2: 8 columns (fewer for long columns) within kColE * kColBlock
   // values
@@ -405,7 +429,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3((nx / cols) * h->npairs), dim3(cblock), lds, st,
                (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2ny,
-               __builtin_ctz((unsigned)cols));
+               __builtin_ctz((unsigned)cols), B, active);
   LDSV_LAUNCHED();
   // pass 3: rows + 1 halo row per block of kRow3Block threads; more rows
   // than pass 1 so the halo row costs less
@@ -428,7 +452,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 3, k_rowifft_grad<T>, dim3(ny / rows3, h->npairs), dim3(block3), lds, st,
                (const Cx<T>*)h->zspec, (const Cx<T>*)h->twx, (const T*)us, (const T*)vs, (T*)uo,
-               (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows3, idx, idy);
+               (T*)vo, (T*)po, nx, ny, h->log2nx, B, rows3, idx, idy, active);
   LDSV_LAUNCHED();
   return LDSV_OK;
 }
@@ -438,7 +462,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
 // u*, v* -> projected u, v (may alias u*, v* only if the caller accepts that
 // pass 3 reads u*[c] before writing out[c] at the same index, which it does).
 int ldsv_launch_project(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo,
-                        void* po, hipStream_t st) {
-  if (h->g.dtype == LDSV_F64) return project_impl<double>(h, us, vs, uo, vo, po, st);
-  return project_impl<float>(h, us, vs, uo, vo, po, st);
+                        void* po, hipStream_t st, const int* active) {
+  if (h->g.dtype == LDSV_F64) return project_impl<double>(h, us, vs, uo, vo, po, st, active);
+  return project_impl<float>(h, us, vs, uo, vo, po, st, active);
 }

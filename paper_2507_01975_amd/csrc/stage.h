@@ -36,6 +36,9 @@ struct StageArgs {
   const float* fbf = nullptr;
   size_t fb_bstride = 0;
   double alpha = 0, beta = 0, delta = 0, eps = 0, gamma = 0, wacc = 0;
+  // per-trajectory mask (int [B], nullable; MAC only): the workgroups of a
+  // trajectory whose entry is 0 return at once and write nothing
+  const int* active = nullptr;
 };
 
 // Flux-block operands of a step (Sec. 3.4, Eqs. 5-8): uniform kernels
@@ -68,5 +71,7 @@ struct DerivCoef {
 
 int ldsv_launch_stage(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a,
                       hipStream_t st);
+// active (int [B], nullable): only trajectories whose entry is nonzero are
+// projected and written; the others' outputs are left untouched
 int ldsv_launch_project(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo,
-                        void* po, hipStream_t st);
+                        void* po, hipStream_t st, const int* active = nullptr);

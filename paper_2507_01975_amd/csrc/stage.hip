@@ -91,6 +91,7 @@ struct StagePtrs {
   const float* fbw;  // flux block: [interp, deriv][kind][20] uniform weights
   const float* fbf;  // flux block: [B][8][Ny][Nx] fields (interp kinds, deriv kinds), nullable
   size_t fbs;
+  const int* active;  // per-trajectory mask, nullable (MAC)
 };
 
 __device__ __forceinline__ float coef_value(const float* p) { return *p; }
@@ -192,6 +193,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   const int tilesx = nx / TX;
   const int tile = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const int b = tile / gridDim.x;
+  if (p.active && !p.active[b]) return;  // uniform per workgroup, before any barrier
   const int tp = tile - b * gridDim.x;
   const int i0 = (tp % tilesx) * TX;
   const int j0 = (tp / tilesx) * TY;
@@ -572,6 +574,7 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   p.fbw = a.fbw;
   p.fbf = a.fbf;
   p.fbs = a.fb_bstride;
+  p.active = a.active;
   const double dx = h->g.lx / h->g.nx, dy = h->g.ly / h->g.ny;
   PhysT<T> ph;
   ph.nu = (T)prm->nu;

@@ -354,21 +354,27 @@ def throughput(N, B, prm, steps, net=None, warmup=3, lx=2 * math.pi, dnet=None,
     N x N, batch B, on device-resident state."""
     s = ldsv.Solver(N, N, B, lx=lx, ly=lx)
     u, v = s.init_state(ic, seed=7)
+    if net is not None:
+        # the learned solver as it runs: the rollout with the guard and the
+        # plain-FV fallback on the device, one snapshot at the end
+        prm = ldsv.params(nu=prm.nu, dt=prm.dt, forcing_amp=prm.forcing_amp,
+                          forcing_k=prm.forcing_k, drag=prm.drag, rk=prm.rk,
+                          mask=prm.physics_mask, k_c=prm.k_c, fallback_enable=1)
+        flags = torch.zeros(B, dtype=torch.int32, device="cuda")
 
-    def one(k):
-        if net is None:
-            s.fv_step(prm, u, v, out=(u, v))
-        elif dnet is None:
-            s.learned_fv_step(prm, net, u, v, k + 1, out=(u, v))
-        else:
-            s.learned_d_fv_step(prm, net, dnet, u, v, k + 1, out=(u, v))
+        def run(k):
+            if dnet is None:
+                s.rollout(prm, u, v, k, save_every=k, net=net, fallback_flags=flags)
+            else:
+                s.rollout_d(prm, net, dnet, u, v, k, k, fallback_flags=flags)
+    else:
+        def run(k):
+            s.fv_step(prm, u, v, nsteps=k, out=(u, v))
 
-    for k in range(warmup):
-        one(k)
+    run(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        one(k)
+    run(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     s.close()

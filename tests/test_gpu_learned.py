@@ -256,12 +256,87 @@ def test_guard_falls_back_to_plain_fv_for_the_failing_trajectory_only():
     for k in range(2):
         u, v = s.learned_fv_step(prm, net, u, v, k + 1)
         pu, pv = s.fv_step(L_.params(**kw), pu, pv)
-    assert torch.equal(tu[1, :2], u[:2]) and torch.equal(tu[1, 2], pu[2])
+    assert torch.equal(tu[1, :2], u[:2])
+    # the redo (detection and the plain step of the pair in one kernel on
+    # grids up to 64^2) evaluates the plain step's expressions in its own
+    # kernel: equal to the plain step up to FP32 rounding
+    assert_fields_close(tu[1, 2], pu[2], rel=1e-6, elem=1e-6, what="redone u")
+    assert_fields_close(tv[1, 2], pv[2], rel=1e-6, elem=1e-6, what="redone v")
     # with the fallback disabled the call reports the failure
     prm = L_.params(k_c=1, guard_threshold=bound, fallback_enable=0, **kw)
     with pytest.raises(L_.LdsvError) as e:
         s.rollout(prm, u0, v0, nsteps=1, save_every=1, net=net)
     assert e.value.code == L_.ENONFINITE
+
+
+@pytest.mark.parametrize("n,b,bad", [(32, 4, 1), (128, 4, 2)])
+def test_guard_fallback_beside_a_good_partner(n, b, bad):
+    """The plain-FV redo of one trajectory of a packed pair (the projection
+    transforms two trajectories at once): its good partner keeps its learned
+    result bit for bit, the redone one follows the oracle's plain steps; at
+    32^2 the one-workgroup projection, at 128^2 the three passes."""
+    L_ = need_gpu()
+    announce("guard beside a good partner", n, b, bad)
+    kw = dict(KW, dt=0.005 * 32 / n)
+    net, _, _ = _net(L_, seed=4)
+    s = L_.Solver(n, n, b)
+    u0, v0 = s.init_state(L_.IC_GRF_PEAK, seed=7)
+    u0[bad] *= 8.0
+    v0[bad] *= 8.0
+    good = [i for i in range(b) if i != bad]
+    bound = 4.0 * float((u0[good].abs() + v0[good].abs()).max())
+    prm = L_.params(k_c=1, guard_threshold=bound, fallback_enable=1, **kw)
+    flags = torch.zeros(b, dtype=torch.int32, device="cuda")
+    tu, tv = s.rollout(prm, u0, v0, nsteps=2, save_every=1, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    assert flags.tolist() == [2 if i == bad else 0 for i in range(b)]
+    # each step of the good trajectories is the learned step of the rollout's
+    # previous state (which holds the redone trajectory), bit for bit
+    prev_u, prev_v = u0, v0
+    for k in range(2):
+        lu, lv = s.learned_fv_step(prm, net, prev_u.contiguous(), prev_v.contiguous(), k + 1)
+        assert torch.equal(tu[k, good], lu[good]) and torch.equal(tv[k, good], lv[good]), k
+        prev_u, prev_v = tu[k], tv[k]
+    oprm = oracle_prm(n, n, k_c=1, **kw)
+    pu, pv = timestep.fv_step(cpu64(u0[bad:bad + 1]), cpu64(v0[bad:bad + 1]), oprm, nsteps=2)
+    assert_fields_close(tu[1, bad], pu[0], what="redone trajectory u")
+    assert_fields_close(tv[1, bad], pv[0], what="redone trajectory v")
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_guarded_rollout_replays_as_a_captured_graph(n):
+    """With the fallback enabled the guarded rollout reads nothing back, so
+    it can be captured in a HIP graph: replays (with a trajectory that trips
+    the guard at every step, so the redo runs inside the graph) match the
+    eager call bit for bit, flags included; at 32^2 the one-kernel redo, at
+    128^2 the masked plain step."""
+    L_ = need_gpu()
+    announce("guarded rollout graph capture", n)
+    b = 3
+    kw = dict(KW, dt=0.005 * 32 / n)
+    net, _, _ = _net(L_, seed=4)
+    s = L_.Solver(n, n, b)
+    u0, v0 = s.init_state(L_.IC_GRF_PEAK, seed=7)
+    u0[1] *= 8.0
+    v0[1] *= 8.0
+    bound = 4.0 * float((u0[0::2].abs() + v0[0::2].abs()).max())
+    prm = L_.params(k_c=2, guard_threshold=bound, fallback_enable=1, **kw)
+    flags = torch.zeros(b, dtype=torch.int32, device="cuda")
+    ru, rv = s.rollout(prm, u0, v0, nsteps=4, save_every=2, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    rflags = flags.clone()
+    assert rflags.tolist() == [0, 4, 0]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gu, gv = s.rollout(prm, u0, v0, nsteps=4, save_every=2, net=net, fallback_flags=flags)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        flags.zero_()
+        s.fv_step(L_.params(**kw), u0, v0)   # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gu, ru) and torch.equal(gv, rv) and torch.equal(flags, rflags)
 
 
 def test_nan_network_falls_back_everywhere():
@@ -279,7 +354,8 @@ def test_nan_network_falls_back_everywhere():
     pu, pv = s.fv_step(L_.params(**KW), u0, v0, nsteps=3)
     torch.cuda.synchronize()
     assert flags.tolist() == [3, 3]
-    assert torch.equal(tu[0], pu) and torch.equal(tv[0], pv)
+    assert_fields_close(tu[0], pu, rel=1e-6, elem=1e-6, what="all redone u")
+    assert_fields_close(tv[0], pv, rel=1e-6, elem=1e-6, what="all redone v")
 
 
 def test_bf16_conversion_rounds_to_nearest_even():
