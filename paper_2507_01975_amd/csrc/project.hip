@@ -21,6 +21,7 @@
 //   k_rowifft_grad   inverse FFT along x for rows j-1..j+R-1, then
 //                    u = u* - (p - p[i-1])/dx, v = v* - (p - p[j-1])/dy
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include <algorithm>
 
 namespace {
@@ -159,6 +160,211 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
     const int t = k * blockDim.x + threadIdx.x;
     if (t < n) zp[(size_t)(t >> log2cols) * nx + x0 + (t & (cols - 1))] = A[t];
   }
+}
+
+// The row passes for FP32 with the row length N = 2^LOGN (= nx) and the
+// rows per workgroup known at compile time (register-resident first and
+// last transform stages, as in k_col_solve_r).
+//
+// Pass 1: the divergence of the pair (d_b + i d_{b+1}) is formed straight
+// into the first stage's registers, the FFT along x runs, and its last
+// stage stores the spectrum rows to global memory.
+template <int LOGN, int LOGR>
+__global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_div_rowfft_r(
+    const float* __restrict__ us, const float* __restrict__ vs, Cx<float>* __restrict__ z,
+    const Cx<float>* __restrict__ twx, int ny, int batch, float idx, float idy,
+    const int* active) {
+  constexpr int N = 1 << LOGN, BLOCK = (N << LOGR) / 8, S = fftreg::plan_stages(LOGN);
+  constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
+  constexpr int R0 = 1 << LR0, RL = 1 << LRL;
+  __shared__ Cx<float> A[fftreg::lds_elems<true, LOGN, LOGR>()];
+  __shared__ Cx<float> W[N];
+  const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int pair = band / gridDim.x;
+  const int b0 = 2 * pair;
+  if (!pair_active(active, b0, batch)) return;
+  const bool has0 = !active || active[b0];
+  const bool has1 = (b0 + 1) < batch && (!active || active[b0 + 1]);
+  const int j0 = (band - pair * gridDim.x) << LOGR;
+  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = twx[e];
+  const size_t plane = (size_t)N * ny;
+  const float* u0 = us + (size_t)b0 * plane;
+  const float* v0 = vs + (size_t)b0 * plane;
+  Cx<float> x[8];
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int t, i;
+      fftreg::point<true, LOGN, LOGR, BLOCK, LR0>(q, r, t, i);
+      const int j = j0 + t;
+      const int ip = (i + 1) & (N - 1);
+      const int jp = (j + 1) & (ny - 1);
+      const size_t c = ((size_t)j << LOGN) + i;
+      float d0 = 0.f, d1 = 0.f;
+      if (has0)
+        d0 = (u0[((size_t)j << LOGN) + ip] - u0[c]) * idx + (v0[((size_t)jp << LOGN) + i] - v0[c]) * idy;
+      if (has1)
+        d1 = (u0[plane + ((size_t)j << LOGN) + ip] - u0[plane + c]) * idx +
+             (v0[plane + ((size_t)jp << LOGN) + i] - v0[plane + c]) * idy;
+      x[q * R0 + r] = Cx<float>{d0, d1};
+    }
+  __syncthreads();
+  fftreg::run<true, LOGN, LOGR, BLOCK, -1, false>(x, A, W);
+  Cx<float>* zo = z + (size_t)pair * plane;
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int t, i;
+      fftreg::point<true, LOGN, LOGR, BLOCK, LRL>(q, r, t, i);
+      zo[((size_t)(j0 + t) << LOGN) + i] = x[q * RL + r];
+    }
+}
+
+// Pass 3: inverse FFT along x of 2^LOGR rows, the first of them the halo row
+// above the band, whose 2^LOGR - 1 rows get u = u* - G p.  Bands of
+// 2^LOGR - 1 output rows (the last one clipped at ny, so that every output
+// row is written by one workgroup and in-place calls stay safe).
+template <int LOGN, int LOGR>
+__global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_rowifft_grad_r(
+    const Cx<float>* __restrict__ z, const Cx<float>* __restrict__ twx,
+    const float* __restrict__ us, const float* __restrict__ vs, float* __restrict__ uo,
+    float* __restrict__ vo, float* __restrict__ po, int ny, int batch, float idx, float idy,
+    const int* active) {
+  constexpr int N = 1 << LOGN, ROWS = 1 << LOGR, BLOCK = (N << LOGR) / 8;
+  constexpr int S = fftreg::plan_stages(LOGN);
+  constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
+  constexpr int R0 = 1 << LR0, RL = 1 << LRL;
+  __shared__ Cx<float> A[fftreg::lds_elems<true, LOGN, LOGR>()];
+  __shared__ Cx<float> W[N];
+  const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int pair = band / gridDim.x;
+  const int b0 = 2 * pair;
+  if (!pair_active(active, b0, batch)) return;
+  const bool w0 = !active || active[b0];
+  const bool w1 = (b0 + 1) < batch && (!active || active[b0 + 1]);
+  const int o0 = (band - pair * gridDim.x) * (ROWS - 1);  // first output row
+  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = twx[e];
+  const size_t plane = (size_t)N * ny;
+  const Cx<float>* zp = z + (size_t)pair * plane;
+  Cx<float> x[8];
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int t, i;
+      fftreg::point<true, LOGN, LOGR, BLOCK, LRL>(q, r, t, i);
+      x[q * RL + r] = zp[((size_t)((o0 - 1 + t) & (ny - 1)) << LOGN) + i];
+    }
+  __syncthreads();
+  fftreg::run<true, LOGN, LOGR, BLOCK, +1, true>(x, A, W);
+  // p of the band's rows into LDS for the neighbour differences (every read
+  // of A by the transform is behind its last barrier)
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int t, i;
+      fftreg::point<true, LOGN, LOGR, BLOCK, LR0>(q, r, t, i);
+      A[fftreg::lds_at<true, LOGN, LOGR>(i, t)] = x[q * R0 + r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < (8 * (ROWS - 1) + ROWS - 1) / ROWS; ++k) {
+    const int e = k * BLOCK + (int)threadIdx.x;
+    if (e >= (ROWS - 1) * N) break;
+    const int t = 1 + (e >> LOGN);
+    const int i = e & (N - 1);
+    const int j = o0 + t - 1;
+    if (j >= ny) break;
+    const Cx<float> pc = A[fftreg::lds_at<true, LOGN, LOGR>(i, t)];
+    const Cx<float> pw = A[fftreg::lds_at<true, LOGN, LOGR>((i - 1) & (N - 1), t)];
+    const Cx<float> ps = A[fftreg::lds_at<true, LOGN, LOGR>(i, t - 1)];
+    const size_t c0 = (size_t)b0 * plane + ((size_t)j << LOGN) + i;
+    if (w0) {
+      uo[c0] = us[c0] - (pc.x - pw.x) * idx;
+      vo[c0] = vs[c0] - (pc.x - ps.x) * idy;
+      if (po) po[c0] = pc.x;
+    }
+    if (w1) {
+      const size_t c1 = c0 + plane;
+      uo[c1] = us[c1] - (pc.y - pw.y) * idx;
+      vo[c1] = vs[c1] - (pc.y - ps.y) * idy;
+      if (po) po[c1] = pc.y;
+    }
+  }
+}
+
+// The column pass for FP32 with the transform length N = 2^LOGN (= ny) and
+// the column count 2^LOGC known at compile time: the same work as
+// k_col_solve (forward FFT along y, the FP64 factor, inverse FFT), with the
+// first forward stage fed straight from the global loads, the factor applied
+// in registers between the last forward stage and the first inverse stage,
+// and the last inverse stage stored straight to global memory (half the LDS
+// traffic and a third of the barriers of the general kernel, and index
+// arithmetic folded into constants).  One thread per radix-8 butterfly.
+template <int LOGN, int LOGC>
+__global__ void __launch_bounds__(((1 << LOGN) << LOGC) / 8) k_col_solve_r(
+    Cx<float>* __restrict__ z, const Cx<float>* __restrict__ twy, const double* __restrict__ pinv,
+    int nx, int batch, const int* active) {
+  constexpr int N = 1 << LOGN, BLOCK = (N << LOGC) / 8;
+  constexpr int S = fftreg::plan_stages(LOGN);
+  constexpr int R0 = 1 << fftreg::plan_lr(LOGN, 0), RL = 1 << fftreg::plan_lr(LOGN, S - 1);
+  __shared__ Cx<float> A[fftreg::lds_elems<false, LOGN, LOGC>()];
+  __shared__ Cx<float> W[N];
+  const int ncx = nx >> LOGC;
+  int cx, pair;
+  {
+    const int lid = blockIdx.x;
+    if ((ncx & 7) == 0) {
+      const int cpx = ncx >> 3, slot = lid >> 3;
+      const int q = slot / cpx;
+      cx = (lid & 7) * cpx + (slot - q * cpx);
+      pair = q;
+    } else {
+      pair = lid / ncx;
+      cx = lid - pair * ncx;
+    }
+  }
+  if (!pair_active(active, 2 * pair, batch)) return;
+  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = twy[e];
+  const int x0 = cx << LOGC;
+  Cx<float>* zp = z + (size_t)pair * nx * N;
+  constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
+  Cx<float> x[8];
+  double f[8];
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int t, y;
+      fftreg::point<false, LOGN, LOGC, BLOCK, LR0>(q, r, t, y);
+      x[q * R0 + r] = zp[(size_t)y * nx + x0 + t];
+    }
+  // the factors of the points the last forward stage leaves in registers
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int t, y;
+      fftreg::point<false, LOGN, LOGC, BLOCK, LRL>(q, r, t, y);
+      f[q * RL + r] = pinv[(size_t)y * nx + x0 + t];
+    }
+  __syncthreads();
+  fftreg::run<false, LOGN, LOGC, BLOCK, -1, false>(x, A, W);
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    x[e] = Cx<float>{(float)((double)x[e].x * f[e]), (float)((double)x[e].y * f[e])};
+  fftreg::run<false, LOGN, LOGC, BLOCK, +1, true>(x, A, W);
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int t, y;
+      fftreg::point<false, LOGN, LOGC, BLOCK, LR0>(q, r, t, y);
+      zp[(size_t)y * nx + x0 + t] = x[q * R0 + r];
+    }
 }
 
 template <typename T>
@@ -357,6 +563,95 @@ __global__ void __launch_bounds__(kOneBlock) k_project_lds(const T* __restrict__
   }
 }
 
+// the compile-time row passes where they exist (FP32, 64 <= threads <=
+// 1024); false: the caller launches the general ones
+template <typename T>
+bool launch_div_rowfft_r(ldsv_handle* h, const void* us, const void* vs, hipStream_t st,
+                         const int* active) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    // 2048 points per workgroup (256 threads), fewer rows for small batches
+    // until the launch has a workgroup per CU
+    int rows = std::max(1, 2048 / h->g.nx);
+    if (rows > h->g.ny) rows = h->g.ny;
+    while (rows > 1 && (size_t)(h->g.ny / rows) * h->npairs < 256) rows >>= 1;
+    const int logn = h->log2nx, logr = __builtin_ctz((unsigned)rows);
+    const dim3 grid(h->g.ny / rows, h->npairs);
+    const float idx = (float)(h->g.nx / h->g.lx), idy = (float)(h->g.ny / h->g.ly);
+#define LDSV_ROWR(LN, LR)                                                                        \
+  if (logn == LN && logr == LR) {                                                                \
+    LDSV_TLAUNCH(h, 1, (k_div_rowfft_r<LN, LR>), grid, dim3(((1 << LN) << LR) / 8), 0, st,        \
+                 (const float*)us, (const float*)vs, (Cx<float>*)h->zspec,                        \
+                 (const Cx<float>*)h->twx, h->g.ny, h->g.batch, idx, idy, active);               \
+    return true;                                                                                 \
+  }
+    LDSV_ROWR(6, 3) LDSV_ROWR(6, 4)
+    LDSV_ROWR(7, 2) LDSV_ROWR(7, 3) LDSV_ROWR(7, 4)
+    LDSV_ROWR(8, 1) LDSV_ROWR(8, 2) LDSV_ROWR(8, 3) LDSV_ROWR(8, 4)
+    LDSV_ROWR(9, 0) LDSV_ROWR(9, 1) LDSV_ROWR(9, 2) LDSV_ROWR(9, 3) LDSV_ROWR(9, 4)
+    LDSV_ROWR(10, 0) LDSV_ROWR(10, 1) LDSV_ROWR(10, 2) LDSV_ROWR(10, 3)
+    LDSV_ROWR(11, 0) LDSV_ROWR(11, 1) LDSV_ROWR(11, 2)
+#undef LDSV_ROWR
+    return false;
+  }
+}
+
+template <typename T>
+bool launch_rowifft_grad_r(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo,
+                           void* po, hipStream_t st, const int* active) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    const int logn = h->log2nx;
+    const float idx = (float)(h->g.nx / h->g.lx), idy = (float)(h->g.ny / h->g.ly);
+    // 8 transformed rows (7 output rows and the halo row) per workgroup, 4 at 2048
+    const int logr = logn >= 11 ? 2 : 3;
+    const int outr = (1 << logr) - 1;
+    const dim3 grid((h->g.ny + outr - 1) / outr, h->npairs);
+#define LDSV_ROW3R(LN, LR)                                                                       \
+  if (logn == LN && logr == LR) {                                                                \
+    LDSV_TLAUNCH(h, 3, (k_rowifft_grad_r<LN, LR>), grid, dim3(((1 << LN) << LR) / 8), 0, st,      \
+                 (const Cx<float>*)h->zspec, (const Cx<float>*)h->twx, (const float*)us,          \
+                 (const float*)vs, (float*)uo, (float*)vo, (float*)po, h->g.ny, h->g.batch, idx,  \
+                 idy, active);                                                                   \
+    return true;                                                                                 \
+  }
+    LDSV_ROW3R(6, 3) LDSV_ROW3R(7, 3) LDSV_ROW3R(8, 3) LDSV_ROW3R(9, 3) LDSV_ROW3R(10, 3)
+    LDSV_ROW3R(11, 2)
+#undef LDSV_ROW3R
+    return false;
+  }
+}
+
+// the compile-time column pass where it exists (FP32; 512 <= cols * ny <=
+// 8192 points per workgroup); false: the caller launches the general one
+template <typename T>
+bool launch_col_solve_r(ldsv_handle* h, int cols, hipStream_t st, const int* active) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    const int logn = h->log2ny, logc = __builtin_ctz((unsigned)cols);
+    const dim3 grid((h->g.nx / cols) * h->npairs);
+    const int B = h->g.batch;
+#define LDSV_COLR(LN, LC)                                                                        \
+  if (logn == LN && logc == LC) {                                                                \
+    LDSV_TLAUNCH(h, 2, (k_col_solve_r<LN, LC>), grid, dim3(((1 << LN) << LC) / 8), 0, st,         \
+                 (Cx<float>*)h->zspec, (const Cx<float>*)h->twy, (const double*)h->pinv,          \
+                 h->g.nx, B, active);                                                            \
+    return true;                                                                                 \
+  }
+    LDSV_COLR(6, 3)
+    LDSV_COLR(7, 2) LDSV_COLR(7, 3)
+    LDSV_COLR(8, 1) LDSV_COLR(8, 2) LDSV_COLR(8, 3)
+    LDSV_COLR(9, 0) LDSV_COLR(9, 1) LDSV_COLR(9, 2) LDSV_COLR(9, 3)
+    LDSV_COLR(10, 0) LDSV_COLR(10, 1) LDSV_COLR(10, 2) LDSV_COLR(10, 3)
+    LDSV_COLR(11, 0) LDSV_COLR(11, 1) LDSV_COLR(11, 2)
+#undef LDSV_COLR
+    return false;
+  }
+}
+
 template <typename T>
 int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo, void* po,
                  hipStream_t st, const int* active) {
@@ -395,16 +690,19 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   // small batches: fewer rows per block until the launch has a workgroup per
   // CU, the block sized to the rows (whole wavefronts)
   while (rows > 1 && (size_t)(ny / rows) * h->npairs < 256) rows >>= 1;
-  const int need1 = rows * nx / kRowE;
-  const int block1 = need1 > kBlock ? kRow1MaxBlock : std::max(64, (need1 + 63) / 64 * 64);
-  LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * block1, LDSV_ESHAPE,
-               "project: nx=%d too large for the LDS row transform", nx);
-  size_t lds = ((size_t)rows * nx + nx) * cs;
-  LDSV_HIP(hipFuncSetAttribute((const void*)k_div_rowfft<T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(block1), lds, st,
-               (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
-               h->log2nx, B, rows, idx, idy, active);
+  size_t lds = 0;
+  if (!launch_div_rowfft_r<T>(h, us, vs, st, active)) {
+    const int need1 = rows * nx / kRowE;
+    const int block1 = need1 > kBlock ? kRow1MaxBlock : std::max(64, (need1 + 63) / 64 * 64);
+    LDSV_REQUIRE((size_t)rows * nx <= (size_t)kRowE * block1, LDSV_ESHAPE,
+                 "project: nx=%d too large for the LDS row transform", nx);
+    lds = ((size_t)rows * nx + nx) * cs;
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_div_rowfft<T>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LDSV_TLAUNCH(h, 1, k_div_rowfft<T>, dim3(ny / rows, h->npairs), dim3(block1), lds, st,
+                 (const T*)us, (const T*)vs, (Cx<T>*)h->zspec, (const Cx<T>*)h->twx, nx, ny,
+                 h->log2nx, B, rows, idx, idy, active);
+  }
   LDSV_LAUNCHED();
   // pass 2: 8 columns (fewer for long columns) within kColE * kColBlock
   // values
@@ -421,18 +719,24 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
                LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
   // 8 values per thread where the block allows it: twice the wavefronts of
   // the minimum, to hide the latency of the transform's LDS round trips
-  int cblock = (int)(((size_t)cols * ny / 8 + 63) / 64 * 64);
-  if (cblock > kColBlock) cblock = kColBlock;
-  if (cblock < 64) cblock = 64;
-  lds = ((size_t)cols * ny + ny) * cs;
-  LDSV_HIP(hipFuncSetAttribute((const void*)k_col_solve<T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3((nx / cols) * h->npairs), dim3(cblock), lds, st,
-               (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny, h->log2ny,
-               __builtin_ctz((unsigned)cols), B, active);
+  if (!launch_col_solve_r<T>(h, cols, st, active)) {
+    int cblock = (int)(((size_t)cols * ny / 8 + 63) / 64 * 64);
+    if (cblock > kColBlock) cblock = kColBlock;
+    if (cblock < 64) cblock = 64;
+    lds = ((size_t)cols * ny + ny) * cs;
+    LDSV_HIP(hipFuncSetAttribute((const void*)k_col_solve<T>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LDSV_TLAUNCH(h, 2, k_col_solve<T>, dim3((nx / cols) * h->npairs), dim3(cblock), lds, st,
+                 (Cx<T>*)h->zspec, (const Cx<T>*)h->twy, (const double*)h->pinv, nx, ny,
+                 h->log2ny, __builtin_ctz((unsigned)cols), B, active);
+  }
   LDSV_LAUNCHED();
   // pass 3: rows + 1 halo row per block of kRow3Block threads; more rows
   // than pass 1 so the halo row costs less
+  if (launch_rowifft_grad_r<T>(h, us, vs, uo, vo, po, st, active)) {
+    LDSV_LAUNCHED();
+    return LDSV_OK;
+  }
   int rows3 = 4096 / nx;
   if (rows3 < 1) rows3 = 1;
   if (rows3 > ny) rows3 = ny;
