@@ -571,8 +571,9 @@ bool launch_div_rowfft_r(ldsv_handle* h, const void* us, const void* vs, hipStre
   if constexpr (!std::is_same<T, float>::value) {
     return false;
   } else {
-    // 2048 points per workgroup (256 threads), fewer rows for small batches
-    // until the launch has a workgroup per CU
+    // 2048 points per workgroup (256 threads; 128 measured slower at
+    // 1024^2 x 128, 512 no faster), fewer rows for small batches until the
+    // launch has a workgroup per CU
     int rows = std::max(1, 2048 / h->g.nx);
     if (rows > h->g.ny) rows = h->g.ny;
     while (rows > 1 && (size_t)(h->g.ny / rows) * h->npairs < 256) rows >>= 1;
@@ -605,7 +606,8 @@ bool launch_rowifft_grad_r(ldsv_handle* h, const void* us, const void* vs, void*
   } else {
     const int logn = h->log2nx;
     const float idx = (float)(h->g.nx / h->g.lx), idy = (float)(h->g.ny / h->g.ly);
-    // 8 transformed rows (7 output rows and the halo row) per workgroup, 4 at 2048
+    // 8 transformed rows (7 output rows and the halo row) per workgroup, 4 at
+    // 2048 (16 measured 13 % slower at 512^2 x 16)
     const int logr = logn >= 11 ? 2 : 3;
     const int outr = (1 << logr) - 1;
     const dim3 grid((h->g.ny + outr - 1) / outr, h->npairs);
@@ -627,10 +629,16 @@ bool launch_rowifft_grad_r(ldsv_handle* h, const void* us, const void* vs, void*
 // the compile-time column pass where it exists (FP32; 512 <= cols * ny <=
 // 8192 points per workgroup); false: the caller launches the general one
 template <typename T>
-bool launch_col_solve_r(ldsv_handle* h, int cols, hipStream_t st, const int* active) {
+bool launch_col_solve_r(ldsv_handle* h, hipStream_t st, const int* active) {
   if constexpr (!std::is_same<T, float>::value) {
     return false;
   } else {
+    // 4096 points per workgroup (512 threads; 256 or 1024 measured slower at
+    // 512^2 x 16 and 1024^2 x 128), narrower column groups for small batches
+    // until the launch has a workgroup per CU
+    int cols = std::max(1, 4096 / h->g.ny);
+    if (cols > h->g.nx) cols = h->g.nx;
+    while (cols > 1 && (size_t)(h->g.nx / cols) * h->npairs < 256) cols >>= 1;
     const int logn = h->log2ny, logc = __builtin_ctz((unsigned)cols);
     const dim3 grid((h->g.nx / cols) * h->npairs);
     const int B = h->g.batch;
@@ -641,12 +649,12 @@ bool launch_col_solve_r(ldsv_handle* h, int cols, hipStream_t st, const int* act
                  h->g.nx, B, active);                                                            \
     return true;                                                                                 \
   }
-    LDSV_COLR(6, 3)
-    LDSV_COLR(7, 2) LDSV_COLR(7, 3)
-    LDSV_COLR(8, 1) LDSV_COLR(8, 2) LDSV_COLR(8, 3)
+    LDSV_COLR(6, 3) LDSV_COLR(6, 4) LDSV_COLR(6, 5) LDSV_COLR(6, 6)
+    LDSV_COLR(7, 2) LDSV_COLR(7, 3) LDSV_COLR(7, 4) LDSV_COLR(7, 5)
+    LDSV_COLR(8, 1) LDSV_COLR(8, 2) LDSV_COLR(8, 3) LDSV_COLR(8, 4)
     LDSV_COLR(9, 0) LDSV_COLR(9, 1) LDSV_COLR(9, 2) LDSV_COLR(9, 3)
-    LDSV_COLR(10, 0) LDSV_COLR(10, 1) LDSV_COLR(10, 2) LDSV_COLR(10, 3)
-    LDSV_COLR(11, 0) LDSV_COLR(11, 1) LDSV_COLR(11, 2)
+    LDSV_COLR(10, 0) LDSV_COLR(10, 1) LDSV_COLR(10, 2)
+    LDSV_COLR(11, 0) LDSV_COLR(11, 1)
 #undef LDSV_COLR
     return false;
   }
@@ -719,7 +727,7 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
                LDSV_ESHAPE, "project: ny=%d too large for the LDS column transform", ny);
   // 8 values per thread where the block allows it: twice the wavefronts of
   // the minimum, to hide the latency of the transform's LDS round trips
-  if (!launch_col_solve_r<T>(h, cols, st, active)) {
+  if (!launch_col_solve_r<T>(h, st, active)) {
     int cblock = (int)(((size_t)cols * ny / 8 + 63) / 64 * 64);
     if (cblock > kColBlock) cblock = kColBlock;
     if (cblock < 64) cblock = 64;
