@@ -660,6 +660,161 @@ bool launch_col_solve_r(ldsv_handle* h, hipStream_t st, const int* active) {
   }
 }
 
+// The whole projection of one pair in one workgroup for square FP32 grids
+// of 2^LOGN x 2^LOGN cells (32^2 and 64^2): the compile-time transforms of
+// fft_reg.h, one thread per radix-8 butterfly.  The divergence goes straight
+// into the row transform's first stage; the row spectrum is transposed
+// through LDS into the column transform, whose last forward stage, the FP64
+// factor and the first inverse stage share registers; the column result is
+// transposed back into the inverse row transform; p goes to LDS once for the
+// neighbour differences.  Each thread keeps u*, v* of the points whose
+// divergence it formed and writes u, v there (in-place calls are safe: no
+// thread reads a u* another thread writes).
+template <int LOGN>
+__global__ void __launch_bounds__((1 << (2 * LOGN)) / 8) k_project_lds_r(
+    const float* __restrict__ us, const float* __restrict__ vs, float* __restrict__ uo,
+    float* __restrict__ vo, float* __restrict__ po, const Cx<float>* __restrict__ tw,
+    const double* __restrict__ pinv, int batch, float idx, float idy, const int* active) {
+  constexpr int N = 1 << LOGN, BLOCK = (N * N) / 8, S = fftreg::plan_stages(LOGN);
+  constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
+  constexpr int R0 = 1 << LR0, RL = 1 << LRL;
+  constexpr int kElems = fftreg::lds_elems<true, LOGN, LOGN>() > fftreg::lds_elems<false, LOGN, LOGN>()
+                             ? fftreg::lds_elems<true, LOGN, LOGN>()
+                             : fftreg::lds_elems<false, LOGN, LOGN>();
+  __shared__ Cx<float> A[kElems];
+  __shared__ Cx<float> W[N];
+  const int b0 = 2 * (int)blockIdx.x;
+  if (!pair_active(active, b0, batch)) return;
+  const bool w0 = !active || active[b0];
+  const bool w1 = b0 + 1 < batch && (!active || active[b0 + 1]);
+  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = tw[e];
+  constexpr unsigned plane = (unsigned)N * N;
+  const float* u0 = us + (size_t)b0 * plane;
+  const float* v0 = vs + (size_t)b0 * plane;
+  // the factors of the points the last forward column stage leaves in
+  // registers, loaded first so that their latency hides behind the transforms
+  double fac[8];
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int kx, ky;
+      fftreg::point<false, LOGN, LOGN, BLOCK, LRL>(q, r, kx, ky);
+      fac[q * RL + r] = pinv[((unsigned)ky << LOGN) + (unsigned)kx];
+    }
+  // divergence of the pair at the row transform's first-stage points
+  Cx<float> x[8];
+  float ku[8][2], kv[8][2];
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int row, i;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, row, i);
+      const unsigned c = ((unsigned)row << LOGN) + (unsigned)i;
+      const unsigned ce = ((unsigned)row << LOGN) + ((unsigned)(i + 1) & (N - 1));
+      const unsigned cn = ((unsigned)((row + 1) & (N - 1)) << LOGN) + (unsigned)i;
+      const int e = q * R0 + r;
+      ku[e][0] = u0[c];
+      kv[e][0] = v0[c];
+      ku[e][1] = kv[e][1] = 0.f;
+      float d0 = 0.f, d1 = 0.f;
+      if (w0) d0 = (u0[ce] - ku[e][0]) * idx + (v0[cn] - kv[e][0]) * idy;
+      if (w1) {
+        ku[e][1] = u0[plane + c];
+        kv[e][1] = v0[plane + c];
+        d1 = (u0[plane + ce] - ku[e][1]) * idx + (v0[plane + cn] - kv[e][1]) * idy;
+      }
+      x[e] = Cx<float>{d0, d1};
+    }
+  __syncthreads();
+  fftreg::run<true, LOGN, LOGN, BLOCK, -1, false>(x, A, W);
+  // rows -> columns: point (row, kx) to column kx's element row
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int row, kx;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, row, kx);
+      A[fftreg::lds_at<false, LOGN, LOGN>(row, kx)] = x[q * RL + r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int kx, y;
+      fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, kx, y);
+      x[q * R0 + r] = A[fftreg::lds_at<false, LOGN, LOGN>(y, kx)];
+    }
+  __syncthreads();
+  fftreg::run<false, LOGN, LOGN, BLOCK, -1, false>(x, A, W);
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const double f = fac[q * RL + r];
+      const Cx<float> v = x[q * RL + r];
+      x[q * RL + r] = Cx<float>{(float)((double)v.x * f), (float)((double)v.y * f)};
+    }
+  fftreg::run<false, LOGN, LOGN, BLOCK, +1, true>(x, A, W);
+  // columns -> rows
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int kx, y;
+      fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, kx, y);
+      A[fftreg::lds_at<true, LOGN, LOGN>(kx, y)] = x[q * R0 + r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int row, kx;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, row, kx);
+      x[q * RL + r] = A[fftreg::lds_at<true, LOGN, LOGN>(kx, row)];
+    }
+  __syncthreads();
+  fftreg::run<true, LOGN, LOGN, BLOCK, +1, true>(x, A, W);
+  float* uo0 = uo + (size_t)b0 * plane;
+  float* vo0 = vo + (size_t)b0 * plane;
+  float* po0 = po ? po + (size_t)b0 * plane : nullptr;
+  // p to LDS for the neighbour differences
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int row, i;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, row, i);
+      A[fftreg::lds_at<true, LOGN, LOGN>(i, row)] = x[q * R0 + r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int row, i;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, row, i);
+      const int e = q * R0 + r;
+      const Cx<float> pc = x[e];
+      const Cx<float> pw = A[fftreg::lds_at<true, LOGN, LOGN>((i - 1) & (N - 1), row)];
+      const Cx<float> ps = A[fftreg::lds_at<true, LOGN, LOGN>(i, (row - 1) & (N - 1))];
+      const unsigned c = ((unsigned)row << LOGN) + (unsigned)i;
+      if (w0) {
+        uo0[c] = ku[e][0] - (pc.x - pw.x) * idx;
+        vo0[c] = kv[e][0] - (pc.x - ps.x) * idy;
+        if (po) po0[c] = pc.x;
+      }
+      if (w1) {
+        uo0[plane + c] = ku[e][1] - (pc.y - pw.y) * idx;
+        vo0[plane + c] = kv[e][1] - (pc.y - ps.y) * idy;
+        if (po) po0[plane + c] = pc.y;
+      }
+    }
+}
+
 template <typename T>
 int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo, void* po,
                  hipStream_t st, const int* active) {
@@ -673,6 +828,21 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   // the three passes below spread the work over many more workgroups
   const bool one_block = (size_t)nx * ny <= (size_t)4 * kOneBlock ||
                          ((size_t)nx * ny <= (size_t)16 * kOneBlock && h->npairs >= 256);
+  if constexpr (std::is_same<T, float>::value) {
+    if (nx == ny && (nx == 32 || nx == 64) && one_block) {
+      const float fx = (float)(nx / h->g.lx), fy = (float)(ny / h->g.ly);
+      if (nx == 64)
+        LDSV_TLAUNCH(h, 2, k_project_lds_r<6>, dim3(h->npairs), dim3(512), 0, st, (const float*)us,
+                     (const float*)vs, (float*)uo, (float*)vo, (float*)po,
+                     (const Cx<float>*)h->twx, (const double*)h->pinv, B, fx, fy, active);
+      else
+        LDSV_TLAUNCH(h, 2, k_project_lds_r<5>, dim3(h->npairs), dim3(128), 0, st, (const float*)us,
+                     (const float*)vs, (float*)uo, (float*)vo, (float*)po,
+                     (const Cx<float>*)h->twx, (const double*)h->pinv, B, fx, fy, active);
+      LDSV_LAUNCHED();
+      return LDSV_OK;
+    }
+  }
   if (one_block && (size_t)nx * ny * cs <= 131072) {
     // u*, v* are read only by the cells that write u, v at the same index
     // after all reads of neighbours are done (the divergence is formed
