@@ -94,6 +94,33 @@ struct StagePtrs {
   const int* active;  // per-trajectory mask, nullable (MAC)
 };
 
+// One trajectory's plane addressed through a buffer resource: a uniform
+// base in scalar registers and a 32-bit element offset per lane (one
+// buffer_load/buffer_store with a vector offset instead of 64-bit address
+// arithmetic per element); accesses past the plane return zero / are
+// dropped by the hardware range check.
+template <typename T>
+struct PlaneBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ PlaneBuf(const T* base, unsigned n)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
+                                            (int)(n * (unsigned)sizeof(T)), 0x00020000)) {}
+  __device__ __forceinline__ T ld(unsigned i) const {
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+  }
+  __device__ __forceinline__ void st(unsigned i, T v) const {
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, i * 4u, 0, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(
+          __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r,
+          i * 8u, 0, 0);
+  }
+};
+
 __device__ __forceinline__ float coef_value(const float* p) { return *p; }
 __device__ __forceinline__ float coef_value(const uint16_t* p) {
   return __uint_as_float(((uint32_t)*p) << 16);  // bf16 -> float, exact
@@ -199,6 +226,10 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   const int j0 = (tp / tilesx) * TY;
   const size_t plane = (size_t)nx * ny;
   const size_t boff = (size_t)b * plane;
+  // the trajectory's planes as buffers: 32-bit offsets within a plane (at
+  // most 2048^2 cells)
+  const unsigned pl = (unsigned)plane;
+  const PlaneBuf<T> usb(p.us + boff, pl), vsb(p.vs + boff, pl);
 
   // stage state with its periodic halo: every load of the thread in flight
   // before the LDS stores
@@ -211,9 +242,9 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
         const int r = t / W, c = t - r * W;
         const int gj = (j0 - kH + r + ny) & (ny - 1);
         const int gi = (i0 - kH + c + nx) & (nx - 1);
-        const size_t g = boff + (size_t)gj * nx + gi;
-        tu[k] = p.us[g];
-        tvv[k] = p.vs[g];
+        const unsigned g = (unsigned)gj * (unsigned)nx + (unsigned)gi;
+        tu[k] = usb.ld(g);
+        tvv[k] = vsb.ld(g);
       }
     }
 #pragma unroll
@@ -239,14 +270,14 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
     pun[k] = pvn[k] = pau[k] = pav[k] = (T)0;
     if (t < kCells) {
       const int r = t / TX, c = t - r * TX;
-      const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
+      const unsigned g = (unsigned)(j0 + r) * (unsigned)nx + (unsigned)(i0 + c);
       if (need_un) {
-        pun[k] = p.un[g];
-        pvn[k] = p.vn[g];
+        pun[k] = PlaneBuf<T>(p.un + boff, pl).ld(g);
+        pvn[k] = PlaneBuf<T>(p.vn + boff, pl).ld(g);
       }
       if (need_acc) {
-        pau[k] = p.accu[g];
-        pav[k] = p.accv[g];
+        pau[k] = PlaneBuf<T>(p.accu + boff, pl).ld(g);
+        pav[k] = PlaneBuf<T>(p.accv + boff, pl).ld(g);
       }
     }
   }
@@ -405,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       ru += frow[r] - drag * uc;
       rv -= drag * vc;
     }
-    const size_t g = boff + (size_t)(j0 + r) * nx + (i0 + c);
+    const unsigned g = (unsigned)(j0 + r) * (unsigned)nx + (unsigned)(i0 + c);
     T ou = cb.beta * uc + cb.eps * ru + cb.alpha * pun[k] + cb.delta * pau[k];
     T ov = cb.beta * vc + cb.eps * rv + cb.alpha * pvn[k] + cb.delta * pav[k];
     if (p.tcu) {
@@ -413,11 +444,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       ou += (T)p.tcu[gt];
       ov += (T)p.tcv[gt];
     }
-    p.ou[g] = ou;
-    p.ov[g] = ov;
+    PlaneBuf<T>(p.ou + boff, pl).st(g, ou);
+    PlaneBuf<T>(p.ov + boff, pl).st(g, ov);
     if (p.oaccu) {
-      p.oaccu[g] = cb.gamma * pau[k] + cb.wacc * ru;
-      p.oaccv[g] = cb.gamma * pav[k] + cb.wacc * rv;
+      PlaneBuf<T>(p.oaccu + boff, pl).st(g, cb.gamma * pau[k] + cb.wacc * ru);
+      PlaneBuf<T>(p.oaccv + boff, pl).st(g, cb.gamma * pav[k] + cb.wacc * rv);
     }
   }
 }
