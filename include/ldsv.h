@@ -216,7 +216,7 @@ LDSV_API int ldsv_cnn_activation(ldsv_handle* h, int layer, uint16_t* dst, void*
  * last projection: u_k = P(FV(u_{k-1}) + TC).  step_index is k, the index
  * of the output state.  net_out (nullable): receives the network output
  * [B][66][Ny][Nx] as ldsv_cnn_forward writes it.  Without net_out the
- * stencil values stay in bf16 planes inside the handle (half the bytes for
+ * stencil values stay in bf16 inside the handle (half the bytes for
  * the stage kernels); the step is the same bit for bit. */
 LDSV_API int ldsv_learned_fv_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net,
                          const float* u_in, const float* v_in, float* u_out, float* v_out,

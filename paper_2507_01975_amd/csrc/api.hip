@@ -234,7 +234,7 @@ int ldsv_internal_step_masked(ldsv_handle* h, const ldsv_params* p, const void* 
                   nullptr, nullptr, nullptr, active);
 }
 
-// the same with the raw coefficients stored as bf16 planes
+// the same with the raw coefficients stored in bf16 [B][8][Ny][Nx][8]
 int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* coef16,
                          size_t cbs16, const void* su, const void* sv, void* du, void* dv,
                          const float* tcu, const float* tcv, size_t tcbs, hipStream_t st) {
@@ -242,7 +242,7 @@ int ldsv_internal_step16(ldsv_handle* h, const ldsv_params* p, const uint16_t* c
 }
 
 // the same with per-cell learned derivative values beside the coefficients
-// (float planes with coef, bf16 planes with coef16; the same strides)
+// (float planes with coef, bf16 blocks of 8 channels with coef16; the same strides)
 int ldsv_internal_step_d(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
                          const uint16_t* coef16, size_t cbs16, const DerivCoef* dc,
                          const void* su, const void* sv, void* du, void* dv, const float* tcu,

@@ -7,9 +7,11 @@ int ldsv_ensure_learned(ldsv_handle* h);
 int ldsv_check_net(const ldsv_net* net);
 // forward through all layers.  Output either as float planes [B][66][Ny][Nx]
 // in `out` (coefficient channels rounded to bf16 values), or, when coef16 is
-// given and the grid is tiled (sides multiples of 16), as bf16 coefficient
-// planes [B][64][Ny][Nx] in coef16 and float correction planes [B][2][Ny][Nx]
-// in tc.  Returns in *bf16_out whether the second form was written.
+// given and the grid is tiled (sides multiples of 16), as bf16 coefficients
+// in blocks of 8 channels [B][8][Ny][Nx][8] in coef16 (a kind's 16 values of
+// a cell are two 16-byte loads, coalesced across cells) and float correction
+// planes [B][2][Ny][Nx] in tc.  Returns in *bf16_out whether the second form
+// was written.
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                     float* out, float* const* zpre, hipStream_t st, uint16_t* coef16 = nullptr,
                     float* tc = nullptr, bool* bf16_out = nullptr);

@@ -91,8 +91,8 @@ struct PixMap {
 // EPI 0: z = acc + bias -> gelu -> bf16 NHWC [P][64] (and z float NHWC if zout)
 // EPI 1: z = acc + bias -> float planar [B][cout][H][W], channels below
 //        LDSV_NCOEF rounded to bf16 values (the coefficient storage precision)
-// EPI 3 (tiled kernel only): channels below LDSV_NCOEF -> bf16 planar Y,
-//        the rest -> float planar out_planar
+// EPI 3 (tiled kernel only): channels below LDSV_NCOEF -> bf16 in blocks of
+//        8 channels Y [B][8][H][W][8], the rest -> float planar out_planar
 // EPI 2: g = acc * gelu'(zin[p][c]) -> bf16 NHWC [P][64] (data gradient)
 template <int MT, int EPI, int CIN>
 __global__ void __launch_bounds__(kBlock) k_conv3x3_mfma(const uint16_t* __restrict__ X,
@@ -396,16 +396,24 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
               out_planar[((size_t)b * cout + c) * hw + r] = c < LDSV_NCOEF ? round_to_bf16(z) : z;
           }
         } else {
-          // EPI 3: the 64 stencil coefficients as bf16 planes [B][64][H][W]
-          // (Y), the 2 correction channels as float planes [B][2][H][W]
+          // EPI 3: the 64 stencil coefficients in bf16, blocks of 8
+          // channels [B][8][H][W][8] (Y: a lane's 4 consecutive channels are
+          // one 8-byte store), the 2 correction channels as float planes
+          // [B][2][H][W]
+          if (c0 + 3 < LDSV_NCOEF) {
+            uint2 pk;
+            pk.x = pack_bf16x2(acc[t][m][0], acc[t][m][1]);
+            pk.y = pack_bf16x2(acc[t][m][2], acc[t][m][3]);
+            *reinterpret_cast<uint2*>(
+                Y + (((size_t)b * 8 + (c0 >> 3)) * hw + r) * 8 + (c0 & 7)) = pk;
+          } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = c0 + i;
-            const float z = acc[t][m][i];
-            if (c < LDSV_NCOEF)
-              Y[((size_t)b * LDSV_NCOEF + c) * hw + r] = f32_to_bf16(z);
-            else if (c < cout)
-              out_planar[((size_t)b * (LDSV_NOUT - LDSV_NCOEF) + (c - LDSV_NCOEF)) * hw + r] = z;
+            for (int i = 0; i < 4; ++i) {
+              const int c = c0 + i;
+              if (c >= LDSV_NCOEF && c < cout)
+                out_planar[((size_t)b * (LDSV_NOUT - LDSV_NCOEF) + (c - LDSV_NCOEF)) * hw + r] =
+                    acc[t][m][i];
+            }
           }
         }
       }

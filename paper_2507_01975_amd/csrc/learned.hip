@@ -86,7 +86,7 @@ __global__ void k_zero_int(int* p, int n) {
 }
 
 // The network's 64 stencil-coefficient outputs are stored in bf16 (like its
-// activations): as bf16 planes when nothing asks for the float output (half
+// activations): in bf16 blocks of 8 channels when nothing asks for the float output (half
 // the bytes the four stage kernels read), else as bf16-rounded values in the
 // float output.  Both forms give the same step.  With a derivative-stencil
 // network (dnet) its 64 raw derivative values take the same form beside them.

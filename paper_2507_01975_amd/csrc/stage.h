@@ -21,7 +21,7 @@ struct StageArgs {
   void* oaccv = nullptr;
   const float* coef = nullptr;  // raw learned stencil values, planar, nullable
   size_t coef_bstride = 0;      // elements between trajectories
-  const uint16_t* coef16 = nullptr;  // the same as bf16 planes (used when set)
+  const uint16_t* coef16 = nullptr;  // the same in bf16 [B][8][Ny][Nx][8] (used when set)
   size_t coef16_bstride = 0;
   // per-cell learned derivative values, raw, with the layout and batch
   // stride of coef (dcoef) or coef16 (dcoef16); used only together with them
@@ -57,7 +57,7 @@ struct FluxBlockArgs {
 
 // Per-cell learned derivative stencils (Sec. 3.4, the m = d operator in
 // per-cell form): raw values r [B][64][Ny][Nx] (channel 16K + s), float (d)
-// or bf16 planes (d16), with the batch stride of the interpolation
+// or bf16 (d16, [B][8][Ny][Nx][8]), with the batch stride of the interpolation
 // coefficients they accompany.  Per kind and cell the weights are
 //   w = w_P + r - mean(r) - x (x . r)/16 - b (b . r)/24
 // (x_s = a_s - 1/2 along the face normal, b_s across, w_P the fourth-order

@@ -126,17 +126,41 @@ __device__ __forceinline__ float coef_value(const uint16_t* p) {
   return __uint_as_float(((uint32_t)*p) << 16);  // bf16 -> float, exact
 }
 
+// The 16 raw values of kind K at the cell with in-plane offset off: float
+// planes [64][Ny][Nx] (point s of kind K in plane 16K + s), or bf16 values
+// in blocks of 8 channels [8][Ny][Nx][8] (channel c of a cell at block c / 8,
+// position c % 8: a kind is two 16-byte loads, and the loads of consecutive
+// cells are consecutive 16-byte chunks)
+__device__ __forceinline__ void kind_values(const float* cb, int kind, size_t plane, size_t off,
+                                            float (&r)[16]) {
+#pragma unroll
+  for (int s = 0; s < 16; ++s) r[s] = cb[(size_t)(16 * kind + s) * plane + off];
+}
+__device__ __forceinline__ void kind_values(const uint16_t* cb, int kind, size_t plane,
+                                            size_t off, float (&r)[16]) {
+  const uint4 a = *reinterpret_cast<const uint4*>(cb + ((size_t)(2 * kind) * plane + off) * 8);
+  const uint4 b = *reinterpret_cast<const uint4*>(cb + ((size_t)(2 * kind + 1) * plane + off) * 8);
+  const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    r[2 * k] = __uint_as_float(w[k] << 16);
+    r[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+  }
+}
+
 // learned interpolation at a face owned by global cell (gi, gj), kind K;
 // q(a, b) is the tile value at along offset a, across offset b; the raw
-// coefficients are float or bf16 planes (CT)
+// coefficients are float planes or bf16 per-cell vectors (CT)
 template <typename T, bool ALONG_X, int W, typename CT>
 __device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const CT* cb,
                                           int kind, size_t plane, size_t off) {
+  float rv[16];
+  kind_values(cb, kind, plane, off, rv);
   T r[16];
   T m = 0;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    r[s] = (T)coef_value(cb + (size_t)(16 * kind + s) * plane + off);
+    r[s] = (T)rv[s];
     m += r[s];
   }
   m *= (T)(1.0 / 16.0);
@@ -159,10 +183,12 @@ __device__ __forceinline__ T learned_face(const T (*S)[W], int lj, int li, const
 template <typename T, bool ALONG_X, int W, typename CT>
 __device__ __forceinline__ T learned_dface(const T (*S)[W], int lj, int li, const CT* cb, int kind,
                                            size_t plane, size_t off) {
+  float rv[16];
+  kind_values(cb, kind, plane, off, rv);
   T rq = 0, sr = 0, sxr = 0, sbr = 0, sq = 0, sxq = 0, sbq = 0;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const T r = (T)coef_value(cb + (size_t)(16 * kind + s) * plane + off);
+    const T r = (T)rv[s];
     const int a = a_off20(s), bb = b_off20(s);
     const T q = ALONG_X ? S[lj + bb][li + a] : S[lj + a][li + bb];
     const T x = (T)a - (T)0.5;

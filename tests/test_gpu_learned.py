@@ -94,6 +94,27 @@ def test_learned_step_matches_oracle_given_network_output():
     assert rel_l2(uo, lu) < 1e-4
 
 
+@pytest.mark.parametrize("n,b", [(32, 3), (64, 4)])
+def test_packed_coefficients_equal_float_output_path(n, b):
+    """Without a requested network output the 64 stencil values stay in bf16
+    per cell inside the handle; the step equals, bit for bit, the step that
+    reads them as bf16-rounded floats from the network output; so does the
+    two-network step with learned derivative stencils."""
+    L_ = need_gpu()
+    announce("packed coefficients", n, b)
+    net, _, _ = _net(L_, seed=2, last_scale=0.05)
+    dnet, _, _ = _net(L_, seed=5, last_scale=0.05)
+    s = L_.Solver(n, n, b)
+    u, v = s.init_state(L_.IC_GRF_PEAK, seed=11)
+    prm = L_.params(k_c=1, **KW)
+    pu, pv = s.learned_fv_step(prm, net, u, v, 1)
+    fu, fv, _ = s.learned_fv_step(prm, net, u, v, 1, want_net_out=True)
+    assert torch.equal(pu, fu) and torch.equal(pv, fv)
+    pu, pv = s.learned_d_fv_step(prm, net, dnet, u, v, 1)
+    fu, fv, _, _ = s.learned_d_fv_step(prm, net, dnet, u, v, 1, want_net_out=True)
+    assert torch.equal(pu, fu) and torch.equal(pv, fv)
+
+
 def test_zero_head_reproduces_plain_fv_and_kc():
     L_ = need_gpu()
     announce("zero head")
