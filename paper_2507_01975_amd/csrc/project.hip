@@ -660,159 +660,222 @@ bool launch_col_solve_r(ldsv_handle* h, hipStream_t st, const int* active) {
   }
 }
 
-// The whole projection of one pair in one workgroup for square FP32 grids
-// of 2^LOGN x 2^LOGN cells (32^2 and 64^2): the compile-time transforms of
-// fft_reg.h, one thread per radix-8 butterfly.  The divergence goes straight
-// into the row transform's first stage; the row spectrum is transposed
-// through LDS into the column transform, whose last forward stage, the FP64
-// factor and the first inverse stage share registers; the column result is
-// transposed back into the inverse row transform; p goes to LDS once for the
-// neighbour differences.  Each thread keeps u*, v* of the points whose
-// divergence it formed and writes u, v there (in-place calls are safe: no
-// thread reads a u* another thread writes).
+// The whole projection of one trajectory in one workgroup for square FP32
+// grids of 2^LOGN x 2^LOGN cells (32^2 and 64^2), with real-input
+// transforms of half the length (twice the workgroups of one workgroup per
+// trajectory pair for the same work per trajectory: 64 at 64^2 x 64).
+//   - u*, v* are read once with 16-byte loads and staged in LDS (the
+//     divergence reads its neighbours there; each thread keeps its own
+//     values for the final write);
+//   - rows 2t and 2t+1 of the divergence form one complex row
+//     z_t = d_2t + i d_2t+1 (N/2 row transforms of length N);
+//   - the transpose unpacks them, D_2t[kx] = (Z_t[kx] + conj Z_t[N-kx]) / 2,
+//     D_2t+1[kx] = (Z_t[kx] - conj Z_t[N-kx]) / 2i, for kx = 1..N/2-1
+//     (the other half is their conjugate), and packs the two real columns
+//     kx = 0 and kx = N/2 into one complex column: N/2 column transforms;
+//   - the FP64 factor multiplies every column in registers; the packed
+//     column's two spectra are separated with its ky <-> -ky partner (one
+//     LDS exchange) before their factors are applied;
+//   - the inverse column transforms, then the packed inverse row transforms
+//     W_t = P_2t + i P_2t+1 (Hermitian continuation for kx > N/2), give
+//     p_2t + i p_2t+1; p goes to LDS for the differences, and u, v leave with
+//     16-byte stores.
+// In-place calls are safe: each thread writes only the values it read.
 template <int LOGN>
-__global__ void __launch_bounds__((1 << (2 * LOGN)) / 8) k_project_lds_r(
+__global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
     const float* __restrict__ us, const float* __restrict__ vs, float* __restrict__ uo,
     float* __restrict__ vo, float* __restrict__ po, const Cx<float>* __restrict__ tw,
-    const double* __restrict__ pinv, int batch, float idx, float idy, const int* active) {
-  constexpr int N = 1 << LOGN, BLOCK = (N * N) / 8, S = fftreg::plan_stages(LOGN);
+    const double* __restrict__ pinv, float idx, float idy, const int* active) {
+  constexpr int N = 1 << LOGN, NH = N / 2, LOGT = LOGN - 1, BLOCK = (N * NH) / 8;
+  constexpr int S = fftreg::plan_stages(LOGN);
   constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
   constexpr int R0 = 1 << LR0, RL = 1 << LRL;
-  constexpr int kElems = fftreg::lds_elems<true, LOGN, LOGN>() > fftreg::lds_elems<false, LOGN, LOGN>()
-                             ? fftreg::lds_elems<true, LOGN, LOGN>()
-                             : fftreg::lds_elems<false, LOGN, LOGN>();
+  constexpr int SP = N + 4;   // row stride of the staged u*, v* and of p (floats)
+  constexpr int ZS = N + 8;   // row stride of the packed row spectra
+  constexpr int QS = NH + 4;  // row stride of the column results
+  constexpr int C4 = N / 4;   // 16-byte chunks per row
+  constexpr int KC = (N * N / 4) / BLOCK;
+  constexpr int kE1 = fftreg::lds_elems<true, LOGN, LOGT>(), kE2 = fftreg::lds_elems<false, LOGN, LOGT>();
+  constexpr int kE3 = NH * ZS > N * QS ? NH * ZS : N * QS;
+  constexpr int kElems = (kE1 > kE2 ? kE1 : kE2) > kE3 ? (kE1 > kE2 ? kE1 : kE2) : kE3;
+  static_assert(KC * BLOCK * 4 == N * N && BLOCK >= N, "thread mapping");
+  __shared__ __align__(16) float su[N * SP];
+  __shared__ __align__(16) float sv[N * SP];
   __shared__ Cx<float> A[kElems];
   __shared__ Cx<float> W[N];
-  const int b0 = 2 * (int)blockIdx.x;
-  if (!pair_active(active, b0, batch)) return;
-  const bool w0 = !active || active[b0];
-  const bool w1 = b0 + 1 < batch && (!active || active[b0 + 1]);
-  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = tw[e];
+  __shared__ Cx<float> X0[N];
+  __shared__ double F1[N];
+  const int b = (int)blockIdx.x;
+  if (active && !active[b]) return;  // uniform per workgroup, before any barrier
+  const int tid = (int)threadIdx.x;
   constexpr unsigned plane = (unsigned)N * N;
-  const float* u0 = us + (size_t)b0 * plane;
-  const float* v0 = vs + (size_t)b0 * plane;
-  // the factors of the points the last forward column stage leaves in
-  // registers, loaded first so that their latency hides behind the transforms
+  const float4* u4 = reinterpret_cast<const float4*>(us + (size_t)b * plane);
+  const float4* v4 = reinterpret_cast<const float4*>(vs + (size_t)b * plane);
+  float4 ku[KC], kv[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    ku[k] = u4[k * BLOCK + tid];
+    kv[k] = v4[k * BLOCK + tid];
+  }
+  // column c of the column transforms is the same for all of a thread's
+  // butterflies; column 0 carries kx = 0 and kx = N/2
+  const int col = tid & (NH - 1);
   double fac[8];
 #pragma unroll
   for (int q = 0; q < 8 / RL; ++q)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
-      int kx, ky;
-      fftreg::point<false, LOGN, LOGN, BLOCK, LRL>(q, r, kx, ky);
-      fac[q * RL + r] = pinv[((unsigned)ky << LOGN) + (unsigned)kx];
+      int c, ky;
+      fftreg::point<false, LOGN, LOGT, BLOCK, LRL>(q, r, c, ky);
+      fac[q * RL + r] = pinv[((unsigned)ky << LOGN) + (unsigned)c];
     }
-  // divergence of the pair at the row transform's first-stage points
+  if (tid < N) {
+    W[tid] = tw[tid];
+    F1[tid] = pinv[((unsigned)tid << LOGN) + NH];
+  }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int id = k * BLOCK + tid;
+    const int y = id / C4, x0 = (id - y * C4) * 4;
+    *reinterpret_cast<float4*>(&su[y * SP + x0]) = ku[k];
+    *reinterpret_cast<float4*>(&sv[y * SP + x0]) = kv[k];
+  }
+  __syncthreads();
+  // divergence of rows 2t and 2t+1 at the row transform's first-stage points
   Cx<float> x[8];
-  float ku[8][2], kv[8][2];
 #pragma unroll
   for (int q = 0; q < 8 / R0; ++q)
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      int row, i;
-      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, row, i);
-      const unsigned c = ((unsigned)row << LOGN) + (unsigned)i;
-      const unsigned ce = ((unsigned)row << LOGN) + ((unsigned)(i + 1) & (N - 1));
-      const unsigned cn = ((unsigned)((row + 1) & (N - 1)) << LOGN) + (unsigned)i;
-      const int e = q * R0 + r;
-      ku[e][0] = u0[c];
-      kv[e][0] = v0[c];
-      ku[e][1] = kv[e][1] = 0.f;
-      float d0 = 0.f, d1 = 0.f;
-      if (w0) d0 = (u0[ce] - ku[e][0]) * idx + (v0[cn] - kv[e][0]) * idy;
-      if (w1) {
-        ku[e][1] = u0[plane + c];
-        kv[e][1] = v0[plane + c];
-        d1 = (u0[plane + ce] - ku[e][1]) * idx + (v0[plane + cn] - kv[e][1]) * idy;
+      int t, i;
+      fftreg::point<true, LOGN, LOGT, BLOCK, LR0>(q, r, t, i);
+      const int ip = (i + 1) & (N - 1);
+      const int y0 = 2 * t * SP, y1 = y0 + SP, y2 = ((2 * t + 2) & (N - 1)) * SP;
+      const float d0 = (su[y0 + ip] - su[y0 + i]) * idx + (sv[y1 + i] - sv[y0 + i]) * idy;
+      const float d1 = (su[y1 + ip] - su[y1 + i]) * idx + (sv[y2 + i] - sv[y1 + i]) * idy;
+      x[q * R0 + r] = Cx<float>{d0, d1};
+    }
+  fftreg::run<true, LOGN, LOGT, BLOCK, -1, false>(x, A, W);
+  // packed row spectra Z_t[kx] to LDS (every LDS read of the transform is
+  // behind its last barrier)
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int t, kx;
+      fftreg::point<true, LOGN, LOGT, BLOCK, LRL>(q, r, t, kx);
+      A[t * ZS + kx] = x[q * RL + r];
+    }
+  __syncthreads();
+  // column inputs at the column transform's first-stage points (c, y)
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int c, y;
+      fftreg::point<false, LOGN, LOGT, BLOCK, LR0>(q, r, c, y);
+      // operand selects rather than branches (every wavefront holds column
+      // 0 and both row parities): with p = Z_t[c], m = Z_t[N - c] (Z_t[N/2]
+      // for column 0), D_2t = ((p.x + m.x) / 2, (p.y - m.y) / 2),
+      // D_2t+1 = ((p.y + m.y) / 2, (m.x - p.x) / 2), packed (p.x, m.x) or
+      // (p.y, m.y)
+      const int zt = (y >> 1) * ZS;
+      const bool odd = (y & 1) != 0;
+      const Cx<float> p = A[zt + c], m = A[zt + (c == 0 ? NH : N - c)];
+      const float a = odd ? p.y : p.x, bb = odd ? m.y : m.x;
+      const float cc = odd ? m.x : p.y, dd = odd ? p.x : m.y;
+      const float ha = c == 0 ? 1.f : 0.5f;
+      x[q * R0 + r] = Cx<float>{c == 0 ? a : ha * (a + bb), c == 0 ? bb : ha * (cc - dd)};
+    }
+  __syncthreads();
+  fftreg::run<false, LOGN, LOGT, BLOCK, -1, false>(x, A, W);
+  // the packed column's values to LDS for the ky <-> -ky pairing
+  if (col == 0) {
+#pragma unroll
+    for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        int c, ky;
+        fftreg::point<false, LOGN, LOGT, BLOCK, LRL>(q, r, c, ky);
+        X0[ky] = x[q * RL + r];
       }
-      x[e] = Cx<float>{d0, d1};
-    }
-  __syncthreads();
-  fftreg::run<true, LOGN, LOGN, BLOCK, -1, false>(x, A, W);
-  // rows -> columns: point (row, kx) to column kx's element row
-#pragma unroll
-  for (int q = 0; q < 8 / RL; ++q)
-#pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      int row, kx;
-      fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, row, kx);
-      A[fftreg::lds_at<false, LOGN, LOGN>(row, kx)] = x[q * RL + r];
-    }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 8 / R0; ++q)
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      int kx, y;
-      fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, kx, y);
-      x[q * R0 + r] = A[fftreg::lds_at<false, LOGN, LOGN>(y, kx)];
-    }
-  __syncthreads();
-  fftreg::run<false, LOGN, LOGN, BLOCK, -1, false>(x, A, W);
-#pragma unroll
-  for (int q = 0; q < 8 / RL; ++q)
-#pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const double f = fac[q * RL + r];
-      const Cx<float> v = x[q * RL + r];
-      x[q * RL + r] = Cx<float>{(float)((double)v.x * f), (float)((double)v.y * f)};
-    }
-  fftreg::run<false, LOGN, LOGN, BLOCK, +1, true>(x, A, W);
-  // columns -> rows
-#pragma unroll
-  for (int q = 0; q < 8 / R0; ++q)
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      int kx, y;
-      fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, kx, y);
-      A[fftreg::lds_at<true, LOGN, LOGN>(kx, y)] = x[q * R0 + r];
-    }
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 8 / RL; ++q)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
-      int row, kx;
-      fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, row, kx);
-      x[q * RL + r] = A[fftreg::lds_at<true, LOGN, LOGN>(kx, row)];
+      int c, ky;
+      fftreg::point<false, LOGN, LOGT, BLOCK, LRL>(q, r, c, ky);
+      const int e = q * RL + r;
+      const Cx<float> v = x[e];
+      // column 0: C = A + i B (A, B the spectra of the real columns kx = 0
+      // and N/2), f0 A + i f1 B = (f0 + f1)/2 C + (f0 - f1)/2 conj C(-ky);
+      // every other column: f C.  X0 and F1 are read by every thread (all of
+      // X0 is written above) and the weights selected, rather than branches.
+      const Cx<float> m = X0[(N - ky) & (N - 1)];
+      const double f0 = fac[e], f1 = F1[ky];
+      const double hp = col == 0 ? 0.5 * (f0 + f1) : f0;
+      const double hm = col == 0 ? 0.5 * (f0 - f1) : 0.0;
+      x[e] = Cx<float>{(float)(hp * (double)v.x + hm * (double)m.x),
+                       (float)(hp * (double)v.y - hm * (double)m.y)};
     }
-  __syncthreads();
-  fftreg::run<true, LOGN, LOGN, BLOCK, +1, true>(x, A, W);
-  float* uo0 = uo + (size_t)b0 * plane;
-  float* vo0 = vo + (size_t)b0 * plane;
-  float* po0 = po ? po + (size_t)b0 * plane : nullptr;
-  // p to LDS for the neighbour differences
+  fftreg::run<false, LOGN, LOGT, BLOCK, +1, true>(x, A, W);
+  // column results P[y][c] to LDS by row
 #pragma unroll
   for (int q = 0; q < 8 / R0; ++q)
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      int row, i;
-      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, row, i);
-      A[fftreg::lds_at<true, LOGN, LOGN>(i, row)] = x[q * R0 + r];
+      int c, y;
+      fftreg::point<false, LOGN, LOGT, BLOCK, LR0>(q, r, c, y);
+      A[y * QS + c] = x[q * R0 + r];
     }
   __syncthreads();
+  // packed inverse row inputs W_t[kx] = P[2t][kx] + i P[2t+1][kx]
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int t, kx;
+      fftreg::point<true, LOGN, LOGT, BLOCK, LRL>(q, r, t, kx);
+      const int q0 = 2 * t * QS, q1 = q0 + QS;
+      const bool edge = (kx & (NH - 1)) == 0, lo = kx < NH;
+      const int mc = edge ? 0 : (lo ? kx : N - kx);
+      const Cx<float> a = A[q0 + mc], h = A[q1 + mc];
+      const Cx<float> ve = kx == 0 ? Cx<float>{a.x, h.x} : Cx<float>{a.y, h.y};
+      const Cx<float> vh = lo ? Cx<float>{a.x - h.y, a.y + h.x} : Cx<float>{a.x + h.y, h.x - a.y};
+      x[q * RL + r] = edge ? ve : vh;
+    }
+  __syncthreads();
+  fftreg::run<true, LOGN, LOGT, BLOCK, +1, true>(x, A, W);
+  // p (rows 2t, 2t+1) into the staging rows of u* (last read before the
+  // first transform)
 #pragma unroll
   for (int q = 0; q < 8 / R0; ++q)
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
-      int row, i;
-      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, row, i);
-      const int e = q * R0 + r;
-      const Cx<float> pc = x[e];
-      const Cx<float> pw = A[fftreg::lds_at<true, LOGN, LOGN>((i - 1) & (N - 1), row)];
-      const Cx<float> ps = A[fftreg::lds_at<true, LOGN, LOGN>(i, (row - 1) & (N - 1))];
-      const unsigned c = ((unsigned)row << LOGN) + (unsigned)i;
-      if (w0) {
-        uo0[c] = ku[e][0] - (pc.x - pw.x) * idx;
-        vo0[c] = kv[e][0] - (pc.x - ps.x) * idy;
-        if (po) po0[c] = pc.x;
-      }
-      if (w1) {
-        uo0[plane + c] = ku[e][1] - (pc.y - pw.y) * idx;
-        vo0[plane + c] = kv[e][1] - (pc.y - ps.y) * idy;
-        if (po) po0[plane + c] = pc.y;
-      }
+      int t, i;
+      fftreg::point<true, LOGN, LOGT, BLOCK, LR0>(q, r, t, i);
+      su[2 * t * SP + i] = x[q * R0 + r].x;
+      su[(2 * t + 1) * SP + i] = x[q * R0 + r].y;
     }
+  __syncthreads();
+  float4* uo4 = reinterpret_cast<float4*>(uo + (size_t)b * plane);
+  float4* vo4 = reinterpret_cast<float4*>(vo + (size_t)b * plane);
+  float4* po4 = po ? reinterpret_cast<float4*>(po + (size_t)b * plane) : nullptr;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int id = k * BLOCK + tid;
+    const int y = id / C4, x0 = (id - y * C4) * 4;
+    const float4 pc = *reinterpret_cast<const float4*>(&su[y * SP + x0]);
+    const float4 ps = *reinterpret_cast<const float4*>(&su[((y - 1) & (N - 1)) * SP + x0]);
+    const float pw = su[y * SP + ((x0 - 1) & (N - 1))];
+    uo4[id] = float4{ku[k].x - (pc.x - pw) * idx, ku[k].y - (pc.y - pc.x) * idx,
+                     ku[k].z - (pc.z - pc.y) * idx, ku[k].w - (pc.w - pc.z) * idx};
+    vo4[id] = float4{kv[k].x - (pc.x - ps.x) * idy, kv[k].y - (pc.y - ps.y) * idy,
+                     kv[k].z - (pc.z - ps.z) * idy, kv[k].w - (pc.w - ps.w) * idy};
+    if (po4) po4[id] = pc;
+  }
 }
 
 template <typename T>
@@ -832,13 +895,13 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
     if (nx == ny && (nx == 32 || nx == 64) && one_block) {
       const float fx = (float)(nx / h->g.lx), fy = (float)(ny / h->g.ly);
       if (nx == 64)
-        LDSV_TLAUNCH(h, 2, k_project_lds_r<6>, dim3(h->npairs), dim3(512), 0, st, (const float*)us,
+        LDSV_TLAUNCH(h, 2, k_project_real_r<6>, dim3(B), dim3(256), 0, st, (const float*)us,
                      (const float*)vs, (float*)uo, (float*)vo, (float*)po,
-                     (const Cx<float>*)h->twx, (const double*)h->pinv, B, fx, fy, active);
+                     (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active);
       else
-        LDSV_TLAUNCH(h, 2, k_project_lds_r<5>, dim3(h->npairs), dim3(128), 0, st, (const float*)us,
+        LDSV_TLAUNCH(h, 2, k_project_real_r<5>, dim3(B), dim3(64), 0, st, (const float*)us,
                      (const float*)vs, (float*)uo, (float*)vo, (float*)po,
-                     (const Cx<float>*)h->twx, (const double*)h->pinv, B, fx, fy, active);
+                     (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active);
       LDSV_LAUNCHED();
       return LDSV_OK;
     }
