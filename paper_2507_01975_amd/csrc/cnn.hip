@@ -33,7 +33,7 @@ using namespace cnnk;
 
 // pixel tiles of 16 per wavefront in layer 1: two keep the accumulators
 // small enough for 4+ wavefronts per SIMD, which the GELU-bound epilogue needs
-constexpr int kFirstTiles = 2;
+constexpr int kFirstTiles = 4;
 
 // layer 1: 2 -> 64 as one K = 32 step of the same MFMA (K = 18 real
 // entries: tap-major, channel-minor, as the weights are stored, zero-padded).

@@ -42,8 +42,8 @@ __device__ __forceinline__ float round_to_bf16(float f) {
 // Numerical Recipes (sec. 6.2, erfcc): t exp(-x^2 + P(t)), t = 1/(1 + x/2),
 // fractional error below 1.2e-7 in exact arithmetic; in float32 the error is
 // dominated by the rounding of -x^2 + P(t), about 1e-6 relative for x < 6.
-// Fewer than half the instructions of erff, which matters because the GELU
-// epilogue, not the MFMA work, bounds the convolution kernels.
+// Fewer than half the instructions of erff (used by the GELU derivative of
+// the backward kernels).
 __device__ __forceinline__ float erfc_pos(float x) {
   const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
   float p = 0.17087277f;
@@ -65,8 +65,30 @@ __device__ __forceinline__ float normal_cdf(float z) {
   return z >= 0.0f ? 1.0f - e : e;
 }
 
-// exact (erf) GELU: z Phi(z)
-__device__ __forceinline__ float gelu_exact(float z) { return z * normal_cdf(z); }
+// exact (erf) GELU: z Phi(z) = max(z, 0) - |z| Q(|z|), Q(a) = Phi(-a) the
+// normal upper tail, taken as 2^P(a) with P the degree-10 least-squares
+// Chebyshev fit of log2 Q on [0, 6] written in powers of a (the fit and its
+// error: gen_gelu_poly.py beside this file): relative error of Q below
+// 1.3e-6 for a < 3 and 4.4e-6 up to 6 in float32, |GELU error| below 7e-8;
+// Q(6) ~ 1e-9 stands in beyond.  Ten FMAs, one exp2, two med3 clamps and
+// one FMA: the forward epilogues' vector-ALU work is dominated by this
+// function (the erfc form above costs a reciprocal, an exponential and
+// eighteen more instructions).  Non-finite z gives a non-finite result.
+__device__ __forceinline__ float gelu_exact(float z) {
+  const float a = __builtin_amdgcn_fmed3f(fabsf(z), 0.0f, 6.0f);
+  float p = -1.149826456e-08f;
+  p = fmaf(p, a, 3.878143104e-07f);
+  p = fmaf(p, a, -5.562967999e-06f);
+  p = fmaf(p, a, 4.235186861e-05f);
+  p = fmaf(p, a, -1.504010288e-04f);
+  p = fmaf(p, a, -3.018268617e-04f);
+  p = fmaf(p, a, 7.375738584e-03f);
+  p = fmaf(p, a, -5.279443413e-02f);
+  p = fmaf(p, a, -4.590685666e-01f);
+  p = fmaf(p, a, -1.151131988e+00f);
+  p = fmaf(p, a, -9.999987483e-01f);
+  return fmaf(-fabsf(z), __builtin_amdgcn_exp2f(p), __builtin_amdgcn_fmed3f(z, 0.0f, 3.0e38f));
+}
 
 // d/dz of the exact GELU: Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_grad(float z) {
