@@ -41,7 +41,7 @@ constexpr int kFirstTiles = 4;
 // lane l gathers the 8 K entries 8(l/16)..+7 of pixel l%16 of each tile
 // (bf16-rounded u, v of the taps), holds the matching 8 weights of 4 channel
 // tiles, and the epilogue is the one of the other layers.
-__global__ void __launch_bounds__(kBlock) k_conv_first(const float* __restrict__ u,
+__global__ void __launch_bounds__(kBlock, 4) k_conv_first(const float* __restrict__ u,
                                                        const float* __restrict__ v,
                                                        const uint16_t* __restrict__ W1,
                                                        const float* __restrict__ b1, PixMap pm,
