@@ -82,8 +82,9 @@ def test_rhs_burgers_f64(nx, ny, b):
 # grids up to 16384 cells (and 128 KB of complex pair field) when there are
 # at least 256 trajectory pairs; the rest take the three-pass version:
 # (64, 64), (128, 128, 3), (128, 128, 512) and (256, 64) cover every side
-@pytest.mark.parametrize("nx,ny,b", SHAPES + [(128, 128, 3), (128, 128, 512), (256, 64, 2),
-                                              (512, 512, 2), (256, 1024, 1)])
+@pytest.mark.parametrize("nx,ny,b", SHAPES + [(32, 32, 3), (64, 64, 5), (128, 128, 3),
+                                              (128, 128, 512), (256, 64, 2), (512, 512, 2),
+                                              (256, 1024, 1)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_projection(nx, ny, b, dtype):
     L_ = need_gpu()
