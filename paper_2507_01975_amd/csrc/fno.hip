@@ -38,6 +38,7 @@
 #include "adjoint.h"
 #include "cnn_common.h"
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include "fno.h"
 #include "stage.h"
 
@@ -181,6 +182,124 @@ __global__ void __launch_bounds__(fno_block<E>()) k_fno_spec(const float* __rest
     const int ky = r < M ? r : ny - 2 * M + r;
     const Cx<float> z1 = A[ky * nx + kx];
     const Cx<float> z2 = A[((ny - ky) & (ny - 1)) * nx + ((nx - kx) & (nx - 1))];
+    X0[e] = c32{0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y)};
+    X1[e] = c32{0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x)};
+  }
+}
+
+// The same forward transform for square FP32 grids of 2^LOGN x 2^LOGN cells
+// (64^2) on the compile-time transforms of fft_reg.h, one thread per radix-8
+// butterfly: the columns first, so that the inputs (or the lift of the
+// inputs) load straight into the first stage with each row of the field
+// read across lanes; an LDS transpose into the row transform; the retained
+// modes unpacked from the row transform's results through LDS.
+template <int LOGN, bool LIFT>
+__global__ void __launch_bounds__((1 << (2 * LOGN)) / 8) k_fno_spec_r(
+    const float* __restrict__ vin, FnoArgs a, float* __restrict__ v0out, c32* __restrict__ X,
+    const Cx<float>* __restrict__ tw, int C, int M, int B) {
+  constexpr int N = 1 << LOGN, BLOCK = (N * N) / 8, S = fftreg::plan_stages(LOGN);
+  constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
+  constexpr int R0 = 1 << LR0, RL = 1 << LRL;
+  constexpr int kE1 = fftreg::lds_elems<true, LOGN, LOGN>();
+  constexpr int kE2 = fftreg::lds_elems<false, LOGN, LOGN>();
+  __shared__ Cx<float> A[kE1 > kE2 ? kE1 : kE2];
+  __shared__ Cx<float> W[N];
+  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = tw[e];
+  int p, b, z;
+  pair_of_block(p, b, z);
+  const int g = a.net[z];
+  const int c0 = 2 * p, c1 = 2 * p + 1;
+  constexpr int n = N * N;
+  Cx<float> x[8];
+  if constexpr (LIFT) {
+    const float* lw = a.lift_w[g];
+    const int nin = a.nin;
+    float q0[8], q1[8];
+    const float b0 = a.lift_b[g][c0], b1 = a.lift_b[g][c1];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      q0[e] = b0;
+      q1[e] = b1;
+    }
+    for (int j = 0; j < nin; ++j) {
+      const float* xj = a.xin[j] + (size_t)b * n;
+      const float w0 = lw[c0 * nin + j], w1 = lw[c1 * nin + j];
+#pragma unroll
+      for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          int t, y;
+          fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, t, y);
+          const float xv = xj[y * N + t];
+          q0[q * R0 + r] += w0 * xv;
+          q1[q * R0 + r] += w1 * xv;
+        }
+    }
+    float* d0 = v0out + ((size_t)(z * B + b) * C + c0) * n;
+#pragma unroll
+    for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int t, y;
+        fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, t, y);
+        const int e = q * R0 + r;
+        d0[y * N + t] = q0[e];  // v_0 kept for the pointwise term and the backward
+        d0[n + y * N + t] = q1[e];
+        x[e] = Cx<float>{q0[e], q1[e]};
+      }
+  } else {
+    const float* s0 = vin + ((size_t)(z * B + b) * C + c0) * n;
+#pragma unroll
+    for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        int t, y;
+        fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, t, y);
+        x[q * R0 + r] = Cx<float>{s0[y * N + t], s0[n + y * N + t]};
+      }
+  }
+  __syncthreads();
+  // along y (column t, then row ky = the last stage's point)
+  fftreg::run<false, LOGN, LOGN, BLOCK, -1, false>(x, A, W);
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int t, ky;
+      fftreg::point<false, LOGN, LOGN, BLOCK, LRL>(q, r, t, ky);
+      A[fftreg::lds_at<true, LOGN, LOGN>(t, ky)] = x[q * RL + r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int ky, i;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, ky, i);
+      x[q * R0 + r] = A[fftreg::lds_at<true, LOGN, LOGN>(i, ky)];
+    }
+  __syncthreads();
+  // along x
+  fftreg::run<true, LOGN, LOGN, BLOCK, -1, false>(x, A, W);
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int ky, kx;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, ky, kx);
+      A[fftreg::lds_at<true, LOGN, LOGN>(kx, ky)] = x[q * RL + r];
+    }
+  __syncthreads();
+  // Z = V0 + i V1 with V0, V1 the transforms of the two real channels:
+  // V0(k) = (Z(k) + conj Z(-k)) / 2, V1(k) = (Z(k) - conj Z(-k)) / (2 i)
+  const int nm = 2 * M * M;
+  c32* X0 = X + ((size_t)(z * B + b) * C + c0) * nm;
+  c32* X1 = X0 + nm;
+  for (int e = threadIdx.x; e < nm; e += BLOCK) {
+    const int r = e / M, kx = e - r * M;
+    const int ky = r < M ? r : N - 2 * M + r;
+    const Cx<float> z1 = A[fftreg::lds_at<true, LOGN, LOGN>(kx, ky)];
+    const Cx<float> z2 = A[fftreg::lds_at<true, LOGN, LOGN>((N - kx) & (N - 1), (N - ky) & (N - 1))];
     X0[e] = c32{0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y)};
     X1[e] = c32{0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x)};
   }
@@ -331,40 +450,209 @@ __global__ void __launch_bounds__(fno_block<E>(), E <= 4 ? 8 : 4) k_fno_inv(cons
   const float sc = 1.0f / (float)n;
   float* d0 = vout + ((size_t)(z * B + b) * C + o0) * n;
   float* e0 = zout ? zout + ((size_t)(z * B + b) * C + o0) * n : nullptr;
-  for (int k = 0; k < E; ++k) {
-    const int t = k * fno_block<E>() + (int)threadIdx.x;
+  // the pointwise term over quads of consecutive pixels: every input-channel
+  // read, output store and spectrum read is 16 bytes per lane
+  static_assert(E % 4 == 0, "pixel quads");
+  const float* srcb = vin + (size_t)(z * B + b) * C * n;
+  for (int k = 0; k < E / 4; ++k) {
+    const int q = k * fno_block<E>() + (int)threadIdx.x;
+    const int t = 4 * q;
     if (t >= n) break;
-    float z0 = A[t].x * sc + bo0, z1 = A[t].y * sc + bo1;
-    const float* src = vin + (size_t)(z * B + b) * C * n + t;
+    float z0[4], z1[4];
 #pragma unroll
-    for (int c0 = 0; c0 < C; c0 += 8) {
-      float vi[8];
+    for (int j = 0; j < 4; ++j) {
+      z0[j] = A[t + j].x * sc + bo0;
+      z1[j] = A[t + j].y * sc + bo1;
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) vi[i] = src[(size_t)(c0 + i) * n];
+    for (int c0 = 0; c0 < C; c0 += 4) {
+      float4 vi[4];
 #pragma unroll
-      for (int i = 0; i < 8; i += 4) {
-        const float4 a0 = *reinterpret_cast<const float4*>(&sw[0][c0 + i]);
-        const float4 a1 = *reinterpret_cast<const float4*>(&sw[1][c0 + i]);
-        z0 += a0.x * vi[i] + a0.y * vi[i + 1] + a0.z * vi[i + 2] + a0.w * vi[i + 3];
-        z1 += a1.x * vi[i] + a1.y * vi[i + 1] + a1.z * vi[i + 2] + a1.w * vi[i + 3];
+      for (int i = 0; i < 4; ++i) vi[i] = *reinterpret_cast<const float4*>(srcb + (size_t)(c0 + i) * n + t);
+      const float4 a0 = *reinterpret_cast<const float4*>(&sw[0][c0]);
+      const float4 a1 = *reinterpret_cast<const float4*>(&sw[1][c0]);
+      const float w0[4] = {a0.x, a0.y, a0.z, a0.w}, w1[4] = {a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        z0[0] += w0[i] * vi[i].x;
+        z0[1] += w0[i] * vi[i].y;
+        z0[2] += w0[i] * vi[i].z;
+        z0[3] += w0[i] * vi[i].w;
+        z1[0] += w1[i] * vi[i].x;
+        z1[1] += w1[i] * vi[i].y;
+        z1[2] += w1[i] * vi[i].z;
+        z1[3] += w1[i] * vi[i].w;
       }
     }
+    float h0[4], h1[4];
     if constexpr (MODE == 0 || MODE == 1) {
+      if (e0) {
+        *reinterpret_cast<float4*>(e0 + t) = float4{z0[0], z0[1], z0[2], z0[3]};
+        *reinterpret_cast<float4*>(e0 + n + t) = float4{z1[0], z1[1], z1[2], z1[3]};
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        h0[j] = MODE == 1 ? z0[j] : cnnk::gelu_exact(z0[j]);
+        h1[j] = MODE == 1 ? z1[j] : cnnk::gelu_exact(z1[j]);
+      }
+    } else if constexpr (MODE == 2) {
+      const float* gp = gpre + ((size_t)(z * B + b) * C + o0) * n;
+      const float4 g0 = *reinterpret_cast<const float4*>(gp + t);
+      const float4 g1 = *reinterpret_cast<const float4*>(gp + n + t);
+      const float gg0[4] = {g0.x, g0.y, g0.z, g0.w}, gg1[4] = {g1.x, g1.y, g1.z, g1.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        h0[j] = z0[j] * cnnk::gelu_grad(gg0[j]);
+        h1[j] = z1[j] * cnnk::gelu_grad(gg1[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        h0[j] = z0[j];
+        h1[j] = z1[j];
+      }
+    }
+    *reinterpret_cast<float4*>(d0 + t) = float4{h0[0], h0[1], h0[2], h0[3]};
+    *reinterpret_cast<float4*>(d0 + n + t) = float4{h1[0], h1[1], h1[2], h1[3]};
+  }
+}
+
+// The forward-mode inverse (MODE 0 and 1 of k_fno_inv) for square FP32
+// grids of 2^LOGN x 2^LOGN cells (64^2) on the compile-time transforms: the
+// Hermitian-extended spectrum of the pair is formed straight into the first
+// stage of the inverse transform along x (rows), an LDS transpose feeds the
+// inverse transform along y (columns), whose last stage leaves each row of
+// the field across lanes for the pointwise term, GELU and the stores.
+template <int LOGN, int C, int MODE>
+__global__ void __launch_bounds__((1 << (2 * LOGN)) / 8) k_fno_inv_r(
+    const c32* __restrict__ Y, const float* __restrict__ vin, FnoArgs a, float* __restrict__ vout,
+    float* __restrict__ zout, const Cx<float>* __restrict__ tw, int M, int B) {
+  static_assert(MODE == 0 || MODE == 1, "forward modes");
+  constexpr int N = 1 << LOGN, BLOCK = (N * N) / 8, S = fftreg::plan_stages(LOGN);
+  constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
+  constexpr int R0 = 1 << LR0, RL = 1 << LRL;
+  constexpr int kE1 = fftreg::lds_elems<true, LOGN, LOGN>();
+  constexpr int kE2 = fftreg::lds_elems<false, LOGN, LOGN>();
+  __shared__ Cx<float> A[kE1 > kE2 ? kE1 : kE2];
+  __shared__ Cx<float> W[N];
+  __shared__ __attribute__((aligned(16))) float sw[2][C];
+  for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = tw[e];
+  int p, b, z;
+  pair_of_block(p, b, z);
+  const int g = a.net[z];
+  const int o0 = 2 * p, o1 = 2 * p + 1;
+  constexpr int n = N * N;
+  const int nm = 2 * M * M;
+  if (threadIdx.x < 2 * C) {
+    const float* pw = a.point_w[g];
+    const int q = threadIdx.x / C, i = threadIdx.x % C;
+    sw[q][i] = pw[(q ? o1 : o0) * C + i];
+  }
+  const float bo0 = a.point_b[g][o0], bo1 = a.point_b[g][o1];
+  const c32* Y0 = Y + ((size_t)(z * B + b) * C + o0) * nm;
+  const c32* Y1 = Y0 + nm;
+  // Hermitian extension at the first inverse stage's points (row ky, column
+  // kx): Y(r, kx) for 0 < kx < M, conj Y(r', N - kx) of the mirrored row for
+  // kx > N - M, (Y(r, 0) + conj Y(r', 0)) / 2 at kx = 0, zero elsewhere
+  Cx<float> x[8];
+  {
+    c32 ya0[8], ya1[8], yb0[8], yb1[8];
+#pragma unroll
+    for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        int ky, kx;
+        fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, ky, kx);
+        const int e = q * RL + r;
+        const int rr = retained_row(ky, N, M);
+        const int rm = retained_row((N - ky) & (N - 1), N, M);
+        int ia = -1, ib = -1;
+        if (kx == 0) {
+          ia = rr >= 0 ? rr * M : -1;
+          ib = rm >= 0 ? rm * M : -1;
+        } else if (kx < M) {
+          ia = rr >= 0 ? rr * M + kx : -1;
+        } else if (kx > N - M) {
+          ib = rm >= 0 ? rm * M + (N - kx) : -1;
+        }
+        ya0[e] = ya1[e] = yb0[e] = yb1[e] = c32{0.f, 0.f};
+        if (ia >= 0) {
+          ya0[e] = Y0[ia];
+          ya1[e] = Y1[ia];
+        }
+        if (ib >= 0) {
+          yb0[e] = Y0[ib];
+          yb1[e] = Y1[ib];
+        }
+      }
+#pragma unroll
+    for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        int ky, kx;
+        fftreg::point<true, LOGN, LOGN, BLOCK, LRL>(q, r, ky, kx);
+        const int e = q * RL + r;
+        // s = ya + conj(yb) (one of the two is zero outside the kx = 0 column)
+        const float h = kx == 0 ? 0.5f : 1.0f;
+        const float s0x = h * (ya0[e].x + yb0[e].x), s0y = h * (ya0[e].y - yb0[e].y);
+        const float s1x = h * (ya1[e].x + yb1[e].x), s1y = h * (ya1[e].y - yb1[e].y);
+        x[e] = Cx<float>{s0x - s1y, s0y + s1x};
+      }
+  }
+  __syncthreads();
+  // along x (rows), the stages in reverse order
+  fftreg::run<true, LOGN, LOGN, BLOCK, +1, true>(x, A, W);
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int ky, xx;
+      fftreg::point<true, LOGN, LOGN, BLOCK, LR0>(q, r, ky, xx);
+      A[fftreg::lds_at<false, LOGN, LOGN>(ky, xx)] = x[q * R0 + r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8 / RL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int xx, ky;
+      fftreg::point<false, LOGN, LOGN, BLOCK, LRL>(q, r, xx, ky);
+      x[q * RL + r] = A[fftreg::lds_at<false, LOGN, LOGN>(ky, xx)];
+    }
+  __syncthreads();
+  // along y (columns): the outputs land at (column xx, row y), each row of
+  // the field across consecutive lanes
+  fftreg::run<false, LOGN, LOGN, BLOCK, +1, true>(x, A, W);
+  const float sc = 1.0f / (float)n;
+  const float* src = vin + (size_t)(z * B + b) * C * n;
+  float* d0 = vout + ((size_t)(z * B + b) * C + o0) * n;
+  float* e0 = zout ? zout + ((size_t)(z * B + b) * C + o0) * n : nullptr;
+#pragma unroll
+  for (int q = 0; q < 8 / R0; ++q)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      int xx, y;
+      fftreg::point<false, LOGN, LOGN, BLOCK, LR0>(q, r, xx, y);
+      const int e = q * R0 + r;
+      const int t = y * N + xx;
+      float z0 = x[e].x * sc + bo0, z1 = x[e].y * sc + bo1;
+#pragma unroll
+      for (int c0 = 0; c0 < C; c0 += 4) {
+        float vi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vi[i] = src[(size_t)(c0 + i) * n + t];
+        const float4 a0 = *reinterpret_cast<const float4*>(&sw[0][c0]);
+        const float4 a1 = *reinterpret_cast<const float4*>(&sw[1][c0]);
+        z0 += a0.x * vi[0] + a0.y * vi[1] + a0.z * vi[2] + a0.w * vi[3];
+        z1 += a1.x * vi[0] + a1.y * vi[1] + a1.z * vi[2] + a1.w * vi[3];
+      }
       if (e0) {
         e0[t] = z0;
         e0[n + t] = z1;
       }
       d0[t] = MODE == 1 ? z0 : cnnk::gelu_exact(z0);
       d0[n + t] = MODE == 1 ? z1 : cnnk::gelu_exact(z1);
-    } else if constexpr (MODE == 2) {
-      const float* gp = gpre + ((size_t)(z * B + b) * C + o0) * n;
-      d0[t] = z0 * cnnk::gelu_grad(gp[t]);
-      d0[n + t] = z1 * cnnk::gelu_grad(gp[n + t]);
-    } else {
-      d0[t] = z0;
-      d0[n + t] = z1;
     }
-  }
 }
 
 // output channel K of network g = Q_g v_L + b_Q (zeros for an absent
@@ -853,6 +1141,7 @@ int fno_forward_e(ldsv_handle* h, const FnoGroup& G, const FnoShape& sh, const F
   const dim3 gmix((nm + 63) / 64, (B + bpg - 1) / bpg, sh.nnet);
   const Cx<float>* twx = (const Cx<float>*)h->twx;
   const Cx<float>* twy = (const Cx<float>*)h->twy;
+  const bool sq64 = nx == 64 && ny == 64;
   for (int l = 0; l < sh.L; ++l) {
     const FnoArgs a = make_args(G, sh, l);
     const bool first = l == 0, last = l == sh.L - 1;
@@ -860,7 +1149,16 @@ int fno_forward_e(ldsv_handle* h, const FnoGroup& G, const FnoShape& sh, const F
     c32* X = w.xs ? w.xs + (size_t)l * w.spec : w.X;
     float* cur = fno_in(w, l);
     float* nxt = fno_out(w, l);
-    if (first) {
+    if (sq64) {
+      // the compile-time transforms (64^2): v_0 = lift(inputs) written to
+      // cur on the way in the first layer
+      if (first)
+        LDSV_TLAUNCH(h, 8, (k_fno_spec_r<6, true>), gfft, dim3(512), 0, st, (const float*)nullptr,
+                     a, cur, X, twx, C, M, B);
+      else
+        LDSV_TLAUNCH(h, 8, (k_fno_spec_r<6, false>), gfft, dim3(512), 0, st, (const float*)cur,
+                     a, (float*)nullptr, X, twx, C, M, B);
+    } else if (first) {
       // v_0 = lift(inputs) is written to cur on the way
       auto k = k_fno_spec<spec_e<E>(), true>;
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -880,7 +1178,12 @@ int fno_forward_e(ldsv_handle* h, const FnoGroup& G, const FnoShape& sh, const F
     else
       LDSV_TLAUNCH(h, 9, (k_fno_mix<8, false>), gmix, dim3(64 * 8), 0, st, (const c32*)X, a,
                    Y, B, nm, bpg);
-    {
+    if (sq64) {
+      auto k = last ? (C == 16 ? k_fno_inv_r<6, 16, 1> : k_fno_inv_r<6, 8, 1>)
+                    : (C == 16 ? k_fno_inv_r<6, 16, 0> : k_fno_inv_r<6, 8, 0>);
+      LDSV_TLAUNCH(h, 8, k, gfft, dim3(512), 0, st, (const c32*)Y, (const float*)cur, a, nxt, zl,
+                   twx, M, B);
+    } else {
       auto k = last ? (C == 16 ? k_fno_inv<E, 16, 1> : k_fno_inv<E, 8, 1>)
                     : (C == 16 ? k_fno_inv<E, 16, 0> : k_fno_inv<E, 8, 0>);
       LDSV_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
