@@ -592,9 +592,10 @@ bool launch_div_rowfft_r(ldsv_handle* h, const void* us, const void* vs, hipStre
     return false;
   } else {
     // 2048 points per workgroup (256 threads; 128 measured slower at
-    // 1024^2 x 128, 512 no faster), fewer rows for small batches until the
-    // launch has a workgroup per CU
-    int rows = std::max(1, 2048 / h->g.nx);
+    // 1024^2 x 128, 512 no faster), 8 rows of 1024 (1024 threads: 7 %
+    // faster than 2 rows at 1024^2 x 128); fewer rows for small batches
+    // until the launch has a workgroup per CU
+    int rows = std::max(1, (h->g.nx == 1024 ? 8192 : 2048) / h->g.nx);
     if (rows > h->g.ny) rows = h->g.ny;
     while (rows > 1 && (size_t)(h->g.ny / rows) * h->npairs < 256) rows >>= 1;
     const int logn = h->log2nx, logr = __builtin_ctz((unsigned)rows);
