@@ -739,7 +739,7 @@ def main():
                     "timed loop, the known-size kernel that calibrates HBM byte counters")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs the batched step on a single MI355X "
+        print("bench.py measures one GPU: the library runs the batched step on a single MI355X "
               "(trajectories would shard across GPUs with no communication); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
