@@ -656,10 +656,13 @@ bool launch_col_solve_r(ldsv_handle* h, hipStream_t st, const int* active) {
   } else {
     // 4096 points per workgroup (512 threads; 256 or 1024 measured slower at
     // 512^2 x 16 and 1024^2 x 128), narrower column groups for small batches
-    // until the launch has a workgroup per CU
+    // until the launch has a workgroup per CU, but not below 512 points (64
+    // threads: at 128^2 x 8 this keeps the compile-time form, 4.9 us against
+    // 8.2 us for the general kernel)
     int cols = std::max(1, 4096 / h->g.ny);
     if (cols > h->g.nx) cols = h->g.nx;
-    while (cols > 1 && (size_t)(h->g.nx / cols) * h->npairs < 256) cols >>= 1;
+    while (cols > 1 && (size_t)(h->g.nx / cols) * h->npairs < 256 && cols * h->g.ny > 512)
+      cols >>= 1;
     const int logn = h->log2ny, logc = __builtin_ctz((unsigned)cols);
     const dim3 grid((h->g.nx / cols) * h->npairs);
     const int B = h->g.batch;
