@@ -688,7 +688,7 @@ bool launch_col_solve_r(ldsv_handle* h, hipStream_t st, const int* active) {
 }
 
 // The whole projection of one trajectory in one workgroup for square FP32
-// grids of 2^LOGN x 2^LOGN cells (32^2 and 64^2), with real-input
+// grids of 2^LOGN x 2^LOGN cells (32^2, 64^2 and 128^2), with real-input
 // transforms of half the length (twice the workgroups of one workgroup per
 // trajectory pair for the same work per trajectory: 64 at 64^2 x 64).
 //   - u*, v* are read once with 16-byte loads and staged in LDS (the
@@ -726,12 +726,17 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
   constexpr int kE3 = NH * ZS > N * QS ? NH * ZS : N * QS;
   constexpr int kElems = (kE1 > kE2 ? kE1 : kE2) > kE3 ? (kE1 > kE2 ? kE1 : kE2) : kE3;
   static_assert(KC * BLOCK * 4 == N * N && BLOCK >= N, "thread mapping");
-  __shared__ __align__(16) float su[N * SP];
-  __shared__ __align__(16) float sv[N * SP];
-  __shared__ Cx<float> A[kElems];
-  __shared__ Cx<float> W[N];
-  __shared__ Cx<float> X0[N];
-  __shared__ double F1[N];
+  // LDS: the staged u* (later p), the transform buffer (which holds the
+  // staged v* until the first transform), twiddles, the packed column's
+  // values, the factors of the kx = N/2 column
+  static_assert(N * SP * 4 <= kElems * 8 && (N * SP * 4) % 16 == 0, "LDS layout");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pr[];
+  float* su = reinterpret_cast<float*>(smem_pr);
+  Cx<float>* A = reinterpret_cast<Cx<float>*>(smem_pr + N * SP * 4);
+  float* sv = reinterpret_cast<float*>(A);
+  Cx<float>* W = A + kElems;
+  Cx<float>* X0 = W + N;
+  double* F1 = reinterpret_cast<double*>(X0 + N);
   const int b = (int)blockIdx.x;
   if (active && !active[b]) return;  // uniform per workgroup, before any barrier
   const int tid = (int)threadIdx.x;
@@ -782,6 +787,7 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
       const float d1 = (su[y1 + ip] - su[y1 + i]) * idx + (sv[y2 + i] - sv[y1 + i]) * idy;
       x[q * R0 + r] = Cx<float>{d0, d1};
     }
+  __syncthreads();  // the staged v* shares the transform's buffer
   fftreg::run<true, LOGN, LOGT, BLOCK, -1, false>(x, A, W);
   // packed row spectra Z_t[kx] to LDS (every LDS read of the transform is
   // behind its last barrier)
@@ -905,6 +911,31 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
   }
 }
 
+// dynamic LDS bytes of k_project_real_r<LOGN>
+template <int LOGN>
+constexpr size_t project_real_lds() {
+  constexpr int N = 1 << LOGN, NH = N / 2, LOGT = LOGN - 1;
+  constexpr int kE1 = fftreg::lds_elems<true, LOGN, LOGT>(), kE2 = fftreg::lds_elems<false, LOGN, LOGT>();
+  constexpr int kE3 = NH * (N + 8) > N * (NH + 4) ? NH * (N + 8) : N * (NH + 4);
+  constexpr int kElems = (kE1 > kE2 ? kE1 : kE2) > kE3 ? (kE1 > kE2 ? kE1 : kE2) : kE3;
+  return (size_t)N * (N + 4) * 4 + (size_t)kElems * 8 + (size_t)N * (8 + 8 + 8);
+}
+
+template <int LOGN>
+int launch_project_real(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo,
+                        void* po, hipStream_t st, const int* active) {
+  constexpr size_t lds = project_real_lds<LOGN>();
+  constexpr int block = (1 << (2 * LOGN)) / 16;
+  const float fx = (float)(h->g.nx / h->g.lx), fy = (float)(h->g.ny / h->g.ly);
+  LDSV_HIP(hipFuncSetAttribute((const void*)k_project_real_r<LOGN>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  LDSV_TLAUNCH(h, 2, k_project_real_r<LOGN>, dim3(h->g.batch), dim3(block), lds, st,
+               (const float*)us, (const float*)vs, (float*)uo, (float*)vo, (float*)po,
+               (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active);
+  LDSV_LAUNCHED();
+  return LDSV_OK;
+}
+
 template <typename T>
 int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void* vo, void* po,
                  hipStream_t st, const int* active) {
@@ -919,19 +950,12 @@ int project_impl(ldsv_handle* h, const void* us, const void* vs, void* uo, void*
   const bool one_block = (size_t)nx * ny <= (size_t)4 * kOneBlock ||
                          ((size_t)nx * ny <= (size_t)16 * kOneBlock && h->npairs >= 256);
   if constexpr (std::is_same<T, float>::value) {
-    if (nx == ny && (nx == 32 || nx == 64) && one_block) {
-      const float fx = (float)(nx / h->g.lx), fy = (float)(ny / h->g.ly);
-      if (nx == 64)
-        LDSV_TLAUNCH(h, 2, k_project_real_r<6>, dim3(B), dim3(256), 0, st, (const float*)us,
-                     (const float*)vs, (float*)uo, (float*)vo, (float*)po,
-                     (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active);
-      else
-        LDSV_TLAUNCH(h, 2, k_project_real_r<5>, dim3(B), dim3(64), 0, st, (const float*)us,
-                     (const float*)vs, (float*)uo, (float*)vo, (float*)po,
-                     (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active);
-      LDSV_LAUNCHED();
-      return LDSV_OK;
-    }
+    if (nx == ny && (nx == 32 || nx == 64) && one_block)
+      return nx == 64 ? launch_project_real<6>(h, us, vs, uo, vo, po, st, active)
+                      : launch_project_real<5>(h, us, vs, uo, vo, po, st, active);
+    // 128^2: one 1024-thread workgroup per trajectory
+    if (nx == ny && nx == 128)
+      return launch_project_real<7>(h, us, vs, uo, vo, po, st, active);
   }
   if (one_block && (size_t)nx * ny * cs <= 131072) {
     // u*, v* are read only by the cells that write u, v at the same index
