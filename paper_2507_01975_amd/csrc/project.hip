@@ -726,17 +726,19 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
   constexpr int kE3 = NH * ZS > N * QS ? NH * ZS : N * QS;
   constexpr int kElems = (kE1 > kE2 ? kE1 : kE2) > kE3 ? (kE1 > kE2 ? kE1 : kE2) : kE3;
   static_assert(KC * BLOCK * 4 == N * N && BLOCK >= N, "thread mapping");
-  // LDS: the staged u* (later p), the transform buffer (which holds the
-  // staged v* until the first transform), twiddles, the packed column's
-  // values, the factors of the kx = N/2 column
+  // LDS: the staged u* (later p), the transform buffer, twiddles, the
+  // packed column's values, the factors of the kx = N/2 column, and the
+  // staged v* -- which at 128^2 (where the two staged fields and the
+  // transform buffer would not fit) shares the transform buffer instead
+  constexpr bool kAlias = LOGN >= 7;
   static_assert(N * SP * 4 <= kElems * 8 && (N * SP * 4) % 16 == 0, "LDS layout");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pr[];
   float* su = reinterpret_cast<float*>(smem_pr);
   Cx<float>* A = reinterpret_cast<Cx<float>*>(smem_pr + N * SP * 4);
-  float* sv = reinterpret_cast<float*>(A);
   Cx<float>* W = A + kElems;
   Cx<float>* X0 = W + N;
   double* F1 = reinterpret_cast<double*>(X0 + N);
+  float* sv = kAlias ? reinterpret_cast<float*>(A) : reinterpret_cast<float*>(F1 + N);
   const int b = (int)blockIdx.x;
   if (active && !active[b]) return;  // uniform per workgroup, before any barrier
   const int tid = (int)threadIdx.x;
@@ -787,7 +789,7 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
       const float d1 = (su[y1 + ip] - su[y1 + i]) * idx + (sv[y2 + i] - sv[y1 + i]) * idy;
       x[q * R0 + r] = Cx<float>{d0, d1};
     }
-  __syncthreads();  // the staged v* shares the transform's buffer
+  if constexpr (kAlias) __syncthreads();  // the staged v* shares the transform's buffer
   fftreg::run<true, LOGN, LOGT, BLOCK, -1, false>(x, A, W);
   // packed row spectra Z_t[kx] to LDS (every LDS read of the transform is
   // behind its last barrier)
@@ -918,7 +920,7 @@ constexpr size_t project_real_lds() {
   constexpr int kE1 = fftreg::lds_elems<true, LOGN, LOGT>(), kE2 = fftreg::lds_elems<false, LOGN, LOGT>();
   constexpr int kE3 = NH * (N + 8) > N * (NH + 4) ? NH * (N + 8) : N * (NH + 4);
   constexpr int kElems = (kE1 > kE2 ? kE1 : kE2) > kE3 ? (kE1 > kE2 ? kE1 : kE2) : kE3;
-  return (size_t)N * (N + 4) * 4 + (size_t)kElems * 8 + (size_t)N * (8 + 8 + 8);
+  return (size_t)N * (N + 4) * 4 * (LOGN >= 7 ? 1 : 2) + (size_t)kElems * 8 + (size_t)N * (8 + 8 + 8);
 }
 
 template <int LOGN>
