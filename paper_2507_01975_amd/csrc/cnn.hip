@@ -10,8 +10,10 @@
 // channel as the M dimension, the pixel as N and (tap, input channel) as K:
 //   A (16 x 32): weights W[co][tap][ci], 8 contiguous bf16 per lane
 //   B (32 x 16): activations X[pixel + tap][ci], 8 contiguous bf16 per lane
-//   D (16 x 16): lane l holds channels 4(l/16)..+3 of pixel l%16, so a lane
-//                stores 4 consecutive channels (8 bytes) of one NHWC pixel.
+//   D (16 x 16): lane l holds rows 4(l/16)..+3 of pixel l%16; in the
+//                64-output layers row r of block m is channel out_chan(m, r),
+//                so that a lane stores 8 consecutive channels (16 bytes) of
+//                one NHWC pixel from two blocks.
 // Kernels (cnn_common.h):
 //   k_conv3x3_dma   64-output layers on grids whose sides are multiples of
 //                   16: persistent, weights and two 16 x 16 halo tiles in LDS
@@ -56,7 +58,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_conv_first(const float* __restric
   f32x4 acc[kFirstTiles][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const int co = m * 16 + col;
+    const int co = out_chan(m, col);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = kq * 8 + e;
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_conv_first(const float* __restric
     }
     f32x4 b0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b0[i] = b1[m * 16 + kq * 4 + i];
+    for (int i = 0; i < 4; ++i) b0[i] = b1[out_chan(m, kq * 4 + i)];
 #pragma unroll
     for (int t = 0; t < kFirstTiles; ++t) acc[t][m] = b0;
   }
@@ -101,15 +103,21 @@ __global__ void __launch_bounds__(kBlock, 4) k_conv_first(const float* __restric
     const int p = pbase + t * 16 + col;
     if (p >= pm.total) continue;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int c0 = m * 16 + kq * 4;
-      uint2 pk;
-      pk.x = pack_bf16x2(gelu_exact(acc[t][m][0]), gelu_exact(acc[t][m][1]));
-      pk.y = pack_bf16x2(gelu_exact(acc[t][m][2]), gelu_exact(acc[t][m][3]));
-      *reinterpret_cast<uint2*>(Y + (size_t)p * kC + c0) = pk;
-      if (zout)
-        *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0) =
-            float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
+    for (int hh = 0; hh < 2; ++hh) {
+      // blocks 2hh and 2hh+1: channels c0 .. c0 + 7 (out_chan)
+      const int c0 = hh * 32 + kq * 8;
+      const f32x4 a0 = acc[t][2 * hh], a1 = acc[t][2 * hh + 1];
+      uint4 pk;
+      pk.x = pack_bf16x2(gelu_exact(a0[0]), gelu_exact(a0[1]));
+      pk.y = pack_bf16x2(gelu_exact(a0[2]), gelu_exact(a0[3]));
+      pk.z = pack_bf16x2(gelu_exact(a1[0]), gelu_exact(a1[1]));
+      pk.w = pack_bf16x2(gelu_exact(a1[2]), gelu_exact(a1[3]));
+      *reinterpret_cast<uint4*>(Y + (size_t)p * kC + c0) = pk;
+      if (zout) {
+        *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0) = float4{a0[0], a0[1], a0[2], a0[3]};
+        *reinterpret_cast<float4*>(zout + (size_t)p * kC + c0 + 4) =
+            float4{a1[0], a1[1], a1[2], a1[3]};
+      }
     }
   }
 }

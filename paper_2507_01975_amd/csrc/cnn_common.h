@@ -95,6 +95,16 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return normal_cdf(z) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
+// Output channel computed by row r of 16 x 16 accumulator block m in the
+// 64-output layers.  Blocks 0 and 1 hold channels 0..31 and blocks 2 and 3
+// channels 32..63, interleaved in groups of four, so that the rows 4q..4q+3
+// a lane holds in blocks 2h and 2h+1 are the eight consecutive channels
+// 32h + 8q .. 32h + 8q + 7 of its pixel: one 16-byte store of bf16 values
+// (two per pixel and lane, each pixel row written in 64-byte pieces).
+__device__ __forceinline__ constexpr int out_chan(int m, int r) {
+  return ((m >> 1) << 5) + ((r >> 2) << 3) + ((m & 1) << 2) + (r & 3);
+}
+
 struct PixMap {
   int H, W;   // powers of two
   int total;  // B * H * W
@@ -249,8 +259,8 @@ __device__ __forceinline__ int xcd_slot_tile(int s, int T, int G) {
 //
 // Eight wavefronts, wavefront w computing tile rows 2w and 2w+1 for every
 // output channel.  The epilogue (bias-initialised accumulators, bf16
-// rounding, and GELU in the hidden layers) costs vector-ALU time comparable
-// to the tile's matrix-core time, so the wavefronts are split into two groups
+// rounding and the scattered stores of the coefficient blocks and planes)
+// costs vector-ALU time comparable to the tile's matrix-core time, so the wavefronts are split into two groups
 // that share each SIMD (w and w + 4 run on the same SIMD): group 0
 // accumulates tile k and then runs its epilogue, group 1 first runs the
 // epilogue of tile k-1 (its accumulators carried across the tile barrier) and
@@ -275,6 +285,10 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
                                                              uint16_t* __restrict__ Y,
                                                              float* __restrict__ zio,
                                                              float* __restrict__ out_planar) {
+  static_assert(MT == 5 && (EPI == 1 || EPI == 3), "the 66-output last layer");
+  // output channel of row r of accumulator block m: the first 64 in the
+  // order of the 64-output layers, the rest in order
+  auto chan = [](int m, int r) { return m < 4 ? out_chan(m, r) : m * 16 + r; };
   extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
   uint16_t* wl = lds_u16;
   uint16_t* xt = lds_u16 + MT * 16 * kWRowAll;
@@ -345,7 +359,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
       if (EPI != 2) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int c = m * 16 + kq * 4 + i;
+          const int c = chan(m, kq * 4 + i);
           b0[i] = c < cout ? bias[c] : 0.f;
         }
       }
@@ -367,7 +381,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-          const int row = m * 16 + col;
+          const int row = chan(m, col);
           const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(
               wl + row * kWRowAll + (((tap * 8 + q) ^ (row & 7)) << 3));
 #pragma unroll
@@ -386,56 +400,43 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
       const int y = y0 + wave * 2 + t / kNX, x = x0 + (t % kNX) * 16 + col;
       const int r = y * pm.W + x;
       const size_t p = (size_t)b * hw + r;
+      if (EPI == 1) {
+        // all 66 channels as float planes, the 64 stencil coefficients
+        // rounded to bf16 values
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int c0 = m * 16 + kq * 4;
-        if (EPI == 0 || EPI == 2) {
-          float h[4];
-          if (EPI == 2) {
-            const float4 zi = *reinterpret_cast<const float4*>(zio + p * kC + c0);
-            const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = acc[t][m][i] * gelu_grad(zz[i]);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = gelu_exact(acc[t][m][i]);
-          }
-          uint2 pk;
-          pk.x = pack_bf16x2(h[0], h[1]);
-          pk.y = pack_bf16x2(h[2], h[3]);
-          *reinterpret_cast<uint2*>(Y + p * kC + c0) = pk;
-          if (EPI == 0 && zio)
-            *reinterpret_cast<float4*>(zio + p * kC + c0) =
-                float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
-        } else if (EPI == 1) {
-          // all 66 channels as float planes, the 64 stencil coefficients
-          // rounded to bf16 values
+        for (int m = 0; m < MT; ++m) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int c = c0 + i;
+            const int c = chan(m, kq * 4 + i);
             const float z = acc[t][m][i];
             if (c < cout)
               out_planar[((size_t)b * cout + c) * hw + r] = c < LDSV_NCOEF ? round_to_bf16(z) : z;
           }
-        } else {
-          // EPI 3: the 64 stencil coefficients in bf16, blocks of 8
-          // channels [B][8][H][W][8] (Y: a lane's 4 consecutive channels are
-          // one 8-byte store), the 2 correction channels as float planes
-          // [B][2][H][W]
-          if (c0 + 3 < LDSV_NCOEF) {
-            uint2 pk;
-            pk.x = pack_bf16x2(acc[t][m][0], acc[t][m][1]);
-            pk.y = pack_bf16x2(acc[t][m][2], acc[t][m][3]);
-            *reinterpret_cast<uint2*>(
-                Y + (((size_t)b * 8 + (c0 >> 3)) * hw + r) * 8 + (c0 & 7)) = pk;
-          } else {
+        }
+      } else {
+        // EPI 3: the 64 stencil coefficients in bf16, blocks of 8 channels
+        // [B][8][H][W][8] (blocks 2hh and 2hh+1 give a lane the 8 channels
+        // of one block entry: one 16-byte store), the 2 correction channels
+        // as float planes [B][2][H][W]
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int c = c0 + i;
-              if (c >= LDSV_NCOEF && c < cout)
-                out_planar[((size_t)b * (LDSV_NOUT - LDSV_NCOEF) + (c - LDSV_NCOEF)) * hw + r] =
-                    acc[t][m][i];
-            }
+        for (int hh = 0; hh < 2; ++hh) {
+          const int c0 = hh * 32 + kq * 8;
+          const f32x4 a0 = acc[t][2 * hh], a1 = acc[t][2 * hh + 1];
+          uint4 pk;
+          pk.x = pack_bf16x2(a0[0], a0[1]);
+          pk.y = pack_bf16x2(a0[2], a0[3]);
+          pk.z = pack_bf16x2(a1[0], a1[1]);
+          pk.w = pack_bf16x2(a1[2], a1[3]);
+          *reinterpret_cast<uint4*>(Y + (((size_t)b * 8 + (c0 >> 3)) * hw + r) * 8) = pk;
+        }
+#pragma unroll
+        for (int m = 4; m < MT; ++m) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = m * 16 + kq * 4 + i;
+            if (c >= LDSV_NCOEF && c < cout)
+              out_planar[((size_t)b * (LDSV_NOUT - LDSV_NCOEF) + (c - LDSV_NCOEF)) * hw + r] =
+                  acc[t][m][i];
           }
         }
       }
@@ -539,7 +540,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
       f32x4 b0 = f32x4{0.f, 0.f, 0.f, 0.f};
       if (EPI != 2) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) b0[i] = bias[m * 16 + kq * 4 + i];
+        for (int i = 0; i < 4; ++i) b0[i] = bias[out_chan(m, kq * 4 + i)];
       }
       acc[0][m] = b0;
       acc[1][m] = b0;
@@ -558,7 +559,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const int row = m * 16 + col;
+          const int row = out_chan(m, col);
           const int c = tap * 8 + q;
           const bf16x8 afrag =
               *reinterpret_cast<const bf16x8*>(wl + row * 576 + ((c ^ (row & 7)) << 3));
@@ -576,25 +577,32 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
     for (int t = 0; t < 2; ++t) {
       const size_t p = (size_t)b * hw + (size_t)(y0 + wave * 2 + t) * pm.W + x0 + col;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int c0 = m * 16 + kq * 4;
-        float h[4];
+      for (int hh = 0; hh < 2; ++hh) {
+        // blocks 2hh and 2hh+1: channels c0 .. c0 + 7 (out_chan)
+        const int c0 = hh * 32 + kq * 8;
+        const f32x4 a0 = acc[t][2 * hh], a1 = acc[t][2 * hh + 1];
+        const float z[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        float h[8];
         if (EPI == 2) {
-          const float4 zi = *reinterpret_cast<const float4*>(zio + p * kC + c0);
-          const float zz[4] = {zi.x, zi.y, zi.z, zi.w};
+          const float4 zi0 = *reinterpret_cast<const float4*>(zio + p * kC + c0);
+          const float4 zi1 = *reinterpret_cast<const float4*>(zio + p * kC + c0 + 4);
+          const float zz[8] = {zi0.x, zi0.y, zi0.z, zi0.w, zi1.x, zi1.y, zi1.z, zi1.w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) h[i] = acc[t][m][i] * gelu_grad(zz[i]);
+          for (int i = 0; i < 8; ++i) h[i] = z[i] * gelu_grad(zz[i]);
         } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) h[i] = gelu_exact(acc[t][m][i]);
+          for (int i = 0; i < 8; ++i) h[i] = gelu_exact(z[i]);
         }
-        uint2 pk;
+        uint4 pk;
         pk.x = pack_bf16x2(h[0], h[1]);
         pk.y = pack_bf16x2(h[2], h[3]);
-        *reinterpret_cast<uint2*>(Y + p * kC + c0) = pk;
-        if (EPI == 0 && zio)
-          *reinterpret_cast<float4*>(zio + p * kC + c0) =
-              float4{acc[t][m][0], acc[t][m][1], acc[t][m][2], acc[t][m][3]};
+        pk.z = pack_bf16x2(h[4], h[5]);
+        pk.w = pack_bf16x2(h[6], h[7]);
+        *reinterpret_cast<uint4*>(Y + p * kC + c0) = pk;
+        if (EPI == 0 && zio) {
+          *reinterpret_cast<float4*>(zio + p * kC + c0) = float4{z[0], z[1], z[2], z[3]};
+          *reinterpret_cast<float4*>(zio + p * kC + c0 + 4) = float4{z[4], z[5], z[6], z[7]};
+        }
       }
     }
   };
