@@ -315,8 +315,9 @@ def learned_block(steps, warmup):
            "bare_steps_ms_per_step": 1e3 * t_bare / steps,
            "guard_overhead": t / t_bare - 1.0, "fallbacks": int(flags.sum())}
     if conv_n:
-        # layers 2..6 on MFMA: 2 * 9 * 64 * Cout FLOP per cell
-        flop = 2 * 9 * 64 * (64 * 4 + 66) * cells
+        # the six layers on MFMA: 2 * 9 * 64 * Cout FLOP per cell for layers
+        # 2..6, 2 * 18 * 64 for layer 1 (computed inside layer 2's launch)
+        flop = (2 * 9 * 64 * (64 * 4 + 66) + 2 * 18 * 64) * cells
         per_launch_ms = conv_ms / conv_n
         launches_per_step = conv_n / steps
         out["mfma_conv"] = {"tflops": flop / launches_per_step / (per_launch_ms * 1e-3) / 1e12,
@@ -383,7 +384,7 @@ def learned_deriv_block(steps, warmup):
                             "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         out["stage_hbm"]["frac"] = out["stage_hbm"]["achieved"] / HBM_PEAK_GBS
     if conv_n:
-        flop = 2 * 2 * 9 * 64 * (64 * 4 + 66) * cells
+        flop = 2 * (2 * 9 * 64 * (64 * 4 + 66) + 2 * 18 * 64) * cells
         per_launch_ms = conv_ms / conv_n
         out["mfma_conv"] = {"tflops": flop / (conv_n / steps) / (per_launch_ms * 1e-3) / 1e12,
                             "peak": BF16_PEAK_TFLOPS, "avg_launch_ms": per_launch_ms}

@@ -206,8 +206,11 @@ LDSV_API int ldsv_cnn_forward(ldsv_handle* h, const ldsv_net* net, const float* 
                      float* out, void* stream);
 
 /* Copy the bf16 NHWC activation [B][Ny][Nx][64] that layer `layer` (0..4)
- * produced in the last network evaluation on this handle into dst (device,
- * uint16 bit patterns).  For per-layer parity checks. */
+ * produced in the last ldsv_cnn_forward call on this handle into dst
+ * (device, uint16 bit patterns).  For per-layer parity checks.  Learned
+ * steps and rollouts evaluate the network too (layers 1..4 then hold their
+ * activations; on grids whose sides are multiples of 16 they compute layer
+ * 0 inside layer 1's tiles without storing it). */
 LDSV_API int ldsv_cnn_activation(ldsv_handle* h, int layer, uint16_t* dst, void* stream);
 
 /* ---- a12-a13: the learned step (Eq. 2) ----

@@ -12,9 +12,12 @@ int ldsv_check_net(const ldsv_net* net);
 // a cell are two 16-byte loads, coalesced across cells) and float correction
 // planes [B][2][Ny][Nx] in tc.  Returns in *bf16_out whether the second form
 // was written.
+// fuse_first (inference only, zpre null): on grids whose sides are multiples
+// of 16, layer 1 is computed inside layer 2's tiles and its activation is
+// not kept in the handle (the network output is the same bit for bit)
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                     float* out, float* const* zpre, hipStream_t st, uint16_t* coef16 = nullptr,
-                    float* tc = nullptr, bool* bf16_out = nullptr);
+                    float* tc = nullptr, bool* bf16_out = nullptr, bool fuse_first = false);
 int ldsv_launch_cnn_backward(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                              const float* gout, float* gu, float* gv, const ldsv_net_grad* dW,
                              hipStream_t st);

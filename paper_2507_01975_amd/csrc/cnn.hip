@@ -152,23 +152,50 @@ int ldsv_check_net(const ldsv_net* net) {
   return LDSV_OK;
 }
 
+namespace {
+
+// layers 1 and 2 of an inference forward in one launch on grids whose sides
+// are multiples of 16: the layer-2 tiles computed from u, v in LDS
+int launch_conv12(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
+                  uint16_t* Y, hipStream_t st) {
+  PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int ntiles = (int)(h->nstate / 256);
+  const int grid = ntiles < ncu ? ntiles : ncu;
+  const size_t lds = conv_dma_lds_bytes();
+  LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_dma<0, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  LDSV_TLAUNCH(h, 4, (k_conv3x3_dma<0, true>), dim3(grid), dim3(kConvBlock), lds, st,
+               (const uint16_t*)nullptr, net->w[1], net->b[1], pm, Y, (float*)nullptr, u, v,
+               net->w[0], net->b[0]);
+  return LDSV_OK;
+}
+
+}  // namespace
+
 // forward through all layers; zpre (nullable): 5 float NHWC pre-activation
-// buffers for the backward pass
+// buffers for the backward pass.  fuse_first without them, on grids whose
+// sides are multiples of 16: layer 1 computed inside layer 2's tiles.
 int ldsv_launch_cnn(ldsv_handle* h, const ldsv_net* net, const float* u, const float* v,
                     float* out, float* const* zpre, hipStream_t st, uint16_t* coef16, float* tc,
-                    bool* bf16_out) {
+                    bool* bf16_out, bool fuse_first) {
   PixMap pm{h->g.ny, h->g.nx, (int)h->nstate};
-  const int first_pix = (kBlock / 64) * kFirstTiles * 16;
-  const int nblk_first = (int)((h->nstate + first_pix - 1) / first_pix);
-  {
+  // 16 x 16 LDS tiles when both sides are multiples of 16
+  const bool tiled = (h->g.nx % 16 == 0) && (h->g.ny % 16 == 0);
+  const bool fuse12 = fuse_first && tiled && !zpre;
+  if (fuse12) {
+    LDSV_TRY(launch_conv12(h, net, u, v, h->act[1], st));
+  } else {
+    const int first_pix = (kBlock / 64) * kFirstTiles * 16;
+    const int nblk_first = (int)((h->nstate + first_pix - 1) / first_pix);
     LDSV_TLAUNCH(h, 5, k_conv_first, dim3(nblk_first), dim3(kBlock), 0, st, u, v, net->w[0],
-                       net->b[0], pm, h->act[0], zpre ? zpre[0] : nullptr);
+                 net->b[0], pm, h->act[0], zpre ? zpre[0] : nullptr);
   }
   LDSV_LAUNCHED();
   const int nblk = (int)((h->nstate + kPixPerBlock - 1) / kPixPerBlock);
-  // 16 x 16 LDS tiles when both sides are multiples of 16
-  const bool tiled = (h->g.nx % 16 == 0) && (h->g.ny % 16 == 0);
-  for (int l = 1; l < 5; ++l) {
+  for (int l = fuse12 ? 2 : 1; l < 5; ++l) {
     if (tiled)
       LDSV_TRY(ldsv_launch_conv_tile(h, 4, 0, h->act[l - 1], net->w[l], net->b[l], kC, h->act[l],
                                      zpre ? zpre[l] : nullptr, nullptr, st));
@@ -214,7 +241,8 @@ int ldsv_launch_conv_tile(ldsv_handle* h, int mt, int epi, const uint16_t* X, co
     LDSV_HIP(hipFuncSetAttribute((const void*)k_conv3x3_dma<EPI_>,                            \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));     \
     LDSV_TLAUNCH(h, 4, (k_conv3x3_dma<EPI_>), dim3(grid), dim3(kConvBlock), lds, st, X, W,    \
-                 bias, pm, Y, zio);                                                          \
+                 bias, pm, Y, zio, (const float*)nullptr, (const float*)nullptr,             \
+                 (const uint16_t*)nullptr, (const float*)nullptr);                           \
   }
   if (mt == 4 && epi == 0 && cout == kC) LDSV_CONV_DMA(0)
   else if (mt == 4 && epi == 2 && cout == kC) LDSV_CONV_DMA(2)

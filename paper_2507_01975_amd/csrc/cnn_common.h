@@ -286,9 +286,11 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
                                                              float* __restrict__ zio,
                                                              float* __restrict__ out_planar) {
   static_assert(MT == 5 && (EPI == 1 || EPI == 3), "the 66-output last layer");
-  // output channel of row r of accumulator block m: the first 64 in the
-  // order of the 64-output layers, the rest in order
-  auto chan = [](int m, int r) { return m < 4 ? out_chan(m, r) : m * 16 + r; };
+  // output channel of row r of accumulator block m: for the bf16 blocks
+  // (EPI 3) the first 64 in the order of the 64-output layers, the rest in
+  // order; in order for the float planes (EPI 1), whose stores are per
+  // channel anyway
+  auto chan = [](int m, int r) { return EPI == 3 && m < 4 ? out_chan(m, r) : m * 16 + r; };
   extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
   uint16_t* wl = lds_u16;
   uint16_t* xt = lds_u16 + MT * 16 * kWRowAll;
@@ -399,7 +401,6 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_tile(const uint16_t* __r
     for (int t = 0; t < NT; ++t) {
       const int y = y0 + wave * 2 + t / kNX, x = x0 + (t % kNX) * 16 + col;
       const int r = y * pm.W + x;
-      const size_t p = (size_t)b * hw + r;
       if (EPI == 1) {
         // all 66 channels as float planes, the 64 stencil coefficients
         // rounded to bf16 values
@@ -485,12 +486,27 @@ constexpr size_t conv_dma_lds_bytes() { return (size_t)(kC * 9 * kC + 2 * kDmaTi
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <int EPI>
+//
+// L1 (inference of the second layer): the staged tile is not read from the
+// first layer's output but computed in place from u, v: the first layer
+// (2 -> 64 channels, one K = 32 step per 16 halo pixels, bias, GELU, bf16
+// rounding, the same operands and operations as k_conv_first, so the tile
+// holds the same values bit for bit) evaluated on the tile's 18 x 18 halo
+// pixels, its 16-byte chunks written to the swizzled LDS positions.  The
+// first layer's activations then never go through HBM (33.5 MB written and
+// read back at 64^2 x 64) and its launch disappears, for 27 % of recomputed
+// halo pixels; X is unused.
+template <int EPI, bool L1 = false>
 __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __restrict__ X,
                                                             const uint16_t* __restrict__ Wt,
                                                             const float* __restrict__ bias,
                                                             PixMap pm, uint16_t* __restrict__ Y,
-                                                            float* __restrict__ zio) {
+                                                            float* __restrict__ zio,
+                                                            const float* __restrict__ u1,
+                                                            const float* __restrict__ v1,
+                                                            const uint16_t* __restrict__ W1,
+                                                            const float* __restrict__ b1) {
+  static_assert(!L1 || EPI == 0, "the fused first layer is an inference forward");
   extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
   uint16_t* wl = lds_u16;                   // [64][576], swizzled chunks
   uint16_t* xbuf = lds_u16 + kC * 9 * kC;   // two tiles [18 * 18][64], swizzled
@@ -515,7 +531,87 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
   // instructions of 64 lanes over the 8 wavefronts (lanes past the end idle)
   constexpr int kTChunks = 18 * 18 * 8;
   constexpr int kTInst = (kTChunks + 63) / 64;
+  // first layer (L1): the weights of the lane's A rows (channel
+  // out_chan(m, col), K entries 8 kq .. 8 kq + 7 of the 18) and the bias of
+  // its accumulator rows, once
+  bf16x8 a1[4];
+  f32x4 bias1[4];
+  if constexpr (L1) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int co = out_chan(m, col);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kq * 8 + e;
+        a1[m][e] = __builtin_bit_cast(__bf16, k < 18 ? W1[co * 18 + k] : (uint16_t)0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bias1[m][i] = b1[out_chan(m, kq * 4 + i)];
+    }
+  }
+  // L1: the 21 groups of 16 of the tile's 324 halo pixels, groups w, w + 8,
+  // w + 16 on wavefront w; each lane gathers the u, v of its K entries
+  // (taps 4 kq .. 4 kq + 3) for its pixel of every group first, then
+  // multiplies, applies GELU and writes its two 16-byte chunks
+  constexpr int kL1Groups = (18 * 18 + 15) / 16;
+  constexpr int kL1PerWave = (kL1Groups + kConvBlock / 64 - 1) / (kConvBlock / 64);
+  auto make_tile = [&](int tile, int sbuf) {
+    const int b = tile / (tiles_x * tiles_y);
+    const int tr = tile - b * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
+    uint16_t* dst = xbuf + sbuf * kDmaTile;
+    const float* ub = u1 + (size_t)b * hw;
+    const float* vb = v1 + (size_t)b * hw;
+    bf16x8 bf[kL1PerWave];
+#pragma unroll
+    for (int k = 0; k < kL1PerWave; ++k) {
+      const int g = wave + k * (kConvBlock / 64);
+      const int px = g * 16 + col;
+      const int ry = px / 18, rx = px - ry * 18;
+      const int gy = y0 - 1 + ry, gx = x0 - 1 + rx;
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const int tap = (kq * 8 + e) / 2;
+        float a = 0.f, c = 0.f;
+        if (g < kL1Groups && px < 18 * 18 && tap < 9) {
+          const int q = ((gy + tap / 3 - 1) & (pm.H - 1)) * pm.W + ((gx + tap % 3 - 1) & (pm.W - 1));
+          a = ub[q];
+          c = vb[q];
+        }
+        const uint32_t pk = pack_bf16x2(a, c);
+        bf[k][e] = __builtin_bit_cast(__bf16, (uint16_t)(pk & 0xffffu));
+        bf[k][e + 1] = __builtin_bit_cast(__bf16, (uint16_t)(pk >> 16));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kL1PerWave; ++k) {
+      const int g = wave + k * (kConvBlock / 64);
+      const int px = g * 16 + col;
+      if (g >= kL1Groups) continue;  // uniform per wavefront
+      f32x4 z[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        z[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[m], bf[k], bias1[m], 0, 0, 0);
+      if (px < 18 * 18) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const f32x4 q0 = z[2 * hh], q1 = z[2 * hh + 1];
+          uint4 pk;
+          pk.x = pack_bf16x2(gelu_exact(q0[0]), gelu_exact(q0[1]));
+          pk.y = pack_bf16x2(gelu_exact(q0[2]), gelu_exact(q0[3]));
+          pk.z = pack_bf16x2(gelu_exact(q1[0]), gelu_exact(q1[1]));
+          pk.w = pack_bf16x2(gelu_exact(q1[2]), gelu_exact(q1[3]));
+          const int chunk = hh * 4 + kq;  // channels 8 chunk .. 8 chunk + 7
+          *reinterpret_cast<uint4*>(dst + px * kC + ((chunk ^ (px & 7)) << 3)) = pk;
+        }
+      }
+    }
+  };
   auto issue_tile = [&](int tile, int sbuf) {
+    if constexpr (L1) {
+      [[clang::always_inline]] make_tile(tile, sbuf);
+      return;
+    }
     const int b = tile / (tiles_x * tiles_y);
     const int tr = tile - b * tiles_x * tiles_y;
     const int y0 = (tr / tiles_x) * 16, x0 = (tr % tiles_x) * 16;
@@ -608,7 +704,7 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
   };
   const int G = gridDim.x;
   int sbuf = 0;
-  if ((int)blockIdx.x < ntiles) issue_tile(xcd_slot_tile(blockIdx.x, ntiles, G), 0);
+  if ((int)blockIdx.x < ntiles) [[clang::always_inline]] issue_tile(xcd_slot_tile(blockIdx.x, ntiles, G), 0);
   int prev = -1;
   for (int s = blockIdx.x; s < ntiles; s += G) {
     const int tile = xcd_slot_tile(s, ntiles, G);
@@ -617,10 +713,23 @@ __global__ void __launch_bounds__(kConvBlock) k_conv3x3_dma(const uint16_t* __re
     // wavefront is done reading the other buffer
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (s + G < ntiles) issue_tile(xcd_slot_tile(s + G, ntiles, G), sbuf ^ 1);
+    const bool more = s + G < ntiles;
+    const int next = more ? xcd_slot_tile(s + G, ntiles, G) : 0;
+    if constexpr (!L1) {
+      if (more) [[clang::always_inline]] issue_tile(next, sbuf ^ 1);
+    }
     if (grp == 1 && prev >= 0) epilogue(prev);
+    // L1: each group computes its share of the next tile while the other
+    // group's wavefront on the same SIMD multiplies (group 1 before its
+    // MFMAs, group 0 after its epilogue); the next barrier publishes it
+    if constexpr (L1) {
+      if (grp == 1 && more) [[clang::always_inline]] make_tile(next, sbuf ^ 1);
+    }
     mma(xbuf + sbuf * kDmaTile);
     if (grp == 0) epilogue(tile);
+    if constexpr (L1) {
+      if (grp == 0 && more) [[clang::always_inline]] make_tile(next, sbuf ^ 1);
+    }
     prev = tile;
     sbuf ^= 1;
   }

@@ -119,9 +119,9 @@ int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
     if (!net_out && !dnet_out) {
       bool dpacked = false;
       LDSV_TRY(ldsv_launch_cnn(h, dnet, u_in, v_in, dout, nullptr, st, h->dcoef16, h->dtcbuf,
-                               &dpacked));
+                               &dpacked, true));
       LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st, h->coef16, h->tcbuf,
-                               &packed));
+                               &packed, true));
       LDSV_REQUIRE(packed == dpacked, LDSV_EINVAL, "learned step: network output forms differ");
       if (packed) {
         DerivCoef dc;
@@ -131,10 +131,12 @@ int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
                                     tc ? h->tcbuf + N : nullptr, ts, st);
       }
     } else {
-      LDSV_TRY(ldsv_launch_cnn(h, dnet, u_in, v_in, dout, nullptr, st));
+      LDSV_TRY(ldsv_launch_cnn(h, dnet, u_in, v_in, dout, nullptr, st, nullptr, nullptr, nullptr,
+                               true));
     }
     float* out = net_out ? net_out : h->netout;
-    if (net_out || dnet_out) LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st));
+    if (net_out || dnet_out)
+      LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st, nullptr, nullptr, nullptr, true));
     DerivCoef dc;
     dc.d = dout;
     return ldsv_internal_step_d(h, prm, out, bs, nullptr, 0, &dc, u_in, v_in, u_out, v_out,
@@ -143,14 +145,15 @@ int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
   }
   if (!net_out) {
     LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st, h->coef16, h->tcbuf,
-                             &packed));
+                             &packed, true));
     if (packed)
       return ldsv_internal_step16(h, prm, h->coef16, (size_t)LDSV_NCOEF * N, u_in, v_in, u_out,
                                   v_out, tc ? h->tcbuf : nullptr, tc ? h->tcbuf + N : nullptr, ts,
                                   st);
   }
   float* out = net_out ? net_out : h->netout;
-  if (net_out) LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st));
+  if (net_out)
+    LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, out, nullptr, st, nullptr, nullptr, nullptr, true));
   return ldsv_internal_step(h, prm, out, bs, u_in, v_in, u_out, v_out,
                             tc ? out + (size_t)LDSV_NCOEF * N : nullptr,
                             tc ? out + (size_t)(LDSV_NCOEF + 1) * N : nullptr, bs, st);
@@ -285,12 +288,14 @@ int learned_bwd_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net
   // the step's coefficients (and derivative values) and correction
   DerivCoef dc;
   if (dnet) {
-    LDSV_TRY(ldsv_launch_cnn(h, dnet, u_in, v_in, h->dnetout, nullptr, st));
+    LDSV_TRY(ldsv_launch_cnn(h, dnet, u_in, v_in, h->dnetout, nullptr, st, nullptr, nullptr,
+                             nullptr, true));
     LDSV_TRY(launch_zero(h, h->gdnet, h->nstate * LDSV_NOUT, st));
     dc.d = h->dnetout;
     dc.gd = h->gdnet;
   }
-  LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st));
+  LDSV_TRY(ldsv_launch_cnn(h, net, u_in, v_in, h->netout, nullptr, st, nullptr, nullptr, nullptr,
+                           true));
   LDSV_TRY(launch_zero(h, h->gnet, h->nstate * LDSV_NOUT, st));
   // FV path: d/du_in and d/d(raw coefficients)
   LDSV_TRY(ldsv_step_bwd(h, prm, h->netout, bs, h->gnet, bs, u_in, v_in, gu_out, gv_out, gu_in,

@@ -115,6 +115,27 @@ def test_packed_coefficients_equal_float_output_path(n, b):
     assert torch.equal(pu, fu) and torch.equal(pv, fv)
 
 
+@pytest.mark.parametrize("nx,ny,b", [(32, 16, 3), (64, 64, 4), (128, 64, 2)])
+def test_fused_first_layer_equals_layer_by_layer_forward(nx, ny, b):
+    """The learned step evaluates the network with layer 1 computed inside
+    layer 2's tiles (grids whose sides are multiples of 16); its network
+    output equals, bit for bit, the layer-by-layer forward of cnn_forward,
+    and so does the derivative network's."""
+    L_ = need_gpu()
+    announce("fused first layer", nx, ny, b)
+    net, _, _ = _net(L_, seed=4, last_scale=1.0)
+    dnet, _, _ = _net(L_, seed=6, last_scale=1.0)
+    s = L_.Solver(nx, ny, b)
+    u, v = s.init_state(L_.IC_GRF_PEAK, seed=13)
+    ref = s.cnn_forward(net, u, v).clone()
+    dref = s.cnn_forward(dnet, u, v).clone()
+    prm = L_.params(k_c=1, **KW)
+    _, _, got = s.learned_fv_step(prm, net, u, v, 1, want_net_out=True)
+    assert torch.equal(got, ref)
+    _, _, got, dgot = s.learned_d_fv_step(prm, net, dnet, u, v, 1, want_net_out=True)
+    assert torch.equal(got, ref) and torch.equal(dgot, dref)
+
+
 def test_zero_head_reproduces_plain_fv_and_kc():
     L_ = need_gpu()
     announce("zero head")
