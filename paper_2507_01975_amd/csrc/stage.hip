@@ -385,9 +385,13 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   }
   // y-faces: owners j in [j0-1, j0+TY-1], columns i in [i0, i0+TX-1]
   constexpr int kYF = (TY + 1) * TX;
+  // the y-face loop numbers the threads from wavefront 1, so that its
+  // partial last iteration and that of the x-face loop (which starts at
+  // wavefront 0) fall on different wavefronts
+  const int ty = ((int)threadIdx.x + kBlock - 64) & (kBlock - 1);
 #pragma unroll
   for (int k = 0; k < (kYF + kBlock - 1) / kBlock; ++k) {
-    const int t = k * kBlock + (int)threadIdx.x;
+    const int t = k * kBlock + ty;
     if (t >= kYF) break;
     const int r = t / TX, c = t - r * TX;
     const int li = c + kH, lj = r + 1;
