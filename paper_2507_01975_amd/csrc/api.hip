@@ -164,8 +164,11 @@ int one_step(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs
         a.ou = h->st_u;
         a.ov = h->st_v;
         LDSV_TRY(ldsv_launch_stage(h, p, a, st));
-        LDSV_TRY(ldsv_launch_project(h, h->st_u, h->st_v, s == 3 ? du : ku(s),
-                                     s == 3 ? dv : kv(s), nullptr, st, active));
+        h->speed_now = s == 3 ? h->speed_out : nullptr;
+        const int rp = ldsv_launch_project(h, h->st_u, h->st_v, s == 3 ? du : ku(s),
+                                           s == 3 ? dv : kv(s), nullptr, st, active);
+        h->speed_now = nullptr;
+        LDSV_TRY(rp);
       } else {
         // collocated RK4 without projection: stage outputs ping-pong
         LDSV_REQUIRE(false, LDSV_EDTYPE, "RK4 on the collocated layout is not provided; use SSPRK3");

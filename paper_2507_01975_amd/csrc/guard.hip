@@ -18,7 +18,7 @@
 
 int ldsv_launch_guard_redo(ldsv_handle* h, const ldsv_params* prm, const float* cu,
                            const float* cv, float* nu, float* nv, double thr, int redo,
-                           int* counts, int* any, hipStream_t st);
+                           int* counts, int* any, const double* smax, hipStream_t st);
 
 namespace {
 
@@ -42,6 +42,7 @@ struct RedoArgs {
   int redo;
   int* counts;
   int* any;
+  const double* smax;  // nullable: max(|u| + |v|) per trajectory of the learned state
 };
 
 __global__ void __launch_bounds__(kRedoBlock) k_guard_redo_pair(RedoArgs a) {
@@ -60,7 +61,12 @@ __global__ void __launch_bounds__(kRedoBlock) k_guard_redo_pair(RedoArgs a) {
   int* flag = reinterpret_cast<int*>(red + 2 * (kRedoBlock / 64));
 
   // 1. the guard: largest |u| + |v| per trajectory of the learned state
+  // (written by the step's last projection when smax is set)
   double m0 = 0.0, m1 = 0.0;
+  if (a.smax) {
+    m0 = a.smax[b0];
+    m1 = has1 ? a.smax[b0 + 1] : 0.0;
+  } else
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int t = k * kRedoBlock + (int)threadIdx.x;
@@ -308,7 +314,7 @@ __global__ void __launch_bounds__(kRedoBlock) k_guard_redo_pair(RedoArgs a) {
 // takes: FP32 MAC RK4 grids of at most 64 x 64 cells.
 int ldsv_launch_guard_redo(ldsv_handle* h, const ldsv_params* prm, const float* cu,
                            const float* cv, float* nu, float* nv, double thr, int redo,
-                           int* counts, int* any, hipStream_t st) {
+                           int* counts, int* any, const double* smax, hipStream_t st) {
   const int nx = h->g.nx, ny = h->g.ny;
   if (h->g.dtype != LDSV_F32 || h->g.layout != LDSV_MAC || prm->rk != LDSV_RK4 ||
       (size_t)nx * ny > (size_t)kRedoE * kRedoBlock)
@@ -363,6 +369,7 @@ int ldsv_launch_guard_redo(ldsv_handle* h, const ldsv_params* prm, const float* 
   a.redo = redo;
   a.counts = counts;
   a.any = any;
+  a.smax = smax;
   LDSV_HIP(hipFuncSetAttribute((const void*)k_guard_redo_pair,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   LDSV_TLAUNCH(h, 7, k_guard_redo_pair, dim3(h->npairs), dim3(kRedoBlock), lds, st, a);

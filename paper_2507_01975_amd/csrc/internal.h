@@ -121,6 +121,14 @@ struct ldsv_handle {
   void* adj_k = nullptr;
   void* adj_g = nullptr;
   void* save_u = nullptr;        // rollout fallback copy of u_{k-1}
+  // rollout guard: while speed_out is set, the last projection of an RK4
+  // step that runs the one-trajectory kernel (all trajectories active)
+  // writes max(|u| + |v|) of each trajectory's new state there (infinity if
+  // a value is not finite) and sets speed_written; speed_now is the target
+  // the step hands to its last projection
+  double* speed_out = nullptr;
+  double* speed_now = nullptr;
+  bool speed_written = false;
   void* zpre_blk = nullptr;      // network backward workspace
   void* roll_blk = nullptr;      // rollout-backward checkpoints and segment states
   size_t roll_bytes = 0;

@@ -27,7 +27,7 @@ int ldsv_internal_step_masked(ldsv_handle* h, const ldsv_params* p, const void* 
                               hipStream_t st);
 int ldsv_launch_guard_redo(ldsv_handle* h, const ldsv_params* prm, const float* cu,
                            const float* cv, float* nu, float* nv, double thr, int redo,
-                           int* counts, int* any, hipStream_t st);
+                           int* counts, int* any, const double* smax, hipStream_t st);
 int ldsv_internal_step_d(ldsv_handle* h, const ldsv_params* p, const float* coef, size_t cbs,
                          const uint16_t* coef16, size_t cbs16, const DerivCoef* dc,
                          const void* su, const void* sv, void* du, void* dv, const float* tcu,
@@ -165,7 +165,9 @@ int learned_step(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
 int ensure_rollout_buffers(ldsv_handle* h) {
   if (h->save_u) return LDSV_OK;
   const size_t sb = h->nstate * h->esize;
-  return ldsv_alloc(h, &h->save_u, 2 * sb + 64 * sizeof(int) + (size_t)h->g.batch * sizeof(int),
+  // u, v of a step, the any-flag, per-trajectory flags and speeds
+  return ldsv_alloc(h, &h->save_u,
+                    2 * sb + 64 * sizeof(int) + (size_t)h->g.batch * (sizeof(int) + sizeof(double)) + 8,
                     "rollout guard buffers");
 }
 
@@ -206,11 +208,14 @@ int rollout_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
   void* nv = nullptr;
   int* any = nullptr;
   int* bad = nullptr;
+  double* speeds = nullptr;
   if (guard) {
     nu = h->save_u;
     nv = (char*)h->save_u + sb;
     any = (int*)((char*)h->save_u + 2 * sb);
     bad = any + 64;
+    const size_t so = (2 * sb + 64 * sizeof(int) + (size_t)h->g.batch * sizeof(int) + 7) & ~(size_t)7;
+    speeds = (double*)((char*)h->save_u + so);
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, any, 1);
     LDSV_LAUNCHED();
   }
@@ -219,14 +224,22 @@ int rollout_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
     const int idx = first_index + k;
     if (net) {
       if (guard) {
-        LDSV_TRY(learned_step(h, prm, net, (const float*)cu, (const float*)cv, (float*)nu,
-                              (float*)nv, idx, nullptr, st, dnet));
+        // the step's last projection reports each trajectory's largest
+        // |u| + |v| where it can (the one-trajectory kernels)
+        h->speed_out = speeds;
+        h->speed_written = false;
+        const int rs = learned_step(h, prm, net, (const float*)cu, (const float*)cv, (float*)nu,
+                                    (float*)nv, idx, nullptr, st, dnet);
+        h->speed_out = nullptr;
+        LDSV_TRY(rs);
+        const double* smax = h->speed_written ? speeds : nullptr;
+        h->speed_written = false;
         // small grids: detection and redo in one launch; otherwise the
         // detection kernel and the plain step masked to the flagged
         // trajectories
         const int rc = ldsv_launch_guard_redo(h, prm, (const float*)cu, (const float*)cv,
                                               (float*)nu, (float*)nv, thr, prm->fallback_enable,
-                                              fallback_flags, any, st);
+                                              fallback_flags, any, smax, st);
         if (rc == LDSV_ESHAPE) {
           hipLaunchKernelGGL(k_guard_detect, dim3(h->g.batch), dim3(kGuardBlock), 0, st,
                              (const float*)nu, (const float*)nv, h->ncell, thr, bad,

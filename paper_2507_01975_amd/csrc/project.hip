@@ -712,7 +712,8 @@ template <int LOGN>
 __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
     const float* __restrict__ us, const float* __restrict__ vs, float* __restrict__ uo,
     float* __restrict__ vo, float* __restrict__ po, const Cx<float>* __restrict__ tw,
-    const double* __restrict__ pinv, float idx, float idy, const int* active) {
+    const double* __restrict__ pinv, float idx, float idy, const int* active,
+    double* __restrict__ smax) {
   constexpr int N = 1 << LOGN, NH = N / 2, LOGT = LOGN - 1, BLOCK = (N * NH) / 8;
   constexpr int S = fftreg::plan_stages(LOGN);
   constexpr int LR0 = fftreg::plan_lr(LOGN, 0), LRL = fftreg::plan_lr(LOGN, S - 1);
@@ -898,6 +899,7 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
   float4* uo4 = reinterpret_cast<float4*>(uo + (size_t)b * plane);
   float4* vo4 = reinterpret_cast<float4*>(vo + (size_t)b * plane);
   float4* po4 = po ? reinterpret_cast<float4*>(po + (size_t)b * plane) : nullptr;
+  double m = 0.0;  // largest |u| + |v| of the thread's cells (smax)
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int id = k * BLOCK + tid;
@@ -905,11 +907,30 @@ __global__ void __launch_bounds__((1 << (2 * LOGN)) / 16) k_project_real_r(
     const float4 pc = *reinterpret_cast<const float4*>(&su[y * SP + x0]);
     const float4 ps = *reinterpret_cast<const float4*>(&su[((y - 1) & (N - 1)) * SP + x0]);
     const float pw = su[y * SP + ((x0 - 1) & (N - 1))];
-    uo4[id] = float4{ku[k].x - (pc.x - pw) * idx, ku[k].y - (pc.y - pc.x) * idx,
-                     ku[k].z - (pc.z - pc.y) * idx, ku[k].w - (pc.w - pc.z) * idx};
-    vo4[id] = float4{kv[k].x - (pc.x - ps.x) * idy, kv[k].y - (pc.y - ps.y) * idy,
-                     kv[k].z - (pc.z - ps.z) * idy, kv[k].w - (pc.w - ps.w) * idy};
+    const float4 un{ku[k].x - (pc.x - pw) * idx, ku[k].y - (pc.y - pc.x) * idx,
+                    ku[k].z - (pc.z - pc.y) * idx, ku[k].w - (pc.w - pc.z) * idx};
+    const float4 vn{kv[k].x - (pc.x - ps.x) * idy, kv[k].y - (pc.y - ps.y) * idy,
+                    kv[k].z - (pc.z - ps.z) * idy, kv[k].w - (pc.w - ps.w) * idy};
+    uo4[id] = un;
+    vo4[id] = vn;
     if (po4) po4[id] = pc;
+    if (smax) {
+      const float ua[4] = {un.x, un.y, un.z, un.w}, va[4] = {vn.x, vn.y, vn.z, vn.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double sp = (double)fabsf(ua[e]) + (double)fabsf(va[e]);
+        m = isfinite(sp) ? fmax(m, sp) : INFINITY;
+      }
+    }
+  }
+  if (smax) {  // uniform: the workgroup's maximum, the wavefronts' through F1
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((tid & 63) == 0) F1[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < BLOCK / 64; ++w) m = fmax(m, F1[w]);
+      smax[b] = m;
+    }
   }
 }
 
@@ -931,10 +952,13 @@ int launch_project_real(ldsv_handle* h, const void* us, const void* vs, void* uo
   const float fx = (float)(h->g.nx / h->g.lx), fy = (float)(h->g.ny / h->g.ly);
   LDSV_HIP(hipFuncSetAttribute((const void*)k_project_real_r<LOGN>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  // the rollout guard's per-trajectory speed, when the step asks for it
+  double* smax = active ? nullptr : h->speed_now;
   LDSV_TLAUNCH(h, 2, k_project_real_r<LOGN>, dim3(h->g.batch), dim3(block), lds, st,
                (const float*)us, (const float*)vs, (float*)uo, (float*)vo, (float*)po,
-               (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active);
+               (const Cx<float>*)h->twx, (const double*)h->pinv, fx, fy, active, smax);
   LDSV_LAUNCHED();
+  if (smax) h->speed_written = true;
   return LDSV_OK;
 }
 
