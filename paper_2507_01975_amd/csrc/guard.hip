@@ -66,17 +66,18 @@ __global__ void __launch_bounds__(kRedoBlock) k_guard_redo_pair(RedoArgs a) {
   if (a.smax) {
     m0 = a.smax[b0];
     m1 = has1 ? a.smax[b0 + 1] : 0.0;
-  } else
+  } else {
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int t = k * kRedoBlock + (int)threadIdx.x;
-    if (t < n) {
-      const size_t g0 = (size_t)b0 * plane + t;
-      const double s0 = (double)fabsf(a.nu[g0]) + (double)fabsf(a.nv[g0]);
-      m0 = isfinite(s0) ? fmax(m0, s0) : INFINITY;
-      if (has1) {
-        const double s1 = (double)fabsf(a.nu[g0 + plane]) + (double)fabsf(a.nv[g0 + plane]);
-        m1 = isfinite(s1) ? fmax(m1, s1) : INFINITY;
+    for (int k = 0; k < E; ++k) {
+      const int t = k * kRedoBlock + (int)threadIdx.x;
+      if (t < n) {
+        const size_t g0 = (size_t)b0 * plane + t;
+        const double s0 = (double)fabsf(a.nu[g0]) + (double)fabsf(a.nv[g0]);
+        m0 = isfinite(s0) ? fmax(m0, s0) : INFINITY;
+        if (has1) {
+          const double s1 = (double)fabsf(a.nu[g0 + plane]) + (double)fabsf(a.nv[g0 + plane]);
+          m1 = isfinite(s1) ? fmax(m1, s1) : INFINITY;
+        }
       }
     }
   }
