@@ -313,10 +313,12 @@ def test_guard_falls_back_to_plain_fv_for_the_failing_trajectory_only():
 
 @pytest.mark.parametrize("n,b,bad", [(32, 4, 1), (128, 4, 2)])
 def test_guard_fallback_beside_a_good_partner(n, b, bad):
-    """The plain-FV redo of one trajectory of a packed pair (the projection
-    transforms two trajectories at once): its good partner keeps its learned
-    result bit for bit, the redone one follows the oracle's plain steps; at
-    32^2 the one-workgroup projection, at 128^2 the three passes."""
+    """The plain-FV redo of one trajectory of a packed pair: its good
+    partner keeps its learned result bit for bit, the redone one follows the
+    oracle's plain steps; at 32^2 the one-launch guard (the redo of the pair
+    in LDS, whose projection transforms the two trajectories at once), at
+    128^2 the detection kernel and the plain step masked to the flagged
+    trajectory."""
     L_ = need_gpu()
     announce("guard beside a good partner", n, b, bad)
     kw = dict(KW, dt=0.005 * 32 / n)
