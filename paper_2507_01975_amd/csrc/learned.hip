@@ -51,21 +51,27 @@ int launch_zero(ldsv_handle* h, float* p, size_t n, hipStream_t st) {
 
 // The rollout guard of one learned step, one workgroup per trajectory: the
 // largest |u| + |v| over the trajectory's cells (in FP64; a non-finite value
-// counts as infinite) against the bound thr.  Writes bad[b] (1: redo with
-// the plain step), adds it to counts[b] (nullable) and raises *any.
+// counts as infinite) against the bound thr, or that maximum as the step's
+// last projection reported it (smax, nullable).  Writes bad[b] (1: redo
+// with the plain step), adds it to counts[b] (nullable) and raises *any.
 constexpr int kGuardBlock = 256;
 __global__ void __launch_bounds__(kGuardBlock) k_guard_detect(const float* __restrict__ u,
                                                               const float* __restrict__ v,
                                                               size_t n, double thr, int* bad,
-                                                              int* counts, int* any) {
+                                                              int* counts, int* any,
+                                                              const double* __restrict__ smax) {
   __shared__ double red[kGuardBlock / 64];
   const int b = blockIdx.x;
   const float* ub = u + (size_t)b * n;
   const float* vb = v + (size_t)b * n;
   double m = 0.0;
-  for (size_t i = threadIdx.x; i < n; i += kGuardBlock) {
-    const double s = (double)fabsf(ub[i]) + (double)fabsf(vb[i]);
-    m = isfinite(s) ? fmax(m, s) : INFINITY;
+  if (smax) {  // written by the step's last projection
+    m = smax[b];
+  } else {
+    for (size_t i = threadIdx.x; i < n; i += kGuardBlock) {
+      const double s = (double)fabsf(ub[i]) + (double)fabsf(vb[i]);
+      m = isfinite(s) ? fmax(m, s) : INFINITY;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -243,7 +249,7 @@ int rollout_impl(ldsv_handle* h, const ldsv_params* prm, const ldsv_net* net, co
         if (rc == LDSV_ESHAPE) {
           hipLaunchKernelGGL(k_guard_detect, dim3(h->g.batch), dim3(kGuardBlock), 0, st,
                              (const float*)nu, (const float*)nv, h->ncell, thr, bad,
-                             fallback_flags, any);
+                             fallback_flags, any, smax);
           LDSV_LAUNCHED();
           if (prm->fallback_enable)
             LDSV_TRY(ldsv_internal_step_masked(h, prm, cu, cv, nu, nv, bad, st));
