@@ -227,7 +227,9 @@ __device__ __forceinline__ float fb_field(const float* f, size_t plane, int ch, 
 // COEF: 0 plain stencil, 1 float raw coefficients, 2 bf16 raw coefficients,
 // 3 flux block (uniform kernels and fields), 4 and 5: as 1 and 2 plus the
 // learned derivative values in the same form
-template <typename T, int COEF, int TX, int TY>
+// ALL: every physics term on (the mask known at compile time, no per-face
+// tests of it)
+template <typename T, int COEF, int TX, int TY, bool ALL = false>
 __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny) {
   constexpr int W = TX + 2 * kH, Hh = TY + 2 * kH;
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       }
     }
   }
-  if ((ph.mask & LDSV_FORCING) && threadIdx.x < TY)
+  if ((ALL || (ph.mask & LDSV_FORCING)) && threadIdx.x < TY)
     frow[threadIdx.x] =
         ph.amp != 0.0 ? (T)(ph.amp * sin(ph.kf * ((j0 + threadIdx.x) + 0.5) * ph.dy)) : (T)0;
   // operands of the RK combination, prefetched before the flux phases
@@ -309,8 +311,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
   }
   __syncthreads();
 
-  const bool adv = ph.mask & LDSV_ADVECTION;
-  const bool visc = ph.mask & LDSV_VISCOSITY;
+  const bool adv = ALL || (ph.mask & LDSV_ADVECTION);
+  const bool visc = ALL || (ph.mask & LDSV_VISCOSITY);
   const T nu = ph.nu;
   const T i24dx = ph.i24dx, i24dy = ph.i24dy;
   constexpr int IC = COEF == 4 ? 1 : (COEF == 5 ? 2 : COEF);  // interpolation form
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
 
   const T idx = ph.idx, idy = ph.idy;
   const T drag = ph.drag;
-  const bool force = ph.mask & LDSV_FORCING;
+  const bool force = ALL || (ph.mask & LDSV_FORCING);
 #pragma unroll
   for (int k = 0; k < kCellPer; ++k) {
     const int t = k * kBlock + (int)threadIdx.x;
@@ -691,6 +693,9 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
     else if (a.coef)                                                                              \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 1, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
+    else if (ph.mask == LDSV_ALL_PHYSICS)                                                         \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, tx, ty, true>), grid, dim3(kBlock), 0, st, p, ph, cb, \
+                   nx, ny);                                                                       \
     else                                                                                          \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
