@@ -600,11 +600,12 @@ __global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, PhysT<T> p
 
 // the learned-derivative stage modes exist for FP32 states only (the
 // learned path's precision)
-template <typename T, int COEF, int TX, int TY>
+template <typename T, int COEF, int TX, int TY, bool ALL = false>
 int launch_learned_d(ldsv_handle* h, dim3 grid, hipStream_t st, const StagePtrs<T>& p,
                      const PhysT<T>& ph, const CombT<T>& cb, int nx, int ny) {
   if constexpr (std::is_same<T, float>::value) {
-    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, COEF, TX, TY>), grid, dim3(kBlock), 0, st, p, ph, cb, nx, ny);
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, COEF, TX, TY, ALL>), grid, dim3(kBlock), 0, st, p, ph, cb,
+                 nx, ny);
     return LDSV_OK;
   } else {
     ldsv_set_error("stage: learned derivative stencils need FP32 states");
@@ -678,22 +679,39 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
       TX /= 2;
   }
   dim3 grid((nx / TX) * (ny / TY), h->g.batch);
+  // every physics term on (all the configurations run so): the mask fixed at
+  // compile time in every mode (the float- and bf16-coefficient forms of a
+  // mode then compile to the same arithmetic and stay equal bit for bit)
+  const bool all = ph.mask == LDSV_ALL_PHYSICS;
 #define LDSV_STAGE_CASE(tx, ty)                                                                   \
   if (TX == tx && TY == ty) {                                                                     \
-    if (a.fbw)                                                                                    \
+    if (a.fbw && all)                                                                             \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 3, tx, ty, true>), grid, dim3(kBlock), 0, st, p, ph, cb, \
+                   nx, ny);                                                                       \
+    else if (a.fbw)                                                                               \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 3, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
+    else if (a.coef16 && a.dcoef16 && all)                                                        \
+      LDSV_TRY((launch_learned_d<T, 5, tx, ty, true>(h, grid, st, p, ph, cb, nx, ny)));           \
     else if (a.coef16 && a.dcoef16)                                                               \
       LDSV_TRY((launch_learned_d<T, 5, tx, ty>(h, grid, st, p, ph, cb, nx, ny)));                 \
+    else if (a.coef16 && all)                                                                     \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 2, tx, ty, true>), grid, dim3(kBlock), 0, st, p, ph, cb, \
+                   nx, ny);                                                                       \
     else if (a.coef16)                                                                            \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 2, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
+    else if (a.coef && a.dcoef && all)                                                            \
+      LDSV_TRY((launch_learned_d<T, 4, tx, ty, true>(h, grid, st, p, ph, cb, nx, ny)));           \
     else if (a.coef && a.dcoef)                                                                   \
       LDSV_TRY((launch_learned_d<T, 4, tx, ty>(h, grid, st, p, ph, cb, nx, ny)));                 \
+    else if (a.coef && all)                                                                       \
+      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 1, tx, ty, true>), grid, dim3(kBlock), 0, st, p, ph, cb, \
+                   nx, ny);                                                                       \
     else if (a.coef)                                                                              \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 1, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
-    else if (ph.mask == LDSV_ALL_PHYSICS)                                                         \
+    else if (all)                                                                                 \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, tx, ty, true>), grid, dim3(kBlock), 0, st, p, ph, cb, \
                    nx, ny);                                                                       \
     else                                                                                          \
