@@ -228,8 +228,12 @@ __device__ __forceinline__ float fb_field(const float* f, size_t plane, int ch, 
 // 3 flux block (uniform kernels and fields), 4 and 5: as 1 and 2 plus the
 // learned derivative values in the same form
 // ALL: every physics term on (the mask known at compile time, no per-face
-// tests of it)
-template <typename T, int COEF, int TX, int TY, bool ALL = false>
+// tests of it).  RK: the stage's combination known at compile time (0: from
+// cb at run time; 1: beta uc + eps R, accumulator wacc R, the first RK4
+// stage; 2: alpha un + eps R, accumulator gamma acc + wacc R, the middle
+// ones; 3: alpha un + eps R + delta acc, no accumulator, the last one), its
+// zero terms and their loads dropped
+template <typename T, int COEF, int TX, int TY, bool ALL = false, int RK = 0>
 __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> ph, CombT<T> cb, int nx,
                                                       int ny) {
   constexpr int W = TX + 2 * kH, Hh = TY + 2 * kH;
@@ -290,8 +294,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
         ph.amp != 0.0 ? (T)(ph.amp * sin(ph.kf * ((j0 + threadIdx.x) + 0.5) * ph.dy)) : (T)0;
   // operands of the RK combination, prefetched before the flux phases
   T pun[kCellPer], pvn[kCellPer], pau[kCellPer], pav[kCellPer];
-  const bool need_un = cb.need_un;
-  const bool need_acc = cb.need_acc;
+  const bool need_un = RK == 0 ? (bool)cb.need_un : RK != 1;
+  const bool need_acc = RK == 0 ? (bool)cb.need_acc : RK != 1;
 #pragma unroll
   for (int k = 0; k < kCellPer; ++k) {
     const int t = k * kBlock + (int)threadIdx.x;
@@ -469,8 +473,20 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
       rv -= drag * vc;
     }
     const unsigned g = (unsigned)(j0 + r) * (unsigned)nx + (unsigned)(i0 + c);
-    T ou = cb.beta * uc + cb.eps * ru + cb.alpha * pun[k] + cb.delta * pau[k];
-    T ov = cb.beta * vc + cb.eps * rv + cb.alpha * pvn[k] + cb.delta * pav[k];
+    T ou, ov;
+    if constexpr (RK == 1) {
+      ou = cb.beta * uc + cb.eps * ru;
+      ov = cb.beta * vc + cb.eps * rv;
+    } else if constexpr (RK == 2) {
+      ou = cb.alpha * pun[k] + cb.eps * ru;
+      ov = cb.alpha * pvn[k] + cb.eps * rv;
+    } else if constexpr (RK == 3) {
+      ou = cb.alpha * pun[k] + cb.eps * ru + cb.delta * pau[k];
+      ov = cb.alpha * pvn[k] + cb.eps * rv + cb.delta * pav[k];
+    } else {
+      ou = cb.beta * uc + cb.eps * ru + cb.alpha * pun[k] + cb.delta * pau[k];
+      ov = cb.beta * vc + cb.eps * rv + cb.alpha * pvn[k] + cb.delta * pav[k];
+    }
     if (p.tcu) {
       const size_t gt = (size_t)b * p.tcbs + (size_t)(j0 + r) * nx + (i0 + c);
       ou += (T)p.tcu[gt];
@@ -478,7 +494,10 @@ __global__ void __launch_bounds__(kBlock) k_stage_mac(StagePtrs<T> p, PhysT<T> p
     }
     PlaneBuf<T>(p.ou + boff, pl).st(g, ou);
     PlaneBuf<T>(p.ov + boff, pl).st(g, ov);
-    if (p.oaccu) {
+    if (RK == 1) {
+      PlaneBuf<T>(p.oaccu + boff, pl).st(g, cb.wacc * ru);
+      PlaneBuf<T>(p.oaccv + boff, pl).st(g, cb.wacc * rv);
+    } else if (RK == 2 || (RK == 0 && p.oaccu)) {
       PlaneBuf<T>(p.oaccu + boff, pl).st(g, cb.gamma * pau[k] + cb.wacc * ru);
       PlaneBuf<T>(p.oaccv + boff, pl).st(g, cb.gamma * pav[k] + cb.wacc * rv);
     }
@@ -598,6 +617,25 @@ __global__ void __launch_bounds__(kBlock) k_stage_col(StagePtrs<T> p, PhysT<T> p
   }
 }
 
+// the plain stage with every physics term on, its RK combination kind rk
+// (see k_stage_mac) fixed at compile time
+template <typename T, int TX, int TY>
+void launch_plain_all(ldsv_handle* h, dim3 grid, hipStream_t st, const StagePtrs<T>& p,
+                      const PhysT<T>& ph, const CombT<T>& cb, int nx, int ny, int rk) {
+  if (rk == 1)
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, TX, TY, true, 1>), grid, dim3(kBlock), 0, st, p, ph, cb,
+                 nx, ny);
+  else if (rk == 2)
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, TX, TY, true, 2>), grid, dim3(kBlock), 0, st, p, ph, cb,
+                 nx, ny);
+  else if (rk == 3)
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, TX, TY, true, 3>), grid, dim3(kBlock), 0, st, p, ph, cb,
+                 nx, ny);
+  else
+    LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, TX, TY, true>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,
+                 ny);
+}
+
 // the learned-derivative stage modes exist for FP32 states only (the
 // learned path's precision)
 template <typename T, int COEF, int TX, int TY, bool ALL = false>
@@ -683,6 +721,18 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
   // compile time in every mode (the float- and bf16-coefficient forms of a
   // mode then compile to the same arithmetic and stay equal bit for bit)
   const bool all = ph.mask == LDSV_ALL_PHYSICS;
+  // the RK4 stages' combination patterns (zero coefficients; SSP-RK3 and
+  // the rest keep the general form)
+  int rk = 0;
+  {
+    const bool acc_out = a.oaccu != nullptr;
+    if (a.alpha == 0.0 && a.delta == 0.0 && a.gamma == 0.0 && acc_out)
+      rk = 1;
+    else if (a.beta == 0.0 && a.delta == 0.0 && a.alpha != 0.0 && a.gamma != 0.0 && acc_out)
+      rk = 2;
+    else if (a.beta == 0.0 && a.alpha != 0.0 && a.delta != 0.0 && !acc_out)
+      rk = 3;
+  }
 #define LDSV_STAGE_CASE(tx, ty)                                                                   \
   if (TX == tx && TY == ty) {                                                                     \
     if (a.fbw && all)                                                                             \
@@ -712,8 +762,7 @@ int launch_stage_t(ldsv_handle* h, const ldsv_params* prm, const StageArgs& a, h
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 1, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
     else if (all)                                                                                 \
-      LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, tx, ty, true>), grid, dim3(kBlock), 0, st, p, ph, cb, \
-                   nx, ny);                                                                       \
+      launch_plain_all<T, tx, ty>(h, grid, st, p, ph, cb, nx, ny, rk);                            \
     else                                                                                          \
       LDSV_TLAUNCH(h, 0, (k_stage_mac<T, 0, tx, ty>), grid, dim3(kBlock), 0, st, p, ph, cb, nx,   \
                    ny);                                                                           \
