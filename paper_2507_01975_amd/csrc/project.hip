@@ -169,7 +169,9 @@ __global__ void __launch_bounds__(kColBlock) k_col_solve(Cx<T>* __restrict__ z,
 // Pass 1: the divergence of the pair (d_b + i d_{b+1}) is formed straight
 // into the first stage's registers, the FFT along x runs, and its last
 // stage stores the spectrum rows to global memory.
-template <int LOGN, int LOGR>
+// FULL: every trajectory active and the batch even (both of every pair
+// present), known at compile time: no per-point tests
+template <int LOGN, int LOGR, bool FULL = false>
 __global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_div_rowfft_r(
     const float* __restrict__ us, const float* __restrict__ vs, Cx<float>* __restrict__ z,
     const Cx<float>* __restrict__ twx, int ny, int batch, float idx, float idy,
@@ -182,9 +184,9 @@ __global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_div_rowfft_r(
   const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const int pair = band / gridDim.x;
   const int b0 = 2 * pair;
-  if (!pair_active(active, b0, batch)) return;
-  const bool has0 = !active || active[b0];
-  const bool has1 = (b0 + 1) < batch && (!active || active[b0 + 1]);
+  if (!FULL && !pair_active(active, b0, batch)) return;
+  const bool has0 = FULL || !active || active[b0];
+  const bool has1 = FULL || ((b0 + 1) < batch && (!active || active[b0 + 1]));
   const int j0 = (band - pair * gridDim.x) << LOGR;
   for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = twx[e];
   const size_t plane = (size_t)N * ny;
@@ -226,7 +228,8 @@ __global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_div_rowfft_r(
 // above the band, whose 2^LOGR - 1 rows get u = u* - G p.  Bands of
 // 2^LOGR - 1 output rows (the last one clipped at ny, so that every output
 // row is written by one workgroup and in-place calls stay safe).
-template <int LOGN, int LOGR>
+// FULL: as in k_div_rowfft_r, and no p output
+template <int LOGN, int LOGR, bool FULL = false>
 __global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_rowifft_grad_r(
     const Cx<float>* __restrict__ z, const Cx<float>* __restrict__ twx,
     const float* __restrict__ us, const float* __restrict__ vs, float* __restrict__ uo,
@@ -241,9 +244,10 @@ __global__ void __launch_bounds__(((1 << LOGN) << LOGR) / 8) k_rowifft_grad_r(
   const int band = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const int pair = band / gridDim.x;
   const int b0 = 2 * pair;
-  if (!pair_active(active, b0, batch)) return;
-  const bool w0 = !active || active[b0];
-  const bool w1 = (b0 + 1) < batch && (!active || active[b0 + 1]);
+  if (!FULL && !pair_active(active, b0, batch)) return;
+  const bool w0 = FULL || !active || active[b0];
+  const bool w1 = FULL || ((b0 + 1) < batch && (!active || active[b0 + 1]));
+  if (FULL) po = nullptr;
   const int o0 = (band - pair * gridDim.x) * (ROWS - 1);  // first output row
   for (int e = threadIdx.x; e < N; e += BLOCK) W[e] = twx[e];
   const size_t plane = (size_t)N * ny;
@@ -601,11 +605,17 @@ bool launch_div_rowfft_r(ldsv_handle* h, const void* us, const void* vs, hipStre
     const int logn = h->log2nx, logr = __builtin_ctz((unsigned)rows);
     const dim3 grid(h->g.ny / rows, h->npairs);
     const float idx = (float)(h->g.nx / h->g.lx), idy = (float)(h->g.ny / h->g.ly);
+    const bool full = !active && h->g.batch % 2 == 0;
 #define LDSV_ROWR(LN, LR)                                                                        \
   if (logn == LN && logr == LR) {                                                                \
-    LDSV_TLAUNCH(h, 1, (k_div_rowfft_r<LN, LR>), grid, dim3(((1 << LN) << LR) / 8), 0, st,        \
-                 (const float*)us, (const float*)vs, (Cx<float>*)h->zspec,                        \
-                 (const Cx<float>*)h->twx, h->g.ny, h->g.batch, idx, idy, active);               \
+    if (full)                                                                                    \
+      LDSV_TLAUNCH(h, 1, (k_div_rowfft_r<LN, LR, true>), grid, dim3(((1 << LN) << LR) / 8), 0,    \
+                   st, (const float*)us, (const float*)vs, (Cx<float>*)h->zspec,                 \
+                   (const Cx<float>*)h->twx, h->g.ny, h->g.batch, idx, idy, active);             \
+    else                                                                                         \
+      LDSV_TLAUNCH(h, 1, (k_div_rowfft_r<LN, LR>), grid, dim3(((1 << LN) << LR) / 8), 0, st,      \
+                   (const float*)us, (const float*)vs, (Cx<float>*)h->zspec,                     \
+                   (const Cx<float>*)h->twx, h->g.ny, h->g.batch, idx, idy, active);             \
     return true;                                                                                 \
   }
     LDSV_ROWR(6, 3) LDSV_ROWR(6, 4)
@@ -632,12 +642,19 @@ bool launch_rowifft_grad_r(ldsv_handle* h, const void* us, const void* vs, void*
     const int logr = logn >= 11 ? 2 : 3;
     const int outr = (1 << logr) - 1;
     const dim3 grid((h->g.ny + outr - 1) / outr, h->npairs);
+    const bool full = !active && h->g.batch % 2 == 0 && !po;
 #define LDSV_ROW3R(LN, LR)                                                                       \
   if (logn == LN && logr == LR) {                                                                \
-    LDSV_TLAUNCH(h, 3, (k_rowifft_grad_r<LN, LR>), grid, dim3(((1 << LN) << LR) / 8), 0, st,      \
-                 (const Cx<float>*)h->zspec, (const Cx<float>*)h->twx, (const float*)us,          \
-                 (const float*)vs, (float*)uo, (float*)vo, (float*)po, h->g.ny, h->g.batch, idx,  \
-                 idy, active);                                                                   \
+    if (full)                                                                                    \
+      LDSV_TLAUNCH(h, 3, (k_rowifft_grad_r<LN, LR, true>), grid, dim3(((1 << LN) << LR) / 8), 0,  \
+                   st, (const Cx<float>*)h->zspec, (const Cx<float>*)h->twx, (const float*)us,   \
+                   (const float*)vs, (float*)uo, (float*)vo, (float*)po, h->g.ny, h->g.batch,    \
+                   idx, idy, active);                                                            \
+    else                                                                                         \
+      LDSV_TLAUNCH(h, 3, (k_rowifft_grad_r<LN, LR>), grid, dim3(((1 << LN) << LR) / 8), 0, st,    \
+                   (const Cx<float>*)h->zspec, (const Cx<float>*)h->twx, (const float*)us,       \
+                   (const float*)vs, (float*)uo, (float*)vo, (float*)po, h->g.ny, h->g.batch,    \
+                   idx, idy, active);                                                            \
     return true;                                                                                 \
   }
     LDSV_ROW3R(6, 3) LDSV_ROW3R(7, 3) LDSV_ROW3R(8, 3) LDSV_ROW3R(9, 3) LDSV_ROW3R(10, 3)
